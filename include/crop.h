@@ -1,0 +1,180 @@
+/*
+ * crop.h -- C ABI of the MI355X column-row parallel (CRoP) library.
+ *
+ * The library computes, on one AMD MI355X (gfx950), the data-parallel hot
+ * path of the column-row method of Campagna, Kutzkov and Pagh, "On
+ * Parallelizing Matrix Multiplication by the Column-Row Method":
+ *
+ *   - enumerate the nonzero terms of C = sum_k a_k b_k^T (Section 4,
+ *     notation: entry (i,j) has weight sum_k a_k(i) b_k(j)), or all item
+ *     pairs of each transaction of a {0,1} stream (Section 7: the pairs of a
+ *     transaction are the entries above the diagonal of v_T v_T^T);
+ *   - route every entry (i,j) to one of P partitions by the consistent hash
+ *     h(i,j) = (h_a(i) + h_b(j)) mod 2^32 (Section 5, Lemma 1 and its proof;
+ *     Figure 1), partition = (h * P) >> 32;
+ *   - accumulate each partition exactly (uint32 supports or fp32 sums), or
+ *     in Space-Saving summaries of ell slots per bucket (Section 4, frequent
+ *     items mining; Figure 1), bucket = (h * P * B) >> 32;
+ *   - read back per-partition results or the top-K entries.
+ *
+ * Hash family (the paper leaves it open): seed -> (alpha_a, beta_a,
+ * alpha_b, beta_b) are the first four outputs of SplitMix64 started at the
+ * seed; h_a(x) = ((alpha_a * x + beta_a) mod 2^64) >> 32, likewise h_b.
+ *
+ * Conventions for every call:
+ *   - Pointers marked "device" must be device memory of the context's GPU;
+ *     pointers marked "host" must be host memory.  Where a crop_mem argument
+ *     is present it says which.
+ *   - Calls return a crop_status; they never throw and never abort.  On a
+ *     non-OK status, crop_last_error_detail() gives a message.
+ *   - Run calls are asynchronous on the context's HIP stream: they return
+ *     after enqueueing.  Read calls synchronize that stream.
+ *   - Results live in library-owned device memory until the next run, load
+ *     or crop_destroy.  The caller owns every buffer it passes in.
+ *   - One context must not be used from two threads at once; separate
+ *     contexts are independent.
+ */
+#ifndef CROP_H
+#define CROP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CROP_ABI_VERSION 1
+
+typedef enum crop_status {
+    CROP_OK = 0,
+    CROP_E_ARG = -1,          /* invalid argument (null pointer, bad size)   */
+    CROP_E_STATE = -2,        /* call out of order, e.g. run before load     */
+    CROP_E_INPUT = -3,        /* input violates the CSR contract; see
+                                 crop_last_error_index()                      */
+    CROP_E_CAPACITY = -4,     /* output buffer too small; *written holds the
+                                 required element count                       */
+    CROP_E_NOMEM = -5,        /* device allocation failed                     */
+    CROP_E_HIP = -6,          /* a HIP runtime call failed; see detail        */
+    CROP_E_UNSUPPORTED = -7   /* parameters outside the supported range       */
+} crop_status;
+
+typedef enum crop_mem { CROP_MEM_HOST = 0, CROP_MEM_DEVICE = 1 } crop_mem;
+typedef enum crop_own { CROP_OWN_COPY = 0, CROP_OWN_BORROW = 1 } crop_own;
+
+typedef struct crop_ctx crop_ctx;
+
+/* Tuning knobs; a zero field means "choose automatically". */
+typedef struct crop_tune {
+    uint32_t bins_per_partition; /* routing bins per partition (S >= 1)       */
+    uint32_t table_slots;        /* LDS hash-table slots per aggregation
+                                    workgroup; power of two, 1024..16384      */
+    uint32_t rows_per_chunk;     /* vectors per enumeration workgroup         */
+    uint32_t block_threads;      /* threads per workgroup: 256, 512 or 1024   */
+} crop_tune;
+
+/* ---- context ----------------------------------------------------------- */
+
+/* Create a context on HIP device `hip_device`.  Defaults: P = 1, seed =
+ * 0x243F6A8885A308D3, 2^14 counters per partition with 16 per bucket, the
+ * library's own non-blocking stream, automatic tuning. */
+crop_status crop_create(crop_ctx **out, int hip_device);
+void crop_destroy(crop_ctx *ctx);
+
+/* Static strings; never freed by the caller. */
+const char *crop_status_string(crop_status s);
+const char *crop_last_error_detail(const crop_ctx *ctx);
+/* For CROP_E_INPUT: index of the first offending vector (transaction or k),
+ * or -1 when the offsets array itself is malformed. */
+int64_t crop_last_error_index(const crop_ctx *ctx);
+int crop_abi_version(void);
+
+/* ---- parameters -------------------------------------------------------- */
+
+/* Number of owners P, 1 <= P <= 8192 (Section 6, Theorem 1: owners hold
+ * disjoint equal intervals of the hash space). */
+crop_status crop_set_partitions(crop_ctx *ctx, uint32_t P);
+/* 64-bit seed of the hash functions (Section 5: the hash description is
+ * broadcast before the computation). */
+crop_status crop_set_seed(crop_ctx *ctx, uint64_t seed);
+/* Space-Saving sizes: counters_per_partition = B * ell, ell slots per bucket
+ * (Section 4; Figure 1 keeps one summary of ell entries per bucket).
+ * ell in [1, 64]; counters_per_partition a multiple of ell. */
+crop_status crop_set_summary(crop_ctx *ctx, uint32_t counters_per_partition,
+                             uint32_t counters_per_bucket);
+/* Borrow a HIP stream (hipStream_t) for all later work; NULL restores the
+ * library's own stream.  The stream must outlive its use. */
+crop_status crop_set_stream(crop_ctx *ctx, void *hip_stream);
+crop_status crop_set_tuning(crop_ctx *ctx, const crop_tune *tune);
+/* The configuration the next (or last) run uses, after automatic choices. */
+crop_status crop_get_tuning(const crop_ctx *ctx, crop_tune *out);
+
+/* ---- input ------------------------------------------------------------- */
+
+/* A {0,1} transaction stream in CSR form (Section 7; the stream order is the
+ * row order, Section 7.3).  off[T+1] with off[0] = 0, non-decreasing,
+ * off[T] = nnz; items[nnz] < n_items and strictly increasing inside each
+ * transaction.  The input is validated on the device; a violation returns
+ * CROP_E_INPUT.  BORROWed device buffers must stay valid until the next load
+ * or destroy; COPY takes a private copy (host or device source). */
+crop_status crop_load_transactions(crop_ctx *ctx, const uint32_t *off, uint64_t T,
+                                   const uint32_t *items, uint64_t nnz, uint32_t n_items,
+                                   crop_mem where, crop_own own);
+
+/* K outer products a_k b_k^T (Section 5: A column-major, B row-major
+ * triples).  a_off[K+1], a_idx[nnz_a] < n_rows, a_val[nnz_a]; likewise b.
+ * Indices strictly increasing inside each vector.  Every stored pair is a
+ * term, also when a value is 0.0. */
+crop_status crop_load_outer(crop_ctx *ctx, const uint32_t *a_off, const uint32_t *a_idx,
+                            const float *a_val, const uint32_t *b_off, const uint32_t *b_idx,
+                            const float *b_val, uint64_t K, uint64_t nnz_a, uint64_t nnz_b,
+                            uint32_t n_rows, uint32_t n_cols, crop_mem where, crop_own own);
+
+/* ---- runs (asynchronous) ----------------------------------------------- */
+
+/* Exact accumulation of every partition: uint32 supports (transactions) or
+ * fp32 sums (outer products), plus the number of terms per partition. */
+crop_status crop_run_exact(crop_ctx *ctx);
+
+/* ---- readback (synchronizes the context stream) ------------------------ */
+
+/* Per-partition distinct-entry counts and term counts of the last exact run
+ * (host arrays of P elements; either may be NULL). */
+crop_status crop_result_sizes(crop_ctx *ctx, uint64_t *sizes, uint64_t *terms);
+
+/* Entries of partition p of the last exact run into host arrays of
+ * capacity cap: i, j (required), count (transactions, or NULL), value
+ * (outer products, or NULL).  Order inside a partition is unspecified. */
+crop_status crop_read_partition(crop_ctx *ctx, uint32_t p, uint32_t *i, uint32_t *j,
+                                uint32_t *count, float *value, uint64_t cap,
+                                uint64_t *written);
+
+/* Every entry of the last exact run, partition by partition, into arrays in
+ * `where` memory of capacity cap; part_off (host, P+1 elements, or NULL)
+ * receives each partition's start. */
+crop_status crop_read_all(crop_ctx *ctx, crop_mem where, uint32_t *i, uint32_t *j,
+                          uint32_t *count, float *value, uint64_t cap, uint64_t *written,
+                          uint64_t *part_off);
+
+/* Wait for all work enqueued by this context. */
+crop_status crop_synchronize(crop_ctx *ctx);
+
+/* Device time in milliseconds of the last run, from HIP events recorded on
+ * the context stream around its kernels (synchronizes). */
+crop_status crop_last_run_ms(crop_ctx *ctx, float *ms);
+
+/* Profiling: when enabled, every run also records one HIP event after each
+ * of its stages (kernels or kernel groups) on the context stream, kept for
+ * the last 64 runs.  Off by default. */
+crop_status crop_set_profiling(crop_ctx *ctx, int enable);
+/* Stage names (static strings) and device milliseconds of run number
+ * `back` counted from the most recent (0) while profiling was on; names or
+ * ms may be NULL.  *n_stages receives the stage count (synchronizes). */
+crop_status crop_run_stages(crop_ctx *ctx, uint32_t back, uint32_t *n_stages,
+                            const char **names, float *ms, uint32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CROP_H */

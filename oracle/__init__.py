@@ -62,6 +62,7 @@ def lib():
     L.orc_tx_exact.argtypes = [_u32p, _u64, _u32p, _u32, _u64, _u64, _u64, _u64p, _u64p,
                                _u32p, _u32p, _u32p, _u64, ctypes.POINTER(_u64)]
     L.orc_tx_exact.restype = ctypes.c_int
+    L.orc_tx_part_terms.argtypes = [_u32p, _u64, _u32p, _u32, _u64, _u64p]
     L.orc_op_exact.argtypes = [_u32p, _u32p, _f32p, _u32p, _u32p, _f32p, _u64, _u32, _u64,
                                _u64, _u64, _u64p, _u64p, _u32p, _u32p, _f64p, _f64p, _u32p,
                                _u64, ctypes.POINTER(_u64)]
@@ -166,6 +167,21 @@ def tx_exact(off, items, P: int, seed: int, q: int = 0, r: int = HASH_SPACE):
     d = n_out.value
     return dict(part_sizes=ps, part_terms=pt, x=x[:d].copy(), y=y[:d].copy(),
                 cnt=c[:d].copy(), n_terms=nt)
+
+
+def tx_part_terms(off, items, P: int, seed: int) -> np.ndarray:
+    """Number of terms of every partition (Section 6, Theorem 1's load X)."""
+    off = _c(off, np.uint32)
+    out = np.zeros(P, np.uint64)
+    lib().orc_tx_part_terms(off, off.shape[0] - 1, _c(items, np.uint32), P, seed, out)
+    return out
+
+
+def partition_interval(p: int, P: int):
+    """Hash interval [q, r) owned by partition p: the h with (h*P)>>32 == p."""
+    q = -(-(p << 32) // P)
+    r = -(-((p + 1) << 32) // P)
+    return q, min(r, HASH_SPACE)
 
 
 def op_exact(op, P: int, seed: int, q: int = 0, r: int = HASH_SPACE):

@@ -485,3 +485,19 @@ void orc_part_bucket_many(const uint32_t *h, uint64_t n, uint32_t P, uint32_t B,
         if (bucket) bucket[k] = orc_bucket(h[k], P, B);
     }
 }
+
+/* Terms per partition of a transaction stream (plain loop, no sort). */
+void orc_tx_part_terms(const uint32_t *off, uint64_t T, const uint32_t *items,
+                       uint32_t P, uint64_t seed, uint64_t *part_terms)
+{
+    uint64_t prm[8];
+    orc_hash_params(seed, prm);
+    for (uint32_t p = 0; p < P; ++p) part_terms[p] = 0;
+    for (uint64_t t = 0; t < T; ++t)
+        for (uint64_t a = off[t]; a < off[t + 1]; ++a)
+            for (uint64_t b = a + 1; b < off[t + 1]; ++b) {
+                uint32_t x = items[a] < items[b] ? items[a] : items[b];
+                uint32_t y = items[a] < items[b] ? items[b] : items[a];
+                part_terms[orc_part(orc_h(prm, x, y), P)] += 1;
+            }
+}

@@ -1,0 +1,347 @@
+"""MI355X column-row parallel (CRoP) library: Python binding.
+
+A thin ctypes binding over the C ABI in ``include/crop.h``: every function
+below has the name of the C function it calls and only marshals arguments
+(tensor or array -> pointer, status -> exception).  All computation runs in
+the HIP kernels of ``libcrop.so``; there is no Python or CPU fallback, and
+importing this package fails loudly when the library has not been built
+(``python -m paper_1210_0461_amd.build`` or ``__graft_entry__.build()``).
+
+PyTorch is used only as a holder of device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcrop.so")
+
+CROP_MEM_HOST = 0
+CROP_MEM_DEVICE = 1
+CROP_OWN_COPY = 0
+CROP_OWN_BORROW = 1
+
+STATUS = {
+    0: "CROP_OK", -1: "CROP_E_ARG", -2: "CROP_E_STATE", -3: "CROP_E_INPUT",
+    -4: "CROP_E_CAPACITY", -5: "CROP_E_NOMEM", -6: "CROP_E_HIP", -7: "CROP_E_UNSUPPORTED",
+}
+
+
+class CropError(RuntimeError):
+    def __init__(self, status: int, detail: str, index: int = -1):
+        super().__init__(f"{STATUS.get(status, status)}: {detail}")
+        self.status = status
+        self.detail = detail
+        self.index = index
+
+
+class crop_tune(ctypes.Structure):
+    _fields_ = [("bins_per_partition", ctypes.c_uint32), ("table_slots", ctypes.c_uint32),
+                ("rows_per_chunk", ctypes.c_uint32), ("block_threads", ctypes.c_uint32)]
+
+
+# torch ships its own HIP runtime under the same soname (libamdhip64.so.7).
+# Importing it first makes the dynamic loader bind libcrop.so to that one
+# runtime instead of loading a second copy from /opt/rocm, so tensors, streams
+# and this library share one HIP runtime in the process.
+try:
+    import torch  # noqa: F401
+except ImportError:  # pragma: no cover - torch is optional for the C ABI
+    torch = None
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                      "(the library has no CPU fallback)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_vp = ctypes.c_void_p
+_u32 = ctypes.c_uint32
+_u64 = ctypes.c_uint64
+_i32 = ctypes.c_int
+_pu64 = ctypes.POINTER(ctypes.c_uint64)
+
+_SIGS = {
+    "crop_abi_version": ([], _i32),
+    "crop_status_string": ([_i32], ctypes.c_char_p),
+    "crop_create": ([ctypes.POINTER(_vp), _i32], _i32),
+    "crop_destroy": ([_vp], None),
+    "crop_last_error_detail": ([_vp], ctypes.c_char_p),
+    "crop_last_error_index": ([_vp], ctypes.c_int64),
+    "crop_set_partitions": ([_vp, _u32], _i32),
+    "crop_set_seed": ([_vp, _u64], _i32),
+    "crop_set_summary": ([_vp, _u32, _u32], _i32),
+    "crop_set_stream": ([_vp, _vp], _i32),
+    "crop_set_tuning": ([_vp, ctypes.POINTER(crop_tune)], _i32),
+    "crop_get_tuning": ([_vp, ctypes.POINTER(crop_tune)], _i32),
+    "crop_load_transactions": ([_vp, _vp, _u64, _vp, _u64, _u32, _i32, _i32], _i32),
+    "crop_load_outer": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64, _u64, _u64, _u32, _u32,
+                         _i32, _i32], _i32),
+    "crop_run_exact": ([_vp], _i32),
+    "crop_result_sizes": ([_vp, _vp, _vp], _i32),
+    "crop_read_partition": ([_vp, _u32, _vp, _vp, _vp, _vp, _u64, _pu64], _i32),
+    "crop_read_all": ([_vp, _i32, _vp, _vp, _vp, _vp, _u64, _pu64, _vp], _i32),
+    "crop_synchronize": ([_vp], _i32),
+    "crop_last_run_ms": ([_vp, ctypes.POINTER(ctypes.c_float)], _i32),
+    "crop_set_profiling": ([_vp, _i32], _i32),
+    "crop_run_stages": ([_vp, _u32, ctypes.POINTER(_u32), _vp, _vp, _u32], _i32),
+}
+
+# Optional entry points (declared in include/crop.h once implemented).
+_OPTIONAL_SIGS = {
+    "crop_run_topk": ([_vp, _u32], _i32),
+    "crop_run_topk_seeded": ([_vp, _u32, _vp, _vp, _u64, _u32], _i32),
+    "crop_read_topk": ([_vp, _vp, _vp, _vp, _vp, _vp, _u64, _pu64], _i32),
+    "crop_read_summary": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64, _pu64], _i32),
+}
+
+for _name, (_args, _res) in _SIGS.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _res
+for _name, (_args, _res) in _OPTIONAL_SIGS.items():
+    if hasattr(_lib, _name):
+        _f = getattr(_lib, _name)
+        _f.argtypes = _args
+        _f.restype = _res
+
+
+def exported_symbols():
+    """Names of the C functions this binding knows about."""
+    return sorted(list(_SIGS) + [n for n in _OPTIONAL_SIGS if hasattr(_lib, n)])
+
+
+# --------------------------------------------------------------------------
+# marshalling helpers
+
+def _ptr(a):
+    """(pointer, where) of a torch tensor or numpy array (None -> NULL)."""
+    if a is None:
+        return None, CROP_MEM_HOST
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            raise ValueError("array must be C-contiguous")
+        return a.ctypes.data, CROP_MEM_HOST
+    try:
+        import torch
+    except ImportError:  # pragma: no cover
+        torch = None
+    if torch is not None and isinstance(a, torch.Tensor):
+        if not a.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return a.data_ptr(), (CROP_MEM_DEVICE if a.is_cuda else CROP_MEM_HOST)
+    if isinstance(a, int):
+        return a, CROP_MEM_DEVICE
+    raise TypeError(f"unsupported buffer type {type(a)}")
+
+
+def _check(ctx, st):
+    if st != 0:
+        detail = _lib.crop_last_error_detail(ctx).decode() if ctx else ""
+        idx = _lib.crop_last_error_index(ctx) if ctx else -1
+        raise CropError(st, detail, idx)
+
+
+# --------------------------------------------------------------------------
+# the C ABI, one Python function per C function
+
+def crop_abi_version() -> int:
+    return _lib.crop_abi_version()
+
+
+def crop_status_string(st: int) -> str:
+    return _lib.crop_status_string(st).decode()
+
+
+def crop_create(hip_device: int = 0):
+    h = _vp()
+    st = _lib.crop_create(ctypes.byref(h), hip_device)
+    if st != 0:
+        raise CropError(st, "crop_create failed")
+    return h
+
+
+def crop_destroy(ctx) -> None:
+    _lib.crop_destroy(ctx)
+
+
+def crop_last_error_detail(ctx) -> str:
+    return _lib.crop_last_error_detail(ctx).decode()
+
+
+def crop_last_error_index(ctx) -> int:
+    return _lib.crop_last_error_index(ctx)
+
+
+def crop_set_partitions(ctx, P: int) -> None:
+    _check(ctx, _lib.crop_set_partitions(ctx, P))
+
+
+def crop_set_seed(ctx, seed: int) -> None:
+    _check(ctx, _lib.crop_set_seed(ctx, seed & 0xFFFFFFFFFFFFFFFF))
+
+
+def crop_set_summary(ctx, counters_per_partition: int, counters_per_bucket: int) -> None:
+    _check(ctx, _lib.crop_set_summary(ctx, counters_per_partition, counters_per_bucket))
+
+
+def crop_set_stream(ctx, stream) -> None:
+    """stream: a torch.cuda.Stream, a raw hipStream_t integer, or None."""
+    if stream is not None and hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    _check(ctx, _lib.crop_set_stream(ctx, stream))
+
+
+def crop_set_tuning(ctx, bins_per_partition=0, table_slots=0, rows_per_chunk=0,
+                    block_threads=0) -> None:
+    t = crop_tune(bins_per_partition, table_slots, rows_per_chunk, block_threads)
+    _check(ctx, _lib.crop_set_tuning(ctx, ctypes.byref(t)))
+
+
+def crop_get_tuning(ctx) -> dict:
+    t = crop_tune()
+    _check(ctx, _lib.crop_get_tuning(ctx, ctypes.byref(t)))
+    return {f: getattr(t, f) for f, _ in crop_tune._fields_}
+
+
+def crop_load_transactions(ctx, off, items, n_items: int, own: int = CROP_OWN_COPY) -> None:
+    """off: uint32[T+1], items: uint32[nnz]; both host (numpy/cpu tensor) or
+    both device (cuda tensor)."""
+    po, wo = _ptr(off)
+    pi, wi = _ptr(items)
+    if int(_len(items)) and wo != wi:
+        raise ValueError("off and items must both be host or both be device memory")
+    _check(ctx, _lib.crop_load_transactions(ctx, po, _len(off) - 1, pi, _len(items), n_items,
+                                            wo, own))
+
+
+def crop_load_outer(ctx, a_off, a_idx, a_val, b_off, b_idx, b_val, n_rows: int, n_cols: int,
+                    own: int = CROP_OWN_COPY) -> None:
+    ptrs = [_ptr(v) for v in (a_off, a_idx, a_val, b_off, b_idx, b_val)]
+    where = ptrs[0][1]
+    _check(ctx, _lib.crop_load_outer(ctx, *[p for p, _ in ptrs], _len(a_off) - 1, _len(a_idx),
+                                     _len(b_idx), n_rows, n_cols, where, own))
+
+
+def crop_run_exact(ctx) -> None:
+    _check(ctx, _lib.crop_run_exact(ctx))
+
+
+def crop_run_topk(ctx, K: int) -> None:
+    _check(ctx, _lib.crop_run_topk(ctx, K))
+
+
+def crop_run_topk_seeded(ctx, K: int, sx, sy, r_max: int) -> None:
+    px, _ = _ptr(sx)
+    py, _ = _ptr(sy)
+    _check(ctx, _lib.crop_run_topk_seeded(ctx, K, px, py, _len(sx), r_max))
+
+
+def crop_result_sizes(ctx, P: int):
+    sizes = np.zeros(P, np.uint64)
+    terms = np.zeros(P, np.uint64)
+    _check(ctx, _lib.crop_result_sizes(ctx, sizes.ctypes.data, terms.ctypes.data))
+    return sizes, terms
+
+
+def crop_read_partition(ctx, p: int, cap: int, outer: bool = False):
+    i = np.zeros(max(cap, 1), np.uint32)
+    j = np.zeros(max(cap, 1), np.uint32)
+    c = None if outer else np.zeros(max(cap, 1), np.uint32)
+    v = np.zeros(max(cap, 1), np.float32) if outer else None
+    w = _u64(0)
+    _check(ctx, _lib.crop_read_partition(ctx, p, i.ctypes.data, j.ctypes.data,
+                                         None if c is None else c.ctypes.data,
+                                         None if v is None else v.ctypes.data, cap,
+                                         ctypes.byref(w)))
+    n = w.value
+    return i[:n], j[:n], (v[:n] if outer else c[:n])
+
+
+def crop_read_all(ctx, P: int, outer: bool = False, device=None):
+    """Whole exact result, partition by partition.  With device=None the
+    arrays are host numpy arrays; with a torch device they are tensors there."""
+    sizes, _ = crop_result_sizes(ctx, P)
+    n = int(sizes.sum())
+    part_off = np.zeros(P + 1, np.uint64)
+    w = _u64(0)
+    if device is None:
+        i = np.zeros(max(n, 1), np.uint32)
+        j = np.zeros(max(n, 1), np.uint32)
+        c = None if outer else np.zeros(max(n, 1), np.uint32)
+        v = np.zeros(max(n, 1), np.float32) if outer else None
+        where = CROP_MEM_HOST
+        ptrs = [i.ctypes.data, j.ctypes.data, None if c is None else c.ctypes.data,
+                None if v is None else v.ctypes.data]
+    else:
+        import torch
+        i = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+        j = torch.empty(max(n, 1), dtype=torch.int32, device=device)
+        c = None if outer else torch.empty(max(n, 1), dtype=torch.int32, device=device)
+        v = torch.empty(max(n, 1), dtype=torch.float32, device=device) if outer else None
+        where = CROP_MEM_DEVICE
+        ptrs = [i.data_ptr(), j.data_ptr(), None if c is None else c.data_ptr(),
+                None if v is None else v.data_ptr()]
+    _check(ctx, _lib.crop_read_all(ctx, where, *ptrs, n, ctypes.byref(w),
+                                   part_off.ctypes.data))
+    return i[:n], j[:n], (v[:n] if outer else c[:n]), part_off
+
+
+def crop_read_topk(ctx, cap: int):
+    i = np.zeros(max(cap, 1), np.uint32)
+    j = np.zeros(max(cap, 1), np.uint32)
+    up = np.zeros(max(cap, 1), np.float64)
+    lo = np.zeros(max(cap, 1), np.float64)
+    val = np.zeros(max(cap, 1), np.float64)
+    w = _u64(0)
+    _check(ctx, _lib.crop_read_topk(ctx, i.ctypes.data, j.ctypes.data, up.ctypes.data,
+                                    lo.ctypes.data, val.ctypes.data, cap, ctypes.byref(w)))
+    n = w.value
+    return i[:n], j[:n], up[:n], lo[:n], val[:n]
+
+
+def crop_read_summary(ctx, n_slots: int):
+    i = np.zeros(max(n_slots, 1), np.uint32)
+    j = np.zeros(max(n_slots, 1), np.uint32)
+    cnt = np.zeros(max(n_slots, 1), np.float64)
+    err = np.zeros(max(n_slots, 1), np.float64)
+    val = np.zeros(max(n_slots, 1), np.float64)
+    flags = np.zeros(max(n_slots, 1), np.uint8)
+    w = _u64(0)
+    _check(ctx, _lib.crop_read_summary(ctx, i.ctypes.data, j.ctypes.data, cnt.ctypes.data,
+                                       err.ctypes.data, val.ctypes.data, flags.ctypes.data,
+                                       n_slots, ctypes.byref(w)))
+    n = w.value
+    return dict(x=i[:n], y=j[:n], cnt=cnt[:n], err=err[:n], val=val[:n],
+                used=(flags[:n] & 1).astype(bool), pinned=(flags[:n] & 2).astype(bool))
+
+
+def crop_synchronize(ctx) -> None:
+    _check(ctx, _lib.crop_synchronize(ctx))
+
+
+def crop_last_run_ms(ctx) -> float:
+    ms = ctypes.c_float(0.0)
+    _check(ctx, _lib.crop_last_run_ms(ctx, ctypes.byref(ms)))
+    return float(ms.value)
+
+
+def crop_set_profiling(ctx, enable: bool) -> None:
+    _check(ctx, _lib.crop_set_profiling(ctx, 1 if enable else 0))
+
+
+def crop_run_stages(ctx, back: int = 0):
+    """[(stage name, device ms)] of the run `back` runs ago (profiling on)."""
+    cap = 16
+    n = _u32(0)
+    names = (ctypes.c_char_p * cap)()
+    ms = (ctypes.c_float * cap)()
+    _check(ctx, _lib.crop_run_stages(ctx, back, ctypes.byref(n), names, ms, cap))
+    return [(names[k].decode(), float(ms[k])) for k in range(n.value)]
+
+
+def _len(a) -> int:
+    return int(a.shape[0]) if hasattr(a, "shape") else len(a)

@@ -1,0 +1,766 @@
+// C ABI of the CRoP library (declared in include/crop.h): context, inputs,
+// planning, run orchestration and readback.  Every step of a run is a HIP
+// kernel on the context's stream; the host only plans and launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "crop_internal.hpp"
+
+using namespace crop;
+
+namespace crop {
+size_t spill_entry_bytes(bool wide, bool sums);
+}
+
+namespace {
+
+constexpr uint32_t kMaxP = 8192;
+constexpr uint64_t kTermsPerBin = 48000;   // routed terms per bin the auto plan aims at
+constexpr size_t kLdsBudget = 64 * 1024;   // enumeration kernels' staging budget
+
+crop_status fail(crop_ctx *c, crop_status s, const std::string &msg)
+{
+    if (c) c->err = msg;
+    return s;
+}
+
+crop_status hip_fail(crop_ctx *c, hipError_t e, const char *what)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    return fail(c, e == hipErrorOutOfMemory ? CROP_E_NOMEM : CROP_E_HIP, m);
+}
+
+#define CK(expr)                                                   \
+    do {                                                           \
+        hipError_t e_ = (expr);                                    \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr);     \
+    } while (0)
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+uint64_t tx_terms_of(const std::vector<uint32_t> &off)
+{
+    uint64_t s = 0;
+    for (size_t t = 0; t + 1 < off.size(); ++t) {
+        uint64_t L = off[t + 1] - off[t];
+        s += L * (L ? L - 1 : 0) / 2;
+    }
+    return s;
+}
+
+// Copy n elements of T from `src` (host or device) into a host vector.
+template <class T>
+hipError_t fetch(std::vector<T> &dst, const T *src, size_t n, crop_mem where)
+{
+    dst.resize(n);
+    if (n == 0) return hipSuccess;
+    if (where == CROP_MEM_HOST) {
+        std::memcpy(dst.data(), src, n * sizeof(T));
+        return hipSuccess;
+    }
+    return hipMemcpy(dst.data(), src, n * sizeof(T), hipMemcpyDeviceToHost);
+}
+
+// Place an input array on the device: borrow it, or copy it into buf.
+template <class T>
+hipError_t place(const T *src, size_t n, crop_mem where, crop_own own, DevBuf &buf,
+                 const T **out, hipStream_t s)
+{
+    if (own == CROP_OWN_BORROW) {
+        *out = src;
+        return hipSuccess;
+    }
+    hipError_t e = buf.ensure(n * sizeof(T) + 16);
+    if (e != hipSuccess) return e;
+    if (n) {
+        e = hipMemcpyAsync(buf.p, src, n * sizeof(T),
+                           where == CROP_MEM_HOST ? hipMemcpyHostToDevice
+                                                  : hipMemcpyDeviceToDevice,
+                           s);
+        if (e != hipSuccess) return e;
+    }
+    *out = buf.as<T>();
+    return hipSuccess;
+}
+
+// Validate CSR contents on the device; returns the first bad vector or -1.
+crop_status validate_on_device(crop_ctx *ctx, const uint32_t *v_off, uint64_t K,
+                               const uint32_t *idx, uint64_t nnz, uint32_t n, int64_t *bad_out)
+{
+    CK(ctx->scratch.ensure(64));
+    auto *bad = ctx->scratch.as<unsigned long long>();
+    unsigned long long init = ~0ull;
+    CK(hipMemcpyAsync(bad, &init, sizeof(init), hipMemcpyHostToDevice, ctx->stream));
+    if (K) CK(launch_validate_tx(v_off, K, idx, nnz, n, bad, ctx->stream));
+    unsigned long long got = 0;
+    CK(hipMemcpyAsync(&got, bad, sizeof(got), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    *bad_out = got == ~0ull ? -1 : (int64_t)got;
+    return CROP_OK;
+}
+
+crop_status check_offsets(crop_ctx *ctx, const std::vector<uint32_t> &off, uint64_t nnz,
+                          const char *name)
+{
+    if (off.empty() || off[0] != 0 || off.back() != nnz) {
+        ctx->err_index = -1;
+        return fail(ctx, CROP_E_INPUT, std::string(name) + ": off[0] must be 0 and off[K] = nnz");
+    }
+    for (size_t t = 0; t + 1 < off.size(); ++t)
+        if (off[t + 1] < off[t]) {
+            ctx->err_index = (int64_t)t;
+            return fail(ctx, CROP_E_INPUT,
+                        std::string(name) + ": offsets decrease at vector " + std::to_string(t));
+        }
+    return CROP_OK;
+}
+
+void reset_input(crop_ctx *ctx)
+{
+    Input &in = ctx->in;
+    in.mode = Mode::None;
+    in.off = in.items = nullptr;
+    in.a_off = in.a_idx = in.b_off = in.b_idx = nullptr;
+    in.a_val = in.b_val = nullptr;
+    in.T = in.nnz = in.K = in.nnz_a = in.nnz_b = 0;
+    in.total_terms = 0;
+    in.h_off.clear();
+    in.h_b_off.clear();
+    in.op_chunks.clear();
+    ctx->result = Result::None;
+}
+
+// ---- planning -------------------------------------------------------------
+
+crop_status plan_tx(crop_ctx *ctx)
+{
+    Input &in = ctx->in;
+    RoutePlan &pl = ctx->plan;
+    const uint32_t P = ctx->P;
+    uint32_t S = ctx->tune.bins_per_partition;
+    if (S == 0) {
+        uint64_t want = (in.total_terms + kTermsPerBin - 1) / kTermsPerBin;
+        S = (uint32_t)std::max<uint64_t>(1, (want + P - 1) / P);
+        while (S > 1 && (uint64_t)P * S > kMaxP) --S;
+    }
+    if ((uint64_t)P * S > kMaxP)
+        return fail(ctx, CROP_E_UNSUPPORTED, "partitions x bins_per_partition exceeds 8192");
+    pl.S = S;
+    pl.NB = P * S;
+    const size_t hist_bytes = (size_t)pl.NB * 4;
+    uint32_t R = ctx->tune.rows_per_chunk ? ctx->tune.rows_per_chunk : 256;
+    auto max_items_for = [&](uint32_t r) {
+        uint32_t mx = 0;
+        for (uint64_t t0 = 0; t0 < in.T; t0 += r) {
+            uint64_t t1 = std::min<uint64_t>(in.T, t0 + r);
+            mx = std::max(mx, in.h_off[t1] - in.h_off[t0]);
+        }
+        return mx;
+    };
+    uint32_t mi = max_items_for(R);
+    while (R > 1 && hist_bytes + 12ull * mi > kLdsBudget) {
+        R /= 2;
+        mi = max_items_for(R);
+    }
+    if (hist_bytes + 12ull * mi + 1024 > 150 * 1024)
+        return fail(ctx, CROP_E_UNSUPPORTED, "a transaction is too long to stage in LDS");
+    pl.R = R;
+    pl.max_items = mi;
+    pl.n_chunks = (uint32_t)((in.T + R - 1) / R);
+    pl.G = std::max<uint32_t>(1, std::min<uint32_t>(64, pl.n_chunks));
+    return CROP_OK;
+}
+
+crop_status plan_outer(crop_ctx *ctx)
+{
+    Input &in = ctx->in;
+    RoutePlan &pl = ctx->plan;
+    const uint32_t P = ctx->P;
+    uint32_t S = ctx->tune.bins_per_partition;
+    if (S == 0) {
+        // outer-product entries rarely repeat and fp32 sums use 8192-slot
+        // tables: aim at about 3000 routed terms per bin
+        uint64_t want = (in.total_terms + kTermsPerBin / 16 - 1) / (kTermsPerBin / 16);
+        S = (uint32_t)std::max<uint64_t>(1, (want + P - 1) / P);
+        while (S > 1 && (uint64_t)P * S > kMaxP) --S;
+    }
+    if ((uint64_t)P * S > kMaxP)
+        return fail(ctx, CROP_E_UNSUPPORTED, "partitions x bins_per_partition exceeds 8192");
+    pl.S = S;
+    pl.NB = P * S;
+    pl.max_items = in.op_max_a;
+    pl.n_chunks = (uint32_t)in.op_chunks.size();
+    pl.G = std::max<uint32_t>(1, std::min<uint32_t>(64, pl.n_chunks));
+    const size_t lds = (size_t)pl.NB * 4 + 20ull * pl.max_items + 1024;
+    if (lds > 150 * 1024)
+        return fail(ctx, CROP_E_UNSUPPORTED, "outer-product chunk does not fit in LDS");
+    return CROP_OK;
+}
+
+// Split the a-entries of the K vectors into chunks of at most kA entries and
+// about kW terms; a vector with many terms is split over several chunks.
+void build_outer_chunks(Input &in)
+{
+    constexpr uint32_t kA = 1024;
+    constexpr uint64_t kW = 32768;
+    in.op_chunks.clear();
+    in.op_max_a = 0;
+    OpChunk cur{0, 0, 0, 0};
+    uint64_t work = 0;
+    bool open = false;
+    auto close = [&]() {
+        if (open && cur.a_hi > cur.a_lo) {
+            in.op_chunks.push_back(cur);
+            in.op_max_a = std::max(in.op_max_a, cur.a_hi - cur.a_lo);
+        }
+        open = false;
+        work = 0;
+    };
+    for (uint32_t k = 0; k < in.K; ++k) {
+        uint32_t a0 = in.h_off[k], a1 = in.h_off[k + 1];
+        uint64_t nb = in.h_b_off[k + 1] - in.h_b_off[k];
+        if (a0 == a1 || nb == 0) continue;
+        for (uint32_t a = a0; a < a1; ++a) {
+            if (!open) {
+                cur = OpChunk{k, k + 1, a, a};
+                open = true;
+            }
+            if (cur.a_hi - cur.a_lo >= kA || (work + nb > kW && cur.a_hi > cur.a_lo)) {
+                close();
+                cur = OpChunk{k, k + 1, a, a};
+                open = true;
+            }
+            cur.k1 = k + 1;
+            cur.a_hi = a + 1;
+            work += nb;
+        }
+    }
+    close();
+}
+
+crop_status ensure_route_buffers(crop_ctx *ctx, size_t key_bytes, bool sums)
+{
+    const RoutePlan &pl = ctx->plan;
+    const uint64_t nt = ctx->in.total_terms;
+    CK(ctx->cnt_mat.ensure((size_t)std::max<uint32_t>(pl.n_chunks, 1) * pl.NB * 4));
+    CK(ctx->part_buf.ensure((size_t)pl.G * pl.NB * 4));
+    CK(ctx->bin_off.ensure(((size_t)pl.NB + 1) * 4));
+    CK(ctx->bin_size.ensure((size_t)pl.NB * 4));
+    CK(ctx->keys.ensure(nt * key_bytes));
+    if (sums)
+        CK(ctx->vals.ensure(nt * 4));
+    else
+        CK(ctx->out_cnt.ensure(nt * 4));
+    CK(ctx->spill.ensure(nt * spill_entry_bytes(ctx->in.wide_keys, sums)));
+    CK(ctx->counter.ensure(64));
+    return CROP_OK;
+}
+
+crop_status require_exact(crop_ctx *ctx)
+{
+    if (ctx->result != Result::Exact)
+        return fail(ctx, CROP_E_STATE, "no exact result: call crop_run_exact first");
+    return CROP_OK;
+}
+
+// Run bracketing: ev0/ev1 around every run; with profiling on, one event
+// after each stage as well, kept for the last kStageRing runs.
+crop_status run_begin(crop_ctx *ctx)
+{
+    hipStream_t s = ctx->stream;
+    CK(hipEventRecord(ctx->ev0, s));
+    ctx->cur_rec = nullptr;
+    if (!ctx->profiling) return CROP_OK;
+    StageRec &r = ctx->ring[ctx->runs % kStageRing];
+    r.n = 0;
+    CK(hipEventRecord(r.ev[0], s));
+    ctx->cur_rec = &r;
+    return CROP_OK;
+}
+
+crop_status stage_end(crop_ctx *ctx, const char *name)
+{
+    StageRec *r = ctx->cur_rec;
+    if (!r || r->n >= kMaxStages) return CROP_OK;
+    r->names[r->n] = name;
+    CK(hipEventRecord(r->ev[r->n + 1], ctx->stream));
+    r->n += 1;
+    return CROP_OK;
+}
+
+crop_status run_end(crop_ctx *ctx)
+{
+    CK(hipEventRecord(ctx->ev1, ctx->stream));
+    ctx->timed = true;
+    if (ctx->cur_rec) ctx->runs += 1;
+    ctx->cur_rec = nullptr;
+    return CROP_OK;
+}
+
+#define STAGE(name)                                   \
+    do {                                              \
+        crop_status st_ = stage_end(ctx, name);       \
+        if (st_ != CROP_OK) return st_;               \
+    } while (0)
+
+}  // namespace
+
+// ============================================================== context
+
+extern "C" {
+
+int crop_abi_version(void) { return CROP_ABI_VERSION; }
+
+const char *crop_status_string(crop_status s)
+{
+    switch (s) {
+    case CROP_OK: return "ok";
+    case CROP_E_ARG: return "invalid argument";
+    case CROP_E_STATE: return "call out of order";
+    case CROP_E_INPUT: return "invalid input";
+    case CROP_E_CAPACITY: return "output buffer too small";
+    case CROP_E_NOMEM: return "out of device memory";
+    case CROP_E_HIP: return "HIP runtime error";
+    case CROP_E_UNSUPPORTED: return "unsupported parameters";
+    }
+    return "unknown status";
+}
+
+crop_status crop_create(crop_ctx **out, int hip_device)
+{
+    if (!out) return CROP_E_ARG;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n)
+        return CROP_E_ARG;
+    DeviceGuard g(hip_device);
+    crop_ctx *ctx = new (std::nothrow) crop_ctx();
+    if (!ctx) return CROP_E_NOMEM;
+    ctx->device = hip_device;
+    ctx->hp = make_hash_params(ctx->seed);
+    if (hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
+        crop_destroy(ctx);
+        return CROP_E_HIP;
+    }
+    ctx->stream = ctx->own_stream;
+    *out = ctx;
+    return CROP_OK;
+}
+
+void crop_destroy(crop_ctx *ctx)
+{
+    if (!ctx) return;
+    DeviceGuard g(ctx->device);
+    if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    for (DevBuf *b : {&ctx->cnt_mat, &ctx->part_buf, &ctx->bin_off, &ctx->bin_size, &ctx->keys,
+                      &ctx->vals, &ctx->out_cnt, &ctx->spill, &ctx->counter, &ctx->ss_state,
+                      &ctx->topk_buf, &ctx->scratch, &ctx->in.d_op_chunks})
+        b->release();
+    for (DevBuf &b : ctx->in.own) b.release();
+    for (StageRec &r : ctx->ring)
+        for (hipEvent_t &e : r.ev)
+            if (e) (void)hipEventDestroy(e);
+    if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+    if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->own_stream);
+    delete ctx;
+}
+
+const char *crop_last_error_detail(const crop_ctx *ctx) { return ctx ? ctx->err.c_str() : ""; }
+int64_t crop_last_error_index(const crop_ctx *ctx) { return ctx ? ctx->err_index : -1; }
+
+crop_status crop_set_partitions(crop_ctx *ctx, uint32_t P)
+{
+    if (!ctx) return CROP_E_ARG;
+    if (P < 1 || P > kMaxP) return fail(ctx, CROP_E_UNSUPPORTED, "P must be in [1, 8192]");
+    ctx->P = P;
+    ctx->result = Result::None;
+    return CROP_OK;
+}
+
+crop_status crop_set_seed(crop_ctx *ctx, uint64_t seed)
+{
+    if (!ctx) return CROP_E_ARG;
+    ctx->seed = seed;
+    ctx->hp = make_hash_params(seed);
+    ctx->result = Result::None;
+    return CROP_OK;
+}
+
+crop_status crop_set_summary(crop_ctx *ctx, uint32_t counters_per_partition,
+                             uint32_t counters_per_bucket)
+{
+    if (!ctx) return CROP_E_ARG;
+    if (counters_per_bucket < 1 || counters_per_bucket > 64 || counters_per_partition == 0 ||
+        counters_per_partition % counters_per_bucket)
+        return fail(ctx, CROP_E_ARG, "need 1 <= ell <= 64 dividing counters_per_partition");
+    ctx->ss_counters = counters_per_partition;
+    ctx->ss_ell = counters_per_bucket;
+    ctx->result = Result::None;
+    return CROP_OK;
+}
+
+crop_status crop_set_stream(crop_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return CROP_E_ARG;
+    ctx->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : ctx->own_stream;
+    return CROP_OK;
+}
+
+crop_status crop_set_tuning(crop_ctx *ctx, const crop_tune *t)
+{
+    if (!ctx) return CROP_E_ARG;
+    if (!t) {
+        ctx->tune = crop_tune{};
+        return CROP_OK;
+    }
+    if (t->table_slots && (t->table_slots & (t->table_slots - 1)))
+        return fail(ctx, CROP_E_ARG, "table_slots must be a power of two");
+    if (t->block_threads && t->block_threads != 256 && t->block_threads != 512 &&
+        t->block_threads != 1024)
+        return fail(ctx, CROP_E_ARG, "block_threads must be 256, 512 or 1024");
+    ctx->tune = *t;
+    return CROP_OK;
+}
+
+crop_status crop_set_profiling(crop_ctx *ctx, int enable)
+{
+    if (!ctx) return CROP_E_ARG;
+    DeviceGuard g(ctx->device);
+    if (enable && ctx->ring.empty()) {
+        ctx->ring.resize(kStageRing);
+        for (StageRec &r : ctx->ring)
+            for (hipEvent_t &e : r.ev) CK(hipEventCreate(&e));
+    }
+    ctx->profiling = enable != 0;
+    ctx->runs = 0;
+    return CROP_OK;
+}
+
+crop_status crop_run_stages(crop_ctx *ctx, uint32_t back, uint32_t *n_stages,
+                            const char **names, float *ms, uint32_t cap)
+{
+    if (!ctx || !n_stages) return CROP_E_ARG;
+    if (!ctx->profiling) return fail(ctx, CROP_E_STATE, "profiling is off");
+    if (back >= ctx->runs || back >= (uint32_t)kStageRing)
+        return fail(ctx, CROP_E_ARG, "no such recorded run");
+    DeviceGuard g(ctx->device);
+    const StageRec &r = ctx->ring[(ctx->runs - 1 - back) % kStageRing];
+    *n_stages = (uint32_t)r.n;
+    if ((uint32_t)r.n > cap) return fail(ctx, CROP_E_CAPACITY, "stage capacity too small");
+    CK(hipEventSynchronize(r.ev[r.n]));
+    for (int k = 0; k < r.n; ++k) {
+        if (names) names[k] = r.names[k];
+        if (ms) CK(hipEventElapsedTime(&ms[k], r.ev[k], r.ev[k + 1]));
+    }
+    return CROP_OK;
+}
+
+crop_status crop_get_tuning(const crop_ctx *ctx, crop_tune *out)
+{
+    if (!ctx || !out) return CROP_E_ARG;
+    out->bins_per_partition = ctx->plan.S;
+    out->table_slots = 1u << ctx->plan.log2_slots;
+    out->rows_per_chunk = ctx->plan.R;
+    out->block_threads = ctx->plan.BS;
+    return CROP_OK;
+}
+
+// ============================================================== input
+
+crop_status crop_load_transactions(crop_ctx *ctx, const uint32_t *off, uint64_t T,
+                                   const uint32_t *items, uint64_t nnz, uint32_t n_items,
+                                   crop_mem where, crop_own own)
+{
+    if (!ctx) return CROP_E_ARG;
+    if (!off || (nnz && !items)) return fail(ctx, CROP_E_ARG, "null input pointer");
+    if (T >= (1ull << 32) || nnz >= (1ull << 32))
+        return fail(ctx, CROP_E_UNSUPPORTED, "T and nnz must be below 2^32");
+    if (own == CROP_OWN_BORROW && where != CROP_MEM_DEVICE)
+        return fail(ctx, CROP_E_ARG, "only device buffers can be borrowed");
+    DeviceGuard g(ctx->device);
+    reset_input(ctx);
+    ctx->err_index = -1;
+    Input &in = ctx->in;
+    CK(fetch(in.h_off, off, T + 1, where));
+    crop_status st = check_offsets(ctx, in.h_off, nnz, "transactions");
+    if (st != CROP_OK) return st;
+    in.total_terms = tx_terms_of(in.h_off);
+    if (in.total_terms >= (1ull << 32))
+        return fail(ctx, CROP_E_UNSUPPORTED, "more than 2^32 - 1 terms in one run");
+    CK(place(off, T + 1, where, own, in.own[0], &in.off, ctx->stream));
+    CK(place(items, nnz, where, own, in.own[1], &in.items, ctx->stream));
+    int64_t bad = -1;
+    st = validate_on_device(ctx, in.off, T, in.items, nnz, n_items, &bad);
+    if (st != CROP_OK) return st;
+    if (bad >= 0) {
+        ctx->err_index = bad;
+        return fail(ctx, CROP_E_INPUT,
+                    "transaction " + std::to_string(bad) +
+                        ": item id out of range or items not strictly increasing");
+    }
+    in.T = T;
+    in.nnz = nnz;
+    in.n_items = n_items;
+    in.wide_keys = n_items > 65536u;
+    in.mode = Mode::Tx;
+    return CROP_OK;
+}
+
+crop_status crop_load_outer(crop_ctx *ctx, const uint32_t *a_off, const uint32_t *a_idx,
+                            const float *a_val, const uint32_t *b_off, const uint32_t *b_idx,
+                            const float *b_val, uint64_t K, uint64_t nnz_a, uint64_t nnz_b,
+                            uint32_t n_rows, uint32_t n_cols, crop_mem where, crop_own own)
+{
+    if (!ctx) return CROP_E_ARG;
+    if (!a_off || !b_off || (nnz_a && (!a_idx || !a_val)) || (nnz_b && (!b_idx || !b_val)))
+        return fail(ctx, CROP_E_ARG, "null input pointer");
+    if (K >= (1ull << 32) || nnz_a >= (1ull << 32) || nnz_b >= (1ull << 32))
+        return fail(ctx, CROP_E_UNSUPPORTED, "K and nnz must be below 2^32");
+    if (own == CROP_OWN_BORROW && where != CROP_MEM_DEVICE)
+        return fail(ctx, CROP_E_ARG, "only device buffers can be borrowed");
+    DeviceGuard g(ctx->device);
+    reset_input(ctx);
+    ctx->err_index = -1;
+    Input &in = ctx->in;
+    CK(fetch(in.h_off, a_off, K + 1, where));
+    CK(fetch(in.h_b_off, b_off, K + 1, where));
+    crop_status st = check_offsets(ctx, in.h_off, nnz_a, "a vectors");
+    if (st != CROP_OK) return st;
+    st = check_offsets(ctx, in.h_b_off, nnz_b, "b vectors");
+    if (st != CROP_OK) return st;
+    uint64_t terms = 0;
+    for (uint64_t k = 0; k < K; ++k)
+        terms += (uint64_t)(in.h_off[k + 1] - in.h_off[k]) * (in.h_b_off[k + 1] - in.h_b_off[k]);
+    if (terms >= (1ull << 32))
+        return fail(ctx, CROP_E_UNSUPPORTED, "more than 2^32 - 1 terms in one run");
+    in.total_terms = terms;
+    CK(place(a_off, K + 1, where, own, in.own[0], &in.a_off, ctx->stream));
+    CK(place(a_idx, nnz_a, where, own, in.own[1], &in.a_idx, ctx->stream));
+    CK(place(a_val, nnz_a, where, own, in.own[2], &in.a_val, ctx->stream));
+    CK(place(b_off, K + 1, where, own, in.own[3], &in.b_off, ctx->stream));
+    CK(place(b_idx, nnz_b, where, own, in.own[4], &in.b_idx, ctx->stream));
+    CK(place(b_val, nnz_b, where, own, in.own[5], &in.b_val, ctx->stream));
+    int64_t bad = -1;
+    st = validate_on_device(ctx, in.a_off, K, in.a_idx, nnz_a, n_rows, &bad);
+    if (st != CROP_OK) return st;
+    if (bad < 0) {
+        st = validate_on_device(ctx, in.b_off, K, in.b_idx, nnz_b, n_cols, &bad);
+        if (st != CROP_OK) return st;
+    }
+    if (bad >= 0) {
+        ctx->err_index = bad;
+        return fail(ctx, CROP_E_INPUT,
+                    "vector pair " + std::to_string(bad) +
+                        ": index out of range or indices not strictly increasing");
+    }
+    in.K = K;
+    in.nnz_a = nnz_a;
+    in.nnz_b = nnz_b;
+    in.n_rows = n_rows;
+    in.n_cols = n_cols;
+    in.wide_keys = true;
+    build_outer_chunks(in);
+    CK(in.d_op_chunks.ensure(std::max<size_t>(1, in.op_chunks.size()) * sizeof(OpChunk)));
+    if (!in.op_chunks.empty())
+        CK(hipMemcpy(in.d_op_chunks.p, in.op_chunks.data(), in.op_chunks.size() * sizeof(OpChunk),
+                     hipMemcpyHostToDevice));
+    in.mode = Mode::Outer;
+    return CROP_OK;
+}
+
+// ============================================================== runs
+
+crop_status crop_run_exact(crop_ctx *ctx)
+{
+    if (!ctx) return CROP_E_ARG;
+    if (ctx->in.mode == Mode::None) return fail(ctx, CROP_E_STATE, "no input loaded");
+    DeviceGuard g(ctx->device);
+    ctx->result = Result::None;
+    const bool outer = ctx->in.mode == Mode::Outer;
+    crop_status st = outer ? plan_outer(ctx) : plan_tx(ctx);
+    if (st != CROP_OK) return st;
+    ctx->plan.log2_slots = (outer || ctx->in.wide_keys) ? 13 : 14;
+    ctx->plan.BS = 256;
+    st = ensure_route_buffers(ctx, ctx->in.wide_keys ? 8 : 4, outer);
+    if (st != CROP_OK) return st;
+    const RoutePlan &pl = ctx->plan;
+    hipStream_t s = ctx->stream;
+    uint32_t *cnt = ctx->cnt_mat.as<uint32_t>();
+    st = run_begin(ctx);
+    if (st != CROP_OK) return st;
+    if (pl.n_chunks) CK(outer ? launch_op_count(ctx, cnt, s) : launch_tx_count(ctx, cnt, s));
+    STAGE("count");
+    CK(launch_scan_counts(cnt, pl.n_chunks, pl.NB, pl.G, ctx->part_buf.as<uint32_t>(),
+                          ctx->bin_off.as<uint32_t>(), ctx->counter.as<uint32_t>(), s));
+    STAGE("scan");
+    if (pl.n_chunks)
+        CK(outer ? launch_op_scatter(ctx, cnt, ctx->keys.p, ctx->vals.as<float>(), s)
+                 : launch_tx_scatter(ctx, cnt, ctx->keys.p, s));
+    STAGE("scatter");
+    CK(outer ? launch_aggregate_sums(ctx, s) : launch_aggregate_counts(ctx, s));
+    STAGE("aggregate");
+    st = run_end(ctx);
+    if (st != CROP_OK) return st;
+    ctx->result = Result::Exact;
+    return CROP_OK;
+}
+
+crop_status crop_synchronize(crop_ctx *ctx)
+{
+    if (!ctx) return CROP_E_ARG;
+    DeviceGuard g(ctx->device);
+    CK(hipStreamSynchronize(ctx->stream));
+    return CROP_OK;
+}
+
+crop_status crop_last_run_ms(crop_ctx *ctx, float *ms)
+{
+    if (!ctx || !ms) return CROP_E_ARG;
+    if (!ctx->timed) return fail(ctx, CROP_E_STATE, "no run recorded");
+    DeviceGuard g(ctx->device);
+    CK(hipEventSynchronize(ctx->ev1));
+    CK(hipEventElapsedTime(ms, ctx->ev0, ctx->ev1));
+    return CROP_OK;
+}
+
+// ============================================================== readback
+
+crop_status crop_result_sizes(crop_ctx *ctx, uint64_t *sizes, uint64_t *terms)
+{
+    if (!ctx) return CROP_E_ARG;
+    crop_status st = require_exact(ctx);
+    if (st != CROP_OK) return st;
+    DeviceGuard g(ctx->device);
+    const RoutePlan &pl = ctx->plan;
+    std::vector<uint32_t> bs(pl.NB), bo(pl.NB + 1);
+    CK(hipStreamSynchronize(ctx->stream));
+    CK(hipMemcpy(bs.data(), ctx->bin_size.p, pl.NB * 4, hipMemcpyDeviceToHost));
+    CK(hipMemcpy(bo.data(), ctx->bin_off.p, (pl.NB + 1) * 4, hipMemcpyDeviceToHost));
+    for (uint32_t p = 0; p < ctx->P; ++p) {
+        uint64_t n = 0;
+        for (uint32_t s = 0; s < pl.S; ++s) n += bs[p * pl.S + s];
+        if (sizes) sizes[p] = n;
+        if (terms) terms[p] = (uint64_t)bo[(p + 1) * pl.S] - bo[p * pl.S];
+    }
+    return CROP_OK;
+}
+
+crop_status crop_read_all(crop_ctx *ctx, crop_mem where, uint32_t *i, uint32_t *j,
+                          uint32_t *count, float *value, uint64_t cap, uint64_t *written,
+                          uint64_t *part_off)
+{
+    if (!ctx || !i || !j) return CROP_E_ARG;
+    crop_status st = require_exact(ctx);
+    if (st != CROP_OK) return st;
+    DeviceGuard g(ctx->device);
+    const RoutePlan &pl = ctx->plan;
+    std::vector<uint32_t> bs(pl.NB);
+    CK(hipStreamSynchronize(ctx->stream));
+    CK(hipMemcpy(bs.data(), ctx->bin_size.p, pl.NB * 4, hipMemcpyDeviceToHost));
+    std::vector<uint32_t> dst(pl.NB);
+    uint64_t tot = 0;
+    for (uint32_t b = 0; b < pl.NB; ++b) {
+        dst[b] = (uint32_t)tot;
+        tot += bs[b];
+    }
+    if (part_off)
+        for (uint32_t p = 0; p <= ctx->P; ++p)
+            part_off[p] = p < ctx->P ? dst[p * pl.S] : tot;
+    if (written) *written = tot;
+    if (tot > cap) return fail(ctx, CROP_E_CAPACITY, "output capacity below the entry count");
+    const bool outer = ctx->in.mode == Mode::Outer;
+    // device staging: dst offsets, and the four outputs when reading to host
+    // scratch layout: dst offsets, then (host readback only) four arrays of n
+    // words starting at the next 256-byte boundary
+    const size_t n = std::max<uint64_t>(tot, 1);
+    const size_t head = ((size_t)pl.NB * 4 + 255) / 256 * 256;
+    CK(ctx->scratch.ensure(head + (where == CROP_MEM_HOST ? 16 * n : 0)));
+    uint32_t *d_dst = ctx->scratch.as<uint32_t>();
+    CK(hipMemcpyAsync(d_dst, dst.data(), pl.NB * 4, hipMemcpyHostToDevice, ctx->stream));
+    uint32_t *oi = i, *oj = j, *oc = count;
+    float *ov = value;
+    if (where == CROP_MEM_HOST) {
+        char *base = reinterpret_cast<char *>(d_dst) + head;
+        oi = reinterpret_cast<uint32_t *>(base);
+        oj = oi + n;
+        oc = count ? oj + n : nullptr;
+        ov = value ? reinterpret_cast<float *>(oj + 2 * n) : nullptr;
+    }
+    CK(launch_gather_result(ctx, d_dst, oi, oj, outer ? nullptr : oc, outer ? ov : nullptr,
+                            ctx->stream));
+    if (where == CROP_MEM_HOST) {
+        CK(hipMemcpyAsync(i, oi, tot * 4, hipMemcpyDeviceToHost, ctx->stream));
+        CK(hipMemcpyAsync(j, oj, tot * 4, hipMemcpyDeviceToHost, ctx->stream));
+        if (count && !outer) CK(hipMemcpyAsync(count, oc, tot * 4, hipMemcpyDeviceToHost, ctx->stream));
+        if (value && outer) CK(hipMemcpyAsync(value, ov, tot * 4, hipMemcpyDeviceToHost, ctx->stream));
+    }
+    CK(hipStreamSynchronize(ctx->stream));
+    return CROP_OK;
+}
+
+crop_status crop_read_partition(crop_ctx *ctx, uint32_t p, uint32_t *i, uint32_t *j,
+                                uint32_t *count, float *value, uint64_t cap, uint64_t *written)
+{
+    if (!ctx || !i || !j) return CROP_E_ARG;
+    crop_status st = require_exact(ctx);
+    if (st != CROP_OK) return st;
+    if (p >= ctx->P) return fail(ctx, CROP_E_ARG, "partition index out of range");
+    DeviceGuard g(ctx->device);
+    const RoutePlan &pl = ctx->plan;
+    std::vector<uint32_t> bs(pl.NB), bo(pl.NB + 1);
+    CK(hipStreamSynchronize(ctx->stream));
+    CK(hipMemcpy(bs.data(), ctx->bin_size.p, pl.NB * 4, hipMemcpyDeviceToHost));
+    CK(hipMemcpy(bo.data(), ctx->bin_off.p, (pl.NB + 1) * 4, hipMemcpyDeviceToHost));
+    uint64_t tot = 0;
+    for (uint32_t s = 0; s < pl.S; ++s) tot += bs[p * pl.S + s];
+    if (written) *written = tot;
+    if (tot > cap) return fail(ctx, CROP_E_CAPACITY, "output capacity below the entry count");
+    const bool outer = ctx->in.mode == Mode::Outer;
+    const bool wide = ctx->in.wide_keys;
+    uint64_t w = 0;
+    for (uint32_t s = 0; s < pl.S; ++s) {
+        uint32_t b = p * pl.S + s, n = bs[b], src = bo[b];
+        if (!n) continue;
+        if (wide) {
+            std::vector<uint64_t> k(n);
+            CK(hipMemcpy(k.data(), ctx->keys.as<uint64_t>() + src, n * 8, hipMemcpyDeviceToHost));
+            for (uint32_t e = 0; e < n; ++e) {
+                i[w + e] = (uint32_t)(k[e] >> 32);
+                j[w + e] = (uint32_t)k[e];
+            }
+        } else {
+            std::vector<uint32_t> k(n);
+            CK(hipMemcpy(k.data(), ctx->keys.as<uint32_t>() + src, n * 4, hipMemcpyDeviceToHost));
+            for (uint32_t e = 0; e < n; ++e) {
+                i[w + e] = k[e] >> 16;
+                j[w + e] = k[e] & 0xFFFFu;
+            }
+        }
+        if (count && !outer)
+            CK(hipMemcpy(count + w, ctx->out_cnt.as<uint32_t>() + src, n * 4, hipMemcpyDeviceToHost));
+        if (value && outer)
+            CK(hipMemcpy(value + w, ctx->vals.as<float>() + src, n * 4, hipMemcpyDeviceToHost));
+        w += n;
+    }
+    return CROP_OK;
+}
+
+}  // extern "C"

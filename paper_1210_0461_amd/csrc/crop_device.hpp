@@ -1,0 +1,97 @@
+// Device-side building blocks shared by the CRoP kernels (wave64, gfx950).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace crop {
+
+constexpr int kWave = 64;
+constexpr uint32_t kEmpty32 = 0xFFFFFFFFu;
+constexpr uint64_t kEmpty64 = 0xFFFFFFFFFFFFFFFFull;
+constexpr int kNumXcd = 8;  // MI355X: 256 CUs in 8 XCDs, one L2 each
+
+// Workgroups are dispatched round-robin over the XCDs (block b runs on XCD
+// b % 8).  Remap so that each XCD receives a contiguous range of logical
+// work items: consecutive items then share that XCD's L2.
+__device__ inline uint32_t xcd_contiguous(uint32_t b, uint32_t n)
+{
+    const uint32_t x = b % kNumXcd, j = b / kNumXcd;
+    const uint32_t q = n / kNumXcd, r = n % kNumXcd;
+    return x * q + (x < r ? x : r) + j;
+}
+
+__device__ inline uint32_t lane_id() { return __lane_id(); }
+
+// Inclusive scan of v across the 64 lanes of a wave.
+__device__ inline uint32_t wave_inclusive_scan(uint32_t v)
+{
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        uint32_t o = __shfl_up(v, d, kWave);
+        if (lane >= (uint32_t)d) v += o;
+    }
+    return v;
+}
+
+// Exclusive scan over the block; returns this thread's prefix and the
+// block total in *total.  s_tmp needs BS/64 + 1 words.  Contains barriers:
+// every thread of the block must call it.
+template <int BS>
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t *s_tmp, uint32_t *total)
+{
+    constexpr int NW = BS / kWave;
+    const uint32_t lane = lane_id();
+    const uint32_t w = threadIdx.x / kWave;
+    uint32_t inc = wave_inclusive_scan(v);
+    if (lane == kWave - 1) s_tmp[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (int k = 0; k < NW; ++k) {
+            uint32_t t = s_tmp[k];
+            s_tmp[k] = run;
+            run += t;
+        }
+        s_tmp[NW] = run;
+    }
+    __syncthreads();
+    uint32_t res = s_tmp[w] + inc - v;
+    *total = s_tmp[NW];
+    __syncthreads();
+    return res;
+}
+
+// In-place exclusive scan of an LDS array a[0..m); writes the total to a[m].
+// Each thread scans a contiguous segment.  Contains barriers.
+template <int BS>
+__device__ inline void lds_exclusive_scan(uint32_t *a, uint32_t m, uint32_t *s_tmp)
+{
+    const uint32_t per = (m + BS - 1) / BS;
+    const uint32_t beg = threadIdx.x * per;
+    const uint32_t end = beg + per < m ? beg + per : m;
+    uint32_t sum = 0;
+    for (uint32_t k = beg; k < end; ++k) sum += a[k];
+    uint32_t total;
+    uint32_t run = block_exclusive_scan<BS>(sum, s_tmp, &total);
+    for (uint32_t k = beg; k < end; ++k) {
+        uint32_t t = a[k];
+        a[k] = run;
+        run += t;
+    }
+    if (threadIdx.x == 0) a[m] = total;
+    __syncthreads();
+}
+
+// Fibonacci hashing of a key to a table slot (Knuth, TAOCP vol. 3, 6.4).
+__device__ inline uint32_t slot_of(uint32_t key, uint32_t log2_slots)
+{
+    return (key * 0x9E3779B1u) >> (32 - log2_slots);
+}
+
+__device__ inline uint32_t slot_of(uint64_t key, uint32_t log2_slots)
+{
+    return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - log2_slots));
+}
+
+}  // namespace crop

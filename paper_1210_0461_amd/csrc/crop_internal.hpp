@@ -1,0 +1,154 @@
+// Host-side internals of the CRoP library: context, buffers, kernel launchers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/crop.h"
+#include "crop_hash.hpp"
+
+namespace crop {
+
+enum class Mode { None = 0, Tx = 1, Outer = 2 };
+enum class Result { None = 0, Exact = 1, TopK = 2 };
+
+// A device allocation that grows on demand (never shrinks).
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t need)
+    {
+        if (need <= bytes && p) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        if (need == 0) need = 256;
+        hipError_t e = hipMalloc(&p, need);
+        if (e == hipSuccess) bytes = need;
+        return e;
+    }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+// One enumeration workgroup's share of an outer-product stream: the
+// a-entries [a_lo, a_hi) of vectors k0..k1-1.
+struct OpChunk {
+    uint32_t k0, k1, a_lo, a_hi;
+};
+
+// Resolved routing configuration of a run.
+struct RoutePlan {
+    uint32_t S = 1;          // routing bins per partition
+    uint32_t NB = 1;         // routing bins in total (P * S)
+    uint32_t n_chunks = 0;   // enumeration workgroups
+    uint32_t R = 256;        // vectors per chunk (transactions)
+    uint32_t max_items = 0;  // largest number of staged entries in a chunk
+    uint32_t G = 1;          // row groups of the count-matrix scan
+    uint32_t log2_slots = 14;
+    uint32_t BS = 256;
+};
+
+struct Input {
+    Mode mode = Mode::None;
+    // transactions
+    const uint32_t *off = nullptr, *items = nullptr;
+    uint64_t T = 0, nnz = 0;
+    uint32_t n_items = 0;
+    // outer products
+    const uint32_t *a_off = nullptr, *a_idx = nullptr, *b_off = nullptr, *b_idx = nullptr;
+    const float *a_val = nullptr, *b_val = nullptr;
+    uint64_t K = 0, nnz_a = 0, nnz_b = 0;
+    uint32_t n_rows = 0, n_cols = 0;
+    // derived
+    uint64_t total_terms = 0;
+    bool wide_keys = false;            // keys need 64 bits
+    std::vector<uint32_t> h_off;       // host copy of the vector offsets
+    std::vector<uint32_t> h_b_off;     // outer products: host copy of b_off
+    std::vector<OpChunk> op_chunks;    // outer products: chunk plan
+    uint32_t op_max_a = 0;             // largest a-range of an outer chunk
+    DevBuf own[6];                     // private copies (COPY mode)
+    DevBuf d_op_chunks;
+};
+
+// Per-stage HIP events of one run (profiling mode).
+constexpr int kStageRing = 64;
+constexpr int kMaxStages = 10;
+struct StageRec {
+    int n = 0;
+    const char *names[kMaxStages] = {};
+    hipEvent_t ev[kMaxStages + 1] = {};
+};
+
+}  // namespace crop
+
+struct crop_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    hipStream_t own_stream = nullptr;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    bool timed = false;
+
+    uint32_t P = 1;
+    uint64_t seed = 0x243F6A8885A308D3ull;
+    crop::HashParams hp{};
+    uint32_t ss_counters = 1u << 14;  // counters per partition
+    uint32_t ss_ell = 16;             // counters per bucket
+    crop_tune tune{};                 // user request (0 = auto)
+    crop::RoutePlan plan{};
+
+    crop::Input in;
+    crop::Result result = crop::Result::None;
+    uint32_t topk_K = 0;
+
+    // work and result buffers
+    crop::DevBuf cnt_mat, part_buf, bin_off, bin_size, keys, vals, out_cnt, spill, counter;
+    crop::DevBuf ss_state, topk_buf, scratch;
+
+    // profiling: per-stage events of the last kStageRing runs
+    bool profiling = false;
+    std::vector<crop::StageRec> ring;
+    uint64_t runs = 0;
+    crop::StageRec *cur_rec = nullptr;
+
+    std::string err;
+    int64_t err_index = -1;
+};
+
+namespace crop {
+
+// ---- launchers (kernels live in the .hip files) ---------------------------
+hipError_t launch_validate_tx(const uint32_t *off, uint64_t T, const uint32_t *items,
+                              uint64_t nnz, uint32_t n_items, unsigned long long *bad,
+                              hipStream_t s);
+hipError_t launch_validate_outer(const uint32_t *v_off, uint64_t K, const uint32_t *idx,
+                                 uint64_t nnz, uint32_t n, unsigned long long *bad,
+                                 hipStream_t s);
+
+hipError_t launch_tx_count(const crop_ctx *c, uint32_t *cnt, hipStream_t s);
+hipError_t launch_tx_scatter(const crop_ctx *c, const uint32_t *cur, void *keys, hipStream_t s);
+hipError_t launch_op_count(const crop_ctx *c, uint32_t *cnt, hipStream_t s);
+hipError_t launch_op_scatter(const crop_ctx *c, const uint32_t *cur, void *keys, float *vals,
+                             hipStream_t s);
+// Count matrix [n_chunks x NB] -> global write offsets in place; bin_off
+// [NB+1] receives the bin starts; *counter is reset to 0.
+hipError_t launch_scan_counts(uint32_t *cnt, uint32_t n_chunks, uint32_t NB, uint32_t G,
+                              uint32_t *part, uint32_t *bin_off, uint32_t *counter,
+                              hipStream_t s);
+
+hipError_t launch_aggregate_counts(const crop_ctx *c, hipStream_t s);
+hipError_t launch_aggregate_sums(const crop_ctx *c, hipStream_t s);
+
+// Gather the bin-segmented exact result into partition-contiguous arrays.
+hipError_t launch_gather_result(const crop_ctx *c, const uint32_t *dst_off, uint32_t *out_i,
+                                uint32_t *out_j, uint32_t *out_cnt, float *out_val,
+                                hipStream_t s);
+
+}  // namespace crop

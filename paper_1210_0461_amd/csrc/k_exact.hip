@@ -1,0 +1,297 @@
+// Exact accumulation of each routing bin in an LDS open-addressing table.
+//
+// A partition's exact result is the weight of every entry it owns
+// (Section 4: sum_k a_k(i) b_k(j); Section 7: pair supports).  The paper
+// contrasts its shared-nothing owners with "a large, shared data structure"
+// updated at random (Section 7.3, throughput discussion): here every routing
+// bin belongs to one workgroup, whose table lives in that CU's LDS, so all
+// random updates are on-chip and no two workgroups share an entry.
+//
+// Persistent workgroups pull bins from a counter.  A bin's keys are read
+// once, coalesced; each wavefront first merges repeated copies of the same
+// key (heavy pairs land thousands of times in one bin) and then inserts with
+// linear probing: compare-and-swap claims an empty slot, an atomic add
+// accumulates.  When the table passes its fill limit the workgroup stops
+// inserting (at a barrier, so the key set is frozen) and entries that are
+// not present are spilled to HBM with their weight; after the table is
+// written out, the spilled entries are accumulated in further rounds.  The
+// table's entries and a later round's entries are disjoint, so every key is
+// written exactly once.  Output: distinct keys in place of the bin's routed
+// keys, weights in a parallel array, and the bin's entry count.
+#include <type_traits>
+
+#include "crop_device.hpp"
+#include "crop_internal.hpp"
+
+namespace crop {
+
+namespace {
+
+template <class KeyT> struct Empty;
+template <> struct Empty<uint32_t> { static constexpr uint32_t v = kEmpty32; };
+template <> struct Empty<uint64_t> { static constexpr uint64_t v = kEmpty64; };
+
+template <class KeyT>
+__device__ inline KeyT shfl_key(KeyT k, int src)
+{
+    if (sizeof(KeyT) == 4) return (KeyT)__shfl((int)k, src, kWave);
+    uint32_t lo = (uint32_t)__shfl((int)(uint32_t)k, src, kWave);
+    uint32_t hi = (uint32_t)__shfl((int)(uint32_t)((uint64_t)k >> 32), src, kWave);
+    return (KeyT)(((uint64_t)hi << 32) | lo);
+}
+
+// Merge lanes of the wavefront that hold the same key as the first open
+// lane (two rounds): the lowest such lane takes the total unit weight, the
+// others drop out.  Lanes with w == 0 do not take part.
+template <class KeyT>
+__device__ inline void wave_merge_unit(KeyT key, uint32_t &w)
+{
+    bool open = w != 0;
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int round = 0; round < 2; ++round) {
+        uint64_t act = __ballot(open);
+        if (act == 0) break;
+        int leader = __ffsll((long long)act) - 1;
+        KeyT lk = shfl_key(key, leader);
+        bool eq = open && key == lk;
+        uint64_t m = __ballot(eq);
+        if (eq) {
+            open = false;
+            w = (lane == (uint32_t)leader) ? (uint32_t)__popcll(m) : 0u;
+        }
+    }
+}
+
+template <class KeyT, class W>
+struct Table {
+    KeyT *k;
+    W *w;
+    uint32_t mask, log2;
+};
+
+__device__ inline void add_weight(uint32_t *p, uint32_t w) { atomicAdd(p, w); }
+__device__ inline void add_weight(float *p, float w) { atomicAdd(p, w); }
+
+// Returns false when the key is absent and may not be inserted.
+template <class KeyT, class W>
+__device__ inline bool table_add(const Table<KeyT, W> &t, KeyT key, W w, bool may_insert,
+                                 uint32_t *s_occ)
+{
+    uint32_t s = slot_of(key, t.log2);
+    for (;;) {
+        KeyT cur = t.k[s];
+        if (cur == key) {
+            add_weight(&t.w[s], w);
+            return true;
+        }
+        if (cur == Empty<KeyT>::v) {
+            if (!may_insert) return false;
+            KeyT old = atomicCAS(&t.k[s], Empty<KeyT>::v, key);
+            if (old == Empty<KeyT>::v) {
+                atomicAdd(s_occ, 1u);
+                add_weight(&t.w[s], w);
+                return true;
+            }
+            if (old == key) {
+                add_weight(&t.w[s], w);
+                return true;
+            }
+        }
+        s = (s + 1) & t.mask;
+    }
+}
+
+template <class KeyT, class W>
+struct Spilled {
+    KeyT key;
+    W w;
+};
+
+// Write the table's entries to keys_out/w_out starting at *s_nout.
+template <int BS, class KeyT, class W>
+__device__ inline void table_dump(const Table<KeyT, W> &t, uint32_t S, KeyT *keys_out, W *w_out,
+                                  uint32_t *s_nout)
+{
+    const uint32_t lane = lane_id();
+    for (uint32_t s0 = 0; s0 < S; s0 += BS) {
+        uint32_t s = s0 + threadIdx.x;
+        bool has = s < S && t.k[s] != Empty<KeyT>::v;
+        uint64_t m = __ballot(has);
+        uint32_t n = (uint32_t)__popcll(m);
+        uint32_t base = 0;
+        if (n) {
+            if (lane == (uint32_t)(__ffsll((long long)m) - 1)) base = atomicAdd(s_nout, n);
+            base = __shfl(base, __ffsll((long long)m) - 1, kWave);
+        }
+        if (has) {
+            uint32_t r = (uint32_t)__popcll(m & ((1ull << lane) - 1));
+            keys_out[base + r] = t.k[s];
+            w_out[base + r] = t.w[s];
+        }
+    }
+}
+
+template <int BS, class KeyT, class W>
+__device__ inline void table_clear(const Table<KeyT, W> &t, uint32_t S)
+{
+    for (uint32_t s = threadIdx.x; s < S; s += BS) {
+        t.k[s] = Empty<KeyT>::v;
+        t.w[s] = (W)0;
+    }
+}
+
+// One persistent workgroup per CU.  Input: keys[bin_off[b] .. bin_off[b+1])
+// (one term each) and, for weighted input (sums), vals.  Output in place of
+// the keys: distinct keys and their weights in w_out, count in bin_size[b].
+template <int BS, class KeyT, class W, int LOG2S>
+__global__ void __launch_bounds__(BS)
+k_aggregate(const uint32_t *__restrict__ bin_off, KeyT *__restrict__ keys,
+            const float *__restrict__ vals, W *__restrict__ w_out, uint32_t *__restrict__ bin_size,
+            Spilled<KeyT, W> *__restrict__ spill, uint32_t NB, uint32_t *counter,
+            uint32_t cap_soft)
+{
+    constexpr uint32_t S = 1u << LOG2S;
+    constexpr int U = 4;  // keys per thread per batch
+    __shared__ KeyT s_k[S];
+    __shared__ W s_w[S];
+    __shared__ uint32_t s_occ, s_nout, s_nspill, s_bin;
+    __shared__ int s_insert;
+    const Table<KeyT, W> t{s_k, s_w, S - 1, LOG2S};
+
+    for (;;) {
+        if (threadIdx.x == 0) s_bin = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t b = s_bin;
+        if (b >= NB) break;
+        const uint32_t k0 = bin_off[b], k1 = bin_off[b + 1];
+        table_clear<BS>(t, S);
+        if (threadIdx.x == 0) {
+            s_occ = 0;
+            s_nout = 0;
+            s_nspill = 0;
+            s_insert = 1;
+        }
+        __syncthreads();
+
+        // first round: the routed terms
+        for (uint32_t base = k0; base < k1; base += BS * U) {
+            KeyT kk[U];
+            W ww[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                uint32_t i = base + u * BS + threadIdx.x;
+                bool valid = i < k1;
+                kk[u] = valid ? keys[i] : Empty<KeyT>::v;
+                if constexpr (std::is_same<W, uint32_t>::value) {
+                    uint32_t w1 = valid ? 1u : 0u;
+                    wave_merge_unit(kk[u], w1);
+                    ww[u] = (W)w1;
+                } else {
+                    ww[u] = valid ? (W)vals[i] : (W)0;
+                    if (!valid) kk[u] = Empty<KeyT>::v;
+                }
+            }
+            const bool ins = s_insert != 0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                bool live = kk[u] != Empty<KeyT>::v;
+                if constexpr (std::is_same<W, uint32_t>::value) live = live && ww[u] != 0;
+                if (live && !table_add(t, kk[u], ww[u], ins, &s_occ)) {
+                    uint32_t p = atomicAdd(&s_nspill, 1u);
+                    spill[k0 + p] = Spilled<KeyT, W>{kk[u], ww[u]};
+                }
+            }
+            __syncthreads();
+            if (threadIdx.x == 0 && s_occ > cap_soft) s_insert = 0;
+            __syncthreads();
+        }
+        table_dump<BS>(t, S, keys + k0, w_out + k0, &s_nout);
+        __syncthreads();
+
+        // later rounds: spilled entries (in place in the spill segment)
+        while (s_nspill != 0) {
+            const uint32_t n = s_nspill;
+            __syncthreads();
+            table_clear<BS>(t, S);
+            if (threadIdx.x == 0) {
+                s_occ = 0;
+                s_nspill = 0;
+                s_insert = 1;
+            }
+            __syncthreads();
+            for (uint32_t base = 0; base < n; base += BS) {
+                uint32_t i = base + threadIdx.x;
+                Spilled<KeyT, W> e{Empty<KeyT>::v, (W)0};
+                if (i < n) e = spill[k0 + i];
+                const bool ins = s_insert != 0;
+                __syncthreads();  // every entry of this batch is read before any rewrite
+                if (i < n && !table_add(t, e.key, e.w, ins, &s_occ)) {
+                    uint32_t p = atomicAdd(&s_nspill, 1u);
+                    spill[k0 + p] = e;
+                }
+                __syncthreads();
+                if (threadIdx.x == 0 && s_occ > cap_soft) s_insert = 0;
+                __syncthreads();
+            }
+            table_dump<BS>(t, S, keys + k0, w_out + k0, &s_nout);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) bin_size[b] = s_nout;
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+static uint32_t persistent_grid(uint32_t NB)
+{
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) == hipSuccess)
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    uint32_t g = (uint32_t)cus;
+    return NB < g ? NB : g;
+}
+
+hipError_t launch_aggregate_counts(const crop_ctx *c, hipStream_t s)
+{
+    const RoutePlan &pl = c->plan;
+    uint32_t grid = persistent_grid(pl.NB);
+    if (!c->in.wide_keys) {
+        constexpr int L = 14;
+        hipLaunchKernelGGL((k_aggregate<512, uint32_t, uint32_t, L>), dim3(grid), dim3(512), 0, s,
+                           c->bin_off.as<uint32_t>(), c->keys.as<uint32_t>(), nullptr,
+                           c->out_cnt.as<uint32_t>(), c->bin_size.as<uint32_t>(),
+                           c->spill.as<Spilled<uint32_t, uint32_t>>(), pl.NB,
+                           c->counter.as<uint32_t>(), (1u << L) * 5 / 8);
+    } else {
+        constexpr int L = 13;
+        hipLaunchKernelGGL((k_aggregate<512, uint64_t, uint32_t, L>), dim3(grid), dim3(512), 0, s,
+                           c->bin_off.as<uint32_t>(), c->keys.as<uint64_t>(), nullptr,
+                           c->out_cnt.as<uint32_t>(), c->bin_size.as<uint32_t>(),
+                           c->spill.as<Spilled<uint64_t, uint32_t>>(), pl.NB,
+                           c->counter.as<uint32_t>(), (1u << L) * 5 / 8);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_aggregate_sums(const crop_ctx *c, hipStream_t s)
+{
+    const RoutePlan &pl = c->plan;
+    uint32_t grid = persistent_grid(pl.NB);
+    constexpr int L = 13;
+    hipLaunchKernelGGL((k_aggregate<512, uint64_t, float, L>), dim3(grid), dim3(512), 0, s,
+                       c->bin_off.as<uint32_t>(), c->keys.as<uint64_t>(),
+                       c->vals.as<float>(), c->vals.as<float>(), c->bin_size.as<uint32_t>(),
+                       c->spill.as<Spilled<uint64_t, float>>(), pl.NB, c->counter.as<uint32_t>(),
+                       (1u << L) * 5 / 8);
+    return hipGetLastError();
+}
+
+size_t spill_entry_bytes(bool wide, bool sums)
+{
+    if (sums) return sizeof(Spilled<uint64_t, float>);
+    return wide ? sizeof(Spilled<uint64_t, uint32_t>) : sizeof(Spilled<uint32_t, uint32_t>);
+}
+
+}  // namespace crop

@@ -1,0 +1,480 @@
+// Term enumeration and routing: every nonzero term of the stream is mapped
+// to its routing bin by the consistent hash and written, bin by bin, into
+// one array of packed keys.
+//
+// Routing bins are equal intervals of the 2^32 hash space, bin =
+// (h * NB) >> 32 with NB = P * S; bin / S is the term's partition, the
+// owner interval of Section 6, Theorem 1 (nested-floor identity).  Each
+// bin is later accumulated by one workgroup in LDS.
+//
+// The pass is split the way a counting sort is: a count kernel builds a
+// [chunk x bin] matrix of term counts, a scan turns it into write offsets
+// (bin-major, so every bin is one contiguous segment), and a scatter kernel
+// enumerates again and writes each key at its offset.  Enumerating twice is
+// cheaper than moving the terms twice: a term is a few ALU operations on
+// staged LDS data, while its key costs HBM traffic.
+//
+// Enumeration inside a chunk.  Transactions (Section 7): the terms of a
+// transaction are its pairs x < y.  Entries of a chunk are staged in LDS with
+// h_b precomputed, and each entry's partner count w = (row end - position - 1)
+// is prefix-summed; every thread then walks an equal share of the chunk's
+// terms in order, so a long transaction does not stall its wavefront.
+// Outer products (Section 4): the terms of vector pair k are all
+// (a_k(i), b_k(j)); the a-entries are staged and the b-entries read through
+// L2, with the same balanced walk over w = |b_k| per a-entry.
+#include "crop_device.hpp"
+#include "crop_internal.hpp"
+
+namespace crop {
+
+namespace {
+
+// ---------------------------------------------------------------- staging
+
+// Stage the entries of rows [r0, r1): s_x[k] = item, s_hb[k] = h_b(item),
+// s_wp = exclusive prefix of the per-entry partner counts (length m + 1).
+// Returns the number of terms of the chunk; *p0 receives its first entry.
+template <int BS>
+__device__ uint32_t stage_tx(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
+                             uint32_t r0, uint32_t r1, const HashParams &hp, uint32_t *s_x,
+                             uint32_t *s_hb, uint32_t *s_wp, uint32_t *s_tmp, uint32_t *m_out)
+{
+    const uint32_t p0 = off[r0];
+    const uint32_t m = off[r1] - p0;
+    for (uint32_t k = threadIdx.x; k < m; k += BS) {
+        uint32_t x = items[p0 + k];
+        s_x[k] = x;
+        s_hb[k] = hash_b(hp, x);
+    }
+    for (uint32_t r = r0 + threadIdx.x; r < r1; r += BS) {
+        uint32_t a = off[r] - p0, e = off[r + 1] - p0;
+        for (uint32_t k = a; k < e; ++k) s_wp[k] = e - k - 1;
+    }
+    __syncthreads();
+    lds_exclusive_scan<BS>(s_wp, m, s_tmp);
+    *m_out = m;
+    return s_wp[m];
+}
+
+// Walk this thread's equal share of the chunk's Tc terms in order and call
+// visit(x, y, h) for each pair x < y of a transaction.
+template <int BS, class Visit>
+__device__ inline void walk_tx(uint32_t Tc, uint32_t m, const uint32_t *s_x, const uint32_t *s_hb,
+                               const uint32_t *s_wp, const HashParams &hp, Visit visit)
+{
+    const uint32_t t0 = (uint32_t)(((uint64_t)Tc * threadIdx.x) / BS);
+    const uint32_t t1 = (uint32_t)(((uint64_t)Tc * (threadIdx.x + 1)) / BS);
+    if (t0 >= t1) return;
+    // entry k with s_wp[k] <= t0 < s_wp[k+1]  (s_wp[0] = 0, s_wp[m] = Tc > t0)
+    uint32_t lo = 0, hi = m;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (s_wp[mid] <= t0) lo = mid; else hi = mid;
+    }
+    uint32_t k = lo;
+    uint32_t q = k + 1 + (t0 - s_wp[k]);
+    uint32_t e = k + 1 + (s_wp[k + 1] - s_wp[k]);
+    uint32_t x = s_x[k];
+    uint32_t ha = hash_a(hp, x);
+    for (uint32_t t = t0; t < t1; ++t) {
+        visit(x, s_x[q], ha + s_hb[q]);
+        if (++q == e && t + 1 < t1) {
+            do { ++k; } while (s_wp[k + 1] == s_wp[k]);
+            q = k + 1;
+            e = k + 1 + (s_wp[k + 1] - s_wp[k]);
+            x = s_x[k];
+            ha = hash_a(hp, x);
+        }
+    }
+}
+
+template <int BS>
+__device__ inline uint32_t *tx_smem_layout(uint32_t *smem, uint32_t NB, uint32_t max_items,
+                                           uint32_t **s_x, uint32_t **s_hb, uint32_t **s_wp,
+                                           uint32_t **s_tmp)
+{
+    uint32_t *hist = smem;
+    *s_x = hist + NB;
+    *s_hb = *s_x + max_items;
+    *s_wp = *s_hb + max_items;
+    *s_tmp = *s_wp + max_items + 1;
+    return hist;
+}
+
+// ---------------------------------------------------------------- kernels
+
+template <int BS>
+__global__ void __launch_bounds__(BS)
+k_tx_count(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items, uint32_t T,
+           uint32_t R, HashParams hp, uint32_t NB, uint32_t max_items, uint32_t *__restrict__ cnt)
+{
+    extern __shared__ uint32_t smem[];
+    uint32_t *s_x, *s_hb, *s_wp, *s_tmp;
+    uint32_t *hist = tx_smem_layout<BS>(smem, NB, max_items, &s_x, &s_hb, &s_wp, &s_tmp);
+    const uint32_t chunk = xcd_contiguous(blockIdx.x, gridDim.x);
+    const uint32_t r0 = chunk * R;
+    const uint32_t r1 = min(r0 + R, T);
+    for (uint32_t b = threadIdx.x; b < NB; b += BS) hist[b] = 0;
+    uint32_t m;
+    const uint32_t Tc = stage_tx<BS>(off, items, r0, r1, hp, s_x, s_hb, s_wp, s_tmp, &m);
+    walk_tx<BS>(Tc, m, s_x, s_hb, s_wp, hp, [&](uint32_t, uint32_t, uint32_t h) {
+        atomicAdd(&hist[interval_of(h, NB)], 1u);
+    });
+    __syncthreads();
+    uint32_t *row = cnt + (size_t)chunk * NB;
+    for (uint32_t b = threadIdx.x; b < NB; b += BS) row[b] = hist[b];
+}
+
+template <int BS, class KeyT>
+__global__ void __launch_bounds__(BS)
+k_tx_scatter(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items, uint32_t T,
+             uint32_t R, HashParams hp, uint32_t NB, uint32_t max_items,
+             const uint32_t *__restrict__ cur, KeyT *__restrict__ keys)
+{
+    extern __shared__ uint32_t smem[];
+    uint32_t *s_x, *s_hb, *s_wp, *s_tmp;
+    uint32_t *pos = tx_smem_layout<BS>(smem, NB, max_items, &s_x, &s_hb, &s_wp, &s_tmp);
+    const uint32_t chunk = xcd_contiguous(blockIdx.x, gridDim.x);
+    const uint32_t r0 = chunk * R;
+    const uint32_t r1 = min(r0 + R, T);
+    const uint32_t *row = cur + (size_t)chunk * NB;
+    for (uint32_t b = threadIdx.x; b < NB; b += BS) pos[b] = row[b];
+    uint32_t m;
+    const uint32_t Tc = stage_tx<BS>(off, items, r0, r1, hp, s_x, s_hb, s_wp, s_tmp, &m);
+    walk_tx<BS>(Tc, m, s_x, s_hb, s_wp, hp, [&](uint32_t x, uint32_t y, uint32_t h) {
+        uint32_t p = atomicAdd(&pos[interval_of(h, NB)], 1u);
+        if (sizeof(KeyT) == 4)
+            keys[p] = (KeyT)((x << 16) | y);
+        else
+            keys[p] = (KeyT)(((uint64_t)x << 32) | y);
+    });
+}
+
+// ---- outer products
+
+// Stage the a-entries [a_lo, a_hi) of vectors k0..k1-1: s_ai = index,
+// s_ha = h_a, s_av = value, s_bs = first b-entry of the vector, s_wp =
+// exclusive prefix of |b_k| per a-entry.
+template <int BS>
+__device__ uint32_t stage_op(const OpChunk ch, const uint32_t *__restrict__ a_off,
+                             const uint32_t *__restrict__ a_idx, const float *__restrict__ a_val,
+                             const uint32_t *__restrict__ b_off, const HashParams &hp,
+                             uint32_t *s_ai, uint32_t *s_ha, float *s_av, uint32_t *s_bs,
+                             uint32_t *s_wp, uint32_t *s_tmp, uint32_t *m_out)
+{
+    const uint32_t m = ch.a_hi - ch.a_lo;
+    for (uint32_t k = threadIdx.x; k < m; k += BS) {
+        uint32_t i = a_idx[ch.a_lo + k];
+        s_ai[k] = i;
+        s_ha[k] = hash_a(hp, i);
+        s_av[k] = a_val[ch.a_lo + k];
+    }
+    for (uint32_t v = ch.k0 + threadIdx.x; v < ch.k1; v += BS) {
+        uint32_t a = max(a_off[v], ch.a_lo), e = min(a_off[v + 1], ch.a_hi);
+        uint32_t bs = b_off[v], nb = b_off[v + 1] - bs;
+        for (uint32_t p = a; p < e; ++p) {
+            s_bs[p - ch.a_lo] = bs;
+            s_wp[p - ch.a_lo] = nb;
+        }
+    }
+    __syncthreads();
+    lds_exclusive_scan<BS>(s_wp, m, s_tmp);
+    *m_out = m;
+    return s_wp[m];
+}
+
+template <int BS, class Visit>
+__device__ inline void walk_op(uint32_t Tc, uint32_t m, const uint32_t *s_ai, const uint32_t *s_ha,
+                               const float *s_av, const uint32_t *s_bs, const uint32_t *s_wp,
+                               const uint32_t *__restrict__ b_idx, const float *__restrict__ b_val,
+                               const HashParams &hp, Visit visit)
+{
+    const uint32_t t0 = (uint32_t)(((uint64_t)Tc * threadIdx.x) / BS);
+    const uint32_t t1 = (uint32_t)(((uint64_t)Tc * (threadIdx.x + 1)) / BS);
+    if (t0 >= t1) return;
+    uint32_t lo = 0, hi = m;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (s_wp[mid] <= t0) lo = mid; else hi = mid;
+    }
+    uint32_t k = lo;
+    uint32_t q = s_bs[k] + (t0 - s_wp[k]);
+    uint32_t e = s_bs[k] + (s_wp[k + 1] - s_wp[k]);
+    uint32_t i = s_ai[k], ha = s_ha[k];
+    float av = s_av[k];
+    for (uint32_t t = t0; t < t1; ++t) {
+        uint32_t j = b_idx[q];
+        visit(i, j, ha + hash_b(hp, j), av * b_val[q]);
+        if (++q == e && t + 1 < t1) {
+            do { ++k; } while (s_wp[k + 1] == s_wp[k]);
+            q = s_bs[k];
+            e = q + (s_wp[k + 1] - s_wp[k]);
+            i = s_ai[k];
+            ha = s_ha[k];
+            av = s_av[k];
+        }
+    }
+}
+
+struct OpArgs {
+    const uint32_t *a_off, *a_idx, *b_off, *b_idx;
+    const float *a_val, *b_val;
+    const OpChunk *chunks;
+};
+
+template <int BS>
+__device__ inline uint32_t *op_smem_layout(uint32_t *smem, uint32_t NB, uint32_t max_a,
+                                           uint32_t **s_ai, uint32_t **s_ha, float **s_av,
+                                           uint32_t **s_bs, uint32_t **s_wp, uint32_t **s_tmp)
+{
+    uint32_t *hist = smem;
+    *s_ai = hist + NB;
+    *s_ha = *s_ai + max_a;
+    *s_av = reinterpret_cast<float *>(*s_ha + max_a);
+    *s_bs = reinterpret_cast<uint32_t *>(*s_av + max_a);
+    *s_wp = *s_bs + max_a;
+    *s_tmp = *s_wp + max_a + 1;
+    return hist;
+}
+
+template <int BS>
+__global__ void __launch_bounds__(BS)
+k_op_count(OpArgs a, HashParams hp, uint32_t NB, uint32_t max_a, uint32_t *__restrict__ cnt)
+{
+    extern __shared__ uint32_t smem[];
+    uint32_t *s_ai, *s_ha, *s_bs, *s_wp, *s_tmp;
+    float *s_av;
+    uint32_t *hist = op_smem_layout<BS>(smem, NB, max_a, &s_ai, &s_ha, &s_av, &s_bs, &s_wp, &s_tmp);
+    const uint32_t chunk = xcd_contiguous(blockIdx.x, gridDim.x);
+    for (uint32_t b = threadIdx.x; b < NB; b += BS) hist[b] = 0;
+    uint32_t m;
+    const uint32_t Tc = stage_op<BS>(a.chunks[chunk], a.a_off, a.a_idx, a.a_val, a.b_off, hp, s_ai,
+                                     s_ha, s_av, s_bs, s_wp, s_tmp, &m);
+    walk_op<BS>(Tc, m, s_ai, s_ha, s_av, s_bs, s_wp, a.b_idx, a.b_val, hp,
+                [&](uint32_t, uint32_t, uint32_t h, float) {
+                    atomicAdd(&hist[interval_of(h, NB)], 1u);
+                });
+    __syncthreads();
+    uint32_t *row = cnt + (size_t)chunk * NB;
+    for (uint32_t b = threadIdx.x; b < NB; b += BS) row[b] = hist[b];
+}
+
+template <int BS>
+__global__ void __launch_bounds__(BS)
+k_op_scatter(OpArgs a, HashParams hp, uint32_t NB, uint32_t max_a,
+             const uint32_t *__restrict__ cur, uint64_t *__restrict__ keys,
+             float *__restrict__ vals)
+{
+    extern __shared__ uint32_t smem[];
+    uint32_t *s_ai, *s_ha, *s_bs, *s_wp, *s_tmp;
+    float *s_av;
+    uint32_t *pos = op_smem_layout<BS>(smem, NB, max_a, &s_ai, &s_ha, &s_av, &s_bs, &s_wp, &s_tmp);
+    const uint32_t chunk = xcd_contiguous(blockIdx.x, gridDim.x);
+    const uint32_t *row = cur + (size_t)chunk * NB;
+    for (uint32_t b = threadIdx.x; b < NB; b += BS) pos[b] = row[b];
+    uint32_t m;
+    const uint32_t Tc = stage_op<BS>(a.chunks[chunk], a.a_off, a.a_idx, a.a_val, a.b_off, hp, s_ai,
+                                     s_ha, s_av, s_bs, s_wp, s_tmp, &m);
+    walk_op<BS>(Tc, m, s_ai, s_ha, s_av, s_bs, s_wp, a.b_idx, a.b_val, hp,
+                [&](uint32_t i, uint32_t j, uint32_t h, float v) {
+                    uint32_t p = atomicAdd(&pos[interval_of(h, NB)], 1u);
+                    keys[p] = ((uint64_t)i << 32) | j;
+                    vals[p] = v;
+                });
+}
+
+// ---------------------------------------------------------------- scan
+
+// part[g][b] = sum of cnt[c][b] over the rows c of group g.
+__global__ void __launch_bounds__(256)
+k_colsum(const uint32_t *__restrict__ cnt, uint32_t n, uint32_t NB, uint32_t rows_per_g,
+         uint32_t *__restrict__ part)
+{
+    const uint32_t b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= NB) return;
+    const uint32_t g = blockIdx.y;
+    const uint32_t c0 = g * rows_per_g, c1 = min(n, c0 + rows_per_g);
+    uint32_t s = 0;
+    for (uint32_t c = c0; c < c1; ++c) s += cnt[(size_t)c * NB + b];
+    part[(size_t)g * NB + b] = s;
+}
+
+// One workgroup: part[g][b] <- exclusive prefix over g; bin_off[b] <-
+// exclusive prefix over b of the bin totals; bin_off[NB] <- total; resets
+// the aggregation work counter.
+__global__ void __launch_bounds__(1024)
+k_colbase(uint32_t *__restrict__ part, uint32_t NB, uint32_t G, uint32_t *__restrict__ bin_off,
+          uint32_t *__restrict__ counter)
+{
+    __shared__ uint32_t s_tmp[1024 / kWave + 1];
+    const uint32_t per = (NB + 1023) / 1024;
+    const uint32_t b0 = threadIdx.x * per, b1 = min(NB, b0 + per);
+    uint32_t sum = 0;
+    for (uint32_t b = b0; b < b1; ++b) {
+        uint32_t run = 0;
+        for (uint32_t g = 0; g < G; ++g) {
+            uint32_t v = part[(size_t)g * NB + b];
+            part[(size_t)g * NB + b] = run;
+            run += v;
+        }
+        bin_off[b] = run;  // bin total, turned into an offset below
+        sum += run;
+    }
+    uint32_t total;
+    uint32_t run = block_exclusive_scan<1024>(sum, s_tmp, &total);
+    for (uint32_t b = b0; b < b1; ++b) {
+        uint32_t t = bin_off[b];
+        bin_off[b] = run;
+        run += t;
+    }
+    if (threadIdx.x == 0) {
+        bin_off[NB] = total;
+        counter[0] = 0;
+        counter[1] = 0;
+    }
+}
+
+// cnt[c][b] <- bin_off[b] + part[g][b] + sum of cnt[c'][b] for earlier c' in g.
+__global__ void __launch_bounds__(256)
+k_colapply(uint32_t *__restrict__ cnt, uint32_t n, uint32_t NB, uint32_t rows_per_g,
+           const uint32_t *__restrict__ part, const uint32_t *__restrict__ bin_off)
+{
+    const uint32_t b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= NB) return;
+    const uint32_t g = blockIdx.y;
+    const uint32_t c0 = g * rows_per_g, c1 = min(n, c0 + rows_per_g);
+    uint32_t run = bin_off[b] + part[(size_t)g * NB + b];
+    for (uint32_t c = c0; c < c1; ++c) {
+        uint32_t v = cnt[(size_t)c * NB + b];
+        cnt[(size_t)c * NB + b] = run;
+        run += v;
+    }
+}
+
+// ---------------------------------------------------------------- validation
+
+// bad <- min over offending vectors v of v (vector v is [v_off[v], v_off[v+1])).
+__global__ void __launch_bounds__(256)
+k_validate_csr(const uint32_t *__restrict__ v_off, uint64_t K, const uint32_t *__restrict__ idx,
+               uint64_t nnz, uint32_t n, unsigned long long *bad)
+{
+    for (uint64_t v = (uint64_t)blockIdx.x * 256 + threadIdx.x; v < K;
+         v += (uint64_t)gridDim.x * 256) {
+        uint32_t a = v_off[v], e = v_off[v + 1];
+        bool ok = a <= e && e <= nnz;
+        if (ok) {
+            for (uint32_t k = a; k < e; ++k) {
+                uint32_t x = idx[k];
+                if (x >= n || (k > a && x <= idx[k - 1])) {
+                    ok = false;
+                    break;
+                }
+            }
+        }
+        if (!ok) atomicMin(bad, (unsigned long long)v);
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+
+static size_t tx_smem_bytes(uint32_t NB, uint32_t max_items, uint32_t BS)
+{
+    return sizeof(uint32_t) * ((size_t)NB + 3 * (size_t)max_items + 1 + BS / kWave + 1);
+}
+
+static size_t op_smem_bytes(uint32_t NB, uint32_t max_a, uint32_t BS)
+{
+    return sizeof(uint32_t) * ((size_t)NB + 5 * (size_t)max_a + 1 + BS / kWave + 1);
+}
+
+hipError_t launch_tx_count(const crop_ctx *c, uint32_t *cnt, hipStream_t s)
+{
+    const RoutePlan &pl = c->plan;
+    size_t sm = tx_smem_bytes(pl.NB, pl.max_items, 256);
+    hipLaunchKernelGGL(k_tx_count<256>, dim3(pl.n_chunks), dim3(256), sm, s, c->in.off,
+                       c->in.items, (uint32_t)c->in.T, pl.R, c->hp, pl.NB, pl.max_items, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_tx_scatter(const crop_ctx *c, const uint32_t *cur, void *keys, hipStream_t s)
+{
+    const RoutePlan &pl = c->plan;
+    size_t sm = tx_smem_bytes(pl.NB, pl.max_items, 256);
+    if (c->in.wide_keys)
+        hipLaunchKernelGGL((k_tx_scatter<256, uint64_t>), dim3(pl.n_chunks), dim3(256), sm, s,
+                           c->in.off, c->in.items, (uint32_t)c->in.T, pl.R, c->hp, pl.NB,
+                           pl.max_items, cur, static_cast<uint64_t *>(keys));
+    else
+        hipLaunchKernelGGL((k_tx_scatter<256, uint32_t>), dim3(pl.n_chunks), dim3(256), sm, s,
+                           c->in.off, c->in.items, (uint32_t)c->in.T, pl.R, c->hp, pl.NB,
+                           pl.max_items, cur, static_cast<uint32_t *>(keys));
+    return hipGetLastError();
+}
+
+static OpArgs op_args(const crop_ctx *c)
+{
+    OpArgs a;
+    a.a_off = c->in.a_off;
+    a.a_idx = c->in.a_idx;
+    a.a_val = c->in.a_val;
+    a.b_off = c->in.b_off;
+    a.b_idx = c->in.b_idx;
+    a.b_val = c->in.b_val;
+    a.chunks = c->in.d_op_chunks.as<OpChunk>();
+    return a;
+}
+
+hipError_t launch_op_count(const crop_ctx *c, uint32_t *cnt, hipStream_t s)
+{
+    const RoutePlan &pl = c->plan;
+    size_t sm = op_smem_bytes(pl.NB, pl.max_items, 256);
+    hipLaunchKernelGGL(k_op_count<256>, dim3(pl.n_chunks), dim3(256), sm, s, op_args(c), c->hp,
+                       pl.NB, pl.max_items, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_op_scatter(const crop_ctx *c, const uint32_t *cur, void *keys, float *vals,
+                             hipStream_t s)
+{
+    const RoutePlan &pl = c->plan;
+    size_t sm = op_smem_bytes(pl.NB, pl.max_items, 256);
+    hipLaunchKernelGGL(k_op_scatter<256>, dim3(pl.n_chunks), dim3(256), sm, s, op_args(c), c->hp,
+                       pl.NB, pl.max_items, cur, static_cast<uint64_t *>(keys), vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_counts(uint32_t *cnt, uint32_t n_chunks, uint32_t NB, uint32_t G,
+                              uint32_t *part, uint32_t *bin_off, uint32_t *counter,
+                              hipStream_t s)
+{
+    const uint32_t rows_per_g = (n_chunks + G - 1) / G;
+    dim3 grid((NB + 255) / 256, G);
+    hipLaunchKernelGGL(k_colsum, grid, dim3(256), 0, s, cnt, n_chunks, NB, rows_per_g, part);
+    hipLaunchKernelGGL(k_colbase, dim3(1), dim3(1024), 0, s, part, NB, G, bin_off, counter);
+    hipLaunchKernelGGL(k_colapply, grid, dim3(256), 0, s, cnt, n_chunks, NB, rows_per_g, part,
+                       bin_off);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_tx(const uint32_t *off, uint64_t T, const uint32_t *items,
+                              uint64_t nnz, uint32_t n_items, unsigned long long *bad,
+                              hipStream_t s)
+{
+    uint64_t blocks = (T + 255) / 256;
+    if (blocks > 65535) blocks = 65535;
+    if (blocks == 0) blocks = 1;
+    hipLaunchKernelGGL(k_validate_csr, dim3((uint32_t)blocks), dim3(256), 0, s, off, T, items,
+                       nnz, n_items, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_outer(const uint32_t *v_off, uint64_t K, const uint32_t *idx,
+                                 uint64_t nnz, uint32_t n, unsigned long long *bad,
+                                 hipStream_t s)
+{
+    return launch_validate_tx(v_off, K, idx, nnz, n, bad, s);
+}
+
+}  // namespace crop

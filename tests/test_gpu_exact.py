@@ -1,0 +1,261 @@
+"""GPU parity of the exact path against the CPU oracle, through the C ABI.
+
+Integer supports and partition assignment must be bit-exact (the oracle is
+the plain definition: Section 7 pairs, Section 5 hash, Theorem 1 owners);
+fp32 sums of outer products must satisfy |c32 - c64| <= 1e-5 * sum|terms|
+against the fp64 oracle (Section 4 entry weights).
+"""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+SEED = 0x243F6A8885A308D3
+
+
+@pytest.fixture(scope="module")
+def crop():
+    import paper_1210_0461_amd as crop
+    return crop
+
+
+@pytest.fixture
+def ctx(crop):
+    h = crop.crop_create(0)
+    yield h
+    crop.crop_destroy(h)
+
+
+def run_tx(crop, ctx, st, P, seed=SEED, **tune):
+    crop.crop_set_partitions(ctx, P)
+    crop.crop_set_seed(ctx, seed)
+    crop.crop_set_tuning(ctx, **tune)
+    crop.crop_load_transactions(ctx, st.off, st.items, st.n)
+    crop.crop_run_exact(ctx)
+    return crop.crop_result_sizes(ctx, P)
+
+
+def sort_xyc(x, y, c):
+    o = np.lexsort((y, x))
+    return x[o], y[o], c[o]
+
+
+def compare_all_partitions(crop, ctx, st, P, seed=SEED, **tune):
+    sizes, terms = run_tx(crop, ctx, st, P, seed, **tune)
+    ref = oracle.tx_exact(st.off, st.items, P, seed)
+    assert np.array_equal(terms, ref["part_terms"]), "terms per partition"
+    assert np.array_equal(sizes, ref["part_sizes"]), "entries per partition"
+    i, j, c, part_off = crop.crop_read_all(ctx, P)
+    start = np.concatenate([[0], np.cumsum(ref["part_sizes"].astype(np.int64))])
+    for p in range(P):
+        a, b = int(part_off[p]), int(part_off[p + 1])
+        g = sort_xyc(i[a:b], j[a:b], c[a:b])
+        r0, r1 = start[p], start[p + 1]
+        o = (ref["x"][r0:r1], ref["y"][r0:r1], ref["cnt"][r0:r1])
+        for u, v in zip(g, o):
+            assert np.array_equal(u, v), f"partition {p}"
+    return sizes
+
+
+def test_small_config_bit_exact(crop, ctx):
+    st = datagen.config_small()
+    print(f"small: T={st.T} nnz={st.nnz}", flush=True)
+    compare_all_partitions(crop, ctx, st, 8)
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_tiny_streams(crop, ctx, seed):
+    st = datagen.tiny_transactions(seed, T=50 + 13 * seed, n=40 + 7 * seed, cap=16)
+    P = [1, 2, 3, 8, 64, 1000][seed % 6]
+    compare_all_partitions(crop, ctx, st, P, seed=seed * 7919 + 1)
+
+
+def test_read_partition_matches_read_all(crop, ctx):
+    st = datagen.config_small()
+    P = 8
+    sizes, _ = run_tx(crop, ctx, st, P)
+    i, j, c, part_off = crop.crop_read_all(ctx, P)
+    for p in (0, 3, 7):
+        pi, pj, pc = crop.crop_read_partition(ctx, p, int(sizes[p]))
+        a, b = int(part_off[p]), int(part_off[p + 1])
+        for u, v in zip(sort_xyc(pi, pj, pc), sort_xyc(i[a:b], j[a:b], c[a:b])):
+            assert np.array_equal(u, v)
+
+
+def test_edge_cases(crop, ctx):
+    # empty stream
+    off = np.zeros(1, np.uint32)
+    sizes, terms = run_tx(crop, ctx, datagen.Transactions(off, np.zeros(0, np.uint32), 10), 4)
+    assert sizes.sum() == 0 and terms.sum() == 0
+    # only singletons and empty transactions: no terms
+    st = datagen.Transactions(np.array([0, 1, 1, 2, 3], np.uint32),
+                              np.array([4, 5, 6], np.uint32), 10)
+    sizes, terms = run_tx(crop, ctx, st, 3)
+    assert sizes.sum() == 0 and terms.sum() == 0
+    # one transaction of 64 items, and one of 2,000 items (C(2000,2) terms)
+    for L in (64, 2000):
+        st = datagen.Transactions(np.array([0, L], np.uint32),
+                                  np.arange(0, 3 * L, 3, dtype=np.uint32), 3 * L)
+        compare_all_partitions(crop, ctx, st, 8)
+
+
+def test_wide_keys(crop, ctx):
+    # more than 2^16 item ids: 64-bit keys
+    st = datagen.transactions(3000, 200_000, 0.9, 8.0, 40, datagen.Raw(77), "wide")
+    compare_all_partitions(crop, ctx, st, 16)
+
+
+def test_forced_spill_rounds(crop, ctx):
+    # one bin holding ~3.2e4 distinct pairs overflows the LDS table, so the
+    # spill rounds must accumulate the rest exactly
+    st = datagen.config_small()
+    compare_all_partitions(crop, ctx, st, 1, bins_per_partition=1)
+    compare_all_partitions(crop, ctx, st, 2, bins_per_partition=1)
+
+
+def test_tuning_does_not_change_results(crop, ctx):
+    st = datagen.tiny_transactions(5, T=3000, n=300, cap=30, mean_len=9.0)
+    ref = None
+    for tune in (dict(), dict(bins_per_partition=4), dict(rows_per_chunk=16),
+                 dict(bins_per_partition=7, rows_per_chunk=100)):
+        run_tx(crop, ctx, st, 8, **tune)
+        i, j, c, _ = crop.crop_read_all(ctx, 8)
+        cur = sort_xyc(i, j, c)
+        if ref is not None:
+            for u, v in zip(cur, ref):
+                assert np.array_equal(u, v), tune
+        ref = cur
+
+
+def test_invalid_input_is_rejected(crop, ctx):
+    bad = [
+        (np.array([0, 2, 3], np.uint32), np.array([1, 1, 2], np.uint32), 5, 0),   # repeat
+        (np.array([0, 2, 3], np.uint32), np.array([2, 1, 2], np.uint32), 5, 0),   # unsorted
+        (np.array([0, 1, 3], np.uint32), np.array([1, 2, 9], np.uint32), 5, 1),   # id >= n
+    ]
+    for off, items, n, row in bad:
+        with pytest.raises(crop.CropError) as e:
+            crop.crop_load_transactions(ctx, off, items, n)
+        assert e.value.status == -3 and e.value.index == row
+    with pytest.raises(crop.CropError) as e:
+        crop.crop_load_transactions(ctx, np.array([0, 3, 2], np.uint32),
+                                    np.array([1, 2], np.uint32), 5)
+    assert e.value.status == -3
+    with pytest.raises(crop.CropError) as e:
+        crop.crop_run_exact(ctx)
+    assert e.value.status == -2
+
+
+def test_device_borrowed_input_and_device_readback(crop, ctx):
+    import torch
+    st = datagen.config_small()
+    off = torch.from_numpy(st.off.astype(np.int32)).cuda()
+    items = torch.from_numpy(st.items.astype(np.int32)).cuda()
+    crop.crop_set_partitions(ctx, 8)
+    crop.crop_set_seed(ctx, SEED)
+    crop.crop_load_transactions(ctx, off, items, st.n, own=crop.CROP_OWN_BORROW)
+    crop.crop_run_exact(ctx)
+    i, j, c, _ = crop.crop_read_all(ctx, 8, device="cuda")
+    ref = oracle.tx_exact(st.off, st.items, 8, SEED)
+    g = sort_xyc(i.cpu().numpy().view(np.uint32), j.cpu().numpy().view(np.uint32),
+                 c.cpu().numpy().view(np.uint32))
+    r = sort_xyc(ref["x"], ref["y"], ref["cnt"])
+    for u, v in zip(g, r):
+        assert np.array_equal(u, v)
+
+
+def test_large_config_sampled_partitions(crop, ctx):
+    """1M transactions, P = 1024, in the benchmark's launch configuration:
+    every partition's term count, the total support, and eight whole
+    partitions compared entry by entry with the oracle."""
+    st = datagen.config_large()
+    P = 1024
+    print(f"large: T={st.T} nnz={st.nnz}", flush=True)
+    sizes, terms = run_tx(crop, ctx, st, P)
+    ref_terms = oracle.tx_part_terms(st.off, st.items, P, SEED)
+    assert np.array_equal(terms, ref_terms)
+    i, j, c, part_off = crop.crop_read_all(ctx, P)
+    L = st.lengths()
+    assert int(c.astype(np.uint64).sum()) == int((L * (L - 1) // 2).sum())
+    for p in (0, 1, 511, 1023) + tuple(np.random.default_rng(3).integers(0, P, 4).tolist()):
+        q, r = oracle.partition_interval(p, P)
+        ref = oracle.tx_exact(st.off, st.items, P, SEED, q, r)
+        a, b = int(part_off[p]), int(part_off[p + 1])
+        g = sort_xyc(i[a:b], j[a:b], c[a:b])
+        o = sort_xyc(ref["x"], ref["y"], ref["cnt"])
+        for u, v in zip(g, o):
+            assert np.array_equal(u, v), f"partition {p}"
+    # every reported key hashes to the partition it was reported in
+    pid = np.repeat(np.arange(P), np.diff(part_off.astype(np.int64)))
+    sel = np.random.default_rng(4).integers(0, i.shape[0], 200000)
+    _, _, _, part = oracle.hash_many(SEED, i[sel], j[sel], P)
+    assert np.array_equal(part, pid[sel])
+    # no key is reported twice
+    keys = oracle.pack_keys(i, j)
+    assert np.unique(keys).shape[0] == keys.shape[0]
+
+
+# ------------------------------------------------------------------ outer products
+
+def run_op(crop, ctx, op, P, seed=SEED, **tune):
+    crop.crop_set_partitions(ctx, P)
+    crop.crop_set_seed(ctx, seed)
+    crop.crop_set_tuning(ctx, **tune)
+    crop.crop_load_outer(ctx, op.a_off, op.a_idx, op.a_val, op.b_off, op.b_idx, op.b_val,
+                         op.n_rows, op.n_cols)
+    crop.crop_run_exact(ctx)
+    return crop.crop_result_sizes(ctx, P)
+
+
+def compare_outer(crop, ctx, op, P, seed=SEED, **tune):
+    sizes, terms = run_op(crop, ctx, op, P, seed, **tune)
+    ref = oracle.op_exact(op, P, seed)
+    assert np.array_equal(terms, ref["part_terms"])
+    assert np.array_equal(sizes, ref["part_sizes"])
+    i, j, v, part_off = crop.crop_read_all(ctx, P, outer=True)
+    start = np.concatenate([[0], np.cumsum(ref["part_sizes"].astype(np.int64))])
+    worst = 0.0
+    for p in range(P):
+        a, b = int(part_off[p]), int(part_off[p + 1])
+        o = np.lexsort((j[a:b], i[a:b]))
+        r0, r1 = start[p], start[p + 1]
+        assert np.array_equal(i[a:b][o], ref["i"][r0:r1])
+        assert np.array_equal(j[a:b][o], ref["j"][r0:r1])
+        err = np.abs(v[a:b][o].astype(np.float64) - ref["sum"][r0:r1])
+        bound = 1e-5 * ref["abs"][r0:r1]
+        assert np.all(err <= bound), f"partition {p}: max excess {np.max(err - bound)}"
+        if b > a:
+            worst = max(worst, float(np.max(err / np.maximum(ref["abs"][r0:r1], 1e-300))))
+        one = ref["nterms"][r0:r1] == 1
+        # a single-term entry is the fp32 product itself, exactly
+        assert np.array_equal(v[a:b][o][one], ref["sum"][r0:r1][one].astype(np.float32))
+    return worst
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_outer_tiny(crop, ctx, seed):
+    op = datagen.tiny_outer(seed, K=40 + seed, n_rows=50, n_cols=60, max_nnz=20)
+    compare_outer(crop, ctx, op, [1, 4, 8, 3, 16, 2][seed], seed=seed + 11)
+
+
+def test_outer_config(crop, ctx):
+    op = datagen.config_outer()
+    print(f"outer: K={op.K} nnz_a={op.a_idx.shape[0]}", flush=True)
+    worst = compare_outer(crop, ctx, op, 8)
+    print(f"outer: worst |c32-c64|/sum|terms| = {worst:.3e}", flush=True)
+
+
+def test_outer_heavy_vector(crop, ctx):
+    # one k with 2,000 x 2,000 terms is split over many workgroups
+    rng = datagen.Raw(9)
+    n = 5000
+    ai = np.sort(np.argsort(rng.raw(n))[:2000]).astype(np.uint32)
+    bi = np.sort(np.argsort(rng.raw(n))[:2000]).astype(np.uint32)
+    op = datagen.OuterProducts(np.array([0, 2000], np.uint32), ai,
+                               rng.uniform(2000).astype(np.float32),
+                               np.array([0, 2000], np.uint32), bi,
+                               (rng.uniform(2000) - 0.5).astype(np.float32), n, n)
+    compare_outer(crop, ctx, op, 4)
