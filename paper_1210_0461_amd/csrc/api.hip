@@ -15,6 +15,7 @@ using namespace crop;
 
 namespace crop {
 size_t spill_entry_bytes(bool wide, bool sums);
+size_t tx_scatter_smem_bytes(uint32_t NB, uint32_t max_items, uint32_t cap, bool wide);
 }
 
 namespace {
@@ -22,6 +23,7 @@ namespace {
 constexpr uint32_t kMaxP = 8192;
 constexpr uint64_t kTermsPerBin = 48000;   // routed terms per bin the auto plan aims at
 constexpr size_t kLdsBudget = 64 * 1024;   // enumeration kernels' staging budget
+constexpr size_t kStageBudget = 150 * 1024; // scatter kernel: dynamic LDS in total
 
 crop_status fail(crop_ctx *c, crop_status s, const std::string &msg)
 {
@@ -183,6 +185,14 @@ crop_status plan_tx(crop_ctx *ctx)
     pl.R = R;
     pl.max_items = mi;
     pl.n_chunks = (uint32_t)((in.T + R - 1) / R);
+    {
+        const size_t fixed = tx_scatter_smem_bytes(pl.NB, mi, 0, in.wide_keys);
+        const size_t per = in.wide_keys ? 8 : 4;
+        const size_t room = fixed < kStageBudget ? (kStageBudget - fixed) / per : 0;
+        if (room < 1024)
+            return fail(ctx, CROP_E_UNSUPPORTED, "routing bins and chunk leave no LDS for staging");
+        pl.stage_cap = (uint32_t)std::min<size_t>(room, 16384);
+    }
     pl.G = std::max<uint32_t>(1, std::min<uint32_t>(64, pl.n_chunks));
     return CROP_OK;
 }

@@ -83,6 +83,15 @@ __device__ inline void lds_exclusive_scan(uint32_t *a, uint32_t m, uint32_t *s_t
     __syncthreads();
 }
 
+// Workgroup barrier that orders LDS only.  __syncthreads() also waits for
+// every outstanding global load, which would drain a register prefetch.
+__device__ inline void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // Fibonacci hashing of a key to a table slot (Knuth, TAOCP vol. 3, 6.4).
 __device__ inline uint32_t slot_of(uint32_t key, uint32_t log2_slots)
 {

@@ -51,6 +51,7 @@ struct RoutePlan {
     uint32_t n_chunks = 0;   // enumeration workgroups
     uint32_t R = 256;        // vectors per chunk (transactions)
     uint32_t max_items = 0;  // largest number of staged entries in a chunk
+    uint32_t stage_cap = 0;  // scatter: terms staged in LDS per window
     uint32_t G = 1;          // row groups of the count-matrix scan
     uint32_t log2_slots = 14;
     uint32_t BS = 256;

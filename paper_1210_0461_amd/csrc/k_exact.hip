@@ -242,6 +242,180 @@ k_aggregate(const uint32_t *__restrict__ bin_off, KeyT *__restrict__ keys,
     }
 }
 
+// ---- packed table for 32-bit keys with 32-bit counts (transaction pairs)
+//
+// One 64-bit LDS word per slot: key in the low half (kEmpty32 when free),
+// count in the high half.  A hit is one 64-bit atomic add of (w << 32); an
+// insertion is one compare-and-swap of the whole word, so key and count
+// appear together.
+
+constexpr uint64_t kFreeSlot = 0x00000000FFFFFFFFull;
+
+enum { kDone = 0, kInserted = 1, kAbsent = 2 };
+
+template <uint32_t MASK, uint32_t LOG2S>
+__device__ inline int packed_add(uint64_t *tab, uint32_t key, uint32_t w, bool may_insert)
+{
+    uint32_t s = slot_of(key, LOG2S);
+    uint64_t v = tab[s];
+    for (;;) {
+        const uint32_t k = (uint32_t)v;
+        if (k == key) {
+            atomicAdd((unsigned long long *)&tab[s], (unsigned long long)w << 32);
+            return kDone;
+        }
+        if (k == kEmpty32) {
+            if (!may_insert) return kAbsent;
+            const uint64_t old = atomicCAS((unsigned long long *)&tab[s], (unsigned long long)v,
+                                           ((unsigned long long)w << 32) | key);
+            if (old == v) return kInserted;
+            v = old;  // taken meanwhile: look at the new occupant of the same slot
+            continue;
+        }
+        s = (s + 1) & MASK;
+        v = tab[s];
+    }
+}
+
+template <int BS, int LOG2S>
+__device__ inline void packed_dump(const uint64_t *tab, uint32_t *keys_out, uint32_t *w_out,
+                                   uint32_t *s_nout)
+{
+    constexpr uint32_t S = 1u << LOG2S;
+    const uint32_t lane = lane_id();
+    for (uint32_t s0 = 0; s0 < S; s0 += BS) {
+        const uint64_t v = tab[s0 + threadIdx.x];
+        const bool has = (uint32_t)v != kEmpty32;
+        const uint64_t m = __ballot(has);
+        const uint32_t n = (uint32_t)__popcll(m);
+        uint32_t base = 0;
+        if (n) {
+            const int first = __ffsll((long long)m) - 1;
+            if (lane == (uint32_t)first) base = atomicAdd(s_nout, n);
+            base = __shfl(base, first, kWave);
+        }
+        if (has) {
+            const uint32_t r = (uint32_t)__popcll(m & ((1ull << lane) - 1));
+            keys_out[base + r] = (uint32_t)v;
+            w_out[base + r] = (uint32_t)(v >> 32);
+        }
+    }
+}
+
+// One persistent workgroup per CU, 16 wavefronts.  The next batch of keys
+// is loaded into registers while the current one is accumulated, and the
+// batch barriers order LDS only, so the prefetch stays in flight.
+template <int BS, int LOG2S>
+__global__ void __launch_bounds__(BS)
+k_aggregate_packed(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ keys,
+                   uint32_t *__restrict__ w_out, uint32_t *__restrict__ bin_size,
+                   Spilled<uint32_t, uint32_t> *__restrict__ spill, uint32_t NB,
+                   uint32_t *counter, uint32_t cap_soft)
+{
+    constexpr uint32_t S = 1u << LOG2S;
+    constexpr uint32_t MASK = S - 1;
+    constexpr int U = 4;
+    static_assert(S % BS == 0, "table size must be a multiple of the block size");
+    __shared__ uint64_t tab[S];
+    __shared__ uint32_t s_occ, s_nout, s_nspill, s_bin;
+    __shared__ int s_insert;
+    const uint32_t lane = lane_id();
+
+    for (;;) {
+        if (threadIdx.x == 0) s_bin = atomicAdd(counter, 1u);
+        __syncthreads();
+        const uint32_t b = s_bin;
+        if (b >= NB) break;
+        const uint32_t k0 = bin_off[b], k1 = bin_off[b + 1];
+        for (uint32_t s = threadIdx.x; s < S; s += BS) tab[s] = kFreeSlot;
+        if (threadIdx.x == 0) {
+            s_occ = 0;
+            s_nout = 0;
+            s_nspill = 0;
+            s_insert = 1;
+        }
+        // Loads are unconditional (clamped to the bin's last key) so that no
+        // value is needed right after its load; validity is checked at use.
+        const uint32_t last = k1 - 1;  // read only when the bin is not empty
+        uint32_t cur[U] = {};
+        if (k1 > k0) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) cur[u] = keys[min(k0 + u * BS + threadIdx.x, last)];
+        }
+        lds_barrier();
+
+        for (uint32_t base = k0; base < k1; base += BS * U) {
+            uint32_t nx[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                nx[u] = keys[min(base + BS * U + u * BS + threadIdx.x, last)];
+            const bool ins = s_insert != 0;
+            uint32_t n_new = 0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (base + u * BS + threadIdx.x >= k1) continue;
+                const int r = packed_add<MASK, LOG2S>(tab, cur[u], 1u, ins);
+                if (r == kInserted) {
+                    ++n_new;
+                } else if (r == kAbsent) {
+                    const uint32_t p = atomicAdd(&s_nspill, 1u);
+                    spill[k0 + p] = Spilled<uint32_t, uint32_t>{cur[u], 1u};
+                }
+            }
+            // one occupancy update per wavefront
+            uint32_t tot = n_new;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) tot += __shfl_xor(tot, d, kWave);
+            if (lane == 0 && tot) atomicAdd(&s_occ, tot);
+            lds_barrier();
+            if (threadIdx.x == 0 && s_occ > cap_soft) s_insert = 0;
+            lds_barrier();
+#pragma unroll
+            for (int u = 0; u < U; ++u) cur[u] = nx[u];
+        }
+        __syncthreads();  // keys of the bin are consumed; the spill list is complete
+        packed_dump<BS, LOG2S>(tab, keys + k0, w_out + k0, &s_nout);
+        __syncthreads();
+
+        while (s_nspill != 0) {
+            const uint32_t n = s_nspill;
+            __syncthreads();
+            for (uint32_t s = threadIdx.x; s < S; s += BS) tab[s] = kFreeSlot;
+            if (threadIdx.x == 0) {
+                s_occ = 0;
+                s_nspill = 0;
+                s_insert = 1;
+            }
+            __syncthreads();
+            for (uint32_t base = 0; base < n; base += BS) {
+                const uint32_t i = base + threadIdx.x;
+                Spilled<uint32_t, uint32_t> e{kEmpty32, 0u};
+                if (i < n) e = spill[k0 + i];
+                const bool ins = s_insert != 0;
+                __syncthreads();  // the batch is read before any entry is rewritten
+                uint32_t n_new = 0;
+                if (i < n) {
+                    const int r = packed_add<MASK, LOG2S>(tab, e.key, e.w, ins);
+                    if (r == kInserted) {
+                        n_new = 1;
+                    } else if (r == kAbsent) {
+                        const uint32_t p = atomicAdd(&s_nspill, 1u);
+                        spill[k0 + p] = e;
+                    }
+                }
+                if (n_new) atomicAdd(&s_occ, 1u);
+                __syncthreads();
+                if (threadIdx.x == 0 && s_occ > cap_soft) s_insert = 0;
+                __syncthreads();
+            }
+            packed_dump<BS, LOG2S>(tab, keys + k0, w_out + k0, &s_nout);
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) bin_size[b] = s_nout;
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 static uint32_t persistent_grid(uint32_t NB)
@@ -259,11 +433,11 @@ hipError_t launch_aggregate_counts(const crop_ctx *c, hipStream_t s)
     uint32_t grid = persistent_grid(pl.NB);
     if (!c->in.wide_keys) {
         constexpr int L = 14;
-        hipLaunchKernelGGL((k_aggregate<512, uint32_t, uint32_t, L>), dim3(grid), dim3(512), 0, s,
-                           c->bin_off.as<uint32_t>(), c->keys.as<uint32_t>(), nullptr,
+        hipLaunchKernelGGL((k_aggregate_packed<1024, L>), dim3(grid), dim3(1024), 0, s,
+                           c->bin_off.as<uint32_t>(), c->keys.as<uint32_t>(),
                            c->out_cnt.as<uint32_t>(), c->bin_size.as<uint32_t>(),
                            c->spill.as<Spilled<uint32_t, uint32_t>>(), pl.NB,
-                           c->counter.as<uint32_t>(), (1u << L) * 5 / 8);
+                           c->counter.as<uint32_t>(), (1u << L) / 2);
     } else {
         constexpr int L = 13;
         hipLaunchKernelGGL((k_aggregate<512, uint64_t, uint32_t, L>), dim3(grid), dim3(512), 0, s,

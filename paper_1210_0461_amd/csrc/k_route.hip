@@ -16,9 +16,8 @@
 //
 // Enumeration inside a chunk.  Transactions (Section 7): the terms of a
 // transaction are its pairs x < y.  Entries of a chunk are staged in LDS with
-// h_b precomputed, and each entry's partner count w = (row end - position - 1)
-// is prefix-summed; every thread then walks an equal share of the chunk's
-// terms in order, so a long transaction does not stall its wavefront.
+// h_b precomputed and ordered by their partner count, and every lane loops
+// over the partners of one entry (stage_tx / enum_tx below).
 // Outer products (Section 4): the terms of vector pair k are all
 // (a_k(i), b_k(j)); the a-entries are staged and the b-entries read through
 // L2, with the same balanced walk over w = |b_k| per a-entry.
@@ -31,74 +30,127 @@ namespace {
 
 // ---------------------------------------------------------------- staging
 
-// Stage the entries of rows [r0, r1): s_x[k] = item, s_hb[k] = h_b(item),
-// s_wp = exclusive prefix of the per-entry partner counts (length m + 1).
-// Returns the number of terms of the chunk; *p0 receives its first entry.
+// LDS image of a chunk of transactions.  For entry k (its position inside
+// the chunk): xh[k] = (item, h_b(item)); w[k] = its partners, the entries
+// after it in its transaction; perm = the entries in order of decreasing w
+// (a 64-bucket counting sort).  Each lane owns one entry and loops over its
+// w partners; because consecutive lanes take consecutive entries of perm,
+// the lanes of a wavefront run loops of nearly equal length and the loop
+// body has no divergent branch.
+struct TxLds {
+    uint2 *xh;
+    uint16_t *w;
+    uint16_t *perm;
+    uint32_t *bucket;  // 64 words
+};
+
 template <int BS>
-__device__ uint32_t stage_tx(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
-                             uint32_t r0, uint32_t r1, const HashParams &hp, uint32_t *s_x,
-                             uint32_t *s_hb, uint32_t *s_wp, uint32_t *s_tmp, uint32_t *m_out)
+__device__ inline uint32_t stage_tx(const uint32_t *__restrict__ off,
+                                    const uint32_t *__restrict__ items, uint32_t r0, uint32_t r1,
+                                    const HashParams &hp, const TxLds &L)
 {
     const uint32_t p0 = off[r0];
     const uint32_t m = off[r1] - p0;
     for (uint32_t k = threadIdx.x; k < m; k += BS) {
         uint32_t x = items[p0 + k];
-        s_x[k] = x;
-        s_hb[k] = hash_b(hp, x);
+        L.xh[k] = make_uint2(x, hash_b(hp, x));
     }
+    if (threadIdx.x < 64) L.bucket[threadIdx.x] = 0;
+    __syncthreads();
     for (uint32_t r = r0 + threadIdx.x; r < r1; r += BS) {
         uint32_t a = off[r] - p0, e = off[r + 1] - p0;
-        for (uint32_t k = a; k < e; ++k) s_wp[k] = e - k - 1;
+        for (uint32_t k = a; k < e; ++k) {
+            uint32_t w = e - k - 1;
+            L.w[k] = (uint16_t)w;
+            atomicAdd(&L.bucket[63 - min(w, 63u)], 1u);
+        }
     }
     __syncthreads();
-    lds_exclusive_scan<BS>(s_wp, m, s_tmp);
-    *m_out = m;
-    return s_wp[m];
+    if (threadIdx.x < 64) {
+        uint32_t v = L.bucket[threadIdx.x];
+        L.bucket[threadIdx.x] = wave_inclusive_scan(v) - v;
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < m; k += BS) {
+        uint32_t w = L.w[k];
+        L.perm[atomicAdd(&L.bucket[63 - min(w, 63u)], 1u)] = (uint16_t)k;
+    }
+    __syncthreads();
+    return m;
 }
 
-// Walk this thread's equal share of the chunk's Tc terms in order and call
-// visit(x, y, h) for each pair x < y of a transaction.
+// visit(x, y, h) for every pair x < y of the staged chunk.
 template <int BS, class Visit>
-__device__ inline void walk_tx(uint32_t Tc, uint32_t m, const uint32_t *s_x, const uint32_t *s_hb,
-                               const uint32_t *s_wp, const HashParams &hp, Visit visit)
+__device__ inline void enum_tx(uint32_t m, const TxLds &L, const HashParams &hp, Visit visit)
 {
-    const uint32_t t0 = (uint32_t)(((uint64_t)Tc * threadIdx.x) / BS);
-    const uint32_t t1 = (uint32_t)(((uint64_t)Tc * (threadIdx.x + 1)) / BS);
-    if (t0 >= t1) return;
-    // entry k with s_wp[k] <= t0 < s_wp[k+1]  (s_wp[0] = 0, s_wp[m] = Tc > t0)
-    uint32_t lo = 0, hi = m;
-    while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (s_wp[mid] <= t0) lo = mid; else hi = mid;
-    }
-    uint32_t k = lo;
-    uint32_t q = k + 1 + (t0 - s_wp[k]);
-    uint32_t e = k + 1 + (s_wp[k + 1] - s_wp[k]);
-    uint32_t x = s_x[k];
-    uint32_t ha = hash_a(hp, x);
-    for (uint32_t t = t0; t < t1; ++t) {
-        visit(x, s_x[q], ha + s_hb[q]);
-        if (++q == e && t + 1 < t1) {
-            do { ++k; } while (s_wp[k + 1] == s_wp[k]);
-            q = k + 1;
-            e = k + 1 + (s_wp[k + 1] - s_wp[k]);
-            x = s_x[k];
-            ha = hash_a(hp, x);
+    for (uint32_t j = threadIdx.x; j < m; j += BS) {
+        const uint32_t k = L.perm[j];
+        const uint32_t w = L.w[k];
+        if (w == 0) break;  // perm is sorted: every later entry of this thread has w == 0
+        const uint32_t x = L.xh[k].x;
+        const uint32_t ha = hash_a(hp, x);
+        for (uint32_t d = 1; d <= w; ++d) {
+            const uint2 yh = L.xh[k + d];
+            visit(x, yh.x, ha + yh.y);
         }
     }
 }
 
-template <int BS>
-__device__ inline uint32_t *tx_smem_layout(uint32_t *smem, uint32_t NB, uint32_t max_items,
-                                           uint32_t **s_x, uint32_t **s_hb, uint32_t **s_wp,
-                                           uint32_t **s_tmp)
+// LDS layout of a chunk image after `lead` words, in 32-bit words: xh (two
+// words per entry, 8-byte aligned), then w and perm (u16 each, both padded to
+// an even count so that bucket stays 4-byte aligned for its atomics), then
+// the 64 bucket words.
+struct TxLayout {
+    size_t xh, w, perm, bucket, end;  // word offsets
+};
+
+__host__ __device__ inline TxLayout tx_layout(uint32_t lead, uint32_t max_items)
 {
-    uint32_t *hist = smem;
-    *s_x = hist + NB;
-    *s_hb = *s_x + max_items;
-    *s_wp = *s_hb + max_items;
-    *s_tmp = *s_wp + max_items + 1;
-    return hist;
+    TxLayout t;
+    const size_t half = (max_items + 1) / 2;  // words of one padded u16 array
+    t.xh = (lead + 1) & ~1u;
+    t.w = t.xh + 2 * (size_t)max_items;
+    t.perm = t.w + half;
+    t.bucket = t.perm + half;
+    t.end = t.bucket + 64;
+    return t;
+}
+
+__device__ inline TxLds tx_lds(uint32_t *smem, uint32_t lead, uint32_t max_items)
+{
+    const TxLayout t = tx_layout(lead, max_items);
+    TxLds L;
+    L.xh = reinterpret_cast<uint2 *>(smem + t.xh);
+    L.w = reinterpret_cast<uint16_t *>(smem + t.w);
+    L.perm = reinterpret_cast<uint16_t *>(smem + t.perm);
+    L.bucket = smem + t.bucket;
+    return L;
+}
+
+__host__ __device__ inline size_t tx_lds_words(uint32_t lead, uint32_t max_items)
+{
+    return tx_layout(lead, max_items).end;
+}
+
+template <class KeyT>
+__device__ inline KeyT pack_key(uint32_t x, uint32_t y)
+{
+    if (sizeof(KeyT) == 4) return (KeyT)((x << 16) | y);
+    return (KeyT)(((uint64_t)x << 32) | y);
+}
+
+template <class KeyT>
+__device__ inline uint32_t bin_of_key(KeyT key, const HashParams &hp, uint32_t NB)
+{
+    uint32_t x, y;
+    if (sizeof(KeyT) == 4) {
+        x = (uint32_t)key >> 16;
+        y = (uint32_t)key & 0xFFFFu;
+    } else {
+        x = (uint32_t)((uint64_t)key >> 32);
+        y = (uint32_t)key;
+    }
+    return interval_of(hash_a(hp, x) + hash_b(hp, y), NB);
 }
 
 // ---------------------------------------------------------------- kernels
@@ -109,15 +161,14 @@ k_tx_count(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
            uint32_t R, HashParams hp, uint32_t NB, uint32_t max_items, uint32_t *__restrict__ cnt)
 {
     extern __shared__ uint32_t smem[];
-    uint32_t *s_x, *s_hb, *s_wp, *s_tmp;
-    uint32_t *hist = tx_smem_layout<BS>(smem, NB, max_items, &s_x, &s_hb, &s_wp, &s_tmp);
+    uint32_t *hist = smem;
+    const TxLds L = tx_lds(smem, NB, max_items);
     const uint32_t chunk = xcd_contiguous(blockIdx.x, gridDim.x);
     const uint32_t r0 = chunk * R;
     const uint32_t r1 = min(r0 + R, T);
     for (uint32_t b = threadIdx.x; b < NB; b += BS) hist[b] = 0;
-    uint32_t m;
-    const uint32_t Tc = stage_tx<BS>(off, items, r0, r1, hp, s_x, s_hb, s_wp, s_tmp, &m);
-    walk_tx<BS>(Tc, m, s_x, s_hb, s_wp, hp, [&](uint32_t, uint32_t, uint32_t h) {
+    const uint32_t m = stage_tx<BS>(off, items, r0, r1, hp, L);
+    enum_tx<BS>(m, L, hp, [&](uint32_t, uint32_t, uint32_t h) {
         atomicAdd(&hist[interval_of(h, NB)], 1u);
     });
     __syncthreads();
@@ -125,29 +176,85 @@ k_tx_count(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
     for (uint32_t b = threadIdx.x; b < NB; b += BS) row[b] = hist[b];
 }
 
+// Scatter with LDS staging.  The chunk's terms of a window of bins are put
+// in LDS sorted by bin (each bin's local run starts at its local offset),
+// then written out run by run, so consecutive lanes store consecutive
+// addresses.  A window holds at most `cap` terms; a bin with more terms than
+// that in one chunk is written directly.  Windows are set by bin, a property
+// of the term itself, so each term lands in exactly one window.
 template <int BS, class KeyT>
 __global__ void __launch_bounds__(BS)
 k_tx_scatter(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items, uint32_t T,
              uint32_t R, HashParams hp, uint32_t NB, uint32_t max_items,
-             const uint32_t *__restrict__ cur, KeyT *__restrict__ keys)
+             const uint32_t *__restrict__ cur, const uint32_t *__restrict__ bin_off,
+             uint32_t n_chunks, KeyT *__restrict__ keys, uint32_t cap)
 {
     extern __shared__ uint32_t smem[];
-    uint32_t *s_x, *s_hb, *s_wp, *s_tmp;
-    uint32_t *pos = tx_smem_layout<BS>(smem, NB, max_items, &s_x, &s_hb, &s_wp, &s_tmp);
+    uint32_t *lstart = smem;               // NB + 1: local start of each bin's run
+    uint32_t *lcur = smem + NB + 1;        // NB: local cursor
+    uint32_t *delta = smem + 2 * NB + 1;   // NB: global start - local start
+    const uint32_t lead = 3 * NB + 1;
+    const TxLds L = tx_lds(smem, lead, max_items);
+    KeyT *stage =
+        reinterpret_cast<KeyT *>(smem + ((tx_lds_words(lead, max_items) + 1) & ~(size_t)1));
+    __shared__ uint32_t s_tmp[BS / kWave + 1];
+    __shared__ uint32_t s_b1, s_direct;
+
     const uint32_t chunk = xcd_contiguous(blockIdx.x, gridDim.x);
     const uint32_t r0 = chunk * R;
     const uint32_t r1 = min(r0 + R, T);
     const uint32_t *row = cur + (size_t)chunk * NB;
-    for (uint32_t b = threadIdx.x; b < NB; b += BS) pos[b] = row[b];
-    uint32_t m;
-    const uint32_t Tc = stage_tx<BS>(off, items, r0, r1, hp, s_x, s_hb, s_wp, s_tmp, &m);
-    walk_tx<BS>(Tc, m, s_x, s_hb, s_wp, hp, [&](uint32_t x, uint32_t y, uint32_t h) {
-        uint32_t p = atomicAdd(&pos[interval_of(h, NB)], 1u);
-        if (sizeof(KeyT) == 4)
-            keys[p] = (KeyT)((x << 16) | y);
-        else
-            keys[p] = (KeyT)(((uint64_t)x << 32) | y);
-    });
+    const uint32_t *nxt = chunk + 1 < n_chunks ? cur + (size_t)(chunk + 1) * NB : bin_off + 1;
+    for (uint32_t b = threadIdx.x; b < NB; b += BS) lstart[b] = nxt[b] - row[b];
+    __syncthreads();
+    lds_exclusive_scan<BS>(lstart, NB, s_tmp);
+    const uint32_t Tc = lstart[NB];
+    for (uint32_t b = threadIdx.x; b < NB; b += BS) {
+        lcur[b] = lstart[b];
+        delta[b] = row[b] - lstart[b];
+    }
+    const uint32_t m = stage_tx<BS>(off, items, r0, r1, hp, L);
+    if (Tc == 0) return;
+
+    for (uint32_t b0 = 0; b0 < NB;) {
+        if (threadIdx.x == 0) {
+            // last b1 in [b0, NB] with lstart[b1] - lstart[b0] <= cap (lstart is
+            // non-decreasing); an empty window means bin b0 alone exceeds cap
+            const uint32_t lim = lstart[b0] + cap;
+            uint32_t lo = b0, hi = NB + 1;  // lstart[lo] <= lim < lstart[hi] (hi = NB+1: +inf)
+            while (hi - lo > 1) {
+                uint32_t mid = (lo + hi) >> 1;
+                if (lstart[mid] <= lim) lo = mid; else hi = mid;
+            }
+            s_direct = lo == b0 ? 1u : 0u;
+            s_b1 = lo == b0 ? b0 + 1 : lo;
+        }
+        __syncthreads();
+        const uint32_t b1 = s_b1;
+        const bool direct = s_direct != 0;
+        const uint32_t s0 = lstart[b0];
+        const bool whole = b0 == 0 && b1 == NB;
+        enum_tx<BS>(m, L, hp, [&](uint32_t x, uint32_t y, uint32_t h) {
+            const uint32_t bin = interval_of(h, NB);
+            if (!whole && (bin < b0 || bin >= b1)) return;
+            const uint32_t p = atomicAdd(&lcur[bin], 1u);
+            const KeyT key = pack_key<KeyT>(x, y);
+            if (direct)
+                keys[p + delta[bin]] = key;
+            else
+                stage[p - s0] = key;
+        });
+        __syncthreads();
+        if (!direct) {
+            const uint32_t n = lstart[b1] - s0;
+            for (uint32_t i = threadIdx.x; i < n; i += BS) {
+                const KeyT key = stage[i];
+                keys[i + s0 + delta[bin_of_key(key, hp, NB)]] = key;
+            }
+        }
+        __syncthreads();
+        b0 = b1;
+    }
 }
 
 // ---- outer products
@@ -379,9 +486,15 @@ k_validate_csr(const uint32_t *__restrict__ v_off, uint64_t K, const uint32_t *_
 
 // ---------------------------------------------------------------- launchers
 
-static size_t tx_smem_bytes(uint32_t NB, uint32_t max_items, uint32_t BS)
+size_t tx_count_smem_bytes(uint32_t NB, uint32_t max_items)
 {
-    return sizeof(uint32_t) * ((size_t)NB + 3 * (size_t)max_items + 1 + BS / kWave + 1);
+    return 4 * tx_lds_words(NB, max_items);
+}
+
+size_t tx_scatter_smem_bytes(uint32_t NB, uint32_t max_items, uint32_t cap, bool wide)
+{
+    size_t w = (tx_lds_words(3 * NB + 1, max_items) + 1) & ~(size_t)1;
+    return 4 * w + (size_t)cap * (wide ? 8 : 4);
 }
 
 static size_t op_smem_bytes(uint32_t NB, uint32_t max_a, uint32_t BS)
@@ -392,7 +505,7 @@ static size_t op_smem_bytes(uint32_t NB, uint32_t max_a, uint32_t BS)
 hipError_t launch_tx_count(const crop_ctx *c, uint32_t *cnt, hipStream_t s)
 {
     const RoutePlan &pl = c->plan;
-    size_t sm = tx_smem_bytes(pl.NB, pl.max_items, 256);
+    size_t sm = tx_count_smem_bytes(pl.NB, pl.max_items);
     hipLaunchKernelGGL(k_tx_count<256>, dim3(pl.n_chunks), dim3(256), sm, s, c->in.off,
                        c->in.items, (uint32_t)c->in.T, pl.R, c->hp, pl.NB, pl.max_items, cnt);
     return hipGetLastError();
@@ -401,15 +514,18 @@ hipError_t launch_tx_count(const crop_ctx *c, uint32_t *cnt, hipStream_t s)
 hipError_t launch_tx_scatter(const crop_ctx *c, const uint32_t *cur, void *keys, hipStream_t s)
 {
     const RoutePlan &pl = c->plan;
-    size_t sm = tx_smem_bytes(pl.NB, pl.max_items, 256);
-    if (c->in.wide_keys)
-        hipLaunchKernelGGL((k_tx_scatter<256, uint64_t>), dim3(pl.n_chunks), dim3(256), sm, s,
+    const bool wide = c->in.wide_keys;
+    size_t sm = tx_scatter_smem_bytes(pl.NB, pl.max_items, pl.stage_cap, wide);
+    if (wide)
+        hipLaunchKernelGGL((k_tx_scatter<512, uint64_t>), dim3(pl.n_chunks), dim3(512), sm, s,
                            c->in.off, c->in.items, (uint32_t)c->in.T, pl.R, c->hp, pl.NB,
-                           pl.max_items, cur, static_cast<uint64_t *>(keys));
+                           pl.max_items, cur, c->bin_off.as<uint32_t>(), pl.n_chunks,
+                           static_cast<uint64_t *>(keys), pl.stage_cap);
     else
-        hipLaunchKernelGGL((k_tx_scatter<256, uint32_t>), dim3(pl.n_chunks), dim3(256), sm, s,
+        hipLaunchKernelGGL((k_tx_scatter<512, uint32_t>), dim3(pl.n_chunks), dim3(512), sm, s,
                            c->in.off, c->in.items, (uint32_t)c->in.T, pl.R, c->hp, pl.NB,
-                           pl.max_items, cur, static_cast<uint32_t *>(keys));
+                           pl.max_items, cur, c->bin_off.as<uint32_t>(), pl.n_chunks,
+                           static_cast<uint32_t *>(keys), pl.stage_cap);
     return hipGetLastError();
 }
 
