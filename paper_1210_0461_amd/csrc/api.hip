@@ -21,7 +21,7 @@ size_t tx_scatter_smem_bytes(uint32_t NB, uint32_t max_items, uint32_t cap, bool
 namespace {
 
 constexpr uint32_t kMaxP = 8192;
-constexpr uint64_t kTermsPerBin = 48000;   // routed terms per bin the auto plan aims at
+constexpr uint64_t kTermsPerBin = 30000;   // routed terms per bin the auto plan aims at
 constexpr size_t kLdsBudget = 64 * 1024;   // enumeration kernels' staging budget
 constexpr size_t kStageBudget = 150 * 1024; // scatter kernel: dynamic LDS in total
 
@@ -166,7 +166,7 @@ crop_status plan_tx(crop_ctx *ctx)
     pl.S = S;
     pl.NB = P * S;
     const size_t hist_bytes = (size_t)pl.NB * 4;
-    uint32_t R = ctx->tune.rows_per_chunk ? ctx->tune.rows_per_chunk : 256;
+    uint32_t R = ctx->tune.rows_per_chunk ? ctx->tune.rows_per_chunk : 128;
     auto max_items_for = [&](uint32_t r) {
         uint32_t mx = 0;
         for (uint64_t t0 = 0; t0 < in.T; t0 += r) {
@@ -191,7 +191,7 @@ crop_status plan_tx(crop_ctx *ctx)
         const size_t room = fixed < kStageBudget ? (kStageBudget - fixed) / per : 0;
         if (room < 1024)
             return fail(ctx, CROP_E_UNSUPPORTED, "routing bins and chunk leave no LDS for staging");
-        pl.stage_cap = (uint32_t)std::min<size_t>(room, 16384);
+        pl.stage_cap = (uint32_t)std::min<size_t>(room, 24576);
     }
     pl.G = std::max<uint32_t>(1, std::min<uint32_t>(64, pl.n_chunks));
     return CROP_OK;
@@ -272,6 +272,7 @@ crop_status ensure_route_buffers(crop_ctx *ctx, size_t key_bytes, bool sums)
     CK(ctx->part_buf.ensure((size_t)pl.G * pl.NB * 4));
     CK(ctx->bin_off.ensure(((size_t)pl.NB + 1) * 4));
     CK(ctx->bin_size.ensure((size_t)pl.NB * 4));
+    CK(ctx->bin_order.ensure((size_t)pl.NB * 4));
     CK(ctx->keys.ensure(nt * key_bytes));
     if (sums)
         CK(ctx->vals.ensure(nt * 4));
@@ -379,7 +380,8 @@ void crop_destroy(crop_ctx *ctx)
     if (!ctx) return;
     DeviceGuard g(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
-    for (DevBuf *b : {&ctx->cnt_mat, &ctx->part_buf, &ctx->bin_off, &ctx->bin_size, &ctx->keys,
+    for (DevBuf *b : {&ctx->cnt_mat, &ctx->part_buf, &ctx->bin_off, &ctx->bin_size,
+                      &ctx->bin_order, &ctx->keys,
                       &ctx->vals, &ctx->out_cnt, &ctx->spill, &ctx->counter, &ctx->ss_state,
                       &ctx->topk_buf, &ctx->scratch, &ctx->in.d_op_chunks})
         b->release();
@@ -620,6 +622,7 @@ crop_status crop_run_exact(crop_ctx *ctx)
     STAGE("count");
     CK(launch_scan_counts(cnt, pl.n_chunks, pl.NB, pl.G, ctx->part_buf.as<uint32_t>(),
                           ctx->bin_off.as<uint32_t>(), ctx->counter.as<uint32_t>(), s));
+    CK(launch_bin_order(pl.NB, ctx->bin_off.as<uint32_t>(), ctx->bin_order.as<uint32_t>(), s));
     STAGE("scan");
     if (pl.n_chunks)
         CK(outer ? launch_op_scatter(ctx, cnt, ctx->keys.p, ctx->vals.as<float>(), s)

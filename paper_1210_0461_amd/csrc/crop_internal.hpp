@@ -110,7 +110,8 @@ struct crop_ctx {
     uint32_t topk_K = 0;
 
     // work and result buffers
-    crop::DevBuf cnt_mat, part_buf, bin_off, bin_size, keys, vals, out_cnt, spill, counter;
+    crop::DevBuf cnt_mat, part_buf, bin_off, bin_size, bin_order, keys, vals, out_cnt, spill,
+        counter;
     crop::DevBuf ss_state, topk_buf, scratch;
 
     // profiling: per-stage events of the last kStageRing runs
@@ -143,6 +144,9 @@ hipError_t launch_op_scatter(const crop_ctx *c, const uint32_t *cur, void *keys,
 hipError_t launch_scan_counts(uint32_t *cnt, uint32_t n_chunks, uint32_t NB, uint32_t G,
                               uint32_t *part, uint32_t *bin_off, uint32_t *counter,
                               hipStream_t s);
+
+// order[] <- bins with more than twice the mean term count first.
+hipError_t launch_bin_order(uint32_t NB, const uint32_t *bin_off, uint32_t *order, hipStream_t s);
 
 hipError_t launch_aggregate_counts(const crop_ctx *c, hipStream_t s);
 hipError_t launch_aggregate_sums(const crop_ctx *c, hipStream_t s);

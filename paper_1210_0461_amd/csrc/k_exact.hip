@@ -251,6 +251,13 @@ k_aggregate(const uint32_t *__restrict__ bin_off, KeyT *__restrict__ keys,
 
 constexpr uint64_t kFreeSlot = 0x00000000FFFFFFFFull;
 
+// The count half of a packed slot (little-endian: the high word).  Adding
+// to it with a 32-bit atomic leaves the key half untouched.
+__device__ inline uint32_t *count_word(uint64_t *slot)
+{
+    return reinterpret_cast<uint32_t *>(slot) + 1;
+}
+
 enum { kDone = 0, kInserted = 1, kAbsent = 2 };
 
 template <uint32_t MASK, uint32_t LOG2S>
@@ -261,7 +268,7 @@ __device__ inline int packed_add(uint64_t *tab, uint32_t key, uint32_t w, bool m
     for (;;) {
         const uint32_t k = (uint32_t)v;
         if (k == key) {
-            atomicAdd((unsigned long long *)&tab[s], (unsigned long long)w << 32);
+            atomicAdd(count_word(&tab[s]), w);
             return kDone;
         }
         if (k == kEmpty32) {
@@ -310,19 +317,26 @@ __global__ void __launch_bounds__(BS)
 k_aggregate_packed(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ keys,
                    uint32_t *__restrict__ w_out, uint32_t *__restrict__ bin_size,
                    Spilled<uint32_t, uint32_t> *__restrict__ spill, uint32_t NB,
-                   uint32_t *counter, uint32_t cap_soft)
+                   uint32_t *counter, uint32_t cap_soft, const uint32_t *__restrict__ order)
 {
     constexpr uint32_t S = 1u << LOG2S;
     constexpr uint32_t MASK = S - 1;
     constexpr int U = 4;
     static_assert(S % BS == 0, "table size must be a multiple of the block size");
+    // Insertion stops at the first batch boundary after the occupancy passes
+    // cap_soft, so the table never holds more than cap_soft + BS * U keys:
+    // that must leave free slots, or a probe could run forever.
+    static_assert(S > BS * U, "a batch must fit in the table");
     __shared__ uint64_t tab[S];
     __shared__ uint32_t s_occ, s_nout, s_nspill, s_bin;
     __shared__ int s_insert;
     const uint32_t lane = lane_id();
 
     for (;;) {
-        if (threadIdx.x == 0) s_bin = atomicAdd(counter, 1u);
+        if (threadIdx.x == 0) {
+            const uint32_t i = atomicAdd(counter, 1u);
+            s_bin = i < NB ? order[i] : NB;
+        }
         __syncthreads();
         const uint32_t b = s_bin;
         if (b >= NB) break;
@@ -350,16 +364,83 @@ k_aggregate_packed(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ 
             for (int u = 0; u < U; ++u)
                 nx[u] = keys[min(base + BS * U + u * BS + threadIdx.x, last)];
             const bool ins = s_insert != 0;
-            uint32_t n_new = 0;
+            // Merge: lanes holding the same key as the wavefront's first lane
+            // hand their unit to it (a heavy pair fills most of its bin).
+            uint32_t wt[U];
+            uint32_t live = 0;  // bit u: key u still to be accumulated
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (base + u * BS + threadIdx.x >= k1) continue;
-                const int r = packed_add<MASK, LOG2S>(tab, cur[u], 1u, ins);
-                if (r == kInserted) {
-                    ++n_new;
-                } else if (r == kAbsent) {
-                    const uint32_t p = atomicAdd(&s_nspill, 1u);
-                    spill[k0 + p] = Spilled<uint32_t, uint32_t>{cur[u], 1u};
+                const bool valid = base + u * BS + threadIdx.x < k1;
+                const uint32_t lk = __builtin_amdgcn_readfirstlane(cur[u]);
+                const uint64_t same = __ballot(valid && cur[u] == lk);
+                wt[u] = 1;
+                bool keep = valid;
+                if (valid && cur[u] == lk) {
+                    if (lane == (uint32_t)(__ffsll((long long)same) - 1))
+                        wt[u] = (uint32_t)__popcll(same);
+                    else
+                        keep = false;
+                }
+                live |= (keep ? 1u : 0u) << u;
+            }
+            // Each lane runs its U keys back to back through one probing loop:
+            // a lane that settles a key starts its next key at the next step,
+            // so a wavefront waits for the longest lane's total probe count,
+            // not for the longest probe of every key.
+            uint32_t n_new = 0;
+            int j = 0;
+            while (j < U && !((live >> j) & 1u)) ++j;
+            uint32_t key = 0, w = 0, sl = 0;
+            if (j < U) {
+                key = cur[0];
+                w = wt[0];
+#pragma unroll
+                for (int u = 1; u < U; ++u)
+                    if (j == u) {
+                        key = cur[u];
+                        w = wt[u];
+                    }
+                sl = slot_of(key, LOG2S);
+            }
+            while (j < U) {
+                const uint64_t v = tab[sl];
+                const uint32_t k = (uint32_t)v;
+                bool settled = false;
+                if (k == key) {
+                    atomicAdd(count_word(&tab[sl]), w);
+                    settled = true;
+                } else if (k == kEmpty32) {
+                    if (!ins) {
+                        const uint32_t p = atomicAdd(&s_nspill, 1u);
+                        spill[k0 + p] = Spilled<uint32_t, uint32_t>{key, w};
+                        settled = true;
+                    } else {
+                        const uint64_t old = atomicCAS((unsigned long long *)&tab[sl],
+                                                       (unsigned long long)kFreeSlot,
+                                                       ((unsigned long long)w << 32) | key);
+                        if (old == kFreeSlot) {
+                            ++n_new;
+                            settled = true;
+                        }
+                        // otherwise the slot was just taken: look at it again
+                    }
+                } else {
+                    sl = (sl + 1) & MASK;
+                }
+                if (settled) {
+                    ++j;
+                    while (j < U && !((live >> j) & 1u)) ++j;
+                    if (j < U) {
+                        key = cur[0];
+                        w = wt[0];
+#pragma unroll
+                        for (int u = 1; u < U; ++u)
+                            if (j == u) {
+                                key = cur[u];
+                                w = wt[u];
+                            }
+                        sl = slot_of(key, LOG2S);
+                    }
                 }
             }
             // one occupancy update per wavefront
@@ -427,6 +508,10 @@ static uint32_t persistent_grid(uint32_t NB)
     return NB < g ? NB : g;
 }
 
+// 10240 + one batch of 4096 keys = at most 14336 of 16384 slots in use.
+constexpr uint32_t kPackedCapSoft = 10240;
+static_assert(kPackedCapSoft + 1024 * 4 < (1u << 14), "packed table must keep free slots");
+
 hipError_t launch_aggregate_counts(const crop_ctx *c, hipStream_t s)
 {
     const RoutePlan &pl = c->plan;
@@ -437,7 +522,7 @@ hipError_t launch_aggregate_counts(const crop_ctx *c, hipStream_t s)
                            c->bin_off.as<uint32_t>(), c->keys.as<uint32_t>(),
                            c->out_cnt.as<uint32_t>(), c->bin_size.as<uint32_t>(),
                            c->spill.as<Spilled<uint32_t, uint32_t>>(), pl.NB,
-                           c->counter.as<uint32_t>(), (1u << L) / 2);
+                           c->counter.as<uint32_t>(), kPackedCapSoft, c->bin_order.as<uint32_t>());
     } else {
         constexpr int L = 13;
         hipLaunchKernelGGL((k_aggregate<512, uint64_t, uint32_t, L>), dim3(grid), dim3(512), 0, s,

@@ -406,31 +406,35 @@ k_colsum(const uint32_t *__restrict__ cnt, uint32_t n, uint32_t NB, uint32_t row
     part[(size_t)g * NB + b] = s;
 }
 
-// One workgroup: part[g][b] <- exclusive prefix over g; bin_off[b] <-
-// exclusive prefix over b of the bin totals; bin_off[NB] <- total; resets
-// the aggregation work counter.
+// Per bin b: part[g][b] <- exclusive prefix over the groups g; tot[b] <- sum.
+__global__ void __launch_bounds__(256)
+k_colprefix(uint32_t *__restrict__ part, uint32_t NB, uint32_t G, uint32_t *__restrict__ tot)
+{
+    const uint32_t b = blockIdx.x * 256 + threadIdx.x;
+    if (b >= NB) return;
+    uint32_t run = 0;
+    for (uint32_t g = 0; g < G; ++g) {
+        const uint32_t v = part[(size_t)g * NB + b];
+        part[(size_t)g * NB + b] = run;
+        run += v;
+    }
+    tot[b] = run;
+}
+
+// One workgroup: bin_off[b] <- exclusive prefix over b of the bin totals
+// (given in bin_off itself); bin_off[NB] <- total; resets the work counters.
 __global__ void __launch_bounds__(1024)
-k_colbase(uint32_t *__restrict__ part, uint32_t NB, uint32_t G, uint32_t *__restrict__ bin_off,
-          uint32_t *__restrict__ counter)
+k_colbase(uint32_t NB, uint32_t *__restrict__ bin_off, uint32_t *__restrict__ counter)
 {
     __shared__ uint32_t s_tmp[1024 / kWave + 1];
     const uint32_t per = (NB + 1023) / 1024;
     const uint32_t b0 = threadIdx.x * per, b1 = min(NB, b0 + per);
     uint32_t sum = 0;
-    for (uint32_t b = b0; b < b1; ++b) {
-        uint32_t run = 0;
-        for (uint32_t g = 0; g < G; ++g) {
-            uint32_t v = part[(size_t)g * NB + b];
-            part[(size_t)g * NB + b] = run;
-            run += v;
-        }
-        bin_off[b] = run;  // bin total, turned into an offset below
-        sum += run;
-    }
+    for (uint32_t b = b0; b < b1; ++b) sum += bin_off[b];
     uint32_t total;
     uint32_t run = block_exclusive_scan<1024>(sum, s_tmp, &total);
     for (uint32_t b = b0; b < b1; ++b) {
-        uint32_t t = bin_off[b];
+        const uint32_t t = bin_off[b];
         bin_off[b] = run;
         run += t;
     }
@@ -438,6 +442,32 @@ k_colbase(uint32_t *__restrict__ part, uint32_t NB, uint32_t G, uint32_t *__rest
         bin_off[NB] = total;
         counter[0] = 0;
         counter[1] = 0;
+    }
+}
+
+// One workgroup: order[] lists the bins with more than twice the mean term
+// count first (in index order), then the others, so that the persistent
+// aggregation workgroups start the longest bins first.
+__global__ void __launch_bounds__(1024)
+k_bin_order(uint32_t NB, const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ order)
+{
+    __shared__ uint32_t s_tmp[1024 / kWave + 1];
+    __shared__ uint32_t s_nheavy;
+    const uint64_t thresh = 2ull * bin_off[NB] / (NB ? NB : 1);
+    const uint32_t per = (NB + 1023) / 1024;
+    const uint32_t b0 = threadIdx.x * per, b1 = min(NB, b0 + per);
+    uint32_t nh = 0;
+    for (uint32_t b = b0; b < b1; ++b) nh += (bin_off[b + 1] - bin_off[b]) > thresh;
+    uint32_t total;
+    uint32_t h = block_exclusive_scan<1024>(nh, s_tmp, &total);
+    if (threadIdx.x == 0) s_nheavy = total;
+    __syncthreads();
+    uint32_t l = s_nheavy + b0 - h;  // light bins before b0 = b0 - heavy bins before b0
+    for (uint32_t b = b0; b < b1; ++b) {
+        if ((bin_off[b + 1] - bin_off[b]) > thresh)
+            order[h++] = b;
+        else
+            order[l++] = b;
     }
 }
 
@@ -517,12 +547,12 @@ hipError_t launch_tx_scatter(const crop_ctx *c, const uint32_t *cur, void *keys,
     const bool wide = c->in.wide_keys;
     size_t sm = tx_scatter_smem_bytes(pl.NB, pl.max_items, pl.stage_cap, wide);
     if (wide)
-        hipLaunchKernelGGL((k_tx_scatter<512, uint64_t>), dim3(pl.n_chunks), dim3(512), sm, s,
+        hipLaunchKernelGGL((k_tx_scatter<1024, uint64_t>), dim3(pl.n_chunks), dim3(1024), sm, s,
                            c->in.off, c->in.items, (uint32_t)c->in.T, pl.R, c->hp, pl.NB,
                            pl.max_items, cur, c->bin_off.as<uint32_t>(), pl.n_chunks,
                            static_cast<uint64_t *>(keys), pl.stage_cap);
     else
-        hipLaunchKernelGGL((k_tx_scatter<512, uint32_t>), dim3(pl.n_chunks), dim3(512), sm, s,
+        hipLaunchKernelGGL((k_tx_scatter<1024, uint32_t>), dim3(pl.n_chunks), dim3(1024), sm, s,
                            c->in.off, c->in.items, (uint32_t)c->in.T, pl.R, c->hp, pl.NB,
                            pl.max_items, cur, c->bin_off.as<uint32_t>(), pl.n_chunks,
                            static_cast<uint32_t *>(keys), pl.stage_cap);
@@ -561,6 +591,12 @@ hipError_t launch_op_scatter(const crop_ctx *c, const uint32_t *cur, void *keys,
     return hipGetLastError();
 }
 
+hipError_t launch_bin_order(uint32_t NB, const uint32_t *bin_off, uint32_t *order, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_bin_order, dim3(1), dim3(1024), 0, s, NB, bin_off, order);
+    return hipGetLastError();
+}
+
 hipError_t launch_scan_counts(uint32_t *cnt, uint32_t n_chunks, uint32_t NB, uint32_t G,
                               uint32_t *part, uint32_t *bin_off, uint32_t *counter,
                               hipStream_t s)
@@ -568,7 +604,8 @@ hipError_t launch_scan_counts(uint32_t *cnt, uint32_t n_chunks, uint32_t NB, uin
     const uint32_t rows_per_g = (n_chunks + G - 1) / G;
     dim3 grid((NB + 255) / 256, G);
     hipLaunchKernelGGL(k_colsum, grid, dim3(256), 0, s, cnt, n_chunks, NB, rows_per_g, part);
-    hipLaunchKernelGGL(k_colbase, dim3(1), dim3(1024), 0, s, part, NB, G, bin_off, counter);
+    hipLaunchKernelGGL(k_colprefix, dim3((NB + 255) / 256), dim3(256), 0, s, part, NB, G, bin_off);
+    hipLaunchKernelGGL(k_colbase, dim3(1), dim3(1024), 0, s, NB, bin_off, counter);
     hipLaunchKernelGGL(k_colapply, grid, dim3(256), 0, s, cnt, n_chunks, NB, rows_per_g, part,
                        bin_off);
     return hipGetLastError();
