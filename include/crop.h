@@ -136,6 +136,19 @@ crop_status crop_load_outer(crop_ctx *ctx, const uint32_t *a_off, const uint32_t
  * fp32 sums (outer products), plus the number of terms per partition. */
 crop_status crop_run_exact(crop_ctx *ctx);
 
+/* Space-Saving summaries per bucket, then the top-K monitored entries over
+ * all partitions by (upper bound descending, key ascending).  Transactions
+ * use weight 1 per term; outer products use |a_k(i) b_k(j)| and keep the
+ * signed sum of an entry's terms since its admission. */
+crop_status crop_run_topk(crop_ctx *ctx, uint32_t K);
+
+/* As crop_run_topk, with learned seeding: seeds (device arrays sx, sy of ns
+ * transaction pairs x < y, highest priority first) are pinned into their
+ * buckets before the stream, at most r_max per bucket (r_max < ell), in the
+ * given order.  A pinned slot is never evicted, so its count is exact. */
+crop_status crop_run_topk_seeded(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
+                                 const uint32_t *sy, uint64_t ns, uint32_t r_max);
+
 /* ---- readback (synchronizes the context stream) ------------------------ */
 
 /* Per-partition distinct-entry counts and term counts of the last exact run
@@ -155,6 +168,19 @@ crop_status crop_read_partition(crop_ctx *ctx, uint32_t p, uint32_t *i, uint32_t
 crop_status crop_read_all(crop_ctx *ctx, crop_mem where, uint32_t *i, uint32_t *j,
                           uint32_t *count, float *value, uint64_t cap, uint64_t *written,
                           uint64_t *part_off);
+
+/* Top-K entries of the last top-K run into host arrays: upper and lower
+ * bounds (Section 4: count and count - overestimation) and, for outer
+ * products, the signed sum since admission (NULL allowed). */
+crop_status crop_read_topk(crop_ctx *ctx, uint32_t *i, uint32_t *j, double *upper,
+                           double *lower, double *value, uint64_t cap, uint64_t *written);
+
+/* Every Space-Saving slot of the last top-K run (P*B*ell slots, bucket
+ * major) into host arrays: entry, count, overestimation, signed sum (outer
+ * products; else 0) and flags (bit 0 used, bit 1 pinned). */
+crop_status crop_read_summary(crop_ctx *ctx, uint32_t *i, uint32_t *j, double *cnt,
+                              double *err, double *value, uint8_t *flags, uint64_t cap,
+                              uint64_t *written);
 
 /* Wait for all work enqueued by this context. */
 crop_status crop_synchronize(crop_ctx *ctx);

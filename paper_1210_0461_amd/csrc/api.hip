@@ -150,12 +150,12 @@ void reset_input(crop_ctx *ctx)
 
 // ---- planning -------------------------------------------------------------
 
-crop_status plan_tx(crop_ctx *ctx)
+crop_status plan_tx(crop_ctx *ctx, uint32_t S_force = 0)
 {
     Input &in = ctx->in;
     RoutePlan &pl = ctx->plan;
     const uint32_t P = ctx->P;
-    uint32_t S = ctx->tune.bins_per_partition;
+    uint32_t S = S_force ? S_force : ctx->tune.bins_per_partition;
     if (S == 0) {
         uint64_t want = (in.total_terms + kTermsPerBin - 1) / kTermsPerBin;
         S = (uint32_t)std::max<uint64_t>(1, (want + P - 1) / P);
@@ -197,12 +197,12 @@ crop_status plan_tx(crop_ctx *ctx)
     return CROP_OK;
 }
 
-crop_status plan_outer(crop_ctx *ctx)
+crop_status plan_outer(crop_ctx *ctx, uint32_t S_force = 0)
 {
     Input &in = ctx->in;
     RoutePlan &pl = ctx->plan;
     const uint32_t P = ctx->P;
-    uint32_t S = ctx->tune.bins_per_partition;
+    uint32_t S = S_force ? S_force : ctx->tune.bins_per_partition;
     if (S == 0) {
         // outer-product entries rarely repeat and fp32 sums use 8192-slot
         // tables: aim at about 3000 routed terms per bin
@@ -288,6 +288,87 @@ crop_status require_exact(crop_ctx *ctx)
     if (ctx->result != Result::Exact)
         return fail(ctx, CROP_E_STATE, "no exact result: call crop_run_exact first");
     return CROP_OK;
+}
+
+// Space-Saving routing: bins hold whole groups of nbk buckets (nbk divides
+// the B buckets of a partition), the bucket summaries of a bin must fit in
+// LDS, and there should be enough bins to occupy the GPU.
+crop_status plan_ss(crop_ctx *ctx, uint32_t *nbk_out, uint64_t *PB_out)
+{
+    const uint32_t P = ctx->P, ell = ctx->ss_ell;
+    const uint64_t B = ctx->ss_counters / ell;
+    const uint64_t PB = (uint64_t)P * B;
+    if (PB > (1ull << 32))
+        return fail(ctx, CROP_E_UNSUPPORTED, "P x buckets per partition exceeds 2^32");
+    const bool outer = ctx->in.mode == Mode::Outer;
+    const bool wide = outer || ctx->in.wide_keys;
+    const uint32_t MB = outer ? 1024 : 2048;
+    std::vector<uint64_t> divs;
+    for (uint64_t d = 1; d * d <= B; ++d)
+        if (B % d == 0) {
+            divs.push_back(d);
+            if (d != B / d) divs.push_back(B / d);
+        }
+    std::sort(divs.begin(), divs.end());
+    uint64_t best = 0, fallback = 0;
+    for (uint64_t nbk : divs) {
+        if (ss_bins_smem_bytes((uint32_t)nbk, ell, wide, outer, MB) > 96 * 1024) continue;
+        const uint64_t NB = (uint64_t)P * (B / nbk);
+        if (NB > kMaxP) continue;
+        if (!fallback) fallback = nbk;  // smallest feasible: the most bins
+        if (NB >= 512) best = nbk;      // largest with enough bins
+    }
+    const uint64_t nbk = best ? best : fallback;
+    if (!nbk)
+        return fail(ctx, CROP_E_UNSUPPORTED, "Space-Saving summaries do not fit the LDS plan");
+    *nbk_out = (uint32_t)nbk;
+    *PB_out = PB;
+    return CROP_OK;
+}
+
+crop_status ensure_ss_buffers(crop_ctx *ctx, uint64_t nslots, uint32_t K, uint32_t ns)
+{
+    const size_t a8 = (nslots * 8 + 255) / 256 * 256, a4 = (nslots * 4 + 255) / 256 * 256;
+    CK(ctx->ss_state.ensure(a8 + 3 * a4 + nslots + 256));
+    char *p = static_cast<char *>(ctx->ss_state.p);
+    ctx->ss.key = reinterpret_cast<uint64_t *>(p);
+    ctx->ss.cnt = reinterpret_cast<uint32_t *>(p + a8);
+    ctx->ss.err = reinterpret_cast<uint32_t *>(p + a8 + a4);
+    ctx->ss.val = reinterpret_cast<float *>(p + a8 + 2 * a4);
+    ctx->ss.flag = reinterpret_cast<uint8_t *>(p + a8 + 3 * a4);
+    ctx->ss.nslots = nslots;
+    // top-K: st (8) + hist (256) + pinned counter | cand | sel | outputs
+    const size_t kk = std::max<uint32_t>(K, 1);
+    CK(ctx->topk_buf.ensure(2048 + 2 * a4 + kk * 32 + ns + 256));
+    return CROP_OK;
+}
+
+struct TopkViews {
+    uint32_t *st, *hist, *n_pinned, *cand, *sel, *oi, *oj;
+    double *ou, *ol, *ov;
+    uint8_t *dup;
+};
+
+TopkViews topk_views(crop_ctx *ctx, uint32_t K)
+{
+    const uint64_t nslots = ctx->ss.nslots;
+    const size_t a4 = (nslots * 4 + 255) / 256 * 256;
+    const size_t kk = std::max<uint32_t>(K, 1);
+    char *p = static_cast<char *>(ctx->topk_buf.p);
+    TopkViews v;
+    v.st = reinterpret_cast<uint32_t *>(p);
+    v.hist = v.st + 8;
+    v.n_pinned = v.st + 8 + 256;
+    v.cand = reinterpret_cast<uint32_t *>(p + 2048);
+    v.sel = reinterpret_cast<uint32_t *>(p + 2048 + a4);
+    char *o = p + 2048 + 2 * a4;
+    v.ou = reinterpret_cast<double *>(o);
+    v.ol = v.ou + kk;
+    v.ov = v.ol + kk;
+    v.oi = reinterpret_cast<uint32_t *>(v.ov + kk);
+    v.oj = v.oi + kk;
+    v.dup = reinterpret_cast<uint8_t *>(v.oj + kk);
+    return v;
 }
 
 // Run bracketing: ev0/ev1 around every run; with profiling on, one event
@@ -633,6 +714,139 @@ crop_status crop_run_exact(crop_ctx *ctx)
     st = run_end(ctx);
     if (st != CROP_OK) return st;
     ctx->result = Result::Exact;
+    return CROP_OK;
+}
+
+static crop_status run_topk_impl(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
+                                 const uint32_t *sy, uint64_t ns, uint32_t r_max)
+{
+    if (!ctx) return CROP_E_ARG;
+    if (ctx->in.mode == Mode::None) return fail(ctx, CROP_E_STATE, "no input loaded");
+    if (K == 0) return fail(ctx, CROP_E_ARG, "K must be positive");
+    if (ns && (!sx || !sy)) return fail(ctx, CROP_E_ARG, "null seed arrays");
+    if (ns >= (1ull << 31)) return fail(ctx, CROP_E_UNSUPPORTED, "too many seeds");
+    if (ns && ctx->in.mode != Mode::Tx)
+        return fail(ctx, CROP_E_UNSUPPORTED, "seeding is defined for transaction streams");
+    if (ns && r_max >= ctx->ss_ell)
+        return fail(ctx, CROP_E_ARG, "r_max must be below the slots per bucket");
+    DeviceGuard g(ctx->device);
+    ctx->result = Result::None;
+    uint32_t nbk = 0;
+    uint64_t PB = 0;
+    crop_status st = plan_ss(ctx, &nbk, &PB);
+    if (st != CROP_OK) return st;
+    const uint32_t S = (uint32_t)(PB / ctx->P / nbk);
+    const bool outer = ctx->in.mode == Mode::Outer;
+    st = outer ? plan_outer(ctx, S) : plan_tx(ctx, S);
+    if (st != CROP_OK) return st;
+    ctx->plan.log2_slots = 0;
+    ctx->plan.BS = 256;
+    st = ensure_route_buffers(ctx, ctx->in.wide_keys ? 8 : 4, outer);
+    if (st != CROP_OK) return st;
+    const uint64_t nslots = PB * ctx->ss_ell;
+    if (nslots >= (1ull << 32))
+        return fail(ctx, CROP_E_UNSUPPORTED, "more than 2^32 summary slots");
+    st = ensure_ss_buffers(ctx, nslots, K, (uint32_t)ns);
+    if (st != CROP_OK) return st;
+    const TopkViews tv = topk_views(ctx, K);
+    const RoutePlan &pl = ctx->plan;
+    hipStream_t s = ctx->stream;
+    uint32_t *cnt = ctx->cnt_mat.as<uint32_t>();
+    st = run_begin(ctx);
+    if (st != CROP_OK) return st;
+    CK(launch_ss_clear(ctx->ss, s));
+    CK(launch_zero32(tv.st, 8 + 256 + 1, s));
+    if (ns)
+        CK(launch_ss_pin(ctx->ss, sx, sy, (uint32_t)ns, tv.dup, r_max, ctx->hp, PB, ctx->ss_ell,
+                         tv.n_pinned, s));
+    STAGE("init");
+    if (pl.n_chunks) CK(outer ? launch_op_count(ctx, cnt, s) : launch_tx_count(ctx, cnt, s));
+    STAGE("count");
+    CK(launch_scan_counts(cnt, pl.n_chunks, pl.NB, pl.G, ctx->part_buf.as<uint32_t>(),
+                          ctx->bin_off.as<uint32_t>(), ctx->counter.as<uint32_t>(), s));
+    STAGE("scan");
+    if (pl.n_chunks)
+        CK(outer ? launch_op_scatter(ctx, cnt, ctx->keys.p, ctx->vals.as<float>(), s)
+                 : launch_tx_scatter(ctx, cnt, ctx->keys.p, s));
+    STAGE("scatter");
+    CK(launch_ss_bins(ctx, ctx->ss, nbk, PB, s));
+    STAGE("summaries");
+    CK(launch_topk(ctx->ss, K, outer, tv.st, tv.hist, tv.cand, tv.sel, tv.oi, tv.oj, tv.ou,
+                   tv.ol, tv.ov, s));
+    STAGE("topk");
+    st = run_end(ctx);
+    if (st != CROP_OK) return st;
+    ctx->result = Result::TopK;
+    ctx->topk_K = K;
+    ctx->ss_buckets = PB;
+    ctx->topk_outer = outer ? 1 : 0;
+    return CROP_OK;
+}
+
+crop_status crop_run_topk(crop_ctx *ctx, uint32_t K)
+{
+    return run_topk_impl(ctx, K, nullptr, nullptr, 0, 0);
+}
+
+crop_status crop_run_topk_seeded(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
+                                 const uint32_t *sy, uint64_t ns, uint32_t r_max)
+{
+    return run_topk_impl(ctx, K, sx, sy, ns, r_max);
+}
+
+crop_status crop_read_topk(crop_ctx *ctx, uint32_t *i, uint32_t *j, double *upper,
+                           double *lower, double *value, uint64_t cap, uint64_t *written)
+{
+    if (!ctx || !i || !j) return CROP_E_ARG;
+    if (ctx->result != Result::TopK) return fail(ctx, CROP_E_STATE, "no top-K result");
+    DeviceGuard g(ctx->device);
+    const TopkViews tv = topk_views(ctx, ctx->topk_K);
+    uint32_t stv[8];
+    CK(hipStreamSynchronize(ctx->stream));
+    CK(hipMemcpy(stv, tv.st, sizeof(stv), hipMemcpyDeviceToHost));
+    const uint64_t n = stv[5];
+    if (written) *written = n;
+    if (n > cap) return fail(ctx, CROP_E_CAPACITY, "output capacity below K");
+    if (!n) return CROP_OK;
+    CK(hipMemcpy(i, tv.oi, n * 4, hipMemcpyDeviceToHost));
+    CK(hipMemcpy(j, tv.oj, n * 4, hipMemcpyDeviceToHost));
+    if (upper) CK(hipMemcpy(upper, tv.ou, n * 8, hipMemcpyDeviceToHost));
+    if (lower) CK(hipMemcpy(lower, tv.ol, n * 8, hipMemcpyDeviceToHost));
+    if (value) CK(hipMemcpy(value, tv.ov, n * 8, hipMemcpyDeviceToHost));
+    return CROP_OK;
+}
+
+crop_status crop_read_summary(crop_ctx *ctx, uint32_t *i, uint32_t *j, double *cnt, double *err,
+                              double *value, uint8_t *flags, uint64_t cap, uint64_t *written)
+{
+    if (!ctx || !i || !j) return CROP_E_ARG;
+    if (ctx->result != Result::TopK) return fail(ctx, CROP_E_STATE, "no top-K result");
+    DeviceGuard g(ctx->device);
+    const uint64_t n = ctx->ss.nslots;
+    if (written) *written = n;
+    if (n > cap) return fail(ctx, CROP_E_CAPACITY, "output capacity below the slot count");
+    CK(hipStreamSynchronize(ctx->stream));
+    std::vector<uint64_t> k(n);
+    std::vector<uint32_t> c(n), e(n);
+    std::vector<float> v(n);
+    std::vector<uint8_t> f(n);
+    CK(hipMemcpy(k.data(), ctx->ss.key, n * 8, hipMemcpyDeviceToHost));
+    CK(hipMemcpy(c.data(), ctx->ss.cnt, n * 4, hipMemcpyDeviceToHost));
+    CK(hipMemcpy(e.data(), ctx->ss.err, n * 4, hipMemcpyDeviceToHost));
+    CK(hipMemcpy(v.data(), ctx->ss.val, n * 4, hipMemcpyDeviceToHost));
+    CK(hipMemcpy(f.data(), ctx->ss.flag, n, hipMemcpyDeviceToHost));
+    const bool outer = ctx->topk_outer != 0;
+    for (uint64_t q = 0; q < n; ++q) {
+        i[q] = (uint32_t)(k[q] >> 32);
+        j[q] = (uint32_t)k[q];
+        float fc, fe;
+        std::memcpy(&fc, &c[q], 4);
+        std::memcpy(&fe, &e[q], 4);
+        if (cnt) cnt[q] = outer ? (double)fc : (double)c[q];
+        if (err) err[q] = outer ? (double)fe : (double)e[q];
+        if (value) value[q] = outer ? (double)v[q] : 0.0;
+        if (flags) flags[q] = f[q];
+    }
     return CROP_OK;
 }
 

@@ -79,6 +79,19 @@ struct Input {
     DevBuf d_op_chunks;
 };
 
+// Space-Saving state in device memory, bucket-major with ell slots per
+// bucket (structure of arrays).  cnt/err hold uint32 counts (transactions)
+// or fp32 bits (outer products); key holds (i << 32) | j; flag bit 0 =
+// used, bit 1 = pinned.
+struct SsState {
+    uint64_t *key = nullptr;
+    uint32_t *cnt = nullptr;
+    uint32_t *err = nullptr;
+    float *val = nullptr;
+    uint8_t *flag = nullptr;
+    uint64_t nslots = 0;
+};
+
 // Per-stage HIP events of one run (profiling mode).
 constexpr int kStageRing = 64;
 constexpr int kMaxStages = 10;
@@ -113,6 +126,9 @@ struct crop_ctx {
     crop::DevBuf cnt_mat, part_buf, bin_off, bin_size, bin_order, keys, vals, out_cnt, spill,
         counter;
     crop::DevBuf ss_state, topk_buf, scratch;
+    crop::SsState ss;          // views into ss_state
+    uint64_t ss_buckets = 0;   // P * B of the last top-K run
+    uint32_t topk_outer = 0;   // the last top-K run was on outer products
 
     // profiling: per-stage events of the last kStageRing runs
     bool profiling = false;
@@ -150,6 +166,19 @@ hipError_t launch_bin_order(uint32_t NB, const uint32_t *bin_off, uint32_t *orde
 
 hipError_t launch_aggregate_counts(const crop_ctx *c, hipStream_t s);
 hipError_t launch_aggregate_sums(const crop_ctx *c, hipStream_t s);
+
+// Space-Saving and top-K (k_topk.hip).
+hipError_t launch_ss_clear(const SsState &S, hipStream_t s);
+hipError_t launch_ss_pin(const SsState &S, const uint32_t *sx, const uint32_t *sy, uint32_t ns,
+                         uint8_t *dup, uint32_t r_max, const HashParams &hp, uint64_t PB,
+                         uint32_t ell, uint32_t *n_pinned, hipStream_t s);
+size_t ss_bins_smem_bytes(uint32_t nbk, uint32_t ell, bool wide_key, bool outer, uint32_t MB);
+hipError_t launch_ss_bins(const crop_ctx *c, const SsState &S, uint32_t nbk, uint64_t PB,
+                          hipStream_t s);
+hipError_t launch_zero32(uint32_t *p, uint32_t n, hipStream_t s);
+hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, uint32_t *st, uint32_t *hist,
+                       uint32_t *cand, uint32_t *sel, uint32_t *oi, uint32_t *oj, double *ou,
+                       double *ol, double *ov, hipStream_t s);
 
 // Gather the bin-segmented exact result into partition-contiguous arrays.
 hipError_t launch_gather_result(const crop_ctx *c, const uint32_t *dst_off, uint32_t *out_i,

@@ -1,0 +1,181 @@
+"""GPU Space-Saving summaries and top-K against the oracle.
+
+Summary contents are not bit-exact (the GPU applies a bucket's updates in
+another order than the stream); they are checked against the Section 4
+invariants with exact counts from the oracle, the special case of at most
+ell distinct entries per bucket (exact), and recall against the exact top-K.
+The top-K selection itself is exact: it must equal the first K monitored
+slots of the GPU summary by (count desc, key asc).
+"""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from _ss_checks import check_invariants  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+SEED = 0x243F6A8885A308D3
+
+
+@pytest.fixture(scope="module")
+def crop():
+    import paper_1210_0461_amd as crop
+    return crop
+
+
+@pytest.fixture
+def ctx(crop):
+    h = crop.crop_create(0)
+    yield h
+    crop.crop_destroy(h)
+
+
+def run_tx_topk(crop, ctx, st, P, C, ell, K, seed=SEED, seeds=None, r_max=0):
+    crop.crop_set_partitions(ctx, P)
+    crop.crop_set_seed(ctx, seed)
+    crop.crop_set_summary(ctx, C, ell)
+    crop.crop_load_transactions(ctx, st.off, st.items, st.n)
+    if seeds is None:
+        crop.crop_run_topk(ctx, K)
+    else:
+        import torch
+        sx = torch.from_numpy(seeds[0].astype(np.int32)).cuda()
+        sy = torch.from_numpy(seeds[1].astype(np.int32)).cuda()
+        crop.crop_run_topk_seeded(ctx, K, sx, sy, r_max)
+        torch.cuda.synchronize()
+    s = crop.crop_read_summary(ctx, P * (C // ell) * ell)
+    s.update(P=P, B=C // ell, ell=ell)
+    top = crop.crop_read_topk(ctx, K)
+    return s, top
+
+
+def exact_map(st, seed=SEED):
+    r = oracle.tx_exact(st.off, st.items, 1, seed)
+    return dict(zip(oracle.pack_keys(r["x"], r["y"]).tolist(), r["cnt"].tolist())), r
+
+
+def check_topk_is_summary_topk(s, top, K):
+    used = s["used"]
+    keys = oracle.pack_keys(s["x"][used], s["y"][used])
+    idx = oracle.topk(keys, s["cnt"][used], K)
+    want = keys[idx]
+    got = oracle.pack_keys(top[0], top[1])
+    assert np.array_equal(got, want)
+    assert np.array_equal(top[2], s["cnt"][used][idx])
+    assert np.array_equal(top[3], (s["cnt"] - s["err"])[used][idx])
+
+
+@pytest.mark.parametrize("P,C,ell", [(1, 64, 4), (2, 256, 16), (8, 512, 8), (3, 96, 2)])
+def test_small_config_invariants_and_topk(crop, ctx, P, C, ell):
+    st = datagen.config_small()
+    exact, _ = exact_map(st)
+    s, top = run_tx_topk(crop, ctx, st, P, C, ell, 100)
+    check_invariants(s, exact, SEED)
+    check_topk_is_summary_topk(s, top, 100)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_tiny_invariants(crop, ctx, seed):
+    st = datagen.tiny_transactions(200 + seed, T=80, n=30, cap=10)
+    exact, _ = exact_map(st, seed + 1)
+    P, ell = 1 + seed % 3, 2 + seed % 3
+    C = ell * (1 + seed % 4)
+    s, top = run_tx_topk(crop, ctx, st, P, C, ell, 10, seed=seed + 1)
+    check_invariants(s, exact, seed + 1)
+    check_topk_is_summary_topk(s, top, 10)
+
+
+def test_few_distinct_per_bucket_is_exact(crop, ctx):
+    st = datagen.tiny_transactions(7, T=50, n=10, cap=6)  # at most 45 distinct pairs
+    exact, _ = exact_map(st)
+    assert len(exact) <= 48
+    s, top = run_tx_topk(crop, ctx, st, 1, 48, 48, 5)
+    assert s["used"].sum() == len(exact)
+    for k in np.flatnonzero(s["used"]):
+        key = int(oracle.pack_keys(s["x"][k], s["y"][k]))
+        assert s["cnt"][k] == exact[key] and s["err"][k] == 0
+
+
+def test_recall_matches_sequential_oracle(crop, ctx):
+    """1/8 of the small stream's distinct pairs fit: GPU recall@100 is
+    close to the sequential oracle's at equal memory."""
+    st = datagen.config_small()
+    exact, r = exact_map(st)
+    P, C, ell, K = 4, 1024, 16, 100
+    s, top = run_tx_topk(crop, ctx, st, P, C, ell, K)
+    check_invariants(s, exact, SEED)
+    ek = oracle.pack_keys(r["x"], r["y"])
+    rec_gpu = oracle.recall_at_k(oracle.pack_keys(top[0], top[1]), ek, r["cnt"], K)
+    o = oracle.tx_spacesaving(st.off, st.items, SEED, P, C // ell, ell)
+    used = o["used"]
+    okeys = oracle.pack_keys(o["x"][used], o["y"][used])
+    oi = oracle.topk(okeys, o["cnt"][used], K)
+    rec_orc = oracle.recall_at_k(okeys[oi], ek, r["cnt"], K)
+    print(f"recall@{K}: gpu {rec_gpu:.3f} oracle {rec_orc:.3f}")
+    assert rec_gpu >= rec_orc - 0.05
+
+
+def test_seeded_pins_exact_and_placement(crop, ctx):
+    st = datagen.config_small()
+    exact, r = exact_map(st)
+    top = oracle.topk(oracle.pack_keys(r["x"], r["y"]), r["cnt"], 60)
+    sx, sy = r["x"][top], r["y"][top]
+    sx = np.concatenate([sx, sx[:5]])  # duplicates are skipped
+    sy = np.concatenate([sy, sy[:5]])
+    P, C, ell, rmax = 2, 128, 8, 3
+    s, _ = run_tx_topk(crop, ctx, st, P, C, ell, 50, seeds=(sx, sy), r_max=rmax)
+    check_invariants(s, exact, SEED)
+    o = oracle.tx_spacesaving(st.off, st.items, SEED, P, C // ell, ell, sx, sy, rmax)
+    # pinned placement is the same as the oracle's: same keys in the same slots
+    assert np.array_equal(s["pinned"], o["pinned"])
+    pk = oracle.pack_keys(s["x"], s["y"])[s["pinned"]]
+    ok = oracle.pack_keys(o["x"], o["y"])[o["pinned"]]
+    assert np.array_equal(pk, ok)
+    assert s["pinned"].reshape(-1, ell).sum(axis=1).max() <= rmax
+
+
+def test_outer_summaries_and_topk(crop, ctx):
+    op = datagen.tiny_outer(3, K=300, n_rows=60, n_cols=50, max_nnz=12)
+    ex = oracle.op_exact(op, 1, SEED)
+    P, C, ell, K = 2, 64, 8, 20
+    crop.crop_set_partitions(ctx, P)
+    crop.crop_set_seed(ctx, SEED)
+    crop.crop_set_summary(ctx, C, ell)
+    crop.crop_load_outer(ctx, op.a_off, op.a_idx, op.a_val, op.b_off, op.b_idx, op.b_val,
+                         op.n_rows, op.n_cols)
+    crop.crop_run_topk(ctx, K)
+    s = crop.crop_read_summary(ctx, P * C)
+    s.update(P=P, B=C // ell, ell=ell)
+    exact = dict(zip(oracle.pack_keys(ex["i"], ex["j"]).tolist(), ex["abs"].tolist()))
+    check_invariants(s, exact, SEED, rtol=1e-5)
+    top = crop.crop_read_topk(ctx, K)
+    check_topk_is_summary_topk(s, top, K)
+    # an entry monitored since its first term carries its exact signed sum
+    signed = dict(zip(oracle.pack_keys(ex["i"], ex["j"]).tolist(), ex["sum"].tolist()))
+    keys = oracle.pack_keys(s["x"], s["y"])
+    for q in np.flatnonzero(s["used"] & (s["err"] == 0)):
+        k = int(keys[q])
+        assert abs(s["val"][q] - signed[k]) <= 1e-5 * exact[k] + 1e-30
+
+
+def test_outer_config_topk_recall(crop, ctx):
+    """100,000 outer products, P = 8, 2^16 counters per partition, top-10,000
+    by |value|: recall against the exact fp64 ranking."""
+    op = datagen.config_outer()
+    ex = oracle.op_exact(op, 1, SEED)
+    P, C, ell, K = 8, 1 << 16, 16, 10000
+    crop.crop_set_partitions(ctx, P)
+    crop.crop_set_seed(ctx, SEED)
+    crop.crop_set_summary(ctx, C, ell)
+    crop.crop_load_outer(ctx, op.a_off, op.a_idx, op.a_val, op.b_off, op.b_idx, op.b_val,
+                         op.n_rows, op.n_cols)
+    crop.crop_run_topk(ctx, K)
+    top = crop.crop_read_topk(ctx, K)
+    assert top[0].shape[0] == K
+    ek = oracle.pack_keys(ex["i"], ex["j"])
+    rec = oracle.recall_at_k(oracle.pack_keys(top[0], top[1]), ek, np.abs(ex["sum"]), K)
+    rec_abs = oracle.recall_at_k(oracle.pack_keys(top[0], top[1]), ek, ex["abs"], K)
+    print(f"outer top-{K}: recall by |sum| {rec:.4f}, by sum|terms| {rec_abs:.4f}")
+    assert rec_abs > 0.9
