@@ -102,9 +102,11 @@ crop_status crop_set_seed(crop_ctx *ctx, uint64_t seed);
  * ell in [1, 64]; counters_per_partition a multiple of ell. */
 crop_status crop_set_summary(crop_ctx *ctx, uint32_t counters_per_partition,
                              uint32_t counters_per_bucket);
-/* Borrow a HIP stream (hipStream_t) for all later work; NULL restores the
- * library's own stream.  The stream must outlive its use. */
+/* Borrow a HIP stream (hipStream_t) for all later work; NULL is HIP's null
+ * stream.  The stream must outlive its use.  A new context works on a
+ * non-blocking stream of its own; crop_use_own_stream returns to it. */
 crop_status crop_set_stream(crop_ctx *ctx, void *hip_stream);
+crop_status crop_use_own_stream(crop_ctx *ctx);
 crop_status crop_set_tuning(crop_ctx *ctx, const crop_tune *tune);
 /* The configuration the next (or last) run uses, after automatic choices. */
 crop_status crop_get_tuning(const crop_ctx *ctx, crop_tune *out);
@@ -188,6 +190,67 @@ crop_status crop_synchronize(crop_ctx *ctx);
 /* Device time in milliseconds of the last run, from HIP events recorded on
  * the context stream around its kernels (synchronizes). */
 crop_status crop_last_run_ms(crop_ctx *ctx, float *ms);
+
+/* ---- learned heavy-pair seeding (an addition; not in the paper) -------- */
+/* All arrays below are device memory; calls are asynchronous on the context
+ * stream unless they return host data.  Section 6 (Theorem 2's proof) names
+ * the failure the seeding targets: a heavy entry is lost when too many heavy
+ * entries or too much light weight share its bucket; pinning predicted heavy
+ * pairs (crop_run_topk_seeded) counts them exactly from the start. */
+
+/* 16 fp32 features per item (feat[n_items * 16]) from the first prefix_T
+ * transactions of the loaded stream: counts, pair occurrences, lengths,
+ * first/second-half counts and the rank of the item's count. */
+crop_status crop_item_features(crop_ctx *ctx, uint32_t prefix_T, float *feat);
+
+/* Candidate pairs x < y among the M items with the largest prefix counts
+ * (ties by smaller id), in (x, y) order: cx, cy of capacity cap >= M(M-1)/2;
+ * *n_pairs receives M(M-1)/2. */
+crop_status crop_top_item_pairs(crop_ctx *ctx, uint32_t prefix_T, uint32_t M, uint32_t *cx,
+                                uint32_t *cy, uint64_t cap, uint64_t *n_pairs);
+
+/* Exact supports of query pairs (qx[q] < qy[q]) in the last exact run of a
+ * transaction stream; 0 for a pair that never occurs.  n <= 2^30. */
+crop_status crop_lookup_exact(crop_ctx *ctx, const uint32_t *qx, const uint32_t *qy, uint64_t n,
+                              uint32_t *count);
+
+/* Network inputs Z[n * 32] = [feat[cx], feat[cy]] and, when count is given,
+ * labels y[n] = log1p(count). */
+crop_status crop_pair_inputs(crop_ctx *ctx, const float *feat, const uint32_t *cx,
+                             const uint32_t *cy, const uint32_t *count, uint64_t n, float *Z,
+                             float *y);
+
+/* A 32 -> 64 -> 64 -> 1 ReLU network with fp32 weights kept on the device.
+ * init: host array of 6337 floats in the order W1[64][32], b1[64],
+ * W2[64][64], b2[64], w3[64], b3. */
+typedef struct crop_mlp crop_mlp;
+crop_status crop_mlp_create(crop_ctx *ctx, const float *init, crop_mlp **out);
+void crop_mlp_destroy(crop_mlp *mlp);
+/* Current weights into a host array of 6337 floats (synchronizes). */
+crop_status crop_mlp_params(crop_ctx *ctx, const crop_mlp *mlp, float *out);
+/* Gradient (host, 6337 floats) and loss of the mean squared error over the
+ * N <= 128 samples Z[N * 32], y[N] at the current weights (synchronizes). */
+crop_status crop_mlp_grad(crop_ctx *ctx, crop_mlp *mlp, const float *Z, const float *y,
+                          uint32_t N, float *grad, float *loss);
+/* Adam (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) over the
+ * minibatches order[0..batch), order[batch..2 batch), ... of sample indices
+ * into Z[n_samples * 32], y[n_samples]; batch <= 128; a trailing partial
+ * batch is ignored.  CROP_E_INPUT (nothing trained) if an index is
+ * >= n_samples.  Synchronizes once to check the indices. */
+crop_status crop_mlp_train(crop_ctx *ctx, crop_mlp *mlp, const float *Z, const float *y,
+                           uint64_t n_samples, const uint32_t *order, uint64_t n_order,
+                           uint32_t batch, float lr);
+/* Mean loss of the last training minibatch (synchronizes). */
+crop_status crop_mlp_loss(crop_ctx *ctx, const crop_mlp *mlp, float *loss);
+/* Scores out[N] with weights and inputs rounded to bfloat16 (ties to even)
+ * and fp32 accumulation. */
+crop_status crop_mlp_score(crop_ctx *ctx, const crop_mlp *mlp, const float *Z, uint64_t N,
+                           float *out);
+/* The R candidates with the highest scores (ties by candidate index), in
+ * rank order, as seeds sx[R], sy[R] for crop_run_topk_seeded. */
+crop_status crop_select_seeds(crop_ctx *ctx, const float *score, const uint32_t *cx,
+                              const uint32_t *cy, uint64_t n, uint32_t R, uint32_t *sx,
+                              uint32_t *sy);
 
 /* Profiling: when enabled, every run also records one HIP event after each
  * of its stages (kernels or kernel groups) on the context stream, kept for

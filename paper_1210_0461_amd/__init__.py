@@ -75,6 +75,7 @@ _SIGS = {
     "crop_set_seed": ([_vp, _u64], _i32),
     "crop_set_summary": ([_vp, _u32, _u32], _i32),
     "crop_set_stream": ([_vp, _vp], _i32),
+    "crop_use_own_stream": ([_vp], _i32),
     "crop_set_tuning": ([_vp, ctypes.POINTER(crop_tune)], _i32),
     "crop_get_tuning": ([_vp, ctypes.POINTER(crop_tune)], _i32),
     "crop_load_transactions": ([_vp, _vp, _u64, _vp, _u64, _u32, _i32, _i32], _i32),
@@ -90,13 +91,27 @@ _SIGS = {
     "crop_run_stages": ([_vp, _u32, ctypes.POINTER(_u32), _vp, _vp, _u32], _i32),
 }
 
-# Optional entry points (declared in include/crop.h once implemented).
-_OPTIONAL_SIGS = {
+_SIGS.update({
     "crop_run_topk": ([_vp, _u32], _i32),
     "crop_run_topk_seeded": ([_vp, _u32, _vp, _vp, _u64, _u32], _i32),
     "crop_read_topk": ([_vp, _vp, _vp, _vp, _vp, _vp, _u64, _pu64], _i32),
     "crop_read_summary": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64, _pu64], _i32),
-}
+    "crop_item_features": ([_vp, _u32, _vp], _i32),
+    "crop_top_item_pairs": ([_vp, _u32, _u32, _vp, _vp, _u64, _pu64], _i32),
+    "crop_lookup_exact": ([_vp, _vp, _vp, _u64, _vp], _i32),
+    "crop_pair_inputs": ([_vp, _vp, _vp, _vp, _vp, _u64, _vp, _vp], _i32),
+    "crop_mlp_create": ([_vp, _vp, ctypes.POINTER(_vp)], _i32),
+    "crop_mlp_destroy": ([_vp], None),
+    "crop_mlp_params": ([_vp, _vp, _vp], _i32),
+    "crop_mlp_grad": ([_vp, _vp, _vp, _vp, _u32, _vp, _vp], _i32),
+    "crop_mlp_train": ([_vp, _vp, _vp, _vp, _u64, _vp, _u64, _u32, ctypes.c_float], _i32),
+    "crop_mlp_loss": ([_vp, _vp, _vp], _i32),
+    "crop_mlp_score": ([_vp, _vp, _vp, _u64, _vp], _i32),
+    "crop_select_seeds": ([_vp, _vp, _vp, _vp, _u64, _u32, _vp, _vp], _i32),
+})
+
+# Entry points bound only when the loaded library exports them.
+_OPTIONAL_SIGS: dict = {}
 
 for _name, (_args, _res) in _SIGS.items():
     _f = getattr(_lib, _name)
@@ -189,10 +204,15 @@ def crop_set_summary(ctx, counters_per_partition: int, counters_per_bucket: int)
 
 
 def crop_set_stream(ctx, stream) -> None:
-    """stream: a torch.cuda.Stream, a raw hipStream_t integer, or None."""
+    """stream: a torch.cuda.Stream or a raw hipStream_t integer (0 or None:
+    HIP's null stream)."""
     if stream is not None and hasattr(stream, "cuda_stream"):
         stream = stream.cuda_stream
-    _check(ctx, _lib.crop_set_stream(ctx, stream))
+    _check(ctx, _lib.crop_set_stream(ctx, stream or None))
+
+
+def crop_use_own_stream(ctx) -> None:
+    _check(ctx, _lib.crop_use_own_stream(ctx))
 
 
 def crop_set_tuning(ctx, bins_per_partition=0, table_slots=0, rows_per_chunk=0,
@@ -317,6 +337,92 @@ def crop_read_summary(ctx, n_slots: int):
     n = w.value
     return dict(x=i[:n], y=j[:n], cnt=cnt[:n], err=err[:n], val=val[:n],
                 used=(flags[:n] & 1).astype(bool), pinned=(flags[:n] & 2).astype(bool))
+
+
+# ---- learned heavy-pair seeding (device tensors in and out)
+
+MLP_PARAMS = 6337
+
+
+def _dev(a, name):
+    p, where = _ptr(a)
+    if a is not None and where != CROP_MEM_DEVICE:
+        raise ValueError(f"{name} must be device memory")
+    return p
+
+
+def crop_item_features(ctx, prefix_T: int, feat) -> None:
+    """feat: float32 device tensor [n_items, 16]."""
+    _check(ctx, _lib.crop_item_features(ctx, prefix_T, _dev(feat, "feat")))
+
+
+def crop_top_item_pairs(ctx, prefix_T: int, M: int, cx, cy) -> int:
+    """cx, cy: uint32/int32 device tensors of capacity >= M(M-1)/2."""
+    n = _u64(0)
+    _check(ctx, _lib.crop_top_item_pairs(ctx, prefix_T, M, _dev(cx, "cx"), _dev(cy, "cy"),
+                                         _len(cx), ctypes.byref(n)))
+    return n.value
+
+
+def crop_lookup_exact(ctx, qx, qy, count) -> None:
+    _check(ctx, _lib.crop_lookup_exact(ctx, _dev(qx, "qx"), _dev(qy, "qy"), _len(qx),
+                                       _dev(count, "count")))
+
+
+def crop_pair_inputs(ctx, feat, cx, cy, count, Z, y=None) -> None:
+    _check(ctx, _lib.crop_pair_inputs(ctx, _dev(feat, "feat"), _dev(cx, "cx"), _dev(cy, "cy"),
+                                      _dev(count, "count"), _len(cx), _dev(Z, "Z"),
+                                      _dev(y, "y")))
+
+
+def crop_mlp_create(ctx, init):
+    """init: float32 host array of MLP_PARAMS values."""
+    init = np.ascontiguousarray(init, np.float32)
+    if init.shape != (MLP_PARAMS,):
+        raise ValueError(f"init must hold {MLP_PARAMS} floats")
+    h = _vp()
+    _check(ctx, _lib.crop_mlp_create(ctx, init.ctypes.data, ctypes.byref(h)))
+    return h
+
+
+def crop_mlp_destroy(mlp) -> None:
+    _lib.crop_mlp_destroy(mlp)
+
+
+def crop_mlp_params(ctx, mlp):
+    out = np.zeros(MLP_PARAMS, np.float32)
+    _check(ctx, _lib.crop_mlp_params(ctx, mlp, out.ctypes.data))
+    return out
+
+
+def crop_mlp_grad(ctx, mlp, Z, y):
+    """(gradient [MLP_PARAMS], loss) of the MSE over the samples Z, y."""
+    g = np.zeros(MLP_PARAMS, np.float32)
+    loss = ctypes.c_float(0.0)
+    _check(ctx, _lib.crop_mlp_grad(ctx, mlp, _dev(Z, "Z"), _dev(y, "y"), _len(y),
+                                   g.ctypes.data, ctypes.byref(loss)))
+    return g, float(loss.value)
+
+
+def crop_mlp_train(ctx, mlp, Z, y, order, batch: int, lr: float) -> None:
+    _check(ctx, _lib.crop_mlp_train(ctx, mlp, _dev(Z, "Z"), _dev(y, "y"), _len(y),
+                                    _dev(order, "order"), _len(order), batch, lr))
+
+
+def crop_mlp_loss(ctx, mlp) -> float:
+    loss = ctypes.c_float(0.0)
+    _check(ctx, _lib.crop_mlp_loss(ctx, mlp, ctypes.byref(loss)))
+    return float(loss.value)
+
+
+def crop_mlp_score(ctx, mlp, Z, out) -> None:
+    _check(ctx, _lib.crop_mlp_score(ctx, mlp, _dev(Z, "Z"), _len(out), _dev(out, "out")))
+
+
+def crop_select_seeds(ctx, score, cx, cy, R: int, sx, sy) -> None:
+    _check(ctx, _lib.crop_select_seeds(ctx, _dev(score, "score"), _dev(cx, "cx"),
+                                       _dev(cy, "cy"), _len(score), R, _dev(sx, "sx"),
+                                       _dev(sy, "sy")))
 
 
 def crop_synchronize(ctx) -> None:

@@ -513,7 +513,14 @@ crop_status crop_set_summary(crop_ctx *ctx, uint32_t counters_per_partition,
 crop_status crop_set_stream(crop_ctx *ctx, void *hip_stream)
 {
     if (!ctx) return CROP_E_ARG;
-    ctx->stream = hip_stream ? static_cast<hipStream_t>(hip_stream) : ctx->own_stream;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return CROP_OK;
+}
+
+crop_status crop_use_own_stream(crop_ctx *ctx)
+{
+    if (!ctx) return CROP_E_ARG;
+    ctx->stream = ctx->own_stream;
     return CROP_OK;
 }
 
@@ -847,6 +854,197 @@ crop_status crop_read_summary(crop_ctx *ctx, uint32_t *i, uint32_t *j, double *c
         if (value) value[q] = outer ? (double)v[q] : 0.0;
         if (flags) flags[q] = f[q];
     }
+    return CROP_OK;
+}
+
+// ============================================================== learned seeding
+
+static crop_status require_tx(crop_ctx *ctx)
+{
+    if (ctx->in.mode != Mode::Tx) return fail(ctx, CROP_E_STATE, "no transaction stream loaded");
+    return CROP_OK;
+}
+
+static crop_status stats_workspace(crop_ctx *ctx, uint32_t prefix_T)
+{
+    const uint32_t n = ctx->in.n_items;
+    const size_t words = item_stats_words(n, prefix_T);
+    CK(ctx->learn_ws.ensure(words * 4 + 4096));
+    CK(launch_zero32(ctx->learn_ws.as<uint32_t>(), (uint32_t)words, ctx->stream));
+    return CROP_OK;
+}
+
+crop_status crop_item_features(crop_ctx *ctx, uint32_t prefix_T, float *feat)
+{
+    if (!ctx || !feat) return CROP_E_ARG;
+    crop_status st = require_tx(ctx);
+    if (st != CROP_OK) return st;
+    if (prefix_T > ctx->in.T) return fail(ctx, CROP_E_ARG, "prefix longer than the stream");
+    DeviceGuard g(ctx->device);
+    st = stats_workspace(ctx, prefix_T);
+    if (st != CROP_OK) return st;
+    CK(launch_item_features(ctx->in.off, ctx->in.items, ctx->in.n_items, prefix_T,
+                            ctx->learn_ws.as<uint32_t>(), feat, ctx->stream));
+    return CROP_OK;
+}
+
+crop_status crop_top_item_pairs(crop_ctx *ctx, uint32_t prefix_T, uint32_t M, uint32_t *cx,
+                                uint32_t *cy, uint64_t cap, uint64_t *n_pairs)
+{
+    if (!ctx || !cx || !cy) return CROP_E_ARG;
+    crop_status st = require_tx(ctx);
+    if (st != CROP_OK) return st;
+    if (prefix_T > ctx->in.T) return fail(ctx, CROP_E_ARG, "prefix longer than the stream");
+    if (M < 2 || M > ctx->in.n_items) return fail(ctx, CROP_E_ARG, "need 2 <= M <= n_items");
+    const uint64_t np = (uint64_t)M * (M - 1) / 2;
+    if (n_pairs) *n_pairs = np;
+    if (np > cap) return fail(ctx, CROP_E_CAPACITY, "pair capacity below M(M-1)/2");
+    DeviceGuard g(ctx->device);
+    st = stats_workspace(ctx, prefix_T);
+    if (st != CROP_OK) return st;
+    CK(ctx->scratch.ensure((size_t)M * 4 + 256));
+    uint32_t *ws = ctx->learn_ws.as<uint32_t>();
+    CK(launch_item_features(ctx->in.off, ctx->in.items, ctx->in.n_items, prefix_T, ws, nullptr,
+                            ctx->stream));
+    CK(launch_top_pairs(ws, ctx->in.n_items, prefix_T, M, ctx->scratch.as<uint32_t>(), cx, cy,
+                        ctx->stream));
+    return CROP_OK;
+}
+
+crop_status crop_lookup_exact(crop_ctx *ctx, const uint32_t *qx, const uint32_t *qy, uint64_t n,
+                              uint32_t *count)
+{
+    if (!ctx || (n && (!qx || !qy || !count))) return CROP_E_ARG;
+    if (n > (1ull << 30)) return fail(ctx, CROP_E_UNSUPPORTED, "at most 2^30 queries per call");
+    crop_status st = require_exact(ctx);
+    if (st != CROP_OK) return st;
+    st = require_tx(ctx);
+    if (st != CROP_OK) return st;
+    DeviceGuard g(ctx->device);
+    CK(launch_lookup(ctx, qx, qy, n, count, ctx->stream));
+    return CROP_OK;
+}
+
+crop_status crop_pair_inputs(crop_ctx *ctx, const float *feat, const uint32_t *cx,
+                             const uint32_t *cy, const uint32_t *count, uint64_t n, float *Z,
+                             float *y)
+{
+    if (!ctx || (n && (!feat || !cx || !cy || !Z))) return CROP_E_ARG;
+    if (y && !count) return fail(ctx, CROP_E_ARG, "labels need counts");
+    DeviceGuard g(ctx->device);
+    CK(launch_pair_inputs(feat, cx, cy, count, n, Z, y, ctx->stream));
+    return CROP_OK;
+}
+
+crop_status crop_mlp_create(crop_ctx *ctx, const float *init, crop_mlp **out)
+{
+    if (!ctx || !init || !out) return CROP_E_ARG;
+    *out = nullptr;
+    DeviceGuard g(ctx->device);
+    crop_mlp *m = new (std::nothrow) crop_mlp();
+    if (!m) return CROP_E_NOMEM;
+    m->device = ctx->device;
+    const size_t nb = (size_t)mlp_param_count() * 4;
+    hipError_t e = hipSuccess;
+    for (DevBuf *b : {&m->params, &m->m, &m->v, &m->gstage})
+        if (e == hipSuccess) e = b->ensure(nb);
+    if (e == hipSuccess) e = m->loss.ensure(256);
+    if (e == hipSuccess) e = hipMemcpy(m->params.p, init, nb, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = launch_zero32(m->m.as<uint32_t>(), mlp_param_count(), ctx->stream);
+    if (e == hipSuccess) e = launch_zero32(m->v.as<uint32_t>(), mlp_param_count(), ctx->stream);
+    if (e == hipSuccess) e = launch_zero32(m->loss.as<uint32_t>(), 64, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        crop_mlp_destroy(m);
+        return hip_fail(ctx, e, "crop_mlp_create");
+    }
+    *out = m;
+    return CROP_OK;
+}
+
+void crop_mlp_destroy(crop_mlp *m)
+{
+    if (!m) return;
+    DeviceGuard g(m->device);
+    for (DevBuf *b : {&m->params, &m->m, &m->v, &m->gstage, &m->loss}) b->release();
+    delete m;
+}
+
+crop_status crop_mlp_params(crop_ctx *ctx, const crop_mlp *m, float *out)
+{
+    if (!ctx || !m || !out) return CROP_E_ARG;
+    DeviceGuard g(ctx->device);
+    CK(hipStreamSynchronize(ctx->stream));
+    CK(hipMemcpy(out, m->params.p, (size_t)mlp_param_count() * 4, hipMemcpyDeviceToHost));
+    return CROP_OK;
+}
+
+crop_status crop_mlp_grad(crop_ctx *ctx, crop_mlp *m, const float *Z, const float *y, uint32_t N,
+                          float *grad, float *loss)
+{
+    if (!ctx || !m || !Z || !y || !grad) return CROP_E_ARG;
+    if (N < 1 || N > (uint32_t)mlp_batch_max())
+        return fail(ctx, CROP_E_ARG, "gradient batch must hold 1..128 samples");
+    DeviceGuard g(ctx->device);
+    CK(launch_mlp_grad(m->params.as<float>(), Z, y, N, m->gstage.as<float>(),
+                       m->loss.as<float>(), ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    CK(hipMemcpy(grad, m->gstage.p, (size_t)mlp_param_count() * 4, hipMemcpyDeviceToHost));
+    if (loss) CK(hipMemcpy(loss, m->loss.p, 4, hipMemcpyDeviceToHost));
+    return CROP_OK;
+}
+
+crop_status crop_mlp_train(crop_ctx *ctx, crop_mlp *m, const float *Z, const float *y,
+                           uint64_t n_samples, const uint32_t *order, uint64_t n_order,
+                           uint32_t batch, float lr)
+{
+    if (!ctx || !m || !Z || !y || !order) return CROP_E_ARG;
+    if (batch < 1 || batch > (uint32_t)mlp_batch_max())
+        return fail(ctx, CROP_E_ARG, "batch must hold 1..128 samples");
+    DeviceGuard g(ctx->device);
+    const uint64_t steps = n_order / batch;
+    if (!steps) return CROP_OK;
+    // every sample index is checked before the training kernel reads Z and y
+    CK(launch_zero32(m->loss.as<uint32_t>() + 1, 1, ctx->stream));
+    CK(launch_max_index(order, steps * batch, m->loss.as<uint32_t>() + 1, ctx->stream));
+    uint32_t mx = 0;
+    CK(hipMemcpyAsync(&mx, m->loss.as<uint32_t>() + 1, 4, hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    if (mx >= n_samples) return fail(ctx, CROP_E_INPUT, "sample index beyond n_samples");
+    CK(launch_mlp_train(m->params.as<float>(), m->m.as<float>(), m->v.as<float>(),
+                        m->gstage.as<float>(), Z, y, order, steps * batch, batch, lr, m->t,
+                        m->loss.as<float>(), ctx->stream));
+    m->t += steps;
+    return CROP_OK;
+}
+
+crop_status crop_mlp_loss(crop_ctx *ctx, const crop_mlp *m, float *loss)
+{
+    if (!ctx || !m || !loss) return CROP_E_ARG;
+    DeviceGuard g(ctx->device);
+    CK(hipStreamSynchronize(ctx->stream));
+    CK(hipMemcpy(loss, m->loss.p, 4, hipMemcpyDeviceToHost));
+    return CROP_OK;
+}
+
+crop_status crop_mlp_score(crop_ctx *ctx, const crop_mlp *m, const float *Z, uint64_t N,
+                           float *out)
+{
+    if (!ctx || !m || (N && (!Z || !out))) return CROP_E_ARG;
+    DeviceGuard g(ctx->device);
+    CK(launch_mlp_score(m->params.as<float>(), Z, N, out, ctx->stream));
+    return CROP_OK;
+}
+
+crop_status crop_select_seeds(crop_ctx *ctx, const float *score, const uint32_t *cx,
+                              const uint32_t *cy, uint64_t n, uint32_t R, uint32_t *sx,
+                              uint32_t *sy)
+{
+    if (!ctx || (n && (!score || !cx || !cy || !sx || !sy))) return CROP_E_ARG;
+    if (n >= (1ull << 32)) return fail(ctx, CROP_E_UNSUPPORTED, "too many candidates");
+    if (R > n) return fail(ctx, CROP_E_ARG, "R exceeds the candidate count");
+    DeviceGuard g(ctx->device);
+    CK(launch_select_seeds(score, cx, cy, (uint32_t)n, R, sx, sy, ctx->stream));
     return CROP_OK;
 }
 

@@ -103,6 +103,12 @@ struct StageRec {
 
 }  // namespace crop
 
+struct crop_mlp {
+    int device = 0;
+    crop::DevBuf params, m, v, gstage, loss;
+    uint64_t t = 0;  // Adam steps taken
+};
+
 struct crop_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -125,7 +131,7 @@ struct crop_ctx {
     // work and result buffers
     crop::DevBuf cnt_mat, part_buf, bin_off, bin_size, bin_order, keys, vals, out_cnt, spill,
         counter;
-    crop::DevBuf ss_state, topk_buf, scratch;
+    crop::DevBuf ss_state, topk_buf, scratch, learn_ws;
     crop::SsState ss;          // views into ss_state
     uint64_t ss_buckets = 0;   // P * B of the last top-K run
     uint32_t topk_outer = 0;   // the last top-K run was on outer products
@@ -179,6 +185,30 @@ hipError_t launch_zero32(uint32_t *p, uint32_t n, hipStream_t s);
 hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, uint32_t *st, uint32_t *hist,
                        uint32_t *cand, uint32_t *sel, uint32_t *oi, uint32_t *oj, double *ou,
                        double *ol, double *ov, hipStream_t s);
+
+// Learned seeding (k_learned.hip).
+size_t item_stats_words(uint32_t n, uint32_t Tp);
+hipError_t launch_item_features(const uint32_t *off, const uint32_t *items, uint32_t n,
+                                uint32_t Tp, uint32_t *ws, float *feat, hipStream_t s);
+hipError_t launch_top_pairs(const uint32_t *ws, uint32_t n, uint32_t Tp, uint32_t M,
+                            uint32_t *top, uint32_t *cx, uint32_t *cy, hipStream_t s);
+hipError_t launch_lookup(const crop_ctx *c, const uint32_t *qx, const uint32_t *qy, uint64_t n,
+                         uint32_t *out, hipStream_t s);
+hipError_t launch_pair_inputs(const float *feat, const uint32_t *cx, const uint32_t *cy,
+                              const uint32_t *count, uint64_t n, float *Z, float *y,
+                              hipStream_t s);
+hipError_t launch_mlp_train(float *params, float *m, float *v, float *gstage, const float *Z,
+                            const float *y, const uint32_t *order, uint64_t n_order,
+                            uint32_t batch, float lr, uint64_t t0, float *loss, hipStream_t s);
+hipError_t launch_mlp_grad(const float *params, const float *Z, const float *y, uint32_t N,
+                           float *grad, float *loss, hipStream_t s);
+hipError_t launch_mlp_score(const float *params, const float *Z, uint64_t N, float *out,
+                            hipStream_t s);
+hipError_t launch_select_seeds(const float *score, const uint32_t *cx, const uint32_t *cy,
+                               uint32_t n, uint32_t R, uint32_t *sx, uint32_t *sy, hipStream_t s);
+hipError_t launch_max_index(const uint32_t *idx, uint64_t n, uint32_t *out, hipStream_t s);
+int mlp_param_count();
+int mlp_batch_max();
 
 // Gather the bin-segmented exact result into partition-contiguous arrays.
 hipError_t launch_gather_result(const crop_ctx *c, const uint32_t *dst_off, uint32_t *out_i,
