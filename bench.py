@@ -12,7 +12,15 @@ second).
 
 Printed: one JSON line with the throughput, the roofline of the dominant
 kernel (HIP events on the library's stream over the timed steps), and the
-CPU oracle timed on a bounded sample of the same stream.
+CPU oracle timed on the same stream (single-threaded, about half a minute),
+whose result also gives the recall@1000 of the GPU's exact top 1000 and a
+whole-result equality check.
+
+--learned runs the learned-seeding comparison instead: an MLP trained on
+the GPU on 20 training streams like the one above, used to pin predicted
+heavy pairs into the Space-Saving summaries of a held-out stream, against
+the plain summaries at equal memory, in two regimes (P = 1024 with 2^14
+counters per partition, and P = 1 with 16,384 counters).
 """
 import argparse
 import hashlib
@@ -38,8 +46,18 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the CPU oracle leg (profiling runs)")
-    ap.add_argument("--cpu-sample", type=int, default=500_000,
-                    help="transactions of the stream the CPU oracle is timed on")
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000,
+                    help="transactions of the stream the CPU oracle is timed on; the "
+                         "whole stream also gives the recall and equality checks")
+    ap.add_argument("--learned", action="store_true",
+                    help="run the learned-seeding comparison instead of the exact bench")
+    ap.add_argument("--train-streams", type=int, default=20)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--candidates", type=int, default=256,
+                    help="top prefix items M; candidates are their M(M-1)/2 pairs")
+    ap.add_argument("--seeds", type=int, default=1000)
+    ap.add_argument("--r-max", type=int, default=4)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only copy a 1 GiB buffer 5 times (HBM counter calibration)")
     return ap.parse_args()
@@ -88,6 +106,8 @@ def traffic_from_profiles(kernel, digest, launches_bytes):
 
 
 def cpu_baseline(st, n_rows):
+    """The oracle timed on the first n_rows transactions; also returns its
+    result (the exact supports of that sample)."""
     import oracle
     sample = st.slice(0, min(n_rows, st.T))
     t0 = time.perf_counter()
@@ -96,7 +116,153 @@ def cpu_baseline(st, n_rows):
     return {"value": r["n_terms"] / dt, "unit": "term-updates/s", "cores": 1, "kind": "oracle",
             "sample": f"first {sample.T} transactions of the 1M stream "
                       f"({r['n_terms']} terms), P={P}, {dt:.2f} s single-threaded",
-            "seconds": round(dt, 3)}
+            "seconds": round(dt, 3)}, r, sample.T
+
+
+def sorted_pairs(x, y, c):
+    import numpy as np
+    k = (np.asarray(x, np.uint64) << np.uint64(32)) | np.asarray(y, np.uint64)
+    o = np.argsort(k, kind="stable")
+    return k[o], np.asarray(c, np.int64)[o]
+
+
+def top_keys(keys, cnt, K):
+    """First K keys by (count desc, key asc) and the K-th count."""
+    import numpy as np
+    o = np.lexsort((keys, -cnt))[:K]
+    return keys[o], int(cnt[o[-1]]) if o.shape[0] else 0
+
+
+def recall_vs(ref_keys, ref_cnt, rep_keys, K):
+    """Tie-tolerant recall@K of reported keys against exact supports
+    (ref_keys sorted): a hit has an exact support >= the K-th largest."""
+    import numpy as np
+    _, cK = top_keys(ref_keys, ref_cnt, K)
+    pos = np.searchsorted(ref_keys, rep_keys)
+    pos = np.minimum(pos, ref_keys.shape[0] - 1)
+    found = ref_keys[pos] == rep_keys
+    exact = np.where(found, ref_cnt[pos], 0)
+    return float((exact >= cK).sum()) / min(K, ref_keys.shape[0]), exact
+
+
+def _gen_learned(i):
+    import datagen
+    st = datagen.config_learned_heldout() if i < 0 else datagen.config_learned_train(i)
+    return st.off, st.items, st.n
+
+
+def run_learned(args):
+    """Plain vs learned-seeded Space-Saving top-1000 on the held-out stream."""
+    import multiprocessing as mp
+    import numpy as np
+    t0 = time.perf_counter()
+    # streams are generated in worker processes before this process touches the GPU
+    with mp.get_context("fork").Pool(min(8, os.cpu_count() or 1)) as pool:
+        streams = pool.map(_gen_learned, list(range(args.train_streams)) + [-1])
+    print(f"# generated {len(streams)} streams in {time.perf_counter() - t0:.1f} s",
+          file=sys.stderr, flush=True)
+    import torch
+    import datagen
+    import oracle
+    import paper_1210_0461_amd as crop
+    from paper_1210_0461_amd import seeding
+
+    M, K, ell = args.candidates, 1000, 16
+    ctx = crop.crop_create(0)
+    crop.crop_set_stream(ctx, torch.cuda.current_stream())
+    out = {"experiment": "learned heavy-pair seeding vs plain Space-Saving, equal memory",
+           "train_streams": args.train_streams, "candidates_per_stream": M * (M - 1) // 2,
+           "top_items_M": M, "K": K, "ell": ell, "seeds": args.seeds, "r_max": args.r_max}
+    try:
+        crop.crop_set_seed(ctx, SEED)
+        crop.crop_set_partitions(ctx, P)
+        Zs, ys = [], []
+        t0 = time.perf_counter()
+        for off, items, n in streams[:-1]:
+            crop.crop_load_transactions(ctx, off, items, n)
+            Z, y, _, _, _ = seeding.training_pairs(ctx, off.shape[0] - 1, n, M)
+            Zs.append(Z)
+            ys.append(y)
+        Z = torch.cat(Zs)
+        y = torch.cat(ys)
+        torch.cuda.synchronize()
+        out["label_seconds"] = round(time.perf_counter() - t0, 3)
+        order = torch.from_numpy(
+            datagen.sample_order(6000, Z.shape[0], args.epochs).astype(np.int32)).cuda()
+        mlp = crop.crop_mlp_create(ctx, seeding.flat_init(datagen.mlp_init_weights(6001)))
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        crop.crop_mlp_train(ctx, mlp, Z, y, order, 128, args.lr)
+        ev1.record()
+        torch.cuda.synchronize()
+        steps = order.shape[0] // 128
+        out["train"] = {"samples": int(Z.shape[0]), "epochs": args.epochs, "batch": 128,
+                        "steps": steps, "lr": args.lr,
+                        "ms": round(ev0.elapsed_time(ev1), 2),
+                        "final_batch_mse": crop.crop_mlp_loss(ctx, mlp)}
+
+        off, items, n = streams[-1]
+        T = off.shape[0] - 1
+        t0 = time.perf_counter()
+        ref = oracle.tx_exact(off, items, 1, SEED)
+        rk, rc = sorted_pairs(ref["x"], ref["y"], ref["cnt"])
+        true_top, cK = top_keys(rk, rc, K)
+        out["oracle_seconds"] = round(time.perf_counter() - t0, 2)
+        out["kth_support"] = cK
+        out["terms"] = int(ref["n_terms"])
+        crop.crop_load_transactions(ctx, off, items, n)
+        # predictor quality on the held-out candidates: precision of the seeds
+        ev0.record()
+        sx, sy, score = seeding.predict_seeds(ctx, mlp, T, n, M, args.seeds)
+        ev1.record()
+        torch.cuda.synchronize()
+        seed_keys = ((sx.cpu().numpy().astype(np.uint32).astype(np.uint64) << np.uint64(32)) |
+                     sy.cpu().numpy().astype(np.uint32).astype(np.uint64))
+        out["seed_ms"] = round(ev0.elapsed_time(ev1), 3)
+        out["seeds_in_true_top1000"] = int(np.isin(seed_keys, true_top).sum())
+
+        regimes = []
+        for Pr, C in ((1024, 1 << 14), (1, 16384)):
+            crop.crop_set_partitions(ctx, Pr)
+            crop.crop_set_summary(ctx, C, ell)
+            row = {"P": Pr, "counters_per_partition": C, "total_counters": Pr * C}
+            for mode in ("plain", "seeded"):
+                def once():
+                    if mode == "plain":
+                        crop.crop_run_topk(ctx, K)
+                    else:
+                        crop.crop_run_topk_seeded(ctx, K, sx, sy, args.r_max)
+                once()
+                torch.cuda.synchronize()
+                ev0.record()
+                for _ in range(args.steps):
+                    once()
+                ev1.record()
+                torch.cuda.synchronize()
+                ms = ev0.elapsed_time(ev1) / args.steps
+                i, j, up, lo, _ = crop.crop_read_topk(ctx, K)
+                rep = (i.astype(np.uint64) << np.uint64(32)) | j.astype(np.uint64)
+                rec, exact = recall_vs(rk, rc, rep, K)
+                # the true top-K pairs as the summary holds them
+                s = crop.crop_read_summary(ctx, Pr * C)
+                sk = (s["x"].astype(np.uint64) << np.uint64(32)) | s["y"].astype(np.uint64)
+                held = np.isin(true_top, sk[s["used"]])
+                sel = np.isin(sk, true_top) & s["used"]
+                row[mode] = {"recall_at_1000": rec,
+                             "max_count_error": float((up - exact).max()) if up.size else 0.0,
+                             "true_top_monitored": int(held.sum()),
+                             "true_top_with_error": int((s["err"][sel] > 0).sum()),
+                             "pinned": int(s["pinned"].sum()),
+                             "ms": round(ms, 4),
+                             "term_updates_per_s": out["terms"] / (ms * 1e-3)}
+            regimes.append(row)
+            print(f"# regime P={Pr} C={C}: {json.dumps(row)}", file=sys.stderr, flush=True)
+        out["regimes"] = regimes
+        crop.crop_mlp_destroy(mlp)
+    finally:
+        crop.crop_destroy(ctx)
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -109,6 +275,9 @@ def main():
               "(the path shards by hash interval across GPUs with no exchange; see DESIGN.md)",
               file=sys.stderr)
         sys.exit(2)
+    if args.learned:
+        run_learned(args)
+        return
     import numpy as np
     import torch
     import datagen
@@ -156,6 +325,7 @@ def main():
         stage_ms = {k: sum(v) / len(v) for k, v in stages.items()}
         sizes, part_terms = crop.crop_result_sizes(ctx, P)
         tune = crop.crop_get_tuning(ctx)
+        gx, gy, gc, _ = crop.crop_read_all(ctx, P)   # result of the last timed step
     finally:
         crop.crop_destroy(ctx)
 
@@ -207,10 +377,20 @@ def main():
                           "frac": round(path_gbs / HBM_PEAK_GBS, 4),
                           "alg_bytes": alg_bytes},
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
-        "recall_top1000": 1.0,
+        "recall_top1000": None,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(st, args.cpu_sample)
+        base, ref, rows = cpu_baseline(st, args.cpu_sample)
+        out["cpu_baseline"] = base
+        if rows == st.T:
+            # the GPU's exact result against the oracle's: whole-result
+            # equality and recall@1000 of the GPU's top 1000 pairs
+            rk, rc = sorted_pairs(ref["x"], ref["y"], ref["cnt"])
+            gk, gcnt = sorted_pairs(gx, gy, gc)
+            top, _ = top_keys(gk, gcnt, 1000)
+            out["recall_top1000"], _ = recall_vs(rk, rc, top, 1000)
+            out["exact_match_vs_oracle"] = bool(np.array_equal(rk, gk) and
+                                                np.array_equal(rc, gcnt))
     print(json.dumps(out), flush=True)
 
 

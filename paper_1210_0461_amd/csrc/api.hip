@@ -24,6 +24,8 @@ constexpr uint32_t kMaxP = 8192;
 constexpr uint64_t kTermsPerBin = 30000;   // routed terms per bin the auto plan aims at
 constexpr size_t kLdsBudget = 64 * 1024;   // enumeration kernels' staging budget
 constexpr size_t kStageBudget = 150 * 1024; // scatter kernel: dynamic LDS in total
+constexpr uint64_t kSsMinBins = 2048;       // Space-Saving bins wanted for parallelism
+constexpr size_t kSsLdsBudget = 80 * 1024;  // two summary workgroups per CU
 
 crop_status fail(crop_ctx *c, crop_status s, const std::string &msg)
 {
@@ -302,7 +304,10 @@ crop_status plan_ss(crop_ctx *ctx, uint32_t *nbk_out, uint64_t *PB_out)
         return fail(ctx, CROP_E_UNSUPPORTED, "P x buckets per partition exceeds 2^32");
     const bool outer = ctx->in.mode == Mode::Outer;
     const bool wide = outer || ctx->in.wide_keys;
-    const uint32_t MB = outer ? 1024 : 2048;
+    const uint32_t MB = outer ? kSsBatchOuter : wide ? kSsBatchWide : kSsBatchTx;
+    // Bins of nbk buckets (nbk divides B), at most kMaxP bins and within the
+    // LDS budget: the largest nbk that still leaves min(kSsMinBins, P*B)
+    // bins, else the smallest feasible nbk.
     std::vector<uint64_t> divs;
     for (uint64_t d = 1; d * d <= B; ++d)
         if (B % d == 0) {
@@ -310,18 +315,17 @@ crop_status plan_ss(crop_ctx *ctx, uint32_t *nbk_out, uint64_t *PB_out)
             if (d != B / d) divs.push_back(B / d);
         }
     std::sort(divs.begin(), divs.end());
-    uint64_t best = 0, fallback = 0;
+    const uint64_t min_bins = std::min<uint64_t>(kSsMinBins, PB);
+    uint64_t pick = 0;
     for (uint64_t nbk : divs) {
-        if (ss_bins_smem_bytes((uint32_t)nbk, ell, wide, outer, MB) > 96 * 1024) continue;
-        const uint64_t NB = (uint64_t)P * (B / nbk);
+        const uint64_t NB = PB / nbk;
         if (NB > kMaxP) continue;
-        if (!fallback) fallback = nbk;  // smallest feasible: the most bins
-        if (NB >= 512) best = nbk;      // largest with enough bins
+        if (ss_bins_smem_bytes((uint32_t)nbk, ell, wide, outer, MB) > kSsLdsBudget) break;
+        if (!pick || NB >= min_bins) pick = nbk;
     }
-    const uint64_t nbk = best ? best : fallback;
-    if (!nbk)
+    if (!pick)
         return fail(ctx, CROP_E_UNSUPPORTED, "Space-Saving summaries do not fit the LDS plan");
-    *nbk_out = (uint32_t)nbk;
+    *nbk_out = (uint32_t)pick;
     *PB_out = PB;
     return CROP_OK;
 }
@@ -771,6 +775,7 @@ static crop_status run_topk_impl(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
     STAGE("count");
     CK(launch_scan_counts(cnt, pl.n_chunks, pl.NB, pl.G, ctx->part_buf.as<uint32_t>(),
                           ctx->bin_off.as<uint32_t>(), ctx->counter.as<uint32_t>(), s));
+    CK(launch_bin_order(pl.NB, ctx->bin_off.as<uint32_t>(), ctx->bin_order.as<uint32_t>(), s));
     STAGE("scan");
     if (pl.n_chunks)
         CK(outer ? launch_op_scatter(ctx, cnt, ctx->keys.p, ctx->vals.as<float>(), s)

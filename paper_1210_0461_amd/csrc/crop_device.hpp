@@ -83,6 +83,41 @@ __device__ inline void lds_exclusive_scan(uint32_t *a, uint32_t m, uint32_t *s_t
     __syncthreads();
 }
 
+// In-place exclusive scan of a[0..m) in LDS for a workgroup of any size
+// that is a multiple of 64 (at most 1024); writes the total to a[m].
+// s_tmp needs blockDim.x / 64 + 1 words.  Contains barriers.
+__device__ inline void lds_exclusive_scan_rt(uint32_t *a, uint32_t m, uint32_t *s_tmp)
+{
+    const uint32_t BS = blockDim.x, NW = BS / kWave;
+    const uint32_t per = (m + BS - 1) / BS;
+    const uint32_t beg = threadIdx.x * per;
+    const uint32_t end = beg + per < m ? beg + per : m;
+    uint32_t sum = 0;
+    for (uint32_t k = beg; k < end; ++k) sum += a[k];
+    const uint32_t inc = wave_inclusive_scan(sum);
+    const uint32_t w = threadIdx.x / kWave;
+    if (lane_id() == kWave - 1) s_tmp[w] = inc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t run = 0;
+        for (uint32_t k = 0; k < NW; ++k) {
+            const uint32_t t = s_tmp[k];
+            s_tmp[k] = run;
+            run += t;
+        }
+        s_tmp[NW] = run;
+    }
+    __syncthreads();
+    uint32_t run = s_tmp[w] + inc - sum;
+    for (uint32_t k = beg; k < end; ++k) {
+        const uint32_t t = a[k];
+        a[k] = run;
+        run += t;
+    }
+    if (threadIdx.x == 0) a[m] = s_tmp[NW];
+    __syncthreads();
+}
+
 // Workgroup barrier that orders LDS only.  __syncthreads() also waits for
 // every outstanding global load, which would drain a register prefetch.
 __device__ inline void lds_barrier()

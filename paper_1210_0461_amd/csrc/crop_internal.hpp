@@ -178,7 +178,11 @@ hipError_t launch_ss_clear(const SsState &S, hipStream_t s);
 hipError_t launch_ss_pin(const SsState &S, const uint32_t *sx, const uint32_t *sy, uint32_t ns,
                          uint8_t *dup, uint32_t r_max, const HashParams &hp, uint64_t PB,
                          uint32_t ell, uint32_t *n_pinned, hipStream_t s);
+constexpr uint32_t kSsBatchTx = 1024;    // routed terms per Space-Saving micro-batch
+constexpr uint32_t kSsBatchWide = 1024;   // ... with 64-bit keys
+constexpr uint32_t kSsBatchOuter = 1024;  // ... of outer-product terms
 size_t ss_bins_smem_bytes(uint32_t nbk, uint32_t ell, bool wide_key, bool outer, uint32_t MB);
+uint32_t ss_block_threads(uint32_t nbk, uint32_t ell);
 hipError_t launch_ss_bins(const crop_ctx *c, const SsState &S, uint32_t nbk, uint64_t PB,
                           hipStream_t s);
 hipError_t launch_zero32(uint32_t *p, uint32_t n, hipStream_t s);

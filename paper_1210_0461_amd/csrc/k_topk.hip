@@ -39,10 +39,6 @@ namespace {
 
 constexpr uint8_t kUsed = 1, kPinned = 2;
 
-template <class W> __device__ inline uint32_t wbits(W w);
-template <> __device__ inline uint32_t wbits<uint32_t>(uint32_t w) { return w; }
-template <> __device__ inline uint32_t wbits<float>(float w) { return __float_as_uint(w); }
-
 template <class KeyT>
 __device__ inline uint32_t bucket_of_key(KeyT key, const HashParams &hp, uint64_t PB,
                                          bool narrow)
@@ -126,138 +122,298 @@ struct SsLds {
     uint8_t *f;
 };
 
-// One Space-Saving update of bucket lb (slots [lb*ell, lb*ell+ell)).
-template <class KeyT, class W, bool OUTER>
-__device__ inline void ss_update(const SsLds<KeyT, W, OUTER> &L, uint32_t base, uint32_t ell,
-                                 KeyT key, W w, float v)
+// LDS layout of a summaries workgroup (byte offsets), shared by the kernel
+// and the host's size computation:
+//   state   keys | counts | overestimations | [values] | flags   (nbk * ell)
+//   table   keys | weights | [values]                            (2 * MB)
+//   staged  keys | weights | [values]                            (MB)
+//   bucket positions (nbk + 1)
+struct SsLayout {
+    uint32_t sk, sc, se, sv, sf, hk, hw, hv, tk, tw, tv, pos, total;
+};
+
+__host__ __device__ inline uint32_t align8(uint32_t x) { return (x + 7u) & ~7u; }
+
+__host__ __device__ inline SsLayout ss_layout(uint32_t nbk, uint32_t ell, uint32_t ksz, bool outer,
+                                              uint32_t MB)
 {
-    int hit = -1, freeslot = -1, mn = -1;
-    W cmin = W(0);
-    for (uint32_t s = 0; s < ell; ++s) {
-        const uint8_t f = L.f[base + s];
-        if (f & kUsed) {
-            if (L.k[base + s] == key) {
-                hit = (int)s;
-                break;
-            }
-            if (!(f & kPinned)) {
-                const W c = L.c[base + s];
-                if (mn < 0 || c < cmin) {
-                    mn = (int)s;
-                    cmin = c;
-                }
-            }
-        } else if (freeslot < 0) {
-            freeslot = (int)s;
-        }
-    }
-    if (hit >= 0) {
-        L.c[base + hit] += w;
-        if (OUTER) L.v[base + hit] += v;
-    } else if (freeslot >= 0) {
-        const uint32_t s = base + freeslot;
-        L.k[s] = key;
-        L.c[s] = w;
-        L.e[s] = W(0);
-        if (OUTER) L.v[s] = v;
-        L.f[s] = kUsed;
-    } else if (mn >= 0) {
-        const uint32_t s = base + mn;
-        L.k[s] = key;
-        L.e[s] = cmin;
-        L.c[s] = cmin + w;
-        if (OUTER) L.v[s] = v;
-    }
-    // every slot pinned: the entry stays unmonitored
+    const uint32_t ns = nbk * ell, hs = 2 * MB;
+    SsLayout L;
+    uint32_t o = 0;
+    L.sk = o; o = align8(o + ns * ksz);
+    L.sc = o; o += ns * 4;
+    L.se = o; o += ns * 4;
+    L.sv = o; o += outer ? ns * 4 : 0;
+    L.hk = o = align8(o);
+    o = align8(o + hs * ksz);
+    L.hw = o; o += hs * 4;
+    L.hv = o; o += outer ? hs * 4 : 0;
+    L.tk = o = align8(o);
+    o = align8(o + MB * ksz);
+    L.tw = o; o += MB * 4;
+    L.tv = o; o += outer ? MB * 4 : 0;
+    L.pos = o; o += (nbk + 1) * 4;
+    L.sf = o; o += ns;
+    L.total = align8(o);
+    return L;
 }
 
-// Persistent workgroups, one routing bin at a time.  Global state is
-// bucket-major with ell slots per bucket; counts and overestimations are
-// stored as 32-bit words (uint32 for transactions, fp32 bits for outer
-// products).
-template <int BS, class KeyT, class W, bool OUTER, int MB>
-__global__ void __launch_bounds__(BS)
-k_ss_bins(const uint32_t *__restrict__ bin_off, const KeyT *__restrict__ keys,
-          const float *__restrict__ vals, uint32_t NB, uint32_t nbk, uint32_t ell,
-          HashParams hp, uint64_t PB, bool narrow, uint32_t *counter,
-          uint64_t *__restrict__ g_key, uint32_t *__restrict__ g_cnt,
-          uint32_t *__restrict__ g_err, float *__restrict__ g_val, uint8_t *__restrict__ g_flag)
+// Minimum over each group of G lanes, in every lane of the group: DPP within
+// rows of 16 lanes (swap neighbours, swap pairs, rotate the row by 4 and 8),
+// then lane shuffles across rows for G = 32 and 64.
+template <int G>
+__device__ inline uint32_t group_min(uint32_t v)
 {
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x124, 0xF, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x128, 0xF, 0xF, false));
+    if (G >= 32) v = min(v, (uint32_t)__shfl_xor((int)v, 16, kWave));
+    if (G >= 64) v = min(v, (uint32_t)__shfl_xor((int)v, 32, kWave));
+    return v;
+}
+
+// The group's bits of a wave ballot, slot j at bit j.
+template <int G> struct GroupMask { using T = uint32_t; };
+template <> struct GroupMask<64> { using T = uint64_t; };
+
+template <int G>
+__device__ inline typename GroupMask<G>::T group_bits(uint64_t b, uint32_t gsh)
+{
+    if constexpr (G == 64)
+        return b;
+    else
+        return (uint32_t)(b >> gsh) & (uint32_t)((1ull << G) - 1ull);
+}
+
+__device__ inline uint32_t lowest_bit(uint32_t m) { return (uint32_t)__builtin_ctz(m); }
+__device__ inline uint32_t lowest_bit(uint64_t m) { return (uint32_t)__builtin_ctzll(m); }
+
+template <class KeyT> __device__ inline KeyT empty_key();
+template <> __device__ inline uint32_t empty_key<uint32_t>() { return kEmpty32; }
+template <> __device__ inline uint64_t empty_key<uint64_t>() { return kEmpty64; }
+
+// Add weight w (and signed value v) of key to the micro-batch table
+// (linear probing, at most half full, so a free slot is always reached).
+template <class KeyT, bool OUTER>
+__device__ inline void table_add(KeyT *hk, uint32_t *hw, float *hv, uint32_t log2hs, KeyT key,
+                                 uint32_t w, float v)
+{
+    const uint32_t mask = (1u << log2hs) - 1;
+    uint32_t s = slot_of(key, log2hs);
+    for (;;) {
+        KeyT cur = hk[s];
+        if (cur == empty_key<KeyT>()) {
+            cur = atomicCAS(&hk[s], empty_key<KeyT>(), key);
+            if (cur == empty_key<KeyT>()) cur = key;
+        }
+        if (cur == key) {
+            if (OUTER) {
+                atomicAdd(reinterpret_cast<float *>(&hw[s]), __uint_as_float(w));
+                atomicAdd(&hv[s], v);
+            } else {
+                atomicAdd(&hw[s], w);
+            }
+            return;
+        }
+        s = (s + 1) & mask;
+    }
+}
+
+// Persistent workgroups take routing bins heaviest first (order[]).  The
+// bin's summaries sit in LDS, bucket-major with ell slots per bucket.  The
+// bin's routed terms are read in micro-batches of MB:
+//   1. equal keys of the micro-batch are merged into one weighted update in
+//      an LDS hash table (a wave first merges the copies of its lead key);
+//   2. the merged updates are grouped by bucket with a counting sort;
+//   3. a group of G lanes (G >= ell) applies one bucket's updates in order,
+//      lane j holding slot j in registers:
+//        hit    one ballot finds the monitored slot;
+//        free   the lowest free slot (ballot, first set bit);
+//        evict  minimum count over the unpinned slots by a G-lane butterfly,
+//               the lowest slot among equal minima by a ballot.
+// Merging and reordering a bucket's updates keeps Space-Saving's bounds
+// (Section 4), which hold for any order of weighted updates.  Counts and
+// overestimations are 32-bit words: uint32 for transactions, fp32 bits for
+// outer products (non-negative fp32 bits order like the values).
+template <int G, class KeyT, bool OUTER, int MB>
+__global__ void __launch_bounds__(256)
+k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ order,
+            const KeyT *__restrict__ keys, const float *__restrict__ vals, uint32_t NB,
+            uint32_t nbk, uint32_t ell, HashParams hp, uint64_t PB, bool narrow,
+            uint32_t *counter, uint64_t *__restrict__ g_key, uint32_t *__restrict__ g_cnt,
+            uint32_t *__restrict__ g_err, float *__restrict__ g_val, uint8_t *__restrict__ g_flag)
+{
+    static_assert(G == 16 || G == 32 || G == 64, "group width");
+    static_assert((MB & (MB - 1)) == 0, "micro-batch is a power of two");
+    constexpr uint32_t HS = 2 * MB;
+    constexpr uint32_t LOG2HS = __builtin_ctz(HS);
     extern __shared__ uint64_t smem64[];
-    const uint32_t nslot = nbk * ell;
-    // layout: keys | counts | overestimations | values | staged keys | staged
-    // values | bucket starts (nbk + 1) | flags
-    KeyT *s_k = reinterpret_cast<KeyT *>(smem64);
-    W *s_c = reinterpret_cast<W *>(s_k + nslot);
-    W *s_e = s_c + nslot;
-    float *s_v = reinterpret_cast<float *>(s_e + nslot);
-    KeyT *t_k = reinterpret_cast<KeyT *>(
-        reinterpret_cast<uint64_t *>(smem64) +
-        ((nslot * sizeof(KeyT) + 2 * nslot * 4 + (OUTER ? nslot * 4 : 0) + 7) / 8));
-    float *t_v = reinterpret_cast<float *>(t_k + MB);
-    uint32_t *s_pos = reinterpret_cast<uint32_t *>(t_v + (OUTER ? MB : 0));
-    uint8_t *s_f = reinterpret_cast<uint8_t *>(s_pos + nbk + 1);
-    const SsLds<KeyT, W, OUTER> L{s_k, s_c, s_e, s_v, s_f};
-    __shared__ uint32_t s_tmp[BS / kWave + 1];
+    char *sm = reinterpret_cast<char *>(smem64);
+    const SsLayout Lo = ss_layout(nbk, ell, sizeof(KeyT), OUTER, MB);
+    KeyT *s_k = reinterpret_cast<KeyT *>(sm + Lo.sk);
+    uint32_t *s_c = reinterpret_cast<uint32_t *>(sm + Lo.sc);
+    uint32_t *s_e = reinterpret_cast<uint32_t *>(sm + Lo.se);
+    float *s_v = reinterpret_cast<float *>(sm + Lo.sv);
+    uint8_t *s_f = reinterpret_cast<uint8_t *>(sm + Lo.sf);
+    KeyT *h_k = reinterpret_cast<KeyT *>(sm + Lo.hk);
+    uint32_t *h_w = reinterpret_cast<uint32_t *>(sm + Lo.hw);
+    float *h_v = reinterpret_cast<float *>(sm + Lo.hv);
+    KeyT *t_k = reinterpret_cast<KeyT *>(sm + Lo.tk);
+    uint32_t *t_w = reinterpret_cast<uint32_t *>(sm + Lo.tw);
+    float *t_v = reinterpret_cast<float *>(sm + Lo.tv);
+    uint32_t *s_pos = reinterpret_cast<uint32_t *>(sm + Lo.pos);
+    __shared__ uint32_t s_tmp[256 / kWave + 1];
     __shared__ uint32_t s_bin;
+
+    const uint32_t BS = blockDim.x;
+    const uint32_t nslot = nbk * ell;
+    const uint32_t lane = lane_id();
+    const uint32_t j = lane & (G - 1);  // slot held by this lane
+    const uint32_t gsh = lane & (uint32_t)(kWave - G);  // first lane of the group
+    const uint32_t group = threadIdx.x / G, n_groups = BS / G;
+    const bool real = j < ell;
 
     for (;;) {
         if (threadIdx.x == 0) s_bin = atomicAdd(counter, 1u);
         __syncthreads();
-        const uint32_t b = s_bin;
-        if (b >= NB) break;
+        const uint32_t q = s_bin;
+        if (q >= NB) break;
+        const uint32_t b = order[q];
         const uint64_t g0 = (uint64_t)b * nslot;
         for (uint32_t s = threadIdx.x; s < nslot; s += BS) {
-            s_k[s] = (KeyT)g_key[g0 + s];
-            s_c[s] = std::is_same<W, float>::value ? (W)__uint_as_float(g_cnt[g0 + s])
-                                                   : (W)g_cnt[g0 + s];
-            s_e[s] = std::is_same<W, float>::value ? (W)__uint_as_float(g_err[g0 + s])
-                                                   : (W)g_err[g0 + s];
+            const uint64_t g = g_key[g0 + s];
+            // seeded slots carry a 64-bit pair key; narrow runs compare packed keys
+            s_k[s] = narrow ? (KeyT)(((uint32_t)(g >> 32) << 16) | (uint32_t)(g & 0xFFFFu))
+                            : (KeyT)g;
+            s_c[s] = g_cnt[g0 + s];
+            s_e[s] = g_err[g0 + s];
             if (OUTER) s_v[s] = g_val[g0 + s];
             s_f[s] = g_flag[g0 + s];
         }
-        // seeded slots carry a 64-bit pair key; narrow runs compare packed keys
-        if (narrow) {
-            for (uint32_t s = threadIdx.x; s < nslot; s += BS) {
-                const uint64_t g = g_key[g0 + s];
-                s_k[s] = (KeyT)(((uint32_t)(g >> 32) << 16) | (uint32_t)(g & 0xFFFFu));
-            }
-        }
-        __syncthreads();
         const uint32_t k0 = bin_off[b], k1 = bin_off[b + 1];
         const uint64_t bucket0 = (uint64_t)b * nbk;
         for (uint32_t base = k0; base < k1; base += MB) {
             const uint32_t n = min((uint32_t)MB, k1 - base);
+            for (uint32_t i = threadIdx.x; i < HS; i += BS) {
+                h_k[i] = empty_key<KeyT>();
+                h_w[i] = 0u;
+                if (OUTER) h_v[i] = 0.0f;
+            }
             for (uint32_t i = threadIdx.x; i <= nbk; i += BS) s_pos[i] = 0;
             __syncthreads();
-            // count per bucket
-            for (uint32_t i = threadIdx.x; i < n; i += BS) {
-                const uint32_t lb =
-                    (uint32_t)(bucket_of_key(keys[base + i], hp, PB, narrow) - bucket0);
-                atomicAdd(&s_pos[lb], 1u);
+            // 1. merge equal keys
+            const uint32_t n_all = (n + BS - 1) / BS * BS;
+            for (uint32_t i = threadIdx.x; i < n_all; i += BS) {
+                const bool valid = i < n;
+                const KeyT key = valid ? keys[base + i] : empty_key<KeyT>();
+                if (OUTER) {
+                    if (valid) {
+                        const float v = vals[base + i];
+                        table_add<KeyT, true>(h_k, h_w, h_v, LOG2HS, key,
+                                              __float_as_uint(fabsf(v)), v);
+                    }
+                } else {
+                    const uint64_t vm = __ballot(valid);
+                    if (!vm) continue;
+                    const KeyT lead = (KeyT)__shfl(key, __ffsll((long long)vm) - 1, kWave);
+                    const bool same = valid && key == lead;
+                    const uint64_t m = __ballot(same);
+                    if (same) {
+                        if (lane == (uint32_t)__ffsll((long long)m) - 1)
+                            table_add<KeyT, false>(h_k, h_w, h_v, LOG2HS, key,
+                                                   (uint32_t)__popcll(m), 0.0f);
+                    } else if (valid) {
+                        table_add<KeyT, false>(h_k, h_w, h_v, LOG2HS, key, 1u, 0.0f);
+                    }
+                }
             }
             __syncthreads();
-            lds_exclusive_scan<BS>(s_pos, nbk, s_tmp);
-            // stage grouped by bucket (s_pos becomes each bucket's end)
-            for (uint32_t i = threadIdx.x; i < n; i += BS) {
-                const KeyT key = keys[base + i];
+            // 2. group the merged updates by bucket
+            for (uint32_t i = threadIdx.x; i < HS; i += BS) {
+                const KeyT key = h_k[i];
+                if (key == empty_key<KeyT>()) continue;
+                atomicAdd(&s_pos[(uint32_t)(bucket_of_key(key, hp, PB, narrow) - bucket0)], 1u);
+            }
+            __syncthreads();
+            lds_exclusive_scan_rt(s_pos, nbk, s_tmp);
+            for (uint32_t i = threadIdx.x; i < HS; i += BS) {
+                const KeyT key = h_k[i];
+                if (key == empty_key<KeyT>()) continue;
                 const uint32_t lb = (uint32_t)(bucket_of_key(key, hp, PB, narrow) - bucket0);
-                const uint32_t p = atomicAdd(&s_pos[lb], 1u);
+                const uint32_t p = atomicAdd(&s_pos[lb], 1u);  // becomes the bucket's end
                 t_k[p] = key;
-                if (OUTER) t_v[p] = vals[base + i];
+                t_w[p] = h_w[i];
+                if (OUTER) t_v[p] = h_v[i];
             }
             __syncthreads();
-            // one lane per bucket: its run is [end of previous bucket, end)
-            for (uint32_t lb = threadIdx.x; lb < nbk; lb += BS) {
+            // 3. one group per bucket applies its updates
+            for (uint32_t lb = group; lb < nbk; lb += n_groups) {
                 const uint32_t e1 = s_pos[lb];
                 const uint32_t e0 = lb ? s_pos[lb - 1] : 0;
+                if (e0 == e1) continue;  // uniform over the group
+                const uint32_t sidx = lb * ell + j;
+                KeyT k = real ? s_k[sidx] : (KeyT)0;
+                uint32_t c = real ? s_c[sidx] : 0u;
+                uint32_t e = real ? s_e[sidx] : 0u;
+                float v = (OUTER && real) ? s_v[sidx] : 0.0f;
+                uint8_t f = real ? s_f[sidx] : (uint8_t)0;
+                KeyT nk = t_k[e0];
+                uint32_t nw = t_w[e0];
+                float nv = OUTER ? t_v[e0] : 0.0f;
                 for (uint32_t p = e0; p < e1; ++p) {
-                    if (OUTER) {
-                        const float v = t_v[p];
-                        ss_update<KeyT, W, OUTER>(L, lb * ell, ell, t_k[p], (W)fabsf(v), v);
-                    } else {
-                        ss_update<KeyT, W, OUTER>(L, lb * ell, ell, t_k[p], (W)1, 0.0f);
+                    const KeyT key = nk;
+                    const uint32_t w = nw;
+                    const float val = nv;
+                    if (p + 1 < e1) {  // prefetch the next update
+                        nk = t_k[p + 1];
+                        nw = t_w[p + 1];
+                        if (OUTER) nv = t_v[p + 1];
                     }
+                    const bool used = (f & kUsed) != 0;
+                    const bool hit = real && used && k == key;
+                    const auto hg = group_bits<G>(__builtin_amdgcn_ballot_w64(hit), gsh);
+                    const auto fg = group_bits<G>(__builtin_amdgcn_ballot_w64(real && !used), gsh);
+                    // hit: the monitored slot takes the weight
+                    if (hit) {
+                        if (OUTER) {
+                            c = __float_as_uint(__uint_as_float(c) + __uint_as_float(w));
+                            v += val;
+                        } else {
+                            c += w;
+                        }
+                    }
+                    // free: the lowest free slot takes the entry
+                    if (!hg && fg && j == lowest_bit(fg)) {
+                        k = key;
+                        c = w;
+                        e = 0u;
+                        v = val;
+                        f = kUsed;
+                    }
+                    // evict: the lowest unpinned slot of minimum count
+                    const bool need = !hg && !fg;  // uniform over the group
+                    if (__builtin_amdgcn_ballot_w64(need)) {
+                        const bool cand = need && real && !(f & kPinned);
+                        const uint32_t mine = cand ? c : 0xFFFFFFFFu;
+                        const uint32_t mn = group_min<G>(mine);
+                        const auto mg =
+                            group_bits<G>(__builtin_amdgcn_ballot_w64(cand && mine == mn), gsh);
+                        if (mg && j == lowest_bit(mg)) {
+                            e = c;
+                            c = OUTER ? __float_as_uint(__uint_as_float(c) + __uint_as_float(w))
+                                      : c + w;
+                            k = key;
+                            v = val;
+                        }
+                    }
+                }
+                if (real) {
+                    s_k[sidx] = k;
+                    s_c[sidx] = c;
+                    s_e[sidx] = e;
+                    if (OUTER) s_v[sidx] = v;
+                    s_f[sidx] = f;
                 }
             }
             __syncthreads();
@@ -271,8 +427,8 @@ k_ss_bins(const uint32_t *__restrict__ bin_off, const KeyT *__restrict__ keys,
                 g = (uint64_t)s_k[s];
             }
             g_key[g0 + s] = (s_f[s] & kUsed) ? g : 0;
-            g_cnt[g0 + s] = wbits<W>(s_c[s]);
-            g_err[g0 + s] = wbits<W>(s_e[s]);
+            g_cnt[g0 + s] = s_c[s];
+            g_err[g0 + s] = s_e[s];
             if (OUTER) g_val[g0 + s] = s_v[s];
             g_flag[g0 + s] = s_f[s];
         }
@@ -289,10 +445,29 @@ struct Comp {
     uint32_t w[3];
 };
 
-__device__ inline Comp comp_of(const uint64_t *key, const uint32_t *cnt, uint64_t i)
+// Counts are shifted left by the leading zeros of the largest count (st[7]),
+// so the first radix digits separate the slots.
+__device__ inline uint32_t count_shift(const uint32_t *st)
+{
+    return st[7] ? (uint32_t)__clz(st[7]) : 0u;
+}
+
+__device__ inline Comp comp_of(const uint64_t *key, const uint32_t *cnt, uint64_t i, uint32_t sh)
 {
     const uint64_t k = key[i];
-    return Comp{{cnt[i], ~(uint32_t)(k >> 32), ~(uint32_t)k}};
+    return Comp{{cnt[i] << sh, ~(uint32_t)(k >> 32), ~(uint32_t)k}};
+}
+
+__global__ void __launch_bounds__(256)
+k_topk_max(const uint32_t *__restrict__ cnt, const uint8_t *__restrict__ flag, uint64_t n,
+           uint32_t *__restrict__ st)
+{
+    uint32_t mx = 0;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * 256)
+        if (flag[i] & kUsed) mx = max(mx, cnt[i]);
+    for (int d = 32; d >= 1; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, kWave));
+    if (lane_id() == 0 && mx) atomicMax(&st[7], mx);
 }
 
 __device__ inline uint32_t digit_of(const Comp &c, uint32_t pass)
@@ -314,7 +489,7 @@ __device__ inline bool prefix_match(const Comp &c, const uint32_t *prefix, uint3
 
 // Selection state in device memory:
 //   st[0..2] prefix words, st[3] remaining rank, st[4] candidate count,
-//   st[5] selected count, st[6] used slots, hist[256].
+//   st[5] selected count, st[6] used slots, st[7] largest count, hist[256].
 __global__ void __launch_bounds__(256)
 k_topk_hist(const uint64_t *__restrict__ key, const uint32_t *__restrict__ cnt,
             const uint8_t *__restrict__ flag, uint64_t n, const uint32_t *__restrict__ cand,
@@ -324,11 +499,12 @@ k_topk_hist(const uint64_t *__restrict__ key, const uint32_t *__restrict__ cnt,
     h[threadIdx.x] = 0;
     __syncthreads();
     const uint64_t m = cand ? st[4] : n;
+    const uint32_t sh = count_shift(st);
     for (uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x; t < m;
          t += (uint64_t)gridDim.x * 256) {
         const uint64_t i = cand ? cand[t] : t;
         if (!(flag[i] & kUsed)) continue;
-        const Comp c = comp_of(key, cnt, i);
+        const Comp c = comp_of(key, cnt, i, sh);
         if (!prefix_match(c, st, pass)) continue;
         atomicAdd(&h[digit_of(c, pass)], 1u);
     }
@@ -384,10 +560,11 @@ k_topk_compact(const uint64_t *__restrict__ key, const uint32_t *__restrict__ cn
                const uint8_t *__restrict__ flag, uint64_t n, uint32_t *__restrict__ st,
                uint32_t *__restrict__ cand)
 {
+    const uint32_t sh = count_shift(st);
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * 256) {
         if (!(flag[i] & kUsed)) continue;
-        if ((cnt[i] >> 16) < (st[0] >> 16)) continue;
+        if (((cnt[i] << sh) >> 16) < (st[0] >> 16)) continue;
         cand[atomicAdd(&st[4], 1u)] = (uint32_t)i;
     }
 }
@@ -399,9 +576,10 @@ k_topk_collect(const uint64_t *__restrict__ key, const uint32_t *__restrict__ cn
                uint32_t *__restrict__ sel)
 {
     const uint32_t m = st[4];
+    const uint32_t sh = count_shift(st);
     for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < m; t += gridDim.x * 256) {
         const uint32_t i = cand[t];
-        if (comp_ge(comp_of(key, cnt, i), st)) sel[atomicAdd(&st[5], 1u)] = i;
+        if (comp_ge(comp_of(key, cnt, i, sh), st)) sel[atomicAdd(&st[5], 1u)] = i;
     }
 }
 
@@ -416,13 +594,14 @@ k_topk_rank(const uint64_t *__restrict__ key, const uint32_t *__restrict__ cnt,
 {
     __shared__ Comp tile[256];
     const uint32_t m = st[5];
+    const uint32_t sh = count_shift(st);
     const uint32_t t = blockIdx.x * 256 + threadIdx.x;
     Comp me{{0, 0, 0}};
-    if (t < m) me = comp_of(key, cnt, sel[t]);
+    if (t < m) me = comp_of(key, cnt, sel[t], sh);
     uint32_t rank = 0;
     for (uint32_t b = 0; b < m; b += 256) {
         __syncthreads();
-        if (b + threadIdx.x < m) tile[threadIdx.x] = comp_of(key, cnt, sel[b + threadIdx.x]);
+        if (b + threadIdx.x < m) tile[threadIdx.x] = comp_of(key, cnt, sel[b + threadIdx.x], sh);
         __syncthreads();
         const uint32_t lim = min(256u, m - b);
         if (t < m)
@@ -484,45 +663,62 @@ hipError_t launch_ss_pin(const SsState &S, const uint32_t *sx, const uint32_t *s
 
 size_t ss_bins_smem_bytes(uint32_t nbk, uint32_t ell, bool wide_key, bool outer, uint32_t MB)
 {
-    const size_t nslot = (size_t)nbk * ell;
-    const size_t ksz = wide_key ? 8 : 4;
-    size_t head = nslot * ksz + 2 * nslot * 4 + (outer ? nslot * 4 : 0);
-    head = (head + 7) / 8 * 8;
-    return head + MB * ksz + (outer ? MB * 4 : 0) + (nbk + 1) * 4 + nslot + 16;
+    return ss_layout(nbk, ell, wide_key ? 8 : 4, outer, MB).total;
+}
+
+uint32_t ss_group_width(uint32_t ell) { return ell <= 16 ? 16u : ell <= 32 ? 32u : 64u; }
+
+uint32_t ss_block_threads(uint32_t nbk, uint32_t ell)
+{
+    const uint32_t t = nbk * ss_group_width(ell);
+    return t <= 64 ? 64u : t >= 256 ? 256u : (t + 63) / 64 * 64;
+}
+
+template <int G>
+static void launch_ss_g(const crop_ctx *c, const SsState &S, uint32_t nbk, uint64_t PB,
+                        uint32_t grid, uint32_t bs, hipStream_t s)
+{
+    const RoutePlan &pl = c->plan;
+    const uint32_t ell = c->ss_ell;
+    if (c->in.mode == Mode::Outer) {
+        constexpr int MB = kSsBatchOuter;
+        const size_t sm = ss_bins_smem_bytes(nbk, ell, true, true, MB);
+        hipLaunchKernelGGL((k_ss_groups<G, uint64_t, true, MB>), dim3(grid), dim3(bs), sm,
+                           s, c->bin_off.as<uint32_t>(), c->bin_order.as<uint32_t>(),
+                           c->keys.as<uint64_t>(), c->vals.as<float>(), pl.NB, nbk, ell, c->hp, PB, false,
+                           c->counter.as<uint32_t>(), S.key, S.cnt, S.err, S.val, S.flag);
+    } else if (c->in.wide_keys) {
+        constexpr int MB = kSsBatchWide;
+        const size_t sm = ss_bins_smem_bytes(nbk, ell, true, false, MB);
+        hipLaunchKernelGGL((k_ss_groups<G, uint64_t, false, MB>), dim3(grid), dim3(bs),
+                           sm, s, c->bin_off.as<uint32_t>(), c->bin_order.as<uint32_t>(),
+                           c->keys.as<uint64_t>(), nullptr,
+                           pl.NB, nbk, ell, c->hp, PB, false, c->counter.as<uint32_t>(), S.key,
+                           S.cnt, S.err, S.val, S.flag);
+    } else {
+        constexpr int MB = kSsBatchTx;
+        const size_t sm = ss_bins_smem_bytes(nbk, ell, false, false, MB);
+        hipLaunchKernelGGL((k_ss_groups<G, uint32_t, false, MB>), dim3(grid), dim3(bs),
+                           sm, s, c->bin_off.as<uint32_t>(), c->bin_order.as<uint32_t>(),
+                           c->keys.as<uint32_t>(), nullptr,
+                           pl.NB, nbk, ell, c->hp, PB, true, c->counter.as<uint32_t>(), S.key,
+                           S.cnt, S.err, S.val, S.flag);
+    }
 }
 
 hipError_t launch_ss_bins(const crop_ctx *c, const SsState &S, uint32_t nbk, uint64_t PB,
                           hipStream_t s)
 {
-    const RoutePlan &pl = c->plan;
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     const uint32_t ell = c->ss_ell;
-    const bool outer = c->in.mode == Mode::Outer;
-    const bool wide = c->in.wide_keys;
-    const uint32_t grid = std::min<uint32_t>(pl.NB, 4u * (uint32_t)cus);
-    if (outer) {
-        constexpr int MB = 1024;
-        size_t sm = ss_bins_smem_bytes(nbk, ell, true, true, MB);
-        hipLaunchKernelGGL((k_ss_bins<256, uint64_t, float, true, MB>), dim3(grid), dim3(256), sm,
-                           s, c->bin_off.as<uint32_t>(), c->keys.as<uint64_t>(),
-                           c->vals.as<float>(), pl.NB, nbk, ell, c->hp, PB, false,
-                           c->counter.as<uint32_t>(), S.key, S.cnt, S.err, S.val, S.flag);
-    } else if (wide) {
-        constexpr int MB = 2048;
-        size_t sm = ss_bins_smem_bytes(nbk, ell, true, false, MB);
-        hipLaunchKernelGGL((k_ss_bins<256, uint64_t, uint32_t, false, MB>), dim3(grid), dim3(256),
-                           sm, s, c->bin_off.as<uint32_t>(), c->keys.as<uint64_t>(), nullptr,
-                           pl.NB, nbk, ell, c->hp, PB, false, c->counter.as<uint32_t>(), S.key,
-                           S.cnt, S.err, S.val, S.flag);
-    } else {
-        constexpr int MB = 2048;
-        size_t sm = ss_bins_smem_bytes(nbk, ell, false, false, MB);
-        hipLaunchKernelGGL((k_ss_bins<256, uint32_t, uint32_t, false, MB>), dim3(grid), dim3(256),
-                           sm, s, c->bin_off.as<uint32_t>(), c->keys.as<uint32_t>(), nullptr,
-                           pl.NB, nbk, ell, c->hp, PB, true, c->counter.as<uint32_t>(), S.key,
-                           S.cnt, S.err, S.val, S.flag);
+    const uint32_t bs = ss_block_threads(nbk, ell);
+    const uint32_t grid = std::min<uint32_t>(c->plan.NB, (256 / bs * 2) * (uint32_t)cus);
+    switch (ss_group_width(ell)) {
+    case 16: launch_ss_g<16>(c, S, nbk, PB, grid, bs, s); break;
+    case 32: launch_ss_g<32>(c, S, nbk, PB, grid, bs, s); break;
+    default: launch_ss_g<64>(c, S, nbk, PB, grid, bs, s); break;
     }
     return hipGetLastError();
 }
@@ -534,6 +730,7 @@ hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, uint32_t *st, u
                        double *ol, double *ov, hipStream_t s)
 {
     const uint32_t g = grid_for(S.nslots);
+    hipLaunchKernelGGL(k_topk_max, dim3(g), dim3(256), 0, s, S.cnt, S.flag, S.nslots, st);
     for (uint32_t pass = 0; pass < 12; ++pass) {
         hipLaunchKernelGGL(k_topk_hist, dim3(g), dim3(256), 0, s, S.key, S.cnt, S.flag, S.nslots,
                            pass < 2 ? nullptr : cand, st, pass, hist);
