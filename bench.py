@@ -227,9 +227,12 @@ def run_learned(args):
             crop.crop_set_partitions(ctx, Pr)
             crop.crop_set_summary(ctx, C, ell)
             row = {"P": Pr, "counters_per_partition": C, "total_counters": Pr * C}
-            for mode in ("plain", "seeded"):
+            for mode, rank in (("plain", 0), ("seeded", 0), ("plain_lower", 1),
+                               ("seeded_lower", 1)):
+                crop.crop_set_topk_rank(ctx, rank)
+
                 def once():
-                    if mode == "plain":
+                    if mode.startswith("plain"):
                         crop.crop_run_topk(ctx, K)
                     else:
                         crop.crop_run_topk_seeded(ctx, K, sx, sy, args.r_max)
@@ -251,6 +254,7 @@ def run_learned(args):
                 sel = np.isin(sk, true_top) & s["used"]
                 row[mode] = {"recall_at_1000": rec,
                              "max_count_error": float((up - exact).max()) if up.size else 0.0,
+                             "max_lower_bound_gap": float((exact - lo).max()) if lo.size else 0.0,
                              "true_top_monitored": int(held.sum()),
                              "true_top_with_error": int((s["err"][sel] > 0).sum()),
                              "pinned": int(s["pinned"].sum()),

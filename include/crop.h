@@ -102,6 +102,11 @@ crop_status crop_set_seed(crop_ctx *ctx, uint64_t seed);
  * ell in [1, 64]; counters_per_partition a multiple of ell. */
 crop_status crop_set_summary(crop_ctx *ctx, uint32_t counters_per_partition,
                              uint32_t counters_per_bucket);
+/* Order of the top-K report: by upper bound (the Space-Saving count, the
+ * default) or by lower bound (count - overestimation, the guaranteed part of
+ * the count; Section 4), ties by smaller key either way. */
+typedef enum { CROP_RANK_UPPER = 0, CROP_RANK_LOWER = 1 } crop_rank;
+crop_status crop_set_topk_rank(crop_ctx *ctx, int rank);
 /* Borrow a HIP stream (hipStream_t) for all later work; NULL is HIP's null
  * stream.  The stream must outlive its use.  A new context works on a
  * non-blocking stream of its own; crop_use_own_stream returns to it. */
@@ -139,7 +144,8 @@ crop_status crop_load_outer(crop_ctx *ctx, const uint32_t *a_off, const uint32_t
 crop_status crop_run_exact(crop_ctx *ctx);
 
 /* Space-Saving summaries per bucket, then the top-K monitored entries over
- * all partitions by (upper bound descending, key ascending).  Transactions
+ * all partitions by (upper bound descending, key ascending), or by lower
+ * bound (crop_set_topk_rank).  Transactions
  * use weight 1 per term; outer products use |a_k(i) b_k(j)| and keep the
  * signed sum of an entry's terms since its admission. */
 crop_status crop_run_topk(crop_ctx *ctx, uint32_t K);

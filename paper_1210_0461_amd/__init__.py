@@ -76,6 +76,7 @@ _SIGS = {
     "crop_set_summary": ([_vp, _u32, _u32], _i32),
     "crop_set_stream": ([_vp, _vp], _i32),
     "crop_use_own_stream": ([_vp], _i32),
+    "crop_set_topk_rank": ([_vp, _i32], _i32),
     "crop_set_tuning": ([_vp, ctypes.POINTER(crop_tune)], _i32),
     "crop_get_tuning": ([_vp, ctypes.POINTER(crop_tune)], _i32),
     "crop_load_transactions": ([_vp, _vp, _u64, _vp, _u64, _u32, _i32, _i32], _i32),
@@ -209,6 +210,14 @@ def crop_set_stream(ctx, stream) -> None:
     if stream is not None and hasattr(stream, "cuda_stream"):
         stream = stream.cuda_stream
     _check(ctx, _lib.crop_set_stream(ctx, stream or None))
+
+
+CROP_RANK_UPPER = 0
+CROP_RANK_LOWER = 1
+
+
+def crop_set_topk_rank(ctx, rank: int) -> None:
+    _check(ctx, _lib.crop_set_topk_rank(ctx, rank))
 
 
 def crop_use_own_stream(ctx) -> None:

@@ -514,6 +514,16 @@ crop_status crop_set_summary(crop_ctx *ctx, uint32_t counters_per_partition,
     return CROP_OK;
 }
 
+crop_status crop_set_topk_rank(crop_ctx *ctx, int rank)
+{
+    if (!ctx) return CROP_E_ARG;
+    if (rank != CROP_RANK_UPPER && rank != CROP_RANK_LOWER)
+        return fail(ctx, CROP_E_ARG, "rank must be CROP_RANK_UPPER or CROP_RANK_LOWER");
+    ctx->topk_rank = rank;
+    ctx->result = Result::None;
+    return CROP_OK;
+}
+
 crop_status crop_set_stream(crop_ctx *ctx, void *hip_stream)
 {
     if (!ctx) return CROP_E_ARG;
@@ -783,7 +793,7 @@ static crop_status run_topk_impl(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
     STAGE("scatter");
     CK(launch_ss_bins(ctx, ctx->ss, nbk, PB, s));
     STAGE("summaries");
-    CK(launch_topk(ctx->ss, K, outer, tv.st, tv.hist, tv.cand, tv.sel, tv.oi, tv.oj, tv.ou,
+    CK(launch_topk(ctx->ss, K, outer, ctx->topk_rank == CROP_RANK_LOWER, tv.st, tv.hist, tv.cand, tv.sel, tv.oi, tv.oj, tv.ou,
                    tv.ol, tv.ov, s));
     STAGE("topk");
     st = run_end(ctx);

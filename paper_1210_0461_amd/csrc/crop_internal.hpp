@@ -121,6 +121,7 @@ struct crop_ctx {
     crop::HashParams hp{};
     uint32_t ss_counters = 1u << 14;  // counters per partition
     uint32_t ss_ell = 16;             // counters per bucket
+    int topk_rank = CROP_RANK_UPPER;  // top-K order
     crop_tune tune{};                 // user request (0 = auto)
     crop::RoutePlan plan{};
 
@@ -186,7 +187,8 @@ uint32_t ss_block_threads(uint32_t nbk, uint32_t ell);
 hipError_t launch_ss_bins(const crop_ctx *c, const SsState &S, uint32_t nbk, uint64_t PB,
                           hipStream_t s);
 hipError_t launch_zero32(uint32_t *p, uint32_t n, hipStream_t s);
-hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, uint32_t *st, uint32_t *hist,
+hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, bool by_lower, uint32_t *st,
+                       uint32_t *hist,
                        uint32_t *cand, uint32_t *sel, uint32_t *oi, uint32_t *oj, double *ou,
                        double *ol, double *ov, hipStream_t s);
 

@@ -452,20 +452,35 @@ __device__ inline uint32_t count_shift(const uint32_t *st)
     return st[7] ? (uint32_t)__clz(st[7]) : 0u;
 }
 
-__device__ inline Comp comp_of(const uint64_t *key, const uint32_t *cnt, uint64_t i, uint32_t sh)
+// The ranked value of a slot as an order-preserving 32-bit word: the count
+// (upper bound) or, when ranking by guaranteed count, count - overestimation
+// (lower bound; fp32 difference for outer products, never negative).
+struct RankBy {
+    const uint32_t *cnt, *err;
+    bool lower, fp;
+    __device__ uint32_t operator()(uint64_t i) const
+    {
+        const uint32_t c = cnt[i];
+        if (!lower) return c;
+        const uint32_t e = err[i];
+        if (!fp) return c - e;
+        return __float_as_uint(fmaxf(__uint_as_float(c) - __uint_as_float(e), 0.0f));
+    }
+};
+
+__device__ inline Comp comp_of(const uint64_t *key, const RankBy &rv, uint64_t i, uint32_t sh)
 {
     const uint64_t k = key[i];
-    return Comp{{cnt[i] << sh, ~(uint32_t)(k >> 32), ~(uint32_t)k}};
+    return Comp{{rv(i) << sh, ~(uint32_t)(k >> 32), ~(uint32_t)k}};
 }
 
 __global__ void __launch_bounds__(256)
-k_topk_max(const uint32_t *__restrict__ cnt, const uint8_t *__restrict__ flag, uint64_t n,
-           uint32_t *__restrict__ st)
+k_topk_max(RankBy rv, const uint8_t *__restrict__ flag, uint64_t n, uint32_t *__restrict__ st)
 {
     uint32_t mx = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * 256)
-        if (flag[i] & kUsed) mx = max(mx, cnt[i]);
+        if (flag[i] & kUsed) mx = max(mx, rv(i));
     for (int d = 32; d >= 1; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, kWave));
     if (lane_id() == 0 && mx) atomicMax(&st[7], mx);
 }
@@ -491,7 +506,7 @@ __device__ inline bool prefix_match(const Comp &c, const uint32_t *prefix, uint3
 //   st[0..2] prefix words, st[3] remaining rank, st[4] candidate count,
 //   st[5] selected count, st[6] used slots, st[7] largest count, hist[256].
 __global__ void __launch_bounds__(256)
-k_topk_hist(const uint64_t *__restrict__ key, const uint32_t *__restrict__ cnt,
+k_topk_hist(const uint64_t *__restrict__ key, RankBy rv,
             const uint8_t *__restrict__ flag, uint64_t n, const uint32_t *__restrict__ cand,
             const uint32_t *__restrict__ st, uint32_t pass, uint32_t *__restrict__ hist)
 {
@@ -504,7 +519,7 @@ k_topk_hist(const uint64_t *__restrict__ key, const uint32_t *__restrict__ cnt,
          t += (uint64_t)gridDim.x * 256) {
         const uint64_t i = cand ? cand[t] : t;
         if (!(flag[i] & kUsed)) continue;
-        const Comp c = comp_of(key, cnt, i, sh);
+        const Comp c = comp_of(key, rv, i, sh);
         if (!prefix_match(c, st, pass)) continue;
         atomicAdd(&h[digit_of(c, pass)], 1u);
     }
@@ -556,22 +571,21 @@ __device__ inline bool comp_gt(const Comp &a, const Comp &b)
 
 // Keep the slots whose top 16 bits of count reach the selected prefix.
 __global__ void __launch_bounds__(256)
-k_topk_compact(const uint64_t *__restrict__ key, const uint32_t *__restrict__ cnt,
-               const uint8_t *__restrict__ flag, uint64_t n, uint32_t *__restrict__ st,
-               uint32_t *__restrict__ cand)
+k_topk_compact(RankBy rv, const uint8_t *__restrict__ flag, uint64_t n,
+               uint32_t *__restrict__ st, uint32_t *__restrict__ cand)
 {
     const uint32_t sh = count_shift(st);
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * 256) {
         if (!(flag[i] & kUsed)) continue;
-        if (((cnt[i] << sh) >> 16) < (st[0] >> 16)) continue;
+        if (((rv(i) << sh) >> 16) < (st[0] >> 16)) continue;
         cand[atomicAdd(&st[4], 1u)] = (uint32_t)i;
     }
 }
 
 // Collect the selected slots (composite >= threshold): exactly st[3]-ranked.
 __global__ void __launch_bounds__(256)
-k_topk_collect(const uint64_t *__restrict__ key, const uint32_t *__restrict__ cnt,
+k_topk_collect(const uint64_t *__restrict__ key, RankBy rv,
                const uint32_t *__restrict__ cand, uint32_t *__restrict__ st,
                uint32_t *__restrict__ sel)
 {
@@ -579,14 +593,14 @@ k_topk_collect(const uint64_t *__restrict__ key, const uint32_t *__restrict__ cn
     const uint32_t sh = count_shift(st);
     for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < m; t += gridDim.x * 256) {
         const uint32_t i = cand[t];
-        if (comp_ge(comp_of(key, cnt, i, sh), st)) sel[atomicAdd(&st[5], 1u)] = i;
+        if (comp_ge(comp_of(key, rv, i, sh), st)) sel[atomicAdd(&st[5], 1u)] = i;
     }
 }
 
 // rank of every selected slot = number of selected slots ranking above it;
 // writes the outputs in rank order.
 __global__ void __launch_bounds__(256)
-k_topk_rank(const uint64_t *__restrict__ key, const uint32_t *__restrict__ cnt,
+k_topk_rank(const uint64_t *__restrict__ key, RankBy rv, const uint32_t *__restrict__ cnt,
             const uint32_t *__restrict__ err, const float *__restrict__ val, bool outer,
             const uint32_t *__restrict__ sel, const uint32_t *__restrict__ st,
             uint32_t *__restrict__ oi, uint32_t *__restrict__ oj, double *__restrict__ ou,
@@ -597,11 +611,11 @@ k_topk_rank(const uint64_t *__restrict__ key, const uint32_t *__restrict__ cnt,
     const uint32_t sh = count_shift(st);
     const uint32_t t = blockIdx.x * 256 + threadIdx.x;
     Comp me{{0, 0, 0}};
-    if (t < m) me = comp_of(key, cnt, sel[t], sh);
+    if (t < m) me = comp_of(key, rv, sel[t], sh);
     uint32_t rank = 0;
     for (uint32_t b = 0; b < m; b += 256) {
         __syncthreads();
-        if (b + threadIdx.x < m) tile[threadIdx.x] = comp_of(key, cnt, sel[b + threadIdx.x], sh);
+        if (b + threadIdx.x < m) tile[threadIdx.x] = comp_of(key, rv, sel[b + threadIdx.x], sh);
         __syncthreads();
         const uint32_t lim = min(256u, m - b);
         if (t < m)
@@ -725,24 +739,25 @@ hipError_t launch_ss_bins(const crop_ctx *c, const SsState &S, uint32_t nbk, uin
 
 // Top-K over the summary slots; st (8 words) and hist (256 words) must be
 // zero on entry; cand and sel hold up to nslots indices.
-hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, uint32_t *st, uint32_t *hist,
-                       uint32_t *cand, uint32_t *sel, uint32_t *oi, uint32_t *oj, double *ou,
-                       double *ol, double *ov, hipStream_t s)
+hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, bool by_lower, uint32_t *st,
+                       uint32_t *hist, uint32_t *cand, uint32_t *sel, uint32_t *oi, uint32_t *oj,
+                       double *ou, double *ol, double *ov, hipStream_t s)
 {
     const uint32_t g = grid_for(S.nslots);
-    hipLaunchKernelGGL(k_topk_max, dim3(g), dim3(256), 0, s, S.cnt, S.flag, S.nslots, st);
+    const RankBy rv{S.cnt, S.err, by_lower, outer};
+    hipLaunchKernelGGL(k_topk_max, dim3(g), dim3(256), 0, s, rv, S.flag, S.nslots, st);
     for (uint32_t pass = 0; pass < 12; ++pass) {
-        hipLaunchKernelGGL(k_topk_hist, dim3(g), dim3(256), 0, s, S.key, S.cnt, S.flag, S.nslots,
+        hipLaunchKernelGGL(k_topk_hist, dim3(g), dim3(256), 0, s, S.key, rv, S.flag, S.nslots,
                            pass < 2 ? nullptr : cand, st, pass, hist);
         hipLaunchKernelGGL(k_topk_pick, dim3(1), dim3(64), 0, s, st, hist, pass, K);
         if (pass == 1)
-            hipLaunchKernelGGL(k_topk_compact, dim3(g), dim3(256), 0, s, S.key, S.cnt, S.flag,
-                               S.nslots, st, cand);
+            hipLaunchKernelGGL(k_topk_compact, dim3(g), dim3(256), 0, s, rv, S.flag, S.nslots, st,
+                               cand);
     }
-    hipLaunchKernelGGL(k_topk_collect, dim3(g), dim3(256), 0, s, S.key, S.cnt, cand, st, sel);
+    hipLaunchKernelGGL(k_topk_collect, dim3(g), dim3(256), 0, s, S.key, rv, cand, st, sel);
     const uint32_t gr = (K + 255) / 256 ? (K + 255) / 256 : 1;
-    hipLaunchKernelGGL(k_topk_rank, dim3(gr), dim3(256), 0, s, S.key, S.cnt, S.err, S.val, outer,
-                       sel, st, oi, oj, ou, ol, ov);
+    hipLaunchKernelGGL(k_topk_rank, dim3(gr), dim3(256), 0, s, S.key, rv, S.cnt, S.err, S.val,
+                       outer, sel, st, oi, oj, ou, ol, ov);
     return hipGetLastError();
 }
 

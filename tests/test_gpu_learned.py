@@ -362,3 +362,58 @@ def test_mlp_train_rejects_bad_index(crop, ctx, torch):
                                torch.from_numpy(y).cuda()[:0])
     finally:
         crop.crop_mlp_destroy(mlp)
+
+
+def test_seeding_gain_over_plain_summary(crop, ctx, torch):
+    """What the trained network adds at equal memory: six training streams
+    and one held-out stream of 200,000 transactions (like the 1M-transaction
+    workload, other seeds), one partition of 4,096 counters (ell = 16) and
+    the top 200 by guaranteed count.  Seeded recall and count error must be
+    at least as good as the plain summary's; pinned pairs carry their exact
+    supports."""
+    from paper_1210_0461_amd import seeding
+    mk = lambda seed: datagen.transactions(200_000, 50_000, 1.1, 10.0, 64, datagen.Raw(seed),
+                                           "g")
+    P, M, K, R = 64, 128, 200, 256
+    Zs, ys = [], []
+    for i in range(6):
+        st = mk(7000 + i)
+        load(crop, ctx, st, P)
+        Z, y, _, _, _ = seeding.training_pairs(ctx, st.T, st.n, M)
+        Zs.append(Z)
+        ys.append(y)
+    Z, y = torch.cat(Zs), torch.cat(ys)
+    mlp = crop.crop_mlp_create(ctx, seeding.flat_init(datagen.mlp_init_weights(2)))
+    try:
+        order = torch.from_numpy(datagen.sample_order(8, Z.shape[0], 8).astype(np.int32)).cuda()
+        crop.crop_mlp_train(ctx, mlp, Z, y, order, 128, 1e-3)
+        st = mk(7100)
+        ref = oracle.tx_exact(st.off, st.items, 1, SEED)
+        rk = oracle.pack_keys(ref["x"], ref["y"])
+        exact = dict(zip(rk.tolist(), ref["cnt"].tolist()))
+        load(crop, ctx, st, 1)
+        sx, sy, _ = seeding.predict_seeds(ctx, mlp, st.T, st.n, M, R)
+        crop.crop_set_summary(ctx, 4096, 16)
+        crop.crop_set_topk_rank(ctx, crop.CROP_RANK_LOWER)
+        res = {}
+        for mode in ("plain", "seeded"):
+            if mode == "plain":
+                crop.crop_run_topk(ctx, K)
+            else:
+                crop.crop_run_topk_seeded(ctx, K, sx, sy, 4)
+            i, j, up, lo, _ = crop.crop_read_topk(ctx, K)
+            keys = oracle.pack_keys(i, j)
+            truth = np.array([exact[int(k)] for k in keys], np.float64)
+            res[mode] = dict(recall=oracle.recall_at_k(keys, rk, ref["cnt"], K),
+                             err=float((up - truth).max()), gap=float((truth - lo).max()))
+            if mode == "seeded":
+                s = crop.crop_read_summary(ctx, 4096)
+                pk = oracle.pack_keys(s["x"], s["y"])
+                for q in np.flatnonzero(s["pinned"]):
+                    assert s["cnt"][q] == exact.get(int(pk[q]), 0) and s["err"][q] == 0
+        crop.crop_set_topk_rank(ctx, crop.CROP_RANK_UPPER)
+        print(f"plain {res['plain']}  seeded {res['seeded']}", flush=True)
+        assert res["seeded"]["recall"] >= res["plain"]["recall"]
+        assert res["seeded"]["gap"] <= res["plain"]["gap"]
+    finally:
+        crop.crop_mlp_destroy(mlp)
