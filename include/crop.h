@@ -197,6 +197,50 @@ crop_status crop_synchronize(crop_ctx *ctx);
  * the context stream around its kernels (synchronizes). */
 crop_status crop_last_run_ms(crop_ctx *ctx, float *ms);
 
+/* ---- batches of transaction streams ----------------------------------- */
+/* Many independent streams in one exact run.  Each stream is accumulated
+ * exactly as crop_run_exact would (Section 7: the pairs x < y of every
+ * transaction), in partitions of its own consistent hash (Section 6,
+ * Theorem 1; the same seed for every stream).  The batch is one pass: one
+ * count, scan, scatter and persistent aggregation launch over every bin of
+ * every stream, replayed as a captured HIP graph.
+ *
+ * Input: one CSR of all transactions, stream after stream; stream s is
+ * transactions [tx_off[s], tx_off[s+1]).  tx_off (n_streams + 1 entries) and
+ * n_items (item ids of stream s are below n_items[s]) are host arrays;
+ * off (tx_off[n_streams] + 1 item offsets, off[0] = 0) and items live in
+ * `where`.  Validation as crop_load_transactions, per stream; the error index
+ * is the global transaction.  Totals must stay below 2^32 terms. */
+crop_status crop_load_batch(crop_ctx *ctx, uint32_t n_streams, const uint64_t *tx_off,
+                            const uint32_t *off, const uint32_t *items, const uint32_t *n_items,
+                            crop_mem where, crop_own own);
+/* Plan knobs: routed terms aimed at per bin (each stream gets
+ * ceil(terms / terms_per_bin) partitions, at most 8192) and transactions per
+ * chunk (rows_per_chunk; halved while a chunk does not fit in LDS). */
+crop_status crop_batch_set_plan(crop_ctx *ctx, uint32_t terms_per_bin, uint32_t rows_per_chunk);
+/* Time every candidate plan (terms_per_bin in {15000, 30000, 60000} x
+ * rows_per_chunk in {64, 128, 256}) reps times on the loaded batch, keep the
+ * fastest, and remember it for later batches of the same shape in this
+ * process.  Outputs (NULL allowed): the chosen knobs and its time. */
+crop_status crop_batch_autotune(crop_ctx *ctx, uint32_t reps, uint32_t *terms_per_bin,
+                                uint32_t *rows_per_chunk, float *best_ms);
+/* Replay the run as a captured HIP graph (default 1) or launch eagerly (0;
+ * per-stage events available with crop_set_profiling). */
+crop_status crop_batch_set_graph(crop_ctx *ctx, int enable);
+crop_status crop_run_exact_batched(crop_ctx *ctx);
+/* Stream s: its partition count (0 before a plan), terms, first transaction
+ * and transaction count (NULL allowed for any output). */
+crop_status crop_batch_info(crop_ctx *ctx, uint32_t stream, uint32_t *partitions,
+                            uint64_t *terms, uint64_t *first_tx, uint64_t *n_tx);
+/* Per partition of stream s: distinct pairs and terms (host arrays of the
+ * stream's partition count). */
+crop_status crop_batch_result_sizes(crop_ctx *ctx, uint32_t stream, uint64_t *sizes,
+                                    uint64_t *terms_per_partition);
+/* Exact result of stream s, partition by partition, as crop_read_all. */
+crop_status crop_batch_read_stream(crop_ctx *ctx, uint32_t stream, crop_mem where, uint32_t *i,
+                                   uint32_t *j, uint32_t *count, uint64_t cap, uint64_t *written,
+                                   uint64_t *part_off);
+
 /* ---- learned heavy-pair seeding (an addition; not in the paper) -------- */
 /* All arrays below are device memory; calls are asynchronous on the context
  * stream unless they return host data.  Section 6 (Theorem 2's proof) names

@@ -97,6 +97,15 @@ _SIGS.update({
     "crop_run_topk_seeded": ([_vp, _u32, _vp, _vp, _u64, _u32], _i32),
     "crop_read_topk": ([_vp, _vp, _vp, _vp, _vp, _vp, _u64, _pu64], _i32),
     "crop_read_summary": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64, _pu64], _i32),
+    "crop_load_batch": ([_vp, _u32, _vp, _vp, _vp, _vp, _i32, _i32], _i32),
+    "crop_batch_set_plan": ([_vp, _u32, _u32], _i32),
+    "crop_batch_autotune": ([_vp, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_u32),
+                             ctypes.POINTER(ctypes.c_float)], _i32),
+    "crop_batch_set_graph": ([_vp, _i32], _i32),
+    "crop_run_exact_batched": ([_vp], _i32),
+    "crop_batch_info": ([_vp, _u32, ctypes.POINTER(_u32), _pu64, _pu64, _pu64], _i32),
+    "crop_batch_result_sizes": ([_vp, _u32, _vp, _vp], _i32),
+    "crop_batch_read_stream": ([_vp, _u32, _i32, _vp, _vp, _vp, _u64, _pu64, _vp], _i32),
     "crop_item_features": ([_vp, _u32, _vp], _i32),
     "crop_top_item_pairs": ([_vp, _u32, _u32, _vp, _vp, _u64, _pu64], _i32),
     "crop_lookup_exact": ([_vp, _vp, _vp, _u64, _vp], _i32),
@@ -346,6 +355,72 @@ def crop_read_summary(ctx, n_slots: int):
     n = w.value
     return dict(x=i[:n], y=j[:n], cnt=cnt[:n], err=err[:n], val=val[:n],
                 used=(flags[:n] & 1).astype(bool), pinned=(flags[:n] & 2).astype(bool))
+
+
+# ---- batches of transaction streams
+
+def crop_load_batch(ctx, tx_off, off, items, n_items, own: int = CROP_OWN_COPY) -> None:
+    """tx_off: uint64[n+1] stream boundaries (host); off, items: the
+    concatenated CSR (host arrays or device tensors); n_items: uint32[n]."""
+    tx = np.ascontiguousarray(tx_off, np.uint64)
+    ni = np.ascontiguousarray(n_items, np.uint32)
+    po, wo = _ptr(off)
+    pi, wi = _ptr(items)
+    if int(_len(items)) and wo != wi:
+        raise ValueError("off and items must both be host or both be device memory")
+    _check(ctx, _lib.crop_load_batch(ctx, tx.shape[0] - 1, tx.ctypes.data, po, pi, ni.ctypes.data,
+                                     wo, own))
+
+
+def crop_batch_set_plan(ctx, terms_per_bin: int, rows_per_chunk: int) -> None:
+    _check(ctx, _lib.crop_batch_set_plan(ctx, terms_per_bin, rows_per_chunk))
+
+
+def crop_batch_autotune(ctx, reps: int = 2):
+    """(terms_per_bin, rows_per_chunk, best ms) of the fastest candidate."""
+    t, r, ms = _u32(0), _u32(0), ctypes.c_float(0.0)
+    _check(ctx, _lib.crop_batch_autotune(ctx, reps, ctypes.byref(t), ctypes.byref(r),
+                                         ctypes.byref(ms)))
+    return t.value, r.value, float(ms.value)
+
+
+def crop_batch_set_graph(ctx, enable: bool) -> None:
+    _check(ctx, _lib.crop_batch_set_graph(ctx, 1 if enable else 0))
+
+
+def crop_run_exact_batched(ctx) -> None:
+    _check(ctx, _lib.crop_run_exact_batched(ctx))
+
+
+def crop_batch_info(ctx, stream: int) -> dict:
+    p, t, f, n = _u32(0), _u64(0), _u64(0), _u64(0)
+    _check(ctx, _lib.crop_batch_info(ctx, stream, ctypes.byref(p), ctypes.byref(t),
+                                     ctypes.byref(f), ctypes.byref(n)))
+    return dict(partitions=p.value, terms=t.value, first_tx=f.value, n_tx=n.value)
+
+
+def crop_batch_result_sizes(ctx, stream: int):
+    P = crop_batch_info(ctx, stream)["partitions"]
+    sizes = np.zeros(max(P, 1), np.uint64)
+    terms = np.zeros(max(P, 1), np.uint64)
+    _check(ctx, _lib.crop_batch_result_sizes(ctx, stream, sizes.ctypes.data, terms.ctypes.data))
+    return sizes[:P], terms[:P]
+
+
+def crop_batch_read_stream(ctx, stream: int):
+    """(i, j, count, part_off) of stream `stream` as host arrays."""
+    sizes, _ = crop_batch_result_sizes(ctx, stream)
+    n = int(sizes.sum())
+    P = sizes.shape[0]
+    i = np.zeros(max(n, 1), np.uint32)
+    j = np.zeros(max(n, 1), np.uint32)
+    c = np.zeros(max(n, 1), np.uint32)
+    part_off = np.zeros(P + 1, np.uint64)
+    w = _u64(0)
+    _check(ctx, _lib.crop_batch_read_stream(ctx, stream, CROP_MEM_HOST, i.ctypes.data,
+                                            j.ctypes.data, c.ctypes.data, n, ctypes.byref(w),
+                                            part_off.ctypes.data))
+    return i[:n], j[:n], c[:n], part_off
 
 
 # ---- learned heavy-pair seeding (device tensors in and out)

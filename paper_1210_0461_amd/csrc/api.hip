@@ -9,23 +9,11 @@
 #include <string>
 #include <vector>
 
-#include "crop_internal.hpp"
+#include "api_util.hpp"
 
 using namespace crop;
 
 namespace crop {
-size_t spill_entry_bytes(bool wide, bool sums);
-size_t tx_scatter_smem_bytes(uint32_t NB, uint32_t max_items, uint32_t cap, bool wide);
-}
-
-namespace {
-
-constexpr uint32_t kMaxP = 8192;
-constexpr uint64_t kTermsPerBin = 30000;   // routed terms per bin the auto plan aims at
-constexpr size_t kLdsBudget = 64 * 1024;   // enumeration kernels' staging budget
-constexpr size_t kStageBudget = 150 * 1024; // scatter kernel: dynamic LDS in total
-constexpr uint64_t kSsMinBins = 2048;       // Space-Saving bins wanted for parallelism
-constexpr size_t kSsLdsBudget = 80 * 1024;  // two summary workgroups per CU
 
 crop_status fail(crop_ctx *c, crop_status s, const std::string &msg)
 {
@@ -39,25 +27,6 @@ crop_status hip_fail(crop_ctx *c, hipError_t e, const char *what)
     return fail(c, e == hipErrorOutOfMemory ? CROP_E_NOMEM : CROP_E_HIP, m);
 }
 
-#define CK(expr)                                                   \
-    do {                                                           \
-        hipError_t e_ = (expr);                                    \
-        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr);     \
-    } while (0)
-
-struct DeviceGuard {
-    int prev = -1;
-    explicit DeviceGuard(int dev)
-    {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) (void)hipSetDevice(dev);
-    }
-    ~DeviceGuard()
-    {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
 uint64_t tx_terms_of(const std::vector<uint32_t> &off)
 {
     uint64_t s = 0;
@@ -66,41 +35,6 @@ uint64_t tx_terms_of(const std::vector<uint32_t> &off)
         s += L * (L ? L - 1 : 0) / 2;
     }
     return s;
-}
-
-// Copy n elements of T from `src` (host or device) into a host vector.
-template <class T>
-hipError_t fetch(std::vector<T> &dst, const T *src, size_t n, crop_mem where)
-{
-    dst.resize(n);
-    if (n == 0) return hipSuccess;
-    if (where == CROP_MEM_HOST) {
-        std::memcpy(dst.data(), src, n * sizeof(T));
-        return hipSuccess;
-    }
-    return hipMemcpy(dst.data(), src, n * sizeof(T), hipMemcpyDeviceToHost);
-}
-
-// Place an input array on the device: borrow it, or copy it into buf.
-template <class T>
-hipError_t place(const T *src, size_t n, crop_mem where, crop_own own, DevBuf &buf,
-                 const T **out, hipStream_t s)
-{
-    if (own == CROP_OWN_BORROW) {
-        *out = src;
-        return hipSuccess;
-    }
-    hipError_t e = buf.ensure(n * sizeof(T) + 16);
-    if (e != hipSuccess) return e;
-    if (n) {
-        e = hipMemcpyAsync(buf.p, src, n * sizeof(T),
-                           where == CROP_MEM_HOST ? hipMemcpyHostToDevice
-                                                  : hipMemcpyDeviceToDevice,
-                           s);
-        if (e != hipSuccess) return e;
-    }
-    *out = buf.as<T>();
-    return hipSuccess;
 }
 
 // Validate CSR contents on the device; returns the first bad vector or -1.
@@ -147,6 +81,7 @@ void reset_input(crop_ctx *ctx)
     in.h_off.clear();
     in.h_b_off.clear();
     in.op_chunks.clear();
+    reset_batch(ctx);
     ctx->result = Result::None;
 }
 
@@ -409,13 +344,7 @@ crop_status run_end(crop_ctx *ctx)
     return CROP_OK;
 }
 
-#define STAGE(name)                                   \
-    do {                                              \
-        crop_status st_ = stage_end(ctx, name);       \
-        if (st_ != CROP_OK) return st_;               \
-    } while (0)
-
-}  // namespace
+}  // namespace crop
 
 // ============================================================== context
 
@@ -465,10 +394,15 @@ void crop_destroy(crop_ctx *ctx)
     if (!ctx) return;
     DeviceGuard g(ctx->device);
     if (ctx->stream) (void)hipStreamSynchronize(ctx->stream);
+    if (ctx->own_stream) (void)hipStreamSynchronize(ctx->own_stream);
+    reset_batch(ctx);
+    BatchState &bt = ctx->batch;
     for (DevBuf *b : {&ctx->cnt_mat, &ctx->part_buf, &ctx->bin_off, &ctx->bin_size,
                       &ctx->bin_order, &ctx->keys,
                       &ctx->vals, &ctx->out_cnt, &ctx->spill, &ctx->counter, &ctx->ss_state,
-                      &ctx->topk_buf, &ctx->scratch, &ctx->in.d_op_chunks})
+                      &ctx->topk_buf, &ctx->scratch, &ctx->learn_ws, &ctx->in.d_op_chunks,
+                      &bt.d_crow, &bt.d_cstream, &bt.d_streams, &bt.d_bin_stream, &bt.tot,
+                      &bt.tiles})
         b->release();
     for (DevBuf &b : ctx->in.own) b.release();
     for (StageRec &r : ctx->ring)
@@ -706,6 +640,8 @@ crop_status crop_run_exact(crop_ctx *ctx)
 {
     if (!ctx) return CROP_E_ARG;
     if (ctx->in.mode == Mode::None) return fail(ctx, CROP_E_STATE, "no input loaded");
+    if (ctx->in.mode == Mode::Batch)
+        return fail(ctx, CROP_E_STATE, "a batch is loaded: use crop_run_exact_batched");
     DeviceGuard g(ctx->device);
     ctx->result = Result::None;
     const bool outer = ctx->in.mode == Mode::Outer;
@@ -743,6 +679,8 @@ static crop_status run_topk_impl(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
 {
     if (!ctx) return CROP_E_ARG;
     if (ctx->in.mode == Mode::None) return fail(ctx, CROP_E_STATE, "no input loaded");
+    if (ctx->in.mode == Mode::Batch)
+        return fail(ctx, CROP_E_UNSUPPORTED, "top-K runs take one stream, not a batch");
     if (K == 0) return fail(ctx, CROP_E_ARG, "K must be positive");
     if (ns && (!sx || !sy)) return fail(ctx, CROP_E_ARG, "null seed arrays");
     if (ns >= (1ull << 31)) return fail(ctx, CROP_E_UNSUPPORTED, "too many seeds");
@@ -1144,8 +1082,8 @@ crop_status crop_read_all(crop_ctx *ctx, crop_mem where, uint32_t *i, uint32_t *
         oc = count ? oj + n : nullptr;
         ov = value ? reinterpret_cast<float *>(oj + 2 * n) : nullptr;
     }
-    CK(launch_gather_result(ctx, d_dst, oi, oj, outer ? nullptr : oc, outer ? ov : nullptr,
-                            ctx->stream));
+    CK(launch_gather_result(ctx, 0, pl.NB, d_dst, oi, oj, outer ? nullptr : oc,
+                            outer ? ov : nullptr, ctx->stream));
     if (where == CROP_MEM_HOST) {
         CK(hipMemcpyAsync(i, oi, tot * 4, hipMemcpyDeviceToHost, ctx->stream));
         CK(hipMemcpyAsync(j, oj, tot * 4, hipMemcpyDeviceToHost, ctx->stream));

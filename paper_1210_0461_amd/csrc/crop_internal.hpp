@@ -11,8 +11,8 @@
 
 namespace crop {
 
-enum class Mode { None = 0, Tx = 1, Outer = 2 };
-enum class Result { None = 0, Exact = 1, TopK = 2 };
+enum class Mode { None = 0, Tx = 1, Outer = 2, Batch = 3 };
+enum class Result { None = 0, Exact = 1, TopK = 2, BatchExact = 3 };
 
 // A device allocation that grows on demand (never shrinks).
 struct DevBuf {
@@ -79,6 +79,23 @@ struct Input {
     DevBuf d_op_chunks;
 };
 
+// Batches of transaction streams (one exact run over all of them).  The
+// streams are concatenated row-wise; stream s owns NB routing bins starting
+// at global bin bin_base, chunks [chunk0, chunk0 + n_chunks), and its count
+// matrix at cnt_base.
+struct BatchStreamDev {
+    uint32_t NB, bin_base, chunk0, n_chunks;
+    uint64_t cnt_base;
+};
+
+struct BatchDev {
+    const uint32_t *crow = nullptr;       // n_chunks + 1 row boundaries
+    const uint32_t *cstream = nullptr;    // stream of each chunk
+    const BatchStreamDev *streams = nullptr;
+    const uint32_t *bin_stream = nullptr; // stream of each global bin
+    uint32_t n_chunks = 0, n_streams = 0, NBtot = 0, NBmax = 0, max_items = 0, stage_cap = 0;
+};
+
 // Space-Saving state in device memory, bucket-major with ell slots per
 // bucket (structure of arrays).  cnt/err hold uint32 counts (transactions)
 // or fp32 bits (outer products); key holds (i << 32) | j; flag bit 0 =
@@ -99,6 +116,32 @@ struct StageRec {
     int n = 0;
     const char *names[kMaxStages] = {};
     hipEvent_t ev[kMaxStages + 1] = {};
+};
+
+}  // namespace crop
+
+namespace crop {
+
+// Host side of a loaded batch and its plan.  Stream s is rows
+// [tx_off[s], tx_off[s+1]) of the concatenated CSR; its P[s] partitions are
+// its routing bins [bin_base[s], bin_base[s] + P[s]) (one bin per partition).
+struct BatchState {
+    uint32_t n = 0;
+    std::vector<uint64_t> tx_off;
+    std::vector<uint32_t> n_items;
+    std::vector<uint64_t> terms;
+    // plan
+    bool planned = false;
+    uint32_t terms_per_bin = 0, rows_per_chunk = 0;
+    std::vector<uint32_t> P, bin_base, chunk0, n_chunks;
+    std::vector<uint64_t> cnt_base;
+    uint64_t cnt_words = 0;
+    BatchDev dev;
+    DevBuf d_crow, d_cstream, d_streams, d_bin_stream, tot, tiles;
+    // captured launch sequence of one run
+    bool use_graph = true;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 }  // namespace crop
@@ -133,6 +176,7 @@ struct crop_ctx {
     crop::DevBuf cnt_mat, part_buf, bin_off, bin_size, bin_order, keys, vals, out_cnt, spill,
         counter;
     crop::DevBuf ss_state, topk_buf, scratch, learn_ws;
+    crop::BatchState batch;    // batched streams
     crop::SsState ss;          // views into ss_state
     uint64_t ss_buckets = 0;   // P * B of the last top-K run
     uint32_t topk_outer = 0;   // the last top-K run was on outer products
@@ -170,6 +214,16 @@ hipError_t launch_scan_counts(uint32_t *cnt, uint32_t n_chunks, uint32_t NB, uin
 
 // order[] <- bins with more than twice the mean term count first.
 hipError_t launch_bin_order(uint32_t NB, const uint32_t *bin_off, uint32_t *order, hipStream_t s);
+
+hipError_t launch_batch_count(const uint32_t *off, const uint32_t *items, const HashParams &hp,
+                              const BatchDev &b, uint32_t *cnt, const uint32_t *bin_off,
+                              hipStream_t s);
+hipError_t launch_batch_scatter(const uint32_t *off, const uint32_t *items, const HashParams &hp,
+                                const BatchDev &b, uint32_t *cur, const uint32_t *bin_off,
+                                void *keys, bool wide, hipStream_t s);
+uint32_t batch_scan_tiles(uint32_t NBtot);
+hipError_t launch_batch_scan(const BatchDev &b, uint32_t *cnt, uint32_t *tot, uint32_t *tiles,
+                             uint32_t *bin_off, uint32_t *counter, hipStream_t s);
 
 hipError_t launch_aggregate_counts(const crop_ctx *c, hipStream_t s);
 hipError_t launch_aggregate_sums(const crop_ctx *c, hipStream_t s);
@@ -217,8 +271,8 @@ int mlp_param_count();
 int mlp_batch_max();
 
 // Gather the bin-segmented exact result into partition-contiguous arrays.
-hipError_t launch_gather_result(const crop_ctx *c, const uint32_t *dst_off, uint32_t *out_i,
-                                uint32_t *out_j, uint32_t *out_cnt, float *out_val,
-                                hipStream_t s);
+hipError_t launch_gather_result(const crop_ctx *c, uint32_t bin0, uint32_t n_bins,
+                                const uint32_t *dst_off, uint32_t *out_i, uint32_t *out_j,
+                                uint32_t *out_cnt, float *out_val, hipStream_t s);
 
 }  // namespace crop

@@ -155,25 +155,77 @@ __device__ inline uint32_t bin_of_key(KeyT key, const HashParams &hp, uint32_t N
 
 // ---------------------------------------------------------------- kernels
 
-template <int BS>
+// ---------------------------------------------------------------- chunks
+
+// One chunk of transactions as the count and scatter kernels see it: rows
+// [r0, r1), the NB routing bins of its stream, its row of the count matrix
+// (counts, later write cursors) and the next row (or the stream's bin ends
+// for its last chunk), which bounds its run in each bin.
+struct ChunkView {
+    uint32_t r0, r1, NB;
+    uint32_t *row;
+    const uint32_t *nxt;
+};
+
+// A single stream: chunk c holds rows [c R, c R + R).
+struct SingleChunks {
+    uint32_t T, R, NB, n_chunks;
+    uint32_t *cnt;
+    const uint32_t *bin_off;
+    __device__ ChunkView view(uint32_t c) const
+    {
+        ChunkView v;
+        v.r0 = c * R;
+        v.r1 = min(v.r0 + R, T);
+        v.NB = NB;
+        v.row = cnt + (size_t)c * NB;
+        v.nxt = c + 1 < n_chunks ? v.row + NB : bin_off + 1;
+        return v;
+    }
+};
+
+// A batch of streams concatenated row-wise: chunk c holds rows
+// [crow[c], crow[c+1]) of stream cstream[c]; no chunk crosses a stream.
+struct BatchChunks {
+    const uint32_t *crow;
+    const uint32_t *cstream;
+    const BatchStreamDev *st;
+    uint32_t *cnt;
+    const uint32_t *bin_off;
+    __device__ ChunkView view(uint32_t c) const
+    {
+        const BatchStreamDev S = st[cstream[c]];
+        ChunkView v;
+        v.r0 = crow[c];
+        v.r1 = crow[c + 1];
+        v.NB = S.NB;
+        v.row = cnt + S.cnt_base + (size_t)(c - S.chunk0) * S.NB;
+        v.nxt = c + 1 < S.chunk0 + S.n_chunks ? v.row + S.NB : bin_off + S.bin_base + 1;
+        return v;
+    }
+};
+
+// ---------------------------------------------------------------- kernels
+
+// NBmax sizes the LDS layout; each chunk uses the NB of its stream.
+template <int BS, class Chunks>
 __global__ void __launch_bounds__(BS)
-k_tx_count(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items, uint32_t T,
-           uint32_t R, HashParams hp, uint32_t NB, uint32_t max_items, uint32_t *__restrict__ cnt)
+k_tx_count(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items, HashParams hp,
+           uint32_t NBmax, uint32_t max_items, Chunks ch)
 {
     extern __shared__ uint32_t smem[];
     uint32_t *hist = smem;
-    const TxLds L = tx_lds(smem, NB, max_items);
+    const TxLds L = tx_lds(smem, NBmax, max_items);
     const uint32_t chunk = xcd_contiguous(blockIdx.x, gridDim.x);
-    const uint32_t r0 = chunk * R;
-    const uint32_t r1 = min(r0 + R, T);
+    const ChunkView cv = ch.view(chunk);
+    const uint32_t NB = cv.NB;
     for (uint32_t b = threadIdx.x; b < NB; b += BS) hist[b] = 0;
-    const uint32_t m = stage_tx<BS>(off, items, r0, r1, hp, L);
+    const uint32_t m = stage_tx<BS>(off, items, cv.r0, cv.r1, hp, L);
     enum_tx<BS>(m, L, hp, [&](uint32_t, uint32_t, uint32_t h) {
         atomicAdd(&hist[interval_of(h, NB)], 1u);
     });
     __syncthreads();
-    uint32_t *row = cnt + (size_t)chunk * NB;
-    for (uint32_t b = threadIdx.x; b < NB; b += BS) row[b] = hist[b];
+    for (uint32_t b = threadIdx.x; b < NB; b += BS) cv.row[b] = hist[b];
 }
 
 // Scatter with LDS staging.  The chunk's terms of a window of bins are put
@@ -182,18 +234,17 @@ k_tx_count(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
 // addresses.  A window holds at most `cap` terms; a bin with more terms than
 // that in one chunk is written directly.  Windows are set by bin, a property
 // of the term itself, so each term lands in exactly one window.
-template <int BS, class KeyT>
+template <int BS, class KeyT, class Chunks>
 __global__ void __launch_bounds__(BS)
-k_tx_scatter(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items, uint32_t T,
-             uint32_t R, HashParams hp, uint32_t NB, uint32_t max_items,
-             const uint32_t *__restrict__ cur, const uint32_t *__restrict__ bin_off,
-             uint32_t n_chunks, KeyT *__restrict__ keys, uint32_t cap)
+k_tx_scatter(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items, HashParams hp,
+             uint32_t NBmax, uint32_t max_items, Chunks ch, KeyT *__restrict__ keys,
+             uint32_t cap)
 {
     extern __shared__ uint32_t smem[];
-    uint32_t *lstart = smem;               // NB + 1: local start of each bin's run
-    uint32_t *lcur = smem + NB + 1;        // NB: local cursor
-    uint32_t *delta = smem + 2 * NB + 1;   // NB: global start - local start
-    const uint32_t lead = 3 * NB + 1;
+    uint32_t *lstart = smem;                  // NB + 1: local start of each bin's run
+    uint32_t *lcur = smem + NBmax + 1;        // NB: local cursor
+    uint32_t *delta = smem + 2 * NBmax + 1;   // NB: global start - local start
+    const uint32_t lead = 3 * NBmax + 1;
     const TxLds L = tx_lds(smem, lead, max_items);
     KeyT *stage =
         reinterpret_cast<KeyT *>(smem + ((tx_lds_words(lead, max_items) + 1) & ~(size_t)1));
@@ -201,10 +252,10 @@ k_tx_scatter(const uint32_t *__restrict__ off, const uint32_t *__restrict__ item
     __shared__ uint32_t s_b1, s_direct;
 
     const uint32_t chunk = xcd_contiguous(blockIdx.x, gridDim.x);
-    const uint32_t r0 = chunk * R;
-    const uint32_t r1 = min(r0 + R, T);
-    const uint32_t *row = cur + (size_t)chunk * NB;
-    const uint32_t *nxt = chunk + 1 < n_chunks ? cur + (size_t)(chunk + 1) * NB : bin_off + 1;
+    const ChunkView cv = ch.view(chunk);
+    const uint32_t NB = cv.NB;
+    const uint32_t *row = cv.row;
+    const uint32_t *nxt = cv.nxt;
     for (uint32_t b = threadIdx.x; b < NB; b += BS) lstart[b] = nxt[b] - row[b];
     __syncthreads();
     lds_exclusive_scan<BS>(lstart, NB, s_tmp);
@@ -213,7 +264,7 @@ k_tx_scatter(const uint32_t *__restrict__ off, const uint32_t *__restrict__ item
         lcur[b] = lstart[b];
         delta[b] = row[b] - lstart[b];
     }
-    const uint32_t m = stage_tx<BS>(off, items, r0, r1, hp, L);
+    const uint32_t m = stage_tx<BS>(off, items, cv.r0, cv.r1, hp, L);
     if (Tc == 0) return;
 
     for (uint32_t b0 = 0; b0 < NB;) {
@@ -488,6 +539,106 @@ k_colapply(uint32_t *__restrict__ cnt, uint32_t n, uint32_t NB, uint32_t rows_pe
     }
 }
 
+// ---- batches: the count matrix of stream s is [its chunks x its NB bins] at
+// cnt_base; global bin g = bin_base + local bin.
+
+// Per global bin: the stream's column of counts -> exclusive prefix over its
+// chunks, in place; tot[g] <- the column total.
+__global__ void __launch_bounds__(256)
+k_bcolscan(BatchDev b, uint32_t *__restrict__ cnt, uint32_t *__restrict__ tot)
+{
+    const uint32_t g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= b.NBtot) return;
+    const BatchStreamDev S = b.streams[b.bin_stream[g]];
+    const uint32_t lb = g - S.bin_base;
+    uint32_t *col = cnt + S.cnt_base + lb;
+    uint32_t run = 0;
+    for (uint32_t c = 0; c < S.n_chunks; ++c) {
+        const uint32_t v = col[(size_t)c * S.NB];
+        col[(size_t)c * S.NB] = run;
+        run += v;
+    }
+    tot[g] = run;
+}
+
+// Device-wide exclusive scan in three launches over tiles of kScanTile.
+constexpr uint32_t kScanTile = 4096;
+
+__global__ void __launch_bounds__(1024)
+k_scan_tiles(const uint32_t *__restrict__ in, uint32_t n, uint32_t *__restrict__ tile_sum)
+{
+    __shared__ uint32_t s_tmp[1024 / kWave + 1];
+    const uint32_t base = blockIdx.x * kScanTile;
+    uint32_t sum = 0;
+    for (uint32_t k = 0; k < kScanTile / 1024; ++k) {
+        const uint32_t i = base + threadIdx.x * (kScanTile / 1024) + k;
+        if (i < n) sum += in[i];
+    }
+    uint32_t total;
+    (void)block_exclusive_scan<1024>(sum, s_tmp, &total);
+    if (threadIdx.x == 0) tile_sum[blockIdx.x] = total;
+}
+
+// One workgroup: exclusive prefix of the tile sums; out[n] <- the total;
+// resets the persistent kernels' work counters.
+__global__ void __launch_bounds__(1024)
+k_scan_top(uint32_t *__restrict__ tile_sum, uint32_t n_tiles, uint32_t *__restrict__ out,
+           uint32_t n, uint32_t *__restrict__ counter)
+{
+    __shared__ uint32_t s_tmp[1024 / kWave + 1];
+    const uint32_t per = (n_tiles + 1023) / 1024;
+    const uint32_t t0 = threadIdx.x * per, t1 = min(n_tiles, t0 + per);
+    uint32_t sum = 0;
+    for (uint32_t t = t0; t < t1; ++t) sum += tile_sum[t];
+    uint32_t total;
+    uint32_t run = block_exclusive_scan<1024>(sum, s_tmp, &total);
+    for (uint32_t t = t0; t < t1; ++t) {
+        const uint32_t v = tile_sum[t];
+        tile_sum[t] = run;
+        run += v;
+    }
+    if (threadIdx.x == 0) {
+        out[n] = total;
+        counter[0] = 0;
+        counter[1] = 0;
+    }
+}
+
+__global__ void __launch_bounds__(1024)
+k_scan_apply(const uint32_t *__restrict__ in, uint32_t n, const uint32_t *__restrict__ tile_sum,
+             uint32_t *__restrict__ out)
+{
+    __shared__ uint32_t s_tmp[1024 / kWave + 1];
+    constexpr uint32_t E = kScanTile / 1024;
+    const uint32_t base = blockIdx.x * kScanTile + threadIdx.x * E;
+    uint32_t v[E];
+    uint32_t sum = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < E; ++k) {
+        v[k] = base + k < n ? in[base + k] : 0u;
+        sum += v[k];
+    }
+    uint32_t total;
+    uint32_t run = tile_sum[blockIdx.x] + block_exclusive_scan<1024>(sum, s_tmp, &total);
+#pragma unroll
+    for (uint32_t k = 0; k < E; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+}
+
+// Per global bin: add the bin's start to its column of chunk prefixes.
+__global__ void __launch_bounds__(256)
+k_bapply(BatchDev b, uint32_t *__restrict__ cnt, const uint32_t *__restrict__ bin_off)
+{
+    const uint32_t g = blockIdx.x * 256 + threadIdx.x;
+    if (g >= b.NBtot) return;
+    const BatchStreamDev S = b.streams[b.bin_stream[g]];
+    uint32_t *col = cnt + S.cnt_base + (g - S.bin_base);
+    const uint32_t base = bin_off[g];
+    for (uint32_t c = 0; c < S.n_chunks; ++c) col[(size_t)c * S.NB] += base;
+}
+
 // ---------------------------------------------------------------- validation
 
 // bad <- min over offending vectors v of v (vector v is [v_off[v], v_off[v+1])).
@@ -532,12 +683,19 @@ static size_t op_smem_bytes(uint32_t NB, uint32_t max_a, uint32_t BS)
     return sizeof(uint32_t) * ((size_t)NB + 5 * (size_t)max_a + 1 + BS / kWave + 1);
 }
 
+static SingleChunks single_chunks(const crop_ctx *c, uint32_t *cnt)
+{
+    const RoutePlan &pl = c->plan;
+    return SingleChunks{(uint32_t)c->in.T, pl.R, pl.NB, pl.n_chunks, cnt,
+                        c->bin_off.as<uint32_t>()};
+}
+
 hipError_t launch_tx_count(const crop_ctx *c, uint32_t *cnt, hipStream_t s)
 {
     const RoutePlan &pl = c->plan;
     size_t sm = tx_count_smem_bytes(pl.NB, pl.max_items);
-    hipLaunchKernelGGL(k_tx_count<256>, dim3(pl.n_chunks), dim3(256), sm, s, c->in.off,
-                       c->in.items, (uint32_t)c->in.T, pl.R, c->hp, pl.NB, pl.max_items, cnt);
+    hipLaunchKernelGGL((k_tx_count<256, SingleChunks>), dim3(pl.n_chunks), dim3(256), sm, s,
+                       c->in.off, c->in.items, c->hp, pl.NB, pl.max_items, single_chunks(c, cnt));
     return hipGetLastError();
 }
 
@@ -546,16 +704,45 @@ hipError_t launch_tx_scatter(const crop_ctx *c, const uint32_t *cur, void *keys,
     const RoutePlan &pl = c->plan;
     const bool wide = c->in.wide_keys;
     size_t sm = tx_scatter_smem_bytes(pl.NB, pl.max_items, pl.stage_cap, wide);
+    const SingleChunks ch = single_chunks(c, const_cast<uint32_t *>(cur));
     if (wide)
-        hipLaunchKernelGGL((k_tx_scatter<1024, uint64_t>), dim3(pl.n_chunks), dim3(1024), sm, s,
-                           c->in.off, c->in.items, (uint32_t)c->in.T, pl.R, c->hp, pl.NB,
-                           pl.max_items, cur, c->bin_off.as<uint32_t>(), pl.n_chunks,
-                           static_cast<uint64_t *>(keys), pl.stage_cap);
+        hipLaunchKernelGGL((k_tx_scatter<1024, uint64_t, SingleChunks>), dim3(pl.n_chunks),
+                           dim3(1024), sm, s, c->in.off, c->in.items, c->hp, pl.NB, pl.max_items,
+                           ch, static_cast<uint64_t *>(keys), pl.stage_cap);
     else
-        hipLaunchKernelGGL((k_tx_scatter<1024, uint32_t>), dim3(pl.n_chunks), dim3(1024), sm, s,
-                           c->in.off, c->in.items, (uint32_t)c->in.T, pl.R, c->hp, pl.NB,
-                           pl.max_items, cur, c->bin_off.as<uint32_t>(), pl.n_chunks,
-                           static_cast<uint32_t *>(keys), pl.stage_cap);
+        hipLaunchKernelGGL((k_tx_scatter<1024, uint32_t, SingleChunks>), dim3(pl.n_chunks),
+                           dim3(1024), sm, s, c->in.off, c->in.items, c->hp, pl.NB, pl.max_items,
+                           ch, static_cast<uint32_t *>(keys), pl.stage_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_count(const uint32_t *off, const uint32_t *items, const HashParams &hp,
+                              const BatchDev &b, uint32_t *cnt, const uint32_t *bin_off,
+                              hipStream_t s)
+{
+    if (!b.n_chunks) return hipSuccess;
+    size_t sm = tx_count_smem_bytes(b.NBmax, b.max_items);
+    const BatchChunks ch{b.crow, b.cstream, b.streams, cnt, bin_off};
+    hipLaunchKernelGGL((k_tx_count<256, BatchChunks>), dim3(b.n_chunks), dim3(256), sm, s, off,
+                       items, hp, b.NBmax, b.max_items, ch);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_scatter(const uint32_t *off, const uint32_t *items, const HashParams &hp,
+                                const BatchDev &b, uint32_t *cur, const uint32_t *bin_off,
+                                void *keys, bool wide, hipStream_t s)
+{
+    if (!b.n_chunks) return hipSuccess;
+    size_t sm = tx_scatter_smem_bytes(b.NBmax, b.max_items, b.stage_cap, wide);
+    const BatchChunks ch{b.crow, b.cstream, b.streams, cur, bin_off};
+    if (wide)
+        hipLaunchKernelGGL((k_tx_scatter<1024, uint64_t, BatchChunks>), dim3(b.n_chunks),
+                           dim3(1024), sm, s, off, items, hp, b.NBmax, b.max_items, ch,
+                           static_cast<uint64_t *>(keys), b.stage_cap);
+    else
+        hipLaunchKernelGGL((k_tx_scatter<1024, uint32_t, BatchChunks>), dim3(b.n_chunks),
+                           dim3(1024), sm, s, off, items, hp, b.NBmax, b.max_items, ch,
+                           static_cast<uint32_t *>(keys), b.stage_cap);
     return hipGetLastError();
 }
 
@@ -608,6 +795,23 @@ hipError_t launch_scan_counts(uint32_t *cnt, uint32_t n_chunks, uint32_t NB, uin
     hipLaunchKernelGGL(k_colbase, dim3(1), dim3(1024), 0, s, NB, bin_off, counter);
     hipLaunchKernelGGL(k_colapply, grid, dim3(256), 0, s, cnt, n_chunks, NB, rows_per_g, part,
                        bin_off);
+    return hipGetLastError();
+}
+
+uint32_t batch_scan_tiles(uint32_t NBtot) { return (NBtot + kScanTile - 1) / kScanTile; }
+
+// tot: NBtot words; tiles: batch_scan_tiles(NBtot) words.
+hipError_t launch_batch_scan(const BatchDev &b, uint32_t *cnt, uint32_t *tot, uint32_t *tiles,
+                             uint32_t *bin_off, uint32_t *counter, hipStream_t s)
+{
+    const uint32_t g = (b.NBtot + 255) / 256;
+    const uint32_t nt = batch_scan_tiles(b.NBtot);
+    hipLaunchKernelGGL(k_bcolscan, dim3(g), dim3(256), 0, s, b, cnt, tot);
+    hipLaunchKernelGGL(k_scan_tiles, dim3(nt), dim3(1024), 0, s, tot, b.NBtot, tiles);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, tiles, nt, bin_off, b.NBtot,
+                       counter);
+    hipLaunchKernelGGL(k_scan_apply, dim3(nt), dim3(1024), 0, s, tot, b.NBtot, tiles, bin_off);
+    hipLaunchKernelGGL(k_bapply, dim3(g), dim3(256), 0, s, b, cnt, bin_off);
     return hipGetLastError();
 }
 
