@@ -16,7 +16,8 @@ CPU oracle timed on the same stream (single-threaded, about half a minute),
 whose result also gives the recall@1000 of the GPU's exact top 1000 and a
 whole-result equality check.
 
---learned runs the learned-seeding comparison instead: an MLP trained on
+--batched times the 256-stream batched workload (one tuned plan replayed as
+a captured HIP graph).  --learned runs the learned-seeding comparison: an MLP trained on
 the GPU on 20 training streams like the one above, used to pin predicted
 heavy pairs into the Space-Saving summaries of a held-out stream, against
 the plain summaries at equal memory, in two regimes (P = 1024 with 2^14
@@ -51,6 +52,8 @@ def parse():
                          "whole stream also gives the recall and equality checks")
     ap.add_argument("--learned", action="store_true",
                     help="run the learned-seeding comparison instead of the exact bench")
+    ap.add_argument("--batched", action="store_true",
+                    help="time the 256-stream batched exact run instead of the exact bench")
     ap.add_argument("--train-streams", type=int, default=20)
     ap.add_argument("--epochs", type=int, default=4)
     ap.add_argument("--lr", type=float, default=1e-3)
@@ -269,6 +272,92 @@ def run_learned(args):
     print(json.dumps(out), flush=True)
 
 
+def _gen_batched(s):
+    import datagen
+    st = datagen.config_batched_stream(s)
+    return st.off, st.items, st.n
+
+
+def run_batched(args):
+    """The 256-stream workload as one batched exact run (tuned plan, captured
+    HIP graph); throughput over all streams."""
+    import multiprocessing as mp
+    import numpy as np
+    t0 = time.perf_counter()
+    # streams are generated in worker processes before this process touches the GPU
+    with mp.get_context("fork").Pool(min(8, os.cpu_count() or 1)) as pool:
+        streams = pool.map(_gen_batched, range(256))
+    print(f"# generated 256 streams in {time.perf_counter() - t0:.1f} s", file=sys.stderr,
+          flush=True)
+    import torch
+    import paper_1210_0461_amd as crop
+    T = np.array([o.shape[0] - 1 for o, _, _ in streams], np.int64)
+    nnz = np.array([i.shape[0] for _, i, _ in streams], np.int64)
+    tx = np.concatenate([[0], np.cumsum(T)]).astype(np.uint64)
+    base = np.concatenate([[0], np.cumsum(nnz)])
+    off = np.concatenate([o[:-1].astype(np.int64) + base[k] for k, (o, _, _) in
+                          enumerate(streams)] + [[base[-1]]]).astype(np.uint32)
+    items = np.concatenate([i for _, i, _ in streams])
+    n_items = np.array([n for _, _, n in streams], np.uint32)
+    dev = torch.device("cuda:0")
+    doff = torch.from_numpy(off.view(np.int32)).to(dev)
+    ditems = torch.from_numpy(items.view(np.int32)).to(dev)
+    stream = torch.cuda.Stream(device=dev)
+    torch.cuda.synchronize(dev)
+    ctx = crop.crop_create(0)
+    try:
+        crop.crop_set_stream(ctx, stream)
+        crop.crop_set_seed(ctx, SEED)
+        crop.crop_load_batch(ctx, tx, doff, ditems, n_items, own=crop.CROP_OWN_BORROW)
+        t0 = time.perf_counter()
+        tpb, R, tune_ms = crop.crop_batch_autotune(ctx, 2)
+        tune_s = time.perf_counter() - t0
+        for _ in range(args.warmup):
+            crop.crop_run_exact_batched(ctx)
+        torch.cuda.synchronize(dev)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            crop.crop_run_exact_batched(ctx)
+        e1.record(stream)
+        torch.cuda.synchronize(dev)
+        ms = e0.elapsed_time(e1) / args.steps
+        terms = 0
+        distinct = 0
+        parts = []
+        for k in range(256):
+            info = crop.crop_batch_info(ctx, k)
+            sizes, pt = crop.crop_batch_result_sizes(ctx, k)
+            terms += int(pt.sum())
+            distinct += int(sizes.sum())
+            parts.append(info["partitions"])
+        # eager run with per-stage times
+        crop.crop_batch_set_graph(ctx, False)
+        crop.crop_set_profiling(ctx, True)
+        crop.crop_run_exact_batched(ctx)
+        crop.crop_synchronize(ctx)
+        stages = {n: round(m, 4) for n, m in crop.crop_run_stages(ctx, 0)}
+    finally:
+        crop.crop_destroy(ctx)
+    L = np.diff(off.astype(np.int64))
+    assert terms == int((L * (L - 1) // 2).sum())
+    alg = 4 * items.shape[0] + 4 * off.shape[0] + 8 * distinct
+    gbs = alg / (ms * 1e-3) / 1e9
+    out = {"experiment": "batched exact run, 256 streams in one captured HIP graph",
+           "streams": 256, "transactions": int(T.sum()), "items": int(items.shape[0]),
+           "terms": terms, "distinct_pairs": distinct, "ms_per_run": round(ms, 4),
+           "term_updates_per_s": terms / (ms * 1e-3),
+           "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "alg_bytes": alg},
+           "autotune": {"terms_per_bin": tpb, "rows_per_chunk": R, "best_ms": round(tune_ms, 4),
+                        "seconds": round(tune_s, 2)},
+           "partitions": {"min": int(min(parts)), "max": int(max(parts)),
+                          "total": int(sum(parts))},
+           "eager_stage_ms": stages}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -281,6 +370,9 @@ def main():
         sys.exit(2)
     if args.learned:
         run_learned(args)
+        return
+    if args.batched:
+        run_batched(args)
         return
     import numpy as np
     import torch

@@ -14,6 +14,7 @@ from .streams import (  # noqa: F401
     config_large,
     config_outer,
     config_batched,
+    config_batched_stream,
     config_learned_train,
     config_learned_heldout,
     tiny_transactions,

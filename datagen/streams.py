@@ -242,19 +242,23 @@ def config_outer(seed: int = 3, K: int = 100_000, n: int = 200_000) -> OuterProd
     return outer_products(K, n, n, 2.0, 2000, Raw(seed), "outer")
 
 
+def config_batched_stream(s: int, base_seed: int = 4000, t_lo: float = 1e3,
+                          t_hi: float = 2e5) -> Transactions:
+    """Stream s of the batched configuration: T log-uniform in [t_lo, t_hi],
+    n ~ U[5e3, 5e4], Zipf s ~ U[0.8, 1.3], lengths Geom(mean 10) <= 64, seed
+    base_seed + s."""
+    rng = Raw(base_seed + s)
+    u = rng.uniform(2)
+    T = int(math.floor(math.exp(math.log(t_lo) + u[0] * (math.log(t_hi) - math.log(t_lo)))))
+    n = int(rng.randint(1, 5000, 50000)[0])
+    zs = 0.8 + 0.5 * float(u[1])
+    return transactions(T, n, zs, 10.0, 64, rng, f"batched{s}")
+
+
 def config_batched(n_streams: int = 256, base_seed: int = 4000,
                    t_lo: float = 1e3, t_hi: float = 2e5):
-    """Independent streams: T log-uniform in [t_lo, t_hi], n ~ U[5e3, 5e4],
-    Zipf s ~ U[0.8, 1.3], lengths Geom(mean 10) <= 64.  One seed per stream."""
-    out = []
-    for s in range(n_streams):
-        rng = Raw(base_seed + s)
-        u = rng.uniform(2)
-        T = int(math.floor(math.exp(math.log(t_lo) + u[0] * (math.log(t_hi) - math.log(t_lo)))))
-        n = int(rng.randint(1, 5000, 50000)[0])
-        zs = 0.8 + 0.5 * float(u[1])
-        out.append(transactions(T, n, zs, 10.0, 64, rng, f"batched{s}"))
-    return out
+    """Independent streams (config_batched_stream), one seed per stream."""
+    return [config_batched_stream(s, base_seed, t_lo, t_hi) for s in range(n_streams)]
 
 
 def config_learned_train(i: int, T: int = 1_000_000) -> Transactions:
