@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define CROP_ABI_VERSION 1
+#define CROP_ABI_VERSION 2
 
 typedef enum crop_status {
     CROP_OK = 0,
@@ -67,11 +67,15 @@ typedef struct crop_ctx crop_ctx;
 /* Tuning knobs; a zero field means "choose automatically". */
 typedef struct crop_tune {
     uint32_t bins_per_partition; /* routing bins per partition (S >= 1)       */
-    uint32_t table_slots;        /* LDS hash-table slots per aggregation
-                                    workgroup; power of two, 1024..16384      */
-    uint32_t rows_per_chunk;     /* vectors per enumeration workgroup         */
-    uint32_t block_threads;      /* threads per workgroup: 256, 512 or 1024   */
+    uint32_t rows_per_chunk;     /* transactions per enumeration chunk        */
+    uint32_t stage_keys;         /* scatter: keys staged in LDS per window    */
+    uint32_t route;              /* transactions: CROP_ROUTE_*                */
 } crop_tune;
+
+/* How the routing offsets of a transaction stream are built: one count row
+ * per chunk (a [chunk x bin] matrix), or one row per workgroup that walks a
+ * contiguous range of chunks and keeps its bin cursors in LDS. */
+enum { CROP_ROUTE_AUTO = 0, CROP_ROUTE_CHUNKS = 1, CROP_ROUTE_RANGES = 2 };
 
 /* ---- context ----------------------------------------------------------- */
 
@@ -196,6 +200,24 @@ crop_status crop_synchronize(crop_ctx *ctx);
 /* Device time in milliseconds of the last run, from HIP events recorded on
  * the context stream around its kernels (synchronizes). */
 crop_status crop_last_run_ms(crop_ctx *ctx, float *ms);
+
+/* ---- Count-Sketch ------------------------------------------------------- */
+/* Count-Sketch per bucket (Section 4, "Frequent items mining algorithms";
+ * Section 6, Theorem 3): B buckets per partition, bucket = (h * P * B) >> 32,
+ * one signed counter per bucket; every term adds s(e) * w(e) (s = +-1 from the
+ * sign hash; w = 1 for transactions, a_k(i) b_k(j) for outer products).
+ * `instances` (1..15) independent sketches use the hash parameters of
+ * seed + i.  Counters are int32 for transactions (exact), fp32 for outer
+ * products.  P * B <= 2^32. */
+crop_status crop_run_countsketch(crop_ctx *ctx, uint32_t buckets_per_partition,
+                                 uint32_t instances);
+/* Median over the instances of s_i(e) * C_i[bucket_i(e)] for each query pair
+ * (qx[q], qy[q]); device arrays; est[n] doubles (the mean of the two middle
+ * estimates for an even instance count). */
+crop_status crop_countsketch_estimate(crop_ctx *ctx, const uint32_t *qx, const uint32_t *qy,
+                                      uint64_t n, double *est);
+/* The P * B counters of one instance into a host array (synchronizes). */
+crop_status crop_read_countsketch(crop_ctx *ctx, uint32_t instance, double *out, uint64_t cap);
 
 /* ---- batches of transaction streams ----------------------------------- */
 /* Many independent streams in one exact run.  Each stream is accumulated

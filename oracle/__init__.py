@@ -75,6 +75,9 @@ def lib():
                                      _u32, _u32, _u32, _u32p, _u32p, _u8p, _u8p, _f64p,
                                      _f64p, _f64p]
     L.orc_tx_countsketch.argtypes = [_u32p, _u64, _u32p, _u64, _u32, _u32, _f64p]
+    L.orc_op_bucket_abs.argtypes = [_u32p, _u32p, _f32p, _u32p, _u32p, _f32p, _u64, _u64,
+                                    _u32, _u32, _f64p]
+    L.orc_sign_many.argtypes = [_u64, _u32p, _u32p, _u64, ctypes.POINTER(ctypes.c_int8)]
     L.orc_op_countsketch.argtypes = [_u32p, _u32p, _f32p, _u32p, _u32p, _f32p, _u64, _u64,
                                      _u32, _u32, _f64p]
     _lib = L
@@ -311,6 +314,35 @@ def op_countsketch(op, seed: int, P: int, B: int):
                              _c(op.b_off, np.uint32), _c(op.b_idx, np.uint32),
                              _c(op.b_val, np.float32), a_off.shape[0] - 1, seed, P, B, cs)
     return cs
+
+
+def op_bucket_abs(op, seed: int, P: int, B: int):
+    """Sum of |a_k(i) b_k(j)| per bucket."""
+    a_off = _c(op.a_off, np.uint32)
+    s = np.zeros(P * B, np.float64)
+    lib().orc_op_bucket_abs(a_off, _c(op.a_idx, np.uint32), _c(op.a_val, np.float32),
+                            _c(op.b_off, np.uint32), _c(op.b_idx, np.uint32),
+                            _c(op.b_val, np.float32), a_off.shape[0] - 1, seed, P, B, s)
+    return s
+
+
+def sign_many(seed: int, x, y) -> np.ndarray:
+    """Count-Sketch sign (+1 / -1) of every pair (x[k], y[k])."""
+    x = _c(x, np.uint32)
+    y = _c(y, np.uint32)
+    out = np.zeros(x.shape[0], np.int8)
+    lib().orc_sign_many(seed, x, y, x.shape[0], out.ctypes.data_as(ctypes.POINTER(ctypes.c_int8)))
+    return out.astype(np.int64)
+
+
+def countsketch_estimates(sketches, seeds, P: int, B: int, x, y) -> np.ndarray:
+    """Median over instances of s_i(e) C_i[bucket_i(e)] (Section 4), in fp64."""
+    est = []
+    for cs, seed in zip(sketches, seeds):
+        _, _, h, _ = hash_many(seed, x, y, P)
+        b = bucket_of(h, P, B)
+        est.append(sign_many(seed, x, y) * np.asarray(cs)[b])
+    return np.median(np.stack(est), axis=0)
 
 
 # ---------------------------------------------------------------------------

@@ -476,6 +476,32 @@ void orc_op_countsketch(const uint32_t *a_off, const uint32_t *a_idx, const floa
             }
 }
 
+/* Sum of |a_k(i) b_k(j)| per bucket: the magnitude a bucket's fp32 counter
+ * is compared against (the plain definition, no signs). */
+void orc_op_bucket_abs(const uint32_t *a_off, const uint32_t *a_idx, const float *a_val,
+                       const uint32_t *b_off, const uint32_t *b_idx, const float *b_val,
+                       uint64_t K, uint64_t seed, uint32_t P, uint32_t B, double *s)
+{
+    uint64_t prm[8];
+    orc_hash_params(seed, prm);
+    for (uint64_t k = 0; k < (uint64_t)P * B; ++k) s[k] = 0.0;
+    for (uint64_t k = 0; k < K; ++k)
+        for (uint64_t a = a_off[k]; a < a_off[k + 1]; ++a)
+            for (uint64_t b = b_off[k]; b < b_off[k + 1]; ++b) {
+                double v = (double)a_val[a] * (double)b_val[b];
+                uint64_t bucket = orc_bucket(orc_h(prm, a_idx[a], b_idx[b]), P, B);
+                s[bucket] += fabs(v);
+            }
+}
+
+/* The Count-Sketch sign of many pairs. */
+void orc_sign_many(uint64_t seed, const uint32_t *x, const uint32_t *y, uint64_t n, int8_t *out)
+{
+    uint64_t prm[8];
+    orc_hash_params(seed, prm);
+    for (uint64_t k = 0; k < n; ++k) out[k] = (int8_t)orc_sign(prm, x[k], y[k]);
+}
+
 /* part and bucket of many hash values (for tests and the Python layer) */
 void orc_part_bucket_many(const uint32_t *h, uint64_t n, uint32_t P, uint32_t B,
                           uint32_t *part, uint32_t *bucket)

@@ -39,8 +39,8 @@ class CropError(RuntimeError):
 
 
 class crop_tune(ctypes.Structure):
-    _fields_ = [("bins_per_partition", ctypes.c_uint32), ("table_slots", ctypes.c_uint32),
-                ("rows_per_chunk", ctypes.c_uint32), ("block_threads", ctypes.c_uint32)]
+    _fields_ = [("bins_per_partition", ctypes.c_uint32), ("rows_per_chunk", ctypes.c_uint32),
+                ("stage_keys", ctypes.c_uint32), ("route", ctypes.c_uint32)]
 
 
 # torch ships its own HIP runtime under the same soname (libamdhip64.so.7).
@@ -97,6 +97,9 @@ _SIGS.update({
     "crop_run_topk_seeded": ([_vp, _u32, _vp, _vp, _u64, _u32], _i32),
     "crop_read_topk": ([_vp, _vp, _vp, _vp, _vp, _vp, _u64, _pu64], _i32),
     "crop_read_summary": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64, _pu64], _i32),
+    "crop_run_countsketch": ([_vp, _u32, _u32], _i32),
+    "crop_countsketch_estimate": ([_vp, _vp, _vp, _u64, _vp], _i32),
+    "crop_read_countsketch": ([_vp, _u32, _vp, _u64], _i32),
     "crop_load_batch": ([_vp, _u32, _vp, _vp, _vp, _vp, _i32, _i32], _i32),
     "crop_batch_set_plan": ([_vp, _u32, _u32], _i32),
     "crop_batch_autotune": ([_vp, _u32, ctypes.POINTER(_u32), ctypes.POINTER(_u32),
@@ -233,9 +236,14 @@ def crop_use_own_stream(ctx) -> None:
     _check(ctx, _lib.crop_use_own_stream(ctx))
 
 
-def crop_set_tuning(ctx, bins_per_partition=0, table_slots=0, rows_per_chunk=0,
-                    block_threads=0) -> None:
-    t = crop_tune(bins_per_partition, table_slots, rows_per_chunk, block_threads)
+CROP_ROUTE_AUTO = 0
+CROP_ROUTE_CHUNKS = 1
+CROP_ROUTE_RANGES = 2
+
+
+def crop_set_tuning(ctx, bins_per_partition=0, rows_per_chunk=0, stage_keys=0,
+                    route=CROP_ROUTE_AUTO) -> None:
+    t = crop_tune(bins_per_partition, rows_per_chunk, stage_keys, route)
     _check(ctx, _lib.crop_set_tuning(ctx, ctypes.byref(t)))
 
 
@@ -355,6 +363,24 @@ def crop_read_summary(ctx, n_slots: int):
     n = w.value
     return dict(x=i[:n], y=j[:n], cnt=cnt[:n], err=err[:n], val=val[:n],
                 used=(flags[:n] & 1).astype(bool), pinned=(flags[:n] & 2).astype(bool))
+
+
+# ---- Count-Sketch
+
+def crop_run_countsketch(ctx, buckets_per_partition: int, instances: int) -> None:
+    _check(ctx, _lib.crop_run_countsketch(ctx, buckets_per_partition, instances))
+
+
+def crop_countsketch_estimate(ctx, qx, qy, est) -> None:
+    """qx, qy: uint32/int32 device tensors; est: float64 device tensor."""
+    _check(ctx, _lib.crop_countsketch_estimate(ctx, _dev(qx, "qx"), _dev(qy, "qy"), _len(qx),
+                                               _dev(est, "est")))
+
+
+def crop_read_countsketch(ctx, instance: int, n_buckets: int):
+    out = np.zeros(max(n_buckets, 1), np.float64)
+    _check(ctx, _lib.crop_read_countsketch(ctx, instance, out.ctypes.data, n_buckets))
+    return out[:n_buckets]
 
 
 # ---- batches of transaction streams

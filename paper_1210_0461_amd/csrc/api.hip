@@ -103,7 +103,10 @@ crop_status plan_tx(crop_ctx *ctx, uint32_t S_force = 0)
     pl.S = S;
     pl.NB = P * S;
     const size_t hist_bytes = (size_t)pl.NB * 4;
-    uint32_t R = ctx->tune.rows_per_chunk ? ctx->tune.rows_per_chunk : 128;
+    // 176 transactions per chunk: about 16,000 terms at ten items per
+    // transaction, one staging window of the scatter (measured best on the
+    // 1M-transaction stream among 64..256)
+    uint32_t R = ctx->tune.rows_per_chunk ? ctx->tune.rows_per_chunk : 176;
     auto max_items_for = [&](uint32_t r) {
         uint32_t mx = 0;
         for (uint64_t t0 = 0; t0 < in.T; t0 += r) {
@@ -122,15 +125,35 @@ crop_status plan_tx(crop_ctx *ctx, uint32_t S_force = 0)
     pl.R = R;
     pl.max_items = mi;
     pl.n_chunks = (uint32_t)((in.T + R - 1) / R);
+    const size_t fixed = tx_scatter_smem_bytes(pl.NB, mi, 0, in.wide_keys);
+    const size_t per = in.wide_keys ? 8 : 4;
     {
-        const size_t fixed = tx_scatter_smem_bytes(pl.NB, mi, 0, in.wide_keys);
-        const size_t per = in.wide_keys ? 8 : 4;
         const size_t room = fixed < kStageBudget ? (kStageBudget - fixed) / per : 0;
         if (room < 1024)
             return fail(ctx, CROP_E_UNSUPPORTED, "routing bins and chunk leave no LDS for staging");
         pl.stage_cap = (uint32_t)std::min<size_t>(room, 24576);
     }
-    pl.G = std::max<uint32_t>(1, std::min<uint32_t>(64, pl.n_chunks));
+    // Range kernels (on request): one workgroup per contiguous range of
+    // chunks, as many as fit on the GPU at once.  Two scatter workgroups share
+    // a CU when half of the LDS still stages a typical chunk in one window.
+    pl.n_wg = 0;
+    if (ctx->tune.route == CROP_ROUTE_RANGES && pl.n_chunks) {
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess)
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        const uint64_t avg_terms = pl.n_chunks ? in.total_terms / pl.n_chunks : 0;
+        const size_t half = kCuLds / 2;
+        const size_t room2 = fixed < half ? (half - fixed) / per : 0;
+        uint32_t per_cu = 1;
+        if (room2 >= 1024 && room2 >= avg_terms + avg_terms / 4) {
+            per_cu = 2;
+            pl.stage_cap = (uint32_t)std::min<size_t>(room2, 24576);
+        }
+        pl.n_wg = (uint32_t)std::min<uint64_t>(pl.n_chunks, (uint64_t)cus * per_cu);
+    }
+    if (ctx->tune.stage_keys)
+        pl.stage_cap = std::min<uint32_t>(pl.stage_cap, ctx->tune.stage_keys);
+    pl.G = std::max<uint32_t>(1, std::min<uint32_t>(64, pl.n_wg ? pl.n_wg / 16 : pl.n_chunks));
     return CROP_OK;
 }
 
@@ -153,6 +176,7 @@ crop_status plan_outer(crop_ctx *ctx, uint32_t S_force = 0)
     pl.NB = P * S;
     pl.max_items = in.op_max_a;
     pl.n_chunks = (uint32_t)in.op_chunks.size();
+    pl.n_wg = 0;
     pl.G = std::max<uint32_t>(1, std::min<uint32_t>(64, pl.n_chunks));
     const size_t lds = (size_t)pl.NB * 4 + 20ull * pl.max_items + 1024;
     if (lds > 150 * 1024)
@@ -402,7 +426,7 @@ void crop_destroy(crop_ctx *ctx)
                       &ctx->vals, &ctx->out_cnt, &ctx->spill, &ctx->counter, &ctx->ss_state,
                       &ctx->topk_buf, &ctx->scratch, &ctx->learn_ws, &ctx->in.d_op_chunks,
                       &bt.d_crow, &bt.d_cstream, &bt.d_streams, &bt.d_bin_stream, &bt.tot,
-                      &bt.tiles})
+                      &bt.tiles, &ctx->cs_buf})
         b->release();
     for (DevBuf &b : ctx->in.own) b.release();
     for (StageRec &r : ctx->ring)
@@ -479,11 +503,10 @@ crop_status crop_set_tuning(crop_ctx *ctx, const crop_tune *t)
         ctx->tune = crop_tune{};
         return CROP_OK;
     }
-    if (t->table_slots && (t->table_slots & (t->table_slots - 1)))
-        return fail(ctx, CROP_E_ARG, "table_slots must be a power of two");
-    if (t->block_threads && t->block_threads != 256 && t->block_threads != 512 &&
-        t->block_threads != 1024)
-        return fail(ctx, CROP_E_ARG, "block_threads must be 256, 512 or 1024");
+    if (t->route > CROP_ROUTE_RANGES)
+        return fail(ctx, CROP_E_ARG, "route must be CROP_ROUTE_AUTO, _CHUNKS or _RANGES");
+    if (t->stage_keys && t->stage_keys < 1024)
+        return fail(ctx, CROP_E_ARG, "stage_keys must be 0 (automatic) or at least 1024");
     ctx->tune = *t;
     return CROP_OK;
 }
@@ -525,9 +548,9 @@ crop_status crop_get_tuning(const crop_ctx *ctx, crop_tune *out)
 {
     if (!ctx || !out) return CROP_E_ARG;
     out->bins_per_partition = ctx->plan.S;
-    out->table_slots = 1u << ctx->plan.log2_slots;
     out->rows_per_chunk = ctx->plan.R;
-    out->block_threads = ctx->plan.BS;
+    out->stage_keys = ctx->plan.stage_cap;
+    out->route = ctx->plan.n_wg ? CROP_ROUTE_RANGES : CROP_ROUTE_CHUNKS;
     return CROP_OK;
 }
 
@@ -656,15 +679,19 @@ crop_status crop_run_exact(crop_ctx *ctx)
     uint32_t *cnt = ctx->cnt_mat.as<uint32_t>();
     st = run_begin(ctx);
     if (st != CROP_OK) return st;
-    if (pl.n_chunks) CK(outer ? launch_op_count(ctx, cnt, s) : launch_tx_count(ctx, cnt, s));
+    if (pl.n_chunks) CK(outer ? launch_op_count(ctx, cnt, s)
+                              : pl.n_wg ? launch_tx_count_ranges(ctx, cnt, s)
+                                        : launch_tx_count(ctx, cnt, s));
     STAGE("count");
-    CK(launch_scan_counts(cnt, pl.n_chunks, pl.NB, pl.G, ctx->part_buf.as<uint32_t>(),
+    CK(launch_scan_counts(cnt, pl.n_wg ? pl.n_wg : pl.n_chunks, pl.NB, pl.G,
+                          ctx->part_buf.as<uint32_t>(),
                           ctx->bin_off.as<uint32_t>(), ctx->counter.as<uint32_t>(), s));
     CK(launch_bin_order(pl.NB, ctx->bin_off.as<uint32_t>(), ctx->bin_order.as<uint32_t>(), s));
     STAGE("scan");
     if (pl.n_chunks)
         CK(outer ? launch_op_scatter(ctx, cnt, ctx->keys.p, ctx->vals.as<float>(), s)
-                 : launch_tx_scatter(ctx, cnt, ctx->keys.p, s));
+                 : pl.n_wg ? launch_tx_scatter_ranges(ctx, cnt, ctx->keys.p, s)
+                           : launch_tx_scatter(ctx, cnt, ctx->keys.p, s));
     STAGE("scatter");
     CK(outer ? launch_aggregate_sums(ctx, s) : launch_aggregate_counts(ctx, s));
     STAGE("aggregate");
@@ -719,15 +746,19 @@ static crop_status run_topk_impl(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
         CK(launch_ss_pin(ctx->ss, sx, sy, (uint32_t)ns, tv.dup, r_max, ctx->hp, PB, ctx->ss_ell,
                          tv.n_pinned, s));
     STAGE("init");
-    if (pl.n_chunks) CK(outer ? launch_op_count(ctx, cnt, s) : launch_tx_count(ctx, cnt, s));
+    if (pl.n_chunks) CK(outer ? launch_op_count(ctx, cnt, s)
+                              : pl.n_wg ? launch_tx_count_ranges(ctx, cnt, s)
+                                        : launch_tx_count(ctx, cnt, s));
     STAGE("count");
-    CK(launch_scan_counts(cnt, pl.n_chunks, pl.NB, pl.G, ctx->part_buf.as<uint32_t>(),
+    CK(launch_scan_counts(cnt, pl.n_wg ? pl.n_wg : pl.n_chunks, pl.NB, pl.G,
+                          ctx->part_buf.as<uint32_t>(),
                           ctx->bin_off.as<uint32_t>(), ctx->counter.as<uint32_t>(), s));
     CK(launch_bin_order(pl.NB, ctx->bin_off.as<uint32_t>(), ctx->bin_order.as<uint32_t>(), s));
     STAGE("scan");
     if (pl.n_chunks)
         CK(outer ? launch_op_scatter(ctx, cnt, ctx->keys.p, ctx->vals.as<float>(), s)
-                 : launch_tx_scatter(ctx, cnt, ctx->keys.p, s));
+                 : pl.n_wg ? launch_tx_scatter_ranges(ctx, cnt, ctx->keys.p, s)
+                           : launch_tx_scatter(ctx, cnt, ctx->keys.p, s));
     STAGE("scatter");
     CK(launch_ss_bins(ctx, ctx->ss, nbk, PB, s));
     STAGE("summaries");
@@ -806,6 +837,89 @@ crop_status crop_read_summary(crop_ctx *ctx, uint32_t *i, uint32_t *j, double *c
         if (err) err[q] = outer ? (double)fe : (double)e[q];
         if (value) value[q] = outer ? (double)v[q] : 0.0;
         if (flags) flags[q] = f[q];
+    }
+    return CROP_OK;
+}
+
+// ============================================================== Count-Sketch
+
+crop_status crop_run_countsketch(crop_ctx *ctx, uint32_t buckets_per_partition,
+                                 uint32_t instances)
+{
+    if (!ctx) return CROP_E_ARG;
+    if (ctx->in.mode == Mode::None) return fail(ctx, CROP_E_STATE, "no input loaded");
+    if (ctx->in.mode == Mode::Batch)
+        return fail(ctx, CROP_E_UNSUPPORTED, "Count-Sketch runs take one stream, not a batch");
+    if (instances < 1 || instances > kCsMaxInstances)
+        return fail(ctx, CROP_E_ARG, "instances must be 1..15");
+    if (buckets_per_partition < 1) return fail(ctx, CROP_E_ARG, "need at least one bucket");
+    const uint64_t PB = (uint64_t)ctx->P * buckets_per_partition;
+    if (PB > (1ull << 32))
+        return fail(ctx, CROP_E_UNSUPPORTED, "P x buckets per partition exceeds 2^32");
+    if (PB * instances > (1ull << 34))
+        return fail(ctx, CROP_E_UNSUPPORTED, "Count-Sketch counters exceed 64 GiB");
+    DeviceGuard g(ctx->device);
+    ctx->result = Result::None;
+    const bool outer = ctx->in.mode == Mode::Outer;
+    crop_status st = outer ? plan_outer(ctx) : plan_tx(ctx);
+    if (st != CROP_OK) return st;
+    CsParams &cp = ctx->cs;
+    cp.t = instances;
+    cp.PB = PB;
+    for (uint32_t i = 0; i < instances; ++i) cp.hp[i] = make_hash_params(ctx->seed + i);
+    ctx->cs_B = buckets_per_partition;
+    const uint64_t words = PB * instances;
+    CK(ctx->cs_buf.ensure(words * 4));
+    hipStream_t s = ctx->stream;
+    st = run_begin(ctx);
+    if (st != CROP_OK) return st;
+    CK(launch_cs_clear(ctx->cs_buf.p, words, s));
+    STAGE("clear");
+    if (outer)
+        CK(launch_cs_op(ctx, cp, ctx->cs_buf.as<float>(), s));
+    else
+        CK(launch_cs_tx(ctx, cp, ctx->cs_buf.as<int32_t>(), s));
+    STAGE("sketch");
+    st = run_end(ctx);
+    if (st != CROP_OK) return st;
+    ctx->result = Result::CountSketch;
+    ctx->topk_outer = outer ? 1u : 0u;
+    return CROP_OK;
+}
+
+crop_status crop_countsketch_estimate(crop_ctx *ctx, const uint32_t *qx, const uint32_t *qy,
+                                      uint64_t n, double *est)
+{
+    if (!ctx || (n && (!qx || !qy || !est))) return CROP_E_ARG;
+    if (ctx->result != Result::CountSketch)
+        return fail(ctx, CROP_E_STATE, "no Count-Sketch: call crop_run_countsketch first");
+    DeviceGuard g(ctx->device);
+    CK(launch_cs_estimate(ctx->cs, ctx->cs_buf.p, ctx->topk_outer != 0, qx, qy, n, est,
+                          ctx->stream));
+    return CROP_OK;
+}
+
+crop_status crop_read_countsketch(crop_ctx *ctx, uint32_t instance, double *out, uint64_t cap)
+{
+    if (!ctx || !out) return CROP_E_ARG;
+    if (ctx->result != Result::CountSketch)
+        return fail(ctx, CROP_E_STATE, "no Count-Sketch: call crop_run_countsketch first");
+    if (instance >= ctx->cs.t) return fail(ctx, CROP_E_ARG, "instance out of range");
+    const uint64_t PB = ctx->cs.PB;
+    if (cap < PB) return fail(ctx, CROP_E_CAPACITY, "capacity below P x buckets");
+    DeviceGuard g(ctx->device);
+    std::vector<uint32_t> raw(PB);
+    CK(hipStreamSynchronize(ctx->stream));
+    CK(hipMemcpy(raw.data(), ctx->cs_buf.as<uint32_t>() + instance * PB, PB * 4,
+                 hipMemcpyDeviceToHost));
+    for (uint64_t k = 0; k < PB; ++k) {
+        if (ctx->topk_outer) {
+            float f;
+            std::memcpy(&f, &raw[k], 4);
+            out[k] = f;
+        } else {
+            out[k] = (double)(int32_t)raw[k];
+        }
     }
     return CROP_OK;
 }

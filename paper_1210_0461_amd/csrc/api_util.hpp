@@ -16,6 +16,7 @@ constexpr uint32_t kMaxP = 8192;
 constexpr uint64_t kTermsPerBin = 30000;   // routed terms per bin the auto plan aims at
 constexpr size_t kLdsBudget = 64 * 1024;   // enumeration kernels' staging budget
 constexpr size_t kStageBudget = 150 * 1024; // scatter kernel: dynamic LDS in total
+constexpr size_t kCuLds = 160 * 1024;       // LDS of one CU
 constexpr uint64_t kSsMinBins = 2048;       // Space-Saving bins wanted for parallelism
 constexpr size_t kSsLdsBudget = 80 * 1024;  // two summary workgroups per CU
 

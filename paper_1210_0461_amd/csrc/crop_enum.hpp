@@ -1,0 +1,231 @@
+// Enumeration of the terms of a chunk, shared by the routing kernels and the
+// Count-Sketch kernels.
+//
+// Transactions (Section 7): the terms of a transaction are its pairs x < y.
+// Entries of a chunk are staged in LDS with h_b precomputed and ordered by
+// their partner count, and every lane loops over the partners of one entry
+// (stage_tx / enum_tx).
+// Outer products (Section 4): the terms of vector pair k are all
+// (a_k(i), b_k(j)); the a-entries are staged and the b-entries read through
+// L2, with the same balanced walk over w = |b_k| per a-entry (stage_op /
+// walk_op).
+#pragma once
+#include "crop_device.hpp"
+#include "crop_hash.hpp"
+#include "crop_internal.hpp"
+
+namespace crop {
+
+// ---------------------------------------------------------------- staging
+
+// LDS image of a chunk of transactions.  For entry k (its position inside
+// the chunk): xh[k] = (item, h_b(item)); w[k] = its partners, the entries
+// after it in its transaction; perm = the entries in order of decreasing w
+// (a 64-bucket counting sort).  Each lane owns one entry and loops over its
+// w partners; because consecutive lanes take consecutive entries of perm,
+// the lanes of a wavefront run loops of nearly equal length and the loop
+// body has no divergent branch.
+struct TxLds {
+    uint2 *xh;
+    uint16_t *w;
+    uint16_t *perm;
+    uint32_t *bucket;  // 64 words
+};
+
+template <int BS>
+__device__ inline uint32_t stage_tx(const uint32_t *__restrict__ off,
+                                    const uint32_t *__restrict__ items, uint32_t r0, uint32_t r1,
+                                    const HashParams &hp, const TxLds &L)
+{
+    const uint32_t p0 = off[r0];
+    const uint32_t m = off[r1] - p0;
+    for (uint32_t k = threadIdx.x; k < m; k += BS) {
+        uint32_t x = items[p0 + k];
+        L.xh[k] = make_uint2(x, hash_b(hp, x));
+    }
+    if (threadIdx.x < 64) L.bucket[threadIdx.x] = 0;
+    __syncthreads();
+    for (uint32_t r = r0 + threadIdx.x; r < r1; r += BS) {
+        uint32_t a = off[r] - p0, e = off[r + 1] - p0;
+        for (uint32_t k = a; k < e; ++k) {
+            uint32_t w = e - k - 1;
+            L.w[k] = (uint16_t)w;
+            atomicAdd(&L.bucket[63 - min(w, 63u)], 1u);
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 64) {
+        uint32_t v = L.bucket[threadIdx.x];
+        L.bucket[threadIdx.x] = wave_inclusive_scan(v) - v;
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < m; k += BS) {
+        uint32_t w = L.w[k];
+        L.perm[atomicAdd(&L.bucket[63 - min(w, 63u)], 1u)] = (uint16_t)k;
+    }
+    __syncthreads();
+    return m;
+}
+
+// visit(x, y, h) for every pair x < y of the staged chunk.
+template <int BS, class Visit>
+__device__ inline void enum_tx(uint32_t m, const TxLds &L, const HashParams &hp, Visit visit)
+{
+    for (uint32_t j = threadIdx.x; j < m; j += BS) {
+        const uint32_t k = L.perm[j];
+        const uint32_t w = L.w[k];
+        if (w == 0) break;  // perm is sorted: every later entry of this thread has w == 0
+        const uint32_t x = L.xh[k].x;
+        const uint32_t ha = hash_a(hp, x);
+        for (uint32_t d = 1; d <= w; ++d) {
+            const uint2 yh = L.xh[k + d];
+            visit(x, yh.x, ha + yh.y);
+        }
+    }
+}
+
+// LDS layout of a chunk image after `lead` words, in 32-bit words: xh (two
+// words per entry, 8-byte aligned), then w and perm (u16 each, both padded to
+// an even count so that bucket stays 4-byte aligned for its atomics), then
+// the 64 bucket words.
+struct TxLayout {
+    size_t xh, w, perm, bucket, end;  // word offsets
+};
+
+__host__ __device__ inline TxLayout tx_layout(uint32_t lead, uint32_t max_items)
+{
+    TxLayout t;
+    const size_t half = (max_items + 1) / 2;  // words of one padded u16 array
+    t.xh = (lead + 1) & ~1u;
+    t.w = t.xh + 2 * (size_t)max_items;
+    t.perm = t.w + half;
+    t.bucket = t.perm + half;
+    t.end = t.bucket + 64;
+    return t;
+}
+
+__device__ inline TxLds tx_lds(uint32_t *smem, uint32_t lead, uint32_t max_items)
+{
+    const TxLayout t = tx_layout(lead, max_items);
+    TxLds L;
+    L.xh = reinterpret_cast<uint2 *>(smem + t.xh);
+    L.w = reinterpret_cast<uint16_t *>(smem + t.w);
+    L.perm = reinterpret_cast<uint16_t *>(smem + t.perm);
+    L.bucket = smem + t.bucket;
+    return L;
+}
+
+__host__ __device__ inline size_t tx_lds_words(uint32_t lead, uint32_t max_items)
+{
+    return tx_layout(lead, max_items).end;
+}
+
+template <class KeyT>
+__device__ inline KeyT pack_key(uint32_t x, uint32_t y)
+{
+    if (sizeof(KeyT) == 4) return (KeyT)((x << 16) | y);
+    return (KeyT)(((uint64_t)x << 32) | y);
+}
+
+template <class KeyT>
+__device__ inline uint32_t bin_of_key(KeyT key, const HashParams &hp, uint32_t NB)
+{
+    uint32_t x, y;
+    if (sizeof(KeyT) == 4) {
+        x = (uint32_t)key >> 16;
+        y = (uint32_t)key & 0xFFFFu;
+    } else {
+        x = (uint32_t)((uint64_t)key >> 32);
+        y = (uint32_t)key;
+    }
+    return interval_of(hash_a(hp, x) + hash_b(hp, y), NB);
+}
+
+// ---- outer products
+
+// Stage the a-entries [a_lo, a_hi) of vectors k0..k1-1: s_ai = index,
+// s_ha = h_a, s_av = value, s_bs = first b-entry of the vector, s_wp =
+// exclusive prefix of |b_k| per a-entry.
+template <int BS>
+__device__ uint32_t stage_op(const OpChunk ch, const uint32_t *__restrict__ a_off,
+                             const uint32_t *__restrict__ a_idx, const float *__restrict__ a_val,
+                             const uint32_t *__restrict__ b_off, const HashParams &hp,
+                             uint32_t *s_ai, uint32_t *s_ha, float *s_av, uint32_t *s_bs,
+                             uint32_t *s_wp, uint32_t *s_tmp, uint32_t *m_out)
+{
+    const uint32_t m = ch.a_hi - ch.a_lo;
+    for (uint32_t k = threadIdx.x; k < m; k += BS) {
+        uint32_t i = a_idx[ch.a_lo + k];
+        s_ai[k] = i;
+        s_ha[k] = hash_a(hp, i);
+        s_av[k] = a_val[ch.a_lo + k];
+    }
+    for (uint32_t v = ch.k0 + threadIdx.x; v < ch.k1; v += BS) {
+        uint32_t a = max(a_off[v], ch.a_lo), e = min(a_off[v + 1], ch.a_hi);
+        uint32_t bs = b_off[v], nb = b_off[v + 1] - bs;
+        for (uint32_t p = a; p < e; ++p) {
+            s_bs[p - ch.a_lo] = bs;
+            s_wp[p - ch.a_lo] = nb;
+        }
+    }
+    __syncthreads();
+    lds_exclusive_scan<BS>(s_wp, m, s_tmp);
+    *m_out = m;
+    return s_wp[m];
+}
+
+template <int BS, class Visit>
+__device__ inline void walk_op(uint32_t Tc, uint32_t m, const uint32_t *s_ai, const uint32_t *s_ha,
+                               const float *s_av, const uint32_t *s_bs, const uint32_t *s_wp,
+                               const uint32_t *__restrict__ b_idx, const float *__restrict__ b_val,
+                               const HashParams &hp, Visit visit)
+{
+    const uint32_t t0 = (uint32_t)(((uint64_t)Tc * threadIdx.x) / BS);
+    const uint32_t t1 = (uint32_t)(((uint64_t)Tc * (threadIdx.x + 1)) / BS);
+    if (t0 >= t1) return;
+    uint32_t lo = 0, hi = m;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (s_wp[mid] <= t0) lo = mid; else hi = mid;
+    }
+    uint32_t k = lo;
+    uint32_t q = s_bs[k] + (t0 - s_wp[k]);
+    uint32_t e = s_bs[k] + (s_wp[k + 1] - s_wp[k]);
+    uint32_t i = s_ai[k], ha = s_ha[k];
+    float av = s_av[k];
+    for (uint32_t t = t0; t < t1; ++t) {
+        uint32_t j = b_idx[q];
+        visit(i, j, ha + hash_b(hp, j), av * b_val[q]);
+        if (++q == e && t + 1 < t1) {
+            do { ++k; } while (s_wp[k + 1] == s_wp[k]);
+            q = s_bs[k];
+            e = q + (s_wp[k + 1] - s_wp[k]);
+            i = s_ai[k];
+            ha = s_ha[k];
+            av = s_av[k];
+        }
+    }
+}
+
+struct OpArgs {
+    const uint32_t *a_off, *a_idx, *b_off, *b_idx;
+    const float *a_val, *b_val;
+    const OpChunk *chunks;
+};
+
+template <int BS>
+__device__ inline uint32_t *op_smem_layout(uint32_t *smem, uint32_t NB, uint32_t max_a,
+                                           uint32_t **s_ai, uint32_t **s_ha, float **s_av,
+                                           uint32_t **s_bs, uint32_t **s_wp, uint32_t **s_tmp)
+{
+    uint32_t *hist = smem;
+    *s_ai = hist + NB;
+    *s_ha = *s_ai + max_a;
+    *s_av = reinterpret_cast<float *>(*s_ha + max_a);
+    *s_bs = reinterpret_cast<uint32_t *>(*s_av + max_a);
+    *s_wp = *s_bs + max_a;
+    *s_tmp = *s_wp + max_a + 1;
+    return hist;
+}
+
+}  // namespace crop

@@ -12,7 +12,7 @@
 namespace crop {
 
 enum class Mode { None = 0, Tx = 1, Outer = 2, Batch = 3 };
-enum class Result { None = 0, Exact = 1, TopK = 2, BatchExact = 3 };
+enum class Result { None = 0, Exact = 1, TopK = 2, BatchExact = 3, CountSketch = 4 };
 
 // A device allocation that grows on demand (never shrinks).
 struct DevBuf {
@@ -53,6 +53,8 @@ struct RoutePlan {
     uint32_t max_items = 0;  // largest number of staged entries in a chunk
     uint32_t stage_cap = 0;  // scatter: terms staged in LDS per window
     uint32_t G = 1;          // row groups of the count-matrix scan
+    uint32_t n_wg = 0;       // transactions: workgroups of the range kernels
+                             // (0: one count row per chunk)
     uint32_t log2_slots = 14;
     uint32_t BS = 256;
 };
@@ -94,6 +96,14 @@ struct BatchDev {
     const BatchStreamDev *streams = nullptr;
     const uint32_t *bin_stream = nullptr; // stream of each global bin
     uint32_t n_chunks = 0, n_streams = 0, NBtot = 0, NBmax = 0, max_items = 0, stage_cap = 0;
+};
+
+// Count-Sketch instances: hash parameters of instance i from seed + i.
+constexpr uint32_t kCsMaxInstances = 15;
+struct CsParams {
+    HashParams hp[kCsMaxInstances];
+    uint32_t t;   // instances
+    uint64_t PB;  // buckets per instance (P * B)
 };
 
 // Space-Saving state in device memory, bucket-major with ell slots per
@@ -177,6 +187,9 @@ struct crop_ctx {
         counter;
     crop::DevBuf ss_state, topk_buf, scratch, learn_ws;
     crop::BatchState batch;    // batched streams
+    crop::DevBuf cs_buf;       // Count-Sketch counters [t][P * B]
+    crop::CsParams cs{};       // ... of the last Count-Sketch run
+    uint32_t cs_B = 0;
     crop::SsState ss;          // views into ss_state
     uint64_t ss_buckets = 0;   // P * B of the last top-K run
     uint32_t topk_outer = 0;   // the last top-K run was on outer products
@@ -202,6 +215,11 @@ hipError_t launch_validate_outer(const uint32_t *v_off, uint64_t K, const uint32
                                  hipStream_t s);
 
 hipError_t launch_tx_count(const crop_ctx *c, uint32_t *cnt, hipStream_t s);
+// Range kernels: n_wg workgroups, each over a contiguous range of chunks;
+// the count matrix is [n_wg x NB].
+hipError_t launch_tx_count_ranges(const crop_ctx *c, uint32_t *cnt, hipStream_t s);
+hipError_t launch_tx_scatter_ranges(const crop_ctx *c, const uint32_t *cur, void *keys,
+                                    hipStream_t s);
 hipError_t launch_tx_scatter(const crop_ctx *c, const uint32_t *cur, void *keys, hipStream_t s);
 hipError_t launch_op_count(const crop_ctx *c, uint32_t *cnt, hipStream_t s);
 hipError_t launch_op_scatter(const crop_ctx *c, const uint32_t *cur, void *keys, float *vals,
@@ -245,6 +263,15 @@ hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, bool by_lower, 
                        uint32_t *hist,
                        uint32_t *cand, uint32_t *sel, uint32_t *oi, uint32_t *oj, double *ou,
                        double *ol, double *ov, hipStream_t s);
+
+size_t tx_count_smem_bytes(uint32_t NB, uint32_t max_items);
+
+// Count-Sketch (k_cs.hip).
+hipError_t launch_cs_clear(void *cs, uint64_t words, hipStream_t s);
+hipError_t launch_cs_tx(const crop_ctx *c, const CsParams &cp, int32_t *cs, hipStream_t s);
+hipError_t launch_cs_op(const crop_ctx *c, const CsParams &cp, float *cs, hipStream_t s);
+hipError_t launch_cs_estimate(const CsParams &cp, const void *cs, bool fp, const uint32_t *qx,
+                              const uint32_t *qy, uint64_t n, double *out, hipStream_t s);
 
 // Learned seeding (k_learned.hip).
 size_t item_stats_words(uint32_t n, uint32_t Tp);

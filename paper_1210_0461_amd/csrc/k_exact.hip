@@ -309,6 +309,55 @@ __device__ inline void packed_dump(const uint64_t *tab, uint32_t *keys_out, uint
     }
 }
 
+// Further rounds over a bin's spilled (key, weight) pairs until none is
+// left: each round fills the emptied table up to cap_soft and dumps it.
+template <int BS, int LOG2S>
+__device__ void packed_spill_rounds(uint64_t *tab, Spilled<uint32_t, uint32_t> *spill,
+                                    uint32_t k0, uint32_t *keys, uint32_t *w_out,
+                                    uint32_t cap_soft, uint32_t *s_occ_p, uint32_t *s_nout,
+                                    uint32_t *s_nspill_p, int *s_insert_p)
+{
+    constexpr uint32_t S = 1u << LOG2S;
+    constexpr uint32_t MASK = S - 1;
+    uint32_t &s_occ = *s_occ_p;
+    uint32_t &s_nspill = *s_nspill_p;
+    int &s_insert = *s_insert_p;
+    while (s_nspill != 0) {
+        const uint32_t n = s_nspill;
+        __syncthreads();
+        for (uint32_t s = threadIdx.x; s < S; s += BS) tab[s] = kFreeSlot;
+        if (threadIdx.x == 0) {
+            s_occ = 0;
+            s_nspill = 0;
+            s_insert = 1;
+        }
+        __syncthreads();
+        for (uint32_t base = 0; base < n; base += BS) {
+            const uint32_t i = base + threadIdx.x;
+            Spilled<uint32_t, uint32_t> e{kEmpty32, 0u};
+            if (i < n) e = spill[k0 + i];
+            const bool ins = s_insert != 0;
+            __syncthreads();  // the batch is read before any entry is rewritten
+            uint32_t n_new = 0;
+            if (i < n) {
+                const int r = packed_add<MASK, LOG2S>(tab, e.key, e.w, ins);
+                if (r == kInserted) {
+                    n_new = 1;
+                } else if (r == kAbsent) {
+                    const uint32_t p = atomicAdd(&s_nspill, 1u);
+                    spill[k0 + p] = e;
+                }
+            }
+            if (n_new) atomicAdd(&s_occ, 1u);
+            __syncthreads();
+            if (threadIdx.x == 0 && s_occ > cap_soft) s_insert = 0;
+            __syncthreads();
+        }
+        packed_dump<BS, LOG2S>(tab, keys + k0, w_out + k0, s_nout);
+        __syncthreads();
+    }
+}
+
 // One persistent workgroup per CU, 16 wavefronts.  The next batch of keys
 // is loaded into registers while the current one is accumulated, and the
 // batch barriers order LDS only, so the prefetch stays in flight.
@@ -383,11 +432,43 @@ k_aggregate_packed(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ 
                 }
                 live |= (keep ? 1u : 0u) << u;
             }
+            // Fast path: the U home slots are read together (no dependency
+            // between the reads), then a key found there takes its weight and
+            // a free home slot takes a new key.  Only the rest probe further.
+            uint32_t n_new = 0;
+            {
+                uint64_t hv[U];
+                uint32_t hs[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    hs[u] = slot_of(cur[u], LOG2S);
+                    hv[u] = tab[hs[u]];
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (!((live >> u) & 1u)) continue;
+                    const uint32_t k = (uint32_t)hv[u];
+                    if (k == cur[u]) {
+                        atomicAdd(count_word(&tab[hs[u]]), wt[u]);
+                        live &= ~(1u << u);
+                    } else if (k == kEmpty32 && ins) {
+                        const uint64_t old = atomicCAS((unsigned long long *)&tab[hs[u]],
+                                                       (unsigned long long)kFreeSlot,
+                                                       ((unsigned long long)wt[u] << 32) | cur[u]);
+                        if (old == kFreeSlot) {
+                            ++n_new;
+                            live &= ~(1u << u);
+                        } else if ((uint32_t)old == cur[u]) {
+                            atomicAdd(count_word(&tab[hs[u]]), wt[u]);
+                            live &= ~(1u << u);
+                        }
+                    }
+                }
+            }
             // Each lane runs its U keys back to back through one probing loop:
             // a lane that settles a key starts its next key at the next step,
             // so a wavefront waits for the longest lane's total probe count,
             // not for the longest probe of every key.
-            uint32_t n_new = 0;
             int j = 0;
             while (j < U && !((live >> j) & 1u)) ++j;
             uint32_t key = 0, w = 0, sl = 0;
@@ -458,40 +539,133 @@ k_aggregate_packed(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ 
         packed_dump<BS, LOG2S>(tab, keys + k0, w_out + k0, &s_nout);
         __syncthreads();
 
-        while (s_nspill != 0) {
-            const uint32_t n = s_nspill;
-            __syncthreads();
-            for (uint32_t s = threadIdx.x; s < S; s += BS) tab[s] = kFreeSlot;
-            if (threadIdx.x == 0) {
-                s_occ = 0;
-                s_nspill = 0;
-                s_insert = 1;
-            }
-            __syncthreads();
-            for (uint32_t base = 0; base < n; base += BS) {
-                const uint32_t i = base + threadIdx.x;
-                Spilled<uint32_t, uint32_t> e{kEmpty32, 0u};
-                if (i < n) e = spill[k0 + i];
-                const bool ins = s_insert != 0;
-                __syncthreads();  // the batch is read before any entry is rewritten
-                uint32_t n_new = 0;
-                if (i < n) {
-                    const int r = packed_add<MASK, LOG2S>(tab, e.key, e.w, ins);
-                    if (r == kInserted) {
-                        n_new = 1;
-                    } else if (r == kAbsent) {
-                        const uint32_t p = atomicAdd(&s_nspill, 1u);
-                        spill[k0 + p] = e;
-                    }
-                }
-                if (n_new) atomicAdd(&s_occ, 1u);
-                __syncthreads();
-                if (threadIdx.x == 0 && s_occ > cap_soft) s_insert = 0;
-                __syncthreads();
-            }
-            packed_dump<BS, LOG2S>(tab, keys + k0, w_out + k0, &s_nout);
-            __syncthreads();
+        packed_spill_rounds<BS, LOG2S>(tab, spill, k0, keys, w_out, cap_soft, &s_occ, &s_nout,
+                                       &s_nspill, &s_insert);
+        if (threadIdx.x == 0) bin_size[b] = s_nout;
+        __syncthreads();
+    }
+}
+
+// Flat variant of the packed aggregation: U keys per thread per batch, the U
+// home slots read together, hits added without waiting for anything,
+// only collisions and new keys going on to probe; one barrier per batch.  The
+// table's occupancy for the insert decision is the sum of the per-batch
+// insert counts of all earlier batches (a ring of three counters: batch q
+// adds into ring[q % 3], zeroes ring[(q + 1) % 3] and reads ring[(q - 1) % 3]
+// after the barrier that ended batch q - 1), so every thread takes the same
+// decision without a second barrier.
+template <int BS, int LOG2S, int U>
+__global__ void __launch_bounds__(BS)
+k_aggregate_flat(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ keys,
+                 uint32_t *__restrict__ w_out, uint32_t *__restrict__ bin_size,
+                 Spilled<uint32_t, uint32_t> *__restrict__ spill, uint32_t NB,
+                 uint32_t *counter, uint32_t cap_soft, const uint32_t *__restrict__ order)
+{
+    constexpr uint32_t S = 1u << LOG2S;
+    constexpr uint32_t MASK = S - 1;
+    static_assert(S % BS == 0, "table size must be a multiple of the block size");
+    static_assert(S > BS * U, "a batch must fit in the table");
+    __shared__ uint64_t tab[S];
+    __shared__ uint32_t s_ring[3];
+    __shared__ uint32_t s_occ, s_nout, s_nspill, s_bin;
+    __shared__ int s_insert;
+    const uint32_t lane = lane_id();
+
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const uint32_t i = atomicAdd(counter, 1u);
+            s_bin = i < NB ? order[i] : NB;
         }
+        __syncthreads();
+        const uint32_t b = s_bin;
+        if (b >= NB) break;
+        const uint32_t k0 = bin_off[b], k1 = bin_off[b + 1];
+        for (uint32_t s = threadIdx.x; s < S; s += BS) tab[s] = kFreeSlot;
+        if (threadIdx.x == 0) {
+            s_ring[0] = s_ring[1] = s_ring[2] = 0;
+            s_nout = 0;
+            s_nspill = 0;
+        }
+        const uint32_t last = k1 - 1;  // read only when the bin is not empty
+        uint32_t cur[U] = {};
+        if (k1 > k0) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) cur[u] = keys[min(k0 + u * BS + threadIdx.x, last)];
+        }
+        lds_barrier();
+        uint32_t occ = 0;  // inserts of the batches before the previous one
+        uint32_t q = 0;
+        for (uint32_t base = k0; base < k1; base += BS * U, ++q) {
+            uint32_t nx[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                nx[u] = keys[min(base + BS * U + u * BS + threadIdx.x, last)];
+            if (q) occ += s_ring[(q + 2) % 3];  // the previous batch's inserts
+            if (threadIdx.x == 0) s_ring[(q + 1) % 3] = 0;
+            const bool ins = occ <= cap_soft;  // at most cap_soft + BS * U keys in the table
+            uint64_t v[U];
+            uint32_t hs[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                hs[u] = slot_of(cur[u], LOG2S);
+                v[u] = tab[hs[u]];
+            }
+            uint32_t pend = 0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool valid = base + u * BS + threadIdx.x < k1;
+                if (!valid) continue;
+                if ((uint32_t)v[u] == cur[u])
+                    atomicAdd(count_word(&tab[hs[u]]), 1u);
+                else
+                    pend |= 1u << u;
+            }
+            uint32_t n_new = 0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (!((pend >> u) & 1u)) continue;
+                const uint32_t key = cur[u];
+                uint32_t sl = hs[u];
+                uint64_t val = v[u];
+                for (;;) {
+                    const uint32_t k = (uint32_t)val;
+                    if (k == key) {
+                        atomicAdd(count_word(&tab[sl]), 1u);
+                        break;
+                    }
+                    if (k == kEmpty32) {
+                        if (!ins) {
+                            const uint32_t p = atomicAdd(&s_nspill, 1u);
+                            spill[k0 + p] = Spilled<uint32_t, uint32_t>{key, 1u};
+                            break;
+                        }
+                        const uint64_t old = atomicCAS((unsigned long long *)&tab[sl],
+                                                       (unsigned long long)kFreeSlot,
+                                                       (1ull << 32) | key);
+                        if (old == kFreeSlot) {
+                            ++n_new;
+                            break;
+                        }
+                        val = old;  // taken meanwhile: look at the new occupant
+                        continue;
+                    }
+                    sl = (sl + 1) & MASK;
+                    val = tab[sl];
+                }
+            }
+            uint32_t tot = n_new;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) tot += __shfl_xor(tot, d, kWave);
+            if (lane == 0 && tot) atomicAdd(&s_ring[q % 3], tot);
+            lds_barrier();
+#pragma unroll
+            for (int u = 0; u < U; ++u) cur[u] = nx[u];
+        }
+        __syncthreads();  // keys of the bin are consumed; the spill list is complete
+        packed_dump<BS, LOG2S>(tab, keys + k0, w_out + k0, &s_nout);
+        __syncthreads();
+        packed_spill_rounds<BS, LOG2S>(tab, spill, k0, keys, w_out, cap_soft, &s_occ, &s_nout,
+                                       &s_nspill, &s_insert);
         if (threadIdx.x == 0) bin_size[b] = s_nout;
         __syncthreads();
     }
@@ -508,9 +682,13 @@ static uint32_t persistent_grid(uint32_t NB)
     return NB < g ? NB : g;
 }
 
-// 10240 + one batch of 4096 keys = at most 14336 of 16384 slots in use.
-constexpr uint32_t kPackedCapSoft = 10240;
-static_assert(kPackedCapSoft + 1024 * 4 < (1u << 14), "packed table must keep free slots");
+// Keys per thread and batch of the flat aggregation.  A batch starts
+// inserting only while the table holds at most kPackedCapSoft keys, so it
+// never holds more than kPackedCapSoft + 1024 * kFlatU: that must leave free
+// slots, or a probe could run forever.
+constexpr int kFlatU = 4;
+constexpr uint32_t kPackedCapSoft = (1u << 14) - 1024 * kFlatU - 1024;
+static_assert(kPackedCapSoft + 1024 * kFlatU < (1u << 14), "packed table must keep free slots");
 
 hipError_t launch_aggregate_counts(const crop_ctx *c, hipStream_t s)
 {
@@ -518,7 +696,7 @@ hipError_t launch_aggregate_counts(const crop_ctx *c, hipStream_t s)
     uint32_t grid = persistent_grid(pl.NB);
     if (!c->in.wide_keys) {
         constexpr int L = 14;
-        hipLaunchKernelGGL((k_aggregate_packed<1024, L>), dim3(grid), dim3(1024), 0, s,
+        hipLaunchKernelGGL((k_aggregate_flat<1024, L, kFlatU>), dim3(grid), dim3(1024), 0, s,
                            c->bin_off.as<uint32_t>(), c->keys.as<uint32_t>(),
                            c->out_cnt.as<uint32_t>(), c->bin_size.as<uint32_t>(),
                            c->spill.as<Spilled<uint32_t, uint32_t>>(), pl.NB,

@@ -14,146 +14,14 @@
 // cheaper than moving the terms twice: a term is a few ALU operations on
 // staged LDS data, while its key costs HBM traffic.
 //
-// Enumeration inside a chunk.  Transactions (Section 7): the terms of a
-// transaction are its pairs x < y.  Entries of a chunk are staged in LDS with
-// h_b precomputed and ordered by their partner count, and every lane loops
-// over the partners of one entry (stage_tx / enum_tx below).
-// Outer products (Section 4): the terms of vector pair k are all
-// (a_k(i), b_k(j)); the a-entries are staged and the b-entries read through
-// L2, with the same balanced walk over w = |b_k| per a-entry.
+// The enumeration inside a chunk is in crop_enum.hpp.
 #include "crop_device.hpp"
+#include "crop_enum.hpp"
 #include "crop_internal.hpp"
 
 namespace crop {
 
 namespace {
-
-// ---------------------------------------------------------------- staging
-
-// LDS image of a chunk of transactions.  For entry k (its position inside
-// the chunk): xh[k] = (item, h_b(item)); w[k] = its partners, the entries
-// after it in its transaction; perm = the entries in order of decreasing w
-// (a 64-bucket counting sort).  Each lane owns one entry and loops over its
-// w partners; because consecutive lanes take consecutive entries of perm,
-// the lanes of a wavefront run loops of nearly equal length and the loop
-// body has no divergent branch.
-struct TxLds {
-    uint2 *xh;
-    uint16_t *w;
-    uint16_t *perm;
-    uint32_t *bucket;  // 64 words
-};
-
-template <int BS>
-__device__ inline uint32_t stage_tx(const uint32_t *__restrict__ off,
-                                    const uint32_t *__restrict__ items, uint32_t r0, uint32_t r1,
-                                    const HashParams &hp, const TxLds &L)
-{
-    const uint32_t p0 = off[r0];
-    const uint32_t m = off[r1] - p0;
-    for (uint32_t k = threadIdx.x; k < m; k += BS) {
-        uint32_t x = items[p0 + k];
-        L.xh[k] = make_uint2(x, hash_b(hp, x));
-    }
-    if (threadIdx.x < 64) L.bucket[threadIdx.x] = 0;
-    __syncthreads();
-    for (uint32_t r = r0 + threadIdx.x; r < r1; r += BS) {
-        uint32_t a = off[r] - p0, e = off[r + 1] - p0;
-        for (uint32_t k = a; k < e; ++k) {
-            uint32_t w = e - k - 1;
-            L.w[k] = (uint16_t)w;
-            atomicAdd(&L.bucket[63 - min(w, 63u)], 1u);
-        }
-    }
-    __syncthreads();
-    if (threadIdx.x < 64) {
-        uint32_t v = L.bucket[threadIdx.x];
-        L.bucket[threadIdx.x] = wave_inclusive_scan(v) - v;
-    }
-    __syncthreads();
-    for (uint32_t k = threadIdx.x; k < m; k += BS) {
-        uint32_t w = L.w[k];
-        L.perm[atomicAdd(&L.bucket[63 - min(w, 63u)], 1u)] = (uint16_t)k;
-    }
-    __syncthreads();
-    return m;
-}
-
-// visit(x, y, h) for every pair x < y of the staged chunk.
-template <int BS, class Visit>
-__device__ inline void enum_tx(uint32_t m, const TxLds &L, const HashParams &hp, Visit visit)
-{
-    for (uint32_t j = threadIdx.x; j < m; j += BS) {
-        const uint32_t k = L.perm[j];
-        const uint32_t w = L.w[k];
-        if (w == 0) break;  // perm is sorted: every later entry of this thread has w == 0
-        const uint32_t x = L.xh[k].x;
-        const uint32_t ha = hash_a(hp, x);
-        for (uint32_t d = 1; d <= w; ++d) {
-            const uint2 yh = L.xh[k + d];
-            visit(x, yh.x, ha + yh.y);
-        }
-    }
-}
-
-// LDS layout of a chunk image after `lead` words, in 32-bit words: xh (two
-// words per entry, 8-byte aligned), then w and perm (u16 each, both padded to
-// an even count so that bucket stays 4-byte aligned for its atomics), then
-// the 64 bucket words.
-struct TxLayout {
-    size_t xh, w, perm, bucket, end;  // word offsets
-};
-
-__host__ __device__ inline TxLayout tx_layout(uint32_t lead, uint32_t max_items)
-{
-    TxLayout t;
-    const size_t half = (max_items + 1) / 2;  // words of one padded u16 array
-    t.xh = (lead + 1) & ~1u;
-    t.w = t.xh + 2 * (size_t)max_items;
-    t.perm = t.w + half;
-    t.bucket = t.perm + half;
-    t.end = t.bucket + 64;
-    return t;
-}
-
-__device__ inline TxLds tx_lds(uint32_t *smem, uint32_t lead, uint32_t max_items)
-{
-    const TxLayout t = tx_layout(lead, max_items);
-    TxLds L;
-    L.xh = reinterpret_cast<uint2 *>(smem + t.xh);
-    L.w = reinterpret_cast<uint16_t *>(smem + t.w);
-    L.perm = reinterpret_cast<uint16_t *>(smem + t.perm);
-    L.bucket = smem + t.bucket;
-    return L;
-}
-
-__host__ __device__ inline size_t tx_lds_words(uint32_t lead, uint32_t max_items)
-{
-    return tx_layout(lead, max_items).end;
-}
-
-template <class KeyT>
-__device__ inline KeyT pack_key(uint32_t x, uint32_t y)
-{
-    if (sizeof(KeyT) == 4) return (KeyT)((x << 16) | y);
-    return (KeyT)(((uint64_t)x << 32) | y);
-}
-
-template <class KeyT>
-__device__ inline uint32_t bin_of_key(KeyT key, const HashParams &hp, uint32_t NB)
-{
-    uint32_t x, y;
-    if (sizeof(KeyT) == 4) {
-        x = (uint32_t)key >> 16;
-        y = (uint32_t)key & 0xFFFFu;
-    } else {
-        x = (uint32_t)((uint64_t)key >> 32);
-        y = (uint32_t)key;
-    }
-    return interval_of(hash_a(hp, x) + hash_b(hp, y), NB);
-}
-
-// ---------------------------------------------------------------- kernels
 
 // ---------------------------------------------------------------- chunks
 
@@ -308,91 +176,128 @@ k_tx_scatter(const uint32_t *__restrict__ off, const uint32_t *__restrict__ item
     }
 }
 
-// ---- outer products
+// ---- chunk ranges: one workgroup per contiguous range of chunks
 
-// Stage the a-entries [a_lo, a_hi) of vectors k0..k1-1: s_ai = index,
-// s_ha = h_a, s_av = value, s_bs = first b-entry of the vector, s_wp =
-// exclusive prefix of |b_k| per a-entry.
-template <int BS>
-__device__ uint32_t stage_op(const OpChunk ch, const uint32_t *__restrict__ a_off,
-                             const uint32_t *__restrict__ a_idx, const float *__restrict__ a_val,
-                             const uint32_t *__restrict__ b_off, const HashParams &hp,
-                             uint32_t *s_ai, uint32_t *s_ha, float *s_av, uint32_t *s_bs,
-                             uint32_t *s_wp, uint32_t *s_tmp, uint32_t *m_out)
+// The range of chunks of workgroup w when n_chunks chunks are split over
+// n_wg workgroups.
+__device__ inline void chunk_range(uint32_t w, uint32_t n_wg, uint32_t n_chunks, uint32_t *c0,
+                                   uint32_t *c1)
 {
-    const uint32_t m = ch.a_hi - ch.a_lo;
-    for (uint32_t k = threadIdx.x; k < m; k += BS) {
-        uint32_t i = a_idx[ch.a_lo + k];
-        s_ai[k] = i;
-        s_ha[k] = hash_a(hp, i);
-        s_av[k] = a_val[ch.a_lo + k];
-    }
-    for (uint32_t v = ch.k0 + threadIdx.x; v < ch.k1; v += BS) {
-        uint32_t a = max(a_off[v], ch.a_lo), e = min(a_off[v + 1], ch.a_hi);
-        uint32_t bs = b_off[v], nb = b_off[v + 1] - bs;
-        for (uint32_t p = a; p < e; ++p) {
-            s_bs[p - ch.a_lo] = bs;
-            s_wp[p - ch.a_lo] = nb;
-        }
+    *c0 = (uint32_t)(((uint64_t)n_chunks * w) / n_wg);
+    *c1 = (uint32_t)(((uint64_t)n_chunks * (w + 1)) / n_wg);
+}
+
+// Count over a range of chunks: one histogram row per workgroup, so the
+// count matrix is [n_wg x NB] rather than [chunk x NB].
+template <int BS>
+__global__ void __launch_bounds__(BS)
+k_tx_count_ranges(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
+                  HashParams hp, uint32_t NB, uint32_t max_items, uint32_t T, uint32_t R,
+                  uint32_t n_chunks, uint32_t *__restrict__ cnt)
+{
+    extern __shared__ uint32_t smem[];
+    uint32_t *hist = smem;
+    const TxLds L = tx_lds(smem, NB, max_items);
+    const uint32_t w = xcd_contiguous(blockIdx.x, gridDim.x);
+    uint32_t c0, c1;
+    chunk_range(w, gridDim.x, n_chunks, &c0, &c1);
+    for (uint32_t b = threadIdx.x; b < NB; b += BS) hist[b] = 0;
+    for (uint32_t c = c0; c < c1; ++c) {
+        __syncthreads();  // the previous chunk's image is no longer read
+        const uint32_t r0 = c * R, r1 = min(r0 + R, T);
+        const uint32_t m = stage_tx<BS>(off, items, r0, r1, hp, L);
+        enum_tx<BS>(m, L, hp, [&](uint32_t, uint32_t, uint32_t h) {
+            atomicAdd(&hist[interval_of(h, NB)], 1u);
+        });
     }
     __syncthreads();
-    lds_exclusive_scan<BS>(s_wp, m, s_tmp);
-    *m_out = m;
-    return s_wp[m];
+    uint32_t *row = cnt + (size_t)w * NB;
+    for (uint32_t b = threadIdx.x; b < NB; b += BS) row[b] = hist[b];
 }
 
-template <int BS, class Visit>
-__device__ inline void walk_op(uint32_t Tc, uint32_t m, const uint32_t *s_ai, const uint32_t *s_ha,
-                               const float *s_av, const uint32_t *s_bs, const uint32_t *s_wp,
-                               const uint32_t *__restrict__ b_idx, const float *__restrict__ b_val,
-                               const HashParams &hp, Visit visit)
+// Scatter over the same ranges.  The workgroup keeps its write cursor of
+// every bin in LDS (started from its row of the scanned count matrix) and,
+// chunk by chunk, counts the chunk's terms per bin, places them in LDS
+// grouped by bin and writes the runs at the cursors.  Chunk ranges and their
+// order are those of k_tx_count_ranges, so every workgroup writes exactly
+// the slots its count reserved.
+template <int BS, class KeyT>
+__global__ void __launch_bounds__(BS)
+k_tx_scatter_ranges(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
+                    HashParams hp, uint32_t NB, uint32_t max_items, uint32_t T, uint32_t R,
+                    uint32_t n_chunks, const uint32_t *__restrict__ cur,
+                    KeyT *__restrict__ keys, uint32_t cap)
 {
-    const uint32_t t0 = (uint32_t)(((uint64_t)Tc * threadIdx.x) / BS);
-    const uint32_t t1 = (uint32_t)(((uint64_t)Tc * (threadIdx.x + 1)) / BS);
-    if (t0 >= t1) return;
-    uint32_t lo = 0, hi = m;
-    while (hi - lo > 1) {
-        uint32_t mid = (lo + hi) >> 1;
-        if (s_wp[mid] <= t0) lo = mid; else hi = mid;
-    }
-    uint32_t k = lo;
-    uint32_t q = s_bs[k] + (t0 - s_wp[k]);
-    uint32_t e = s_bs[k] + (s_wp[k + 1] - s_wp[k]);
-    uint32_t i = s_ai[k], ha = s_ha[k];
-    float av = s_av[k];
-    for (uint32_t t = t0; t < t1; ++t) {
-        uint32_t j = b_idx[q];
-        visit(i, j, ha + hash_b(hp, j), av * b_val[q]);
-        if (++q == e && t + 1 < t1) {
-            do { ++k; } while (s_wp[k + 1] == s_wp[k]);
-            q = s_bs[k];
-            e = q + (s_wp[k + 1] - s_wp[k]);
-            i = s_ai[k];
-            ha = s_ha[k];
-            av = s_av[k];
+    extern __shared__ uint32_t smem[];
+    uint32_t *gcur = smem;                 // NB: global cursor of each bin
+    uint32_t *lstart = smem + NB;          // NB + 1: local start of each bin's run
+    uint32_t *lpos = smem + 2 * NB + 1;    // NB: local cursor
+    const uint32_t lead = 3 * NB + 1;
+    const TxLds L = tx_lds(smem, lead, max_items);
+    KeyT *stage =
+        reinterpret_cast<KeyT *>(smem + ((tx_lds_words(lead, max_items) + 1) & ~(size_t)1));
+    __shared__ uint32_t s_tmp[BS / kWave + 1];
+    __shared__ uint32_t s_b1, s_direct;
+
+    const uint32_t w = xcd_contiguous(blockIdx.x, gridDim.x);
+    uint32_t c0, c1;
+    chunk_range(w, gridDim.x, n_chunks, &c0, &c1);
+    for (uint32_t b = threadIdx.x; b < NB; b += BS) gcur[b] = cur[(size_t)w * NB + b];
+    for (uint32_t c = c0; c < c1; ++c) {
+        __syncthreads();  // previous chunk: runs written, cursors advanced
+        for (uint32_t b = threadIdx.x; b < NB; b += BS) lstart[b] = 0;
+        const uint32_t r0 = c * R, r1 = min(r0 + R, T);
+        const uint32_t m = stage_tx<BS>(off, items, r0, r1, hp, L);  // ends with a barrier
+        enum_tx<BS>(m, L, hp, [&](uint32_t, uint32_t, uint32_t h) {
+            atomicAdd(&lstart[interval_of(h, NB)], 1u);
+        });
+        __syncthreads();
+        lds_exclusive_scan<BS>(lstart, NB, s_tmp);
+        const uint32_t Tc = lstart[NB];
+        for (uint32_t b = threadIdx.x; b < NB; b += BS) lpos[b] = lstart[b];
+        __syncthreads();
+        for (uint32_t b0 = 0; b0 < NB && Tc;) {
+            if (threadIdx.x == 0) {
+                // last b1 in [b0, NB] with lstart[b1] - lstart[b0] <= cap; an
+                // empty window means bin b0 alone exceeds cap
+                const uint32_t lim = lstart[b0] + cap;
+                uint32_t lo = b0, hi = NB + 1;
+                while (hi - lo > 1) {
+                    const uint32_t mid = (lo + hi) >> 1;
+                    if (lstart[mid] <= lim) lo = mid; else hi = mid;
+                }
+                s_direct = lo == b0 ? 1u : 0u;
+                s_b1 = lo == b0 ? b0 + 1 : lo;
+            }
+            __syncthreads();
+            const uint32_t b1 = s_b1;
+            const bool direct = s_direct != 0;
+            const uint32_t s0 = lstart[b0];
+            const bool whole = b0 == 0 && b1 == NB;
+            enum_tx<BS>(m, L, hp, [&](uint32_t x, uint32_t y, uint32_t h) {
+                const uint32_t bin = interval_of(h, NB);
+                if (!whole && (bin < b0 || bin >= b1)) return;
+                const uint32_t p = atomicAdd(&lpos[bin], 1u);
+                const KeyT key = pack_key<KeyT>(x, y);
+                if (direct)
+                    keys[gcur[bin] + (p - lstart[bin])] = key;
+                else
+                    stage[p - s0] = key;
+            });
+            __syncthreads();
+            if (!direct) {
+                const uint32_t n = lstart[b1] - s0;
+                for (uint32_t i = threadIdx.x; i < n; i += BS) {
+                    const KeyT key = stage[i];
+                    const uint32_t bin = bin_of_key(key, hp, NB);
+                    keys[gcur[bin] + (i + s0 - lstart[bin])] = key;
+                }
+            }
+            __syncthreads();
+            b0 = b1;
         }
+        for (uint32_t b = threadIdx.x; b < NB; b += BS) gcur[b] += lstart[b + 1] - lstart[b];
     }
-}
-
-struct OpArgs {
-    const uint32_t *a_off, *a_idx, *b_off, *b_idx;
-    const float *a_val, *b_val;
-    const OpChunk *chunks;
-};
-
-template <int BS>
-__device__ inline uint32_t *op_smem_layout(uint32_t *smem, uint32_t NB, uint32_t max_a,
-                                           uint32_t **s_ai, uint32_t **s_ha, float **s_av,
-                                           uint32_t **s_bs, uint32_t **s_wp, uint32_t **s_tmp)
-{
-    uint32_t *hist = smem;
-    *s_ai = hist + NB;
-    *s_ha = *s_ai + max_a;
-    *s_av = reinterpret_cast<float *>(*s_ha + max_a);
-    *s_bs = reinterpret_cast<uint32_t *>(*s_av + max_a);
-    *s_wp = *s_bs + max_a;
-    *s_tmp = *s_wp + max_a + 1;
-    return hist;
 }
 
 template <int BS>
@@ -713,6 +618,35 @@ hipError_t launch_tx_scatter(const crop_ctx *c, const uint32_t *cur, void *keys,
         hipLaunchKernelGGL((k_tx_scatter<1024, uint32_t, SingleChunks>), dim3(pl.n_chunks),
                            dim3(1024), sm, s, c->in.off, c->in.items, c->hp, pl.NB, pl.max_items,
                            ch, static_cast<uint32_t *>(keys), pl.stage_cap);
+    return hipGetLastError();
+}
+
+hipError_t launch_tx_count_ranges(const crop_ctx *c, uint32_t *cnt, hipStream_t s)
+{
+    const RoutePlan &pl = c->plan;
+    size_t sm = tx_count_smem_bytes(pl.NB, pl.max_items);
+    hipLaunchKernelGGL(k_tx_count_ranges<1024>, dim3(pl.n_wg), dim3(1024), sm, s, c->in.off,
+                       c->in.items, c->hp, pl.NB, pl.max_items, (uint32_t)c->in.T, pl.R,
+                       pl.n_chunks, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_tx_scatter_ranges(const crop_ctx *c, const uint32_t *cur, void *keys,
+                                    hipStream_t s)
+{
+    const RoutePlan &pl = c->plan;
+    const bool wide = c->in.wide_keys;
+    size_t sm = tx_scatter_smem_bytes(pl.NB, pl.max_items, pl.stage_cap, wide);
+    if (wide)
+        hipLaunchKernelGGL((k_tx_scatter_ranges<1024, uint64_t>), dim3(pl.n_wg), dim3(1024), sm,
+                           s, c->in.off, c->in.items, c->hp, pl.NB, pl.max_items,
+                           (uint32_t)c->in.T, pl.R, pl.n_chunks, cur,
+                           static_cast<uint64_t *>(keys), pl.stage_cap);
+    else
+        hipLaunchKernelGGL((k_tx_scatter_ranges<1024, uint32_t>), dim3(pl.n_wg), dim3(1024), sm,
+                           s, c->in.off, c->in.items, c->hp, pl.NB, pl.max_items,
+                           (uint32_t)c->in.T, pl.R, pl.n_chunks, cur,
+                           static_cast<uint32_t *>(keys), pl.stage_cap);
     return hipGetLastError();
 }
 

@@ -120,7 +120,10 @@ def test_tuning_does_not_change_results(crop, ctx):
     st = datagen.tiny_transactions(5, T=3000, n=300, cap=30, mean_len=9.0)
     ref = None
     for tune in (dict(), dict(bins_per_partition=4), dict(rows_per_chunk=16),
-                 dict(bins_per_partition=7, rows_per_chunk=100)):
+                 dict(bins_per_partition=7, rows_per_chunk=100),
+                 dict(route=crop.CROP_ROUTE_RANGES),
+                 dict(route=crop.CROP_ROUTE_RANGES, rows_per_chunk=32, stage_keys=1024),
+                 dict(route=crop.CROP_ROUTE_CHUNKS, stage_keys=1024)):
         run_tx(crop, ctx, st, 8, **tune)
         i, j, c, _ = crop.crop_read_all(ctx, 8)
         cur = sort_xyc(i, j, c)

@@ -204,6 +204,47 @@ def _sign_words(seed, x, y):
     return out
 
 
+def test_sign_many_matches_python_sign_words():
+    x = np.array([0, 1, 5, 65535, 4000000000], np.uint32)
+    y = np.array([1, 2, 9, 70000, 4000000001], np.uint32)
+    want = [1 if (g >> 31) == 0 else -1 for g in _sign_words(SEED, x, y)]
+    assert oracle.sign_many(SEED, x, y).tolist() == want
+
+
+def test_countsketch_estimates_isolated_and_median():
+    """With isolated buckets every instance's estimate is the exact weight, so
+    the median is too; the median of three instances lies between their
+    smallest and largest estimates."""
+    st = datagen.tiny_transactions(4, T=30, n=15, cap=6)
+    exact, r = exact_lookup(st)
+    P, B, seeds = 16, 4096, [SEED, SEED + 1, SEED + 2]
+    sk = [oracle.tx_countsketch(st.off, st.items, sd, P, B) for sd in seeds]
+    est = oracle.countsketch_estimates(sk, seeds, P, B, r["x"], r["y"])
+    per = []
+    for cs, sd in zip(sk, seeds):
+        _, _, h, _ = oracle.hash_many(sd, r["x"], r["y"])
+        per.append(oracle.sign_many(sd, r["x"], r["y"]) * cs[oracle.bucket_of(h, P, B)])
+    per = np.stack(per)
+    assert np.all(est >= per.min(axis=0)) and np.all(est <= per.max(axis=0))
+    alone = np.all(per == r["cnt"][None, :].astype(np.float64), axis=0)
+    assert alone.mean() > 0.9
+    assert np.array_equal(est[alone], r["cnt"][alone].astype(np.float64))
+
+
+def test_op_bucket_abs_totals_and_bounds():
+    op = datagen.tiny_outer(6, K=40, n_rows=30, n_cols=25, max_nnz=8)
+    P, B = 2, 8
+    s = oracle.op_bucket_abs(op, SEED, P, B)
+    cs = oracle.op_countsketch(op, SEED, P, B)
+    tot = 0.0
+    for k in range(op.K):
+        a = op.a_val[op.a_off[k]:op.a_off[k + 1]].astype(np.float64)
+        b = op.b_val[op.b_off[k]:op.b_off[k + 1]].astype(np.float64)
+        tot += np.abs(np.outer(a, b)).sum()
+    assert abs(s.sum() - tot) <= 1e-9 * tot
+    assert np.all(np.abs(cs) <= s + 1e-9 * tot)
+
+
 def test_topk_ties_and_recall():
     keys = np.array([50, 10, 30, 20, 40, 60], np.uint64)
     w = np.array([5, 7, 5, 5, 1, 7])
