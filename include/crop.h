@@ -68,7 +68,9 @@ typedef struct crop_ctx crop_ctx;
 typedef struct crop_tune {
     uint32_t bins_per_partition; /* routing bins per partition (S >= 1)       */
     uint32_t rows_per_chunk;     /* transactions per enumeration chunk        */
-    uint32_t stage_keys;         /* scatter: keys staged in LDS per window    */
+    uint32_t stage_keys;         /* scatter: 0 writes every key straight to
+                                    its slot; >= 1024 stages up to that many
+                                    keys per window in LDS, sorted by bin     */
     uint32_t route;              /* transactions: CROP_ROUTE_*                */
 } crop_tune;
 

@@ -119,15 +119,9 @@ crop_status plan_batch(crop_ctx *ctx, uint32_t tpb, uint32_t R)
         sd[s] = BatchStreamDev{b.P[s], b.bin_base[s], b.chunk0[s], b.n_chunks[s], b.cnt_base[s]};
         for (uint32_t k = 0; k < b.P[s]; ++k) bin_stream[b.bin_base[s] + k] = s;
     }
-    uint32_t stage_cap;
-    {
-        const size_t fixed = tx_scatter_smem_bytes(NBmax, mi, 0, in.wide_keys);
-        const size_t per = in.wide_keys ? 8 : 4;
-        const size_t room = fixed < kStageBudget ? (kStageBudget - fixed) / per : 0;
-        if (room < 1024)
-            return fail(ctx, CROP_E_UNSUPPORTED, "routing bins and chunk leave no LDS for staging");
-        stage_cap = (uint32_t)std::min<size_t>(room, 24576);
-    }
+    const uint32_t stage_cap = 0;  // direct scatter writes (as for single streams)
+    if (tx_scatter_smem_bytes(NBmax, mi, 0, in.wide_keys) > kStageBudget)
+        return fail(ctx, CROP_E_UNSUPPORTED, "routing bins and chunk do not fit in LDS");
     CK(b.d_crow.ensure(crow.size() * 4));
     CK(b.d_cstream.ensure(std::max<size_t>(cstream.size(), 1) * 4));
     CK(b.d_streams.ensure(std::max<size_t>(n, 1) * sizeof(BatchStreamDev)));

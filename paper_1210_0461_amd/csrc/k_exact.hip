@@ -620,7 +620,33 @@ k_aggregate_flat(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ ke
                 else
                     pend |= 1u << u;
             }
+            // New keys whose home slot was free: all compare-and-swaps are
+            // issued before any result is looked at.
             uint32_t n_new = 0;
+            if (ins) {
+                uint64_t old[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    old[u] = v[u];
+                    if (((pend >> u) & 1u) && (uint32_t)v[u] == kEmpty32)
+                        old[u] = atomicCAS((unsigned long long *)&tab[hs[u]],
+                                           (unsigned long long)kFreeSlot,
+                                           (1ull << 32) | cur[u]);
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (!((pend >> u) & 1u) || (uint32_t)v[u] != kEmpty32) continue;
+                    if (old[u] == kFreeSlot) {
+                        ++n_new;
+                        pend &= ~(1u << u);
+                    } else if ((uint32_t)old[u] == cur[u]) {
+                        atomicAdd(count_word(&tab[hs[u]]), 1u);
+                        pend &= ~(1u << u);
+                    } else {
+                        v[u] = old[u];  // another key took the home slot: probe on
+                    }
+                }
+            }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (!((pend >> u) & 1u)) continue;

@@ -96,12 +96,15 @@ k_tx_count(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
     for (uint32_t b = threadIdx.x; b < NB; b += BS) cv.row[b] = hist[b];
 }
 
-// Scatter with LDS staging.  The chunk's terms of a window of bins are put
-// in LDS sorted by bin (each bin's local run starts at its local offset),
-// then written out run by run, so consecutive lanes store consecutive
-// addresses.  A window holds at most `cap` terms; a bin with more terms than
-// that in one chunk is written directly.  Windows are set by bin, a property
-// of the term itself, so each term lands in exactly one window.
+// Scatter.  Every term takes a slot of its bin's run in this chunk with an
+// LDS atomic on the bin's local cursor and, with cap == 0, is written
+// straight to that slot (the L2 merges the chunk's neighbouring keys of a
+// bin into whole lines).  With cap > 0 the chunk's terms of a window of bins
+// are put in LDS sorted by bin first and written out run by run, so
+// consecutive lanes store consecutive addresses; a window holds at most cap
+// terms, a bin with more terms than that in one chunk is written directly,
+// and windows are set by bin, a property of the term itself, so each term
+// lands in exactly one window.
 template <int BS, class KeyT, class Chunks>
 __global__ void __launch_bounds__(BS)
 k_tx_scatter(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items, HashParams hp,
@@ -136,7 +139,10 @@ k_tx_scatter(const uint32_t *__restrict__ off, const uint32_t *__restrict__ item
     if (Tc == 0) return;
 
     for (uint32_t b0 = 0; b0 < NB;) {
-        if (threadIdx.x == 0) {
+        if (threadIdx.x == 0 && cap == 0) {
+            s_direct = 1u;  // no staging: every term goes straight to its slot
+            s_b1 = NB;
+        } else if (threadIdx.x == 0) {
             // last b1 in [b0, NB] with lstart[b1] - lstart[b0] <= cap (lstart is
             // non-decreasing); an empty window means bin b0 alone exceeds cap
             const uint32_t lim = lstart[b0] + cap;
@@ -257,7 +263,10 @@ k_tx_scatter_ranges(const uint32_t *__restrict__ off, const uint32_t *__restrict
         for (uint32_t b = threadIdx.x; b < NB; b += BS) lpos[b] = lstart[b];
         __syncthreads();
         for (uint32_t b0 = 0; b0 < NB && Tc;) {
-            if (threadIdx.x == 0) {
+            if (threadIdx.x == 0 && cap == 0) {
+                s_direct = 1u;
+                s_b1 = NB;
+            } else if (threadIdx.x == 0) {
                 // last b1 in [b0, NB] with lstart[b1] - lstart[b0] <= cap; an
                 // empty window means bin b0 alone exceeds cap
                 const uint32_t lim = lstart[b0] + cap;
