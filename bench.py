@@ -52,6 +52,8 @@ def parse():
                          "whole stream also gives the recall and equality checks")
     ap.add_argument("--learned", action="store_true",
                     help="run the learned-seeding comparison instead of the exact bench")
+    ap.add_argument("--shards", type=int, default=0,
+                    help="time each of G owned-partition shares of the exact run")
     ap.add_argument("--batched", action="store_true",
                     help="time the 256-stream batched exact run instead of the exact bench")
     ap.add_argument("--train-streams", type=int, default=20)
@@ -358,6 +360,65 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def run_shards(args):
+    """One GPU's share of a G-GPU run: the exact path owning P/G partitions of
+    the 1M-transaction stream (every term enumerated, 1/G routed and kept),
+    for each of the G shares, against the whole run."""
+    import numpy as np
+    import torch
+    import datagen
+    import paper_1210_0461_amd as crop
+    G = args.shards
+    st = datagen.config_large()
+    dev = torch.device("cuda:0")
+    off = torch.from_numpy(st.off.view(np.int32)).to(dev)
+    items = torch.from_numpy(st.items.view(np.int32)).to(dev)
+    stream = torch.cuda.Stream(device=dev)
+    ctx = crop.crop_create(0)
+    out = {"experiment": f"one GPU's share of a {G}-GPU run (owned partitions)",
+           "P": P, "shards": G}
+    try:
+        crop.crop_set_stream(ctx, stream)
+        crop.crop_set_partitions(ctx, P)
+        crop.crop_set_seed(ctx, SEED)
+        crop.crop_load_transactions(ctx, off, items, st.n, own=crop.CROP_OWN_BORROW)
+        crop.crop_set_profiling(ctx, True)
+
+        def timed(p0, p1):
+            crop.crop_set_owned_partitions(ctx, p0, p1)
+            for _ in range(2):
+                crop.crop_run_exact(ctx)
+            torch.cuda.synchronize(dev)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                crop.crop_run_exact(ctx)
+            e1.record(stream)
+            torch.cuda.synchronize(dev)
+            stages = {}
+            for back in range(min(args.steps, 64)):
+                for name, ms in crop.crop_run_stages(ctx, back):
+                    stages.setdefault(name, []).append(ms)
+            _, terms = crop.crop_result_sizes(ctx, P)
+            return (e0.elapsed_time(e1) / args.steps, int(terms.sum()),
+                    {k: round(sum(v) / len(v), 4) for k, v in stages.items()})
+
+        full_ms, full_terms, full_st = timed(0, P)
+        out["full"] = {"ms": round(full_ms, 4), "terms": full_terms, "stage_ms": full_st}
+        shares = []
+        for g in range(G):
+            ms, terms, stg = timed(g * P // G, (g + 1) * P // G)
+            shares.append({"partitions": [g * P // G, (g + 1) * P // G], "ms": round(ms, 4),
+                           "terms": terms, "stage_ms": stg})
+        out["shares"] = shares
+        out["max_share_ms"] = max(x["ms"] for x in shares)
+        out["speedup_bound_at_G"] = round(full_ms / out["max_share_ms"], 2)
+    finally:
+        crop.crop_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.calibrate_copy:
@@ -373,6 +434,9 @@ def main():
         return
     if args.batched:
         run_batched(args)
+        return
+    if args.shards:
+        run_shards(args)
         return
     import numpy as np
     import torch

@@ -108,6 +108,13 @@ crop_status crop_set_seed(crop_ctx *ctx, uint64_t seed);
  * ell in [1, 64]; counters_per_partition a multiple of ell. */
 crop_status crop_set_summary(crop_ctx *ctx, uint32_t counters_per_partition,
                              uint32_t counters_per_bucket);
+/* Own only partitions [p_begin, p_end) (0, 0: all, the default): exact runs
+ * then enumerate every term but route and keep only those whose hash lies in
+ * the owned interval [ceil(p_begin 2^32 / P), ceil(p_end 2^32 / P)) -- the
+ * share of one processor in Section 5 (Lemma 1) and Section 6 (Theorem 1).
+ * Partitions outside the range read back empty.  crop_set_partitions resets
+ * the range; top-K and Count-Sketch runs reject an owned range. */
+crop_status crop_set_owned_partitions(crop_ctx *ctx, uint32_t p_begin, uint32_t p_end);
 /* Order of the top-K report: by upper bound (the Space-Saving count, the
  * default) or by lower bound (count - overestimation, the guaranteed part of
  * the count; Section 4), ties by smaller key either way. */

@@ -77,6 +77,7 @@ _SIGS = {
     "crop_set_stream": ([_vp, _vp], _i32),
     "crop_use_own_stream": ([_vp], _i32),
     "crop_set_topk_rank": ([_vp, _i32], _i32),
+    "crop_set_owned_partitions": ([_vp, _u32, _u32], _i32),
     "crop_set_tuning": ([_vp, ctypes.POINTER(crop_tune)], _i32),
     "crop_get_tuning": ([_vp, ctypes.POINTER(crop_tune)], _i32),
     "crop_load_transactions": ([_vp, _vp, _u64, _vp, _u64, _u32, _i32, _i32], _i32),
@@ -226,6 +227,10 @@ def crop_set_stream(ctx, stream) -> None:
 
 CROP_RANK_UPPER = 0
 CROP_RANK_LOWER = 1
+
+
+def crop_set_owned_partitions(ctx, p_begin: int, p_end: int) -> None:
+    _check(ctx, _lib.crop_set_owned_partitions(ctx, p_begin, p_end))
 
 
 def crop_set_topk_rank(ctx, rank: int) -> None:

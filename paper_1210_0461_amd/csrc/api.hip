@@ -87,21 +87,48 @@ void reset_input(crop_ctx *ctx)
 
 // ---- planning -------------------------------------------------------------
 
-crop_status plan_tx(crop_ctx *ctx, uint32_t S_force = 0)
+// Owned partitions [p0, p1) of the context (all by default).
+static void owned_range(const crop_ctx *ctx, uint32_t *p0, uint32_t *p1)
+{
+    const bool all = ctx->own_p0 == 0 && ctx->own_p1 == 0;
+    *p0 = all ? 0 : ctx->own_p0;
+    *p1 = all ? ctx->P : ctx->own_p1;
+}
+
+// Bins of the run: P * S over the hash space, of which the owned partitions'
+// S bins each are kept.  S aims at kTermsPerBin routed terms per bin, and
+// the kept bins must fit the count kernels' LDS histogram (kMaxP words).
+static crop_status plan_bins(crop_ctx *ctx, uint32_t S, uint64_t terms_per_bin)
 {
     Input &in = ctx->in;
     RoutePlan &pl = ctx->plan;
     const uint32_t P = ctx->P;
-    uint32_t S = S_force ? S_force : ctx->tune.bins_per_partition;
+    uint32_t p0, p1;
+    owned_range(ctx, &p0, &p1);
+    const uint32_t Pown = p1 - p0;
     if (S == 0) {
-        uint64_t want = (in.total_terms + kTermsPerBin - 1) / kTermsPerBin;
+        const uint64_t want = (in.total_terms + terms_per_bin - 1) / terms_per_bin;
         S = (uint32_t)std::max<uint64_t>(1, (want + P - 1) / P);
-        while (S > 1 && (uint64_t)P * S > kMaxP) --S;
+        while (S > 1 && (uint64_t)Pown * S > kMaxP) --S;
     }
-    if ((uint64_t)P * S > kMaxP)
-        return fail(ctx, CROP_E_UNSUPPORTED, "partitions x bins_per_partition exceeds 8192");
+    if ((uint64_t)Pown * S > kMaxP)
+        return fail(ctx, CROP_E_UNSUPPORTED, "owned partitions x bins_per_partition exceeds 8192");
+    if ((uint64_t)P * S > (1ull << 32))
+        return fail(ctx, CROP_E_UNSUPPORTED, "partitions x bins_per_partition exceeds 2^32");
     pl.S = S;
-    pl.NB = P * S;
+    pl.NB = Pown * S;
+    pl.NBall = (uint64_t)P * S;
+    pl.bin0 = p0 * S;
+    return CROP_OK;
+}
+
+crop_status plan_tx(crop_ctx *ctx, uint32_t S_force = 0)
+{
+    Input &in = ctx->in;
+    RoutePlan &pl = ctx->plan;
+    crop_status st = plan_bins(ctx, S_force ? S_force : ctx->tune.bins_per_partition,
+                               kTermsPerBin);
+    if (st != CROP_OK) return st;
     const size_t hist_bytes = (size_t)pl.NB * 4;
     // 128 transactions per chunk: about 11,000 terms at ten items per
     // transaction (measured best on the 1M-transaction stream among 64..352
@@ -163,19 +190,11 @@ crop_status plan_outer(crop_ctx *ctx, uint32_t S_force = 0)
 {
     Input &in = ctx->in;
     RoutePlan &pl = ctx->plan;
-    const uint32_t P = ctx->P;
-    uint32_t S = S_force ? S_force : ctx->tune.bins_per_partition;
-    if (S == 0) {
-        // outer-product entries rarely repeat and fp32 sums use 8192-slot
-        // tables: aim at about 3000 routed terms per bin
-        uint64_t want = (in.total_terms + kTermsPerBin / 16 - 1) / (kTermsPerBin / 16);
-        S = (uint32_t)std::max<uint64_t>(1, (want + P - 1) / P);
-        while (S > 1 && (uint64_t)P * S > kMaxP) --S;
-    }
-    if ((uint64_t)P * S > kMaxP)
-        return fail(ctx, CROP_E_UNSUPPORTED, "partitions x bins_per_partition exceeds 8192");
-    pl.S = S;
-    pl.NB = P * S;
+    // outer-product entries rarely repeat and fp32 sums use 8192-slot
+    // tables: aim at about 2000 routed terms per bin
+    crop_status st = plan_bins(ctx, S_force ? S_force : ctx->tune.bins_per_partition,
+                               kTermsPerBin / 16);
+    if (st != CROP_OK) return st;
     pl.max_items = in.op_max_a;
     pl.n_chunks = (uint32_t)in.op_chunks.size();
     pl.n_wg = 0;
@@ -244,6 +263,14 @@ crop_status ensure_route_buffers(crop_ctx *ctx, size_t key_bytes, bool sums)
     CK(ctx->spill.ensure(nt * spill_entry_bytes(ctx->in.wide_keys, sums)));
     CK(ctx->counter.ensure(64));
     return CROP_OK;
+}
+
+// First local bin of partition p in the last run, or -1 when p is not owned.
+static int64_t partition_bin(const crop_ctx *ctx, uint32_t p)
+{
+    const RoutePlan &pl = ctx->plan;
+    const uint32_t p0 = pl.bin0 / pl.S, p1 = p0 + pl.NB / pl.S;
+    return (p >= p0 && p < p1) ? (int64_t)(p - p0) * pl.S : -1;
 }
 
 crop_status require_exact(crop_ctx *ctx)
@@ -448,6 +475,7 @@ crop_status crop_set_partitions(crop_ctx *ctx, uint32_t P)
     if (!ctx) return CROP_E_ARG;
     if (P < 1 || P > kMaxP) return fail(ctx, CROP_E_UNSUPPORTED, "P must be in [1, 8192]");
     ctx->P = P;
+    ctx->own_p0 = ctx->own_p1 = 0;  // a new partition count owns all partitions again
     ctx->result = Result::None;
     return CROP_OK;
 }
@@ -470,6 +498,18 @@ crop_status crop_set_summary(crop_ctx *ctx, uint32_t counters_per_partition,
         return fail(ctx, CROP_E_ARG, "need 1 <= ell <= 64 dividing counters_per_partition");
     ctx->ss_counters = counters_per_partition;
     ctx->ss_ell = counters_per_bucket;
+    ctx->result = Result::None;
+    return CROP_OK;
+}
+
+crop_status crop_set_owned_partitions(crop_ctx *ctx, uint32_t p_begin, uint32_t p_end)
+{
+    if (!ctx) return CROP_E_ARG;
+    if (!(p_begin == 0 && p_end == 0) && !(p_begin < p_end && p_end <= ctx->P))
+        return fail(ctx, CROP_E_ARG, "need 0 <= p_begin < p_end <= P (or 0, 0 for all)");
+    ctx->own_p0 = p_begin;
+    ctx->own_p1 = (p_begin == 0 && p_end == ctx->P) ? 0 : p_end;
+    if (ctx->own_p1 == 0) ctx->own_p0 = 0;
     ctx->result = Result::None;
     return CROP_OK;
 }
@@ -710,6 +750,8 @@ static crop_status run_topk_impl(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
     if (ctx->in.mode == Mode::None) return fail(ctx, CROP_E_STATE, "no input loaded");
     if (ctx->in.mode == Mode::Batch)
         return fail(ctx, CROP_E_UNSUPPORTED, "top-K runs take one stream, not a batch");
+    if (ctx->own_p0 || ctx->own_p1)
+        return fail(ctx, CROP_E_UNSUPPORTED, "owned partitions apply to exact runs");
     if (K == 0) return fail(ctx, CROP_E_ARG, "K must be positive");
     if (ns && (!sx || !sy)) return fail(ctx, CROP_E_ARG, "null seed arrays");
     if (ns >= (1ull << 31)) return fail(ctx, CROP_E_UNSUPPORTED, "too many seeds");
@@ -852,6 +894,8 @@ crop_status crop_run_countsketch(crop_ctx *ctx, uint32_t buckets_per_partition,
     if (ctx->in.mode == Mode::None) return fail(ctx, CROP_E_STATE, "no input loaded");
     if (ctx->in.mode == Mode::Batch)
         return fail(ctx, CROP_E_UNSUPPORTED, "Count-Sketch runs take one stream, not a batch");
+    if (ctx->own_p0 || ctx->own_p1)
+        return fail(ctx, CROP_E_UNSUPPORTED, "owned partitions apply to exact runs");
     if (instances < 1 || instances > kCsMaxInstances)
         return fail(ctx, CROP_E_ARG, "instances must be 1..15");
     if (buckets_per_partition < 1) return fail(ctx, CROP_E_ARG, "need at least one bucket");
@@ -1149,10 +1193,14 @@ crop_status crop_result_sizes(crop_ctx *ctx, uint64_t *sizes, uint64_t *terms)
     CK(hipMemcpy(bs.data(), ctx->bin_size.p, pl.NB * 4, hipMemcpyDeviceToHost));
     CK(hipMemcpy(bo.data(), ctx->bin_off.p, (pl.NB + 1) * 4, hipMemcpyDeviceToHost));
     for (uint32_t p = 0; p < ctx->P; ++p) {
-        uint64_t n = 0;
-        for (uint32_t s = 0; s < pl.S; ++s) n += bs[p * pl.S + s];
+        const int64_t b0 = partition_bin(ctx, p);
+        uint64_t n = 0, t = 0;
+        if (b0 >= 0) {
+            for (uint32_t s = 0; s < pl.S; ++s) n += bs[b0 + s];
+            t = (uint64_t)bo[b0 + pl.S] - bo[b0];
+        }
         if (sizes) sizes[p] = n;
-        if (terms) terms[p] = (uint64_t)bo[(p + 1) * pl.S] - bo[p * pl.S];
+        if (terms) terms[p] = t;
     }
     return CROP_OK;
 }
@@ -1175,9 +1223,18 @@ crop_status crop_read_all(crop_ctx *ctx, crop_mem where, uint32_t *i, uint32_t *
         dst[b] = (uint32_t)tot;
         tot += bs[b];
     }
-    if (part_off)
-        for (uint32_t p = 0; p <= ctx->P; ++p)
-            part_off[p] = p < ctx->P ? dst[p * pl.S] : tot;
+    if (part_off) {
+        // partitions outside the owned range are empty
+        uint64_t run = 0;
+        for (uint32_t p = 0; p < ctx->P; ++p) {
+            const int64_t b0 = partition_bin(ctx, p);
+            if (b0 >= 0) run = dst[b0];
+            part_off[p] = run;
+            if (b0 >= 0)
+                for (uint32_t s = 0; s < pl.S; ++s) run += bs[b0 + s];
+        }
+        part_off[ctx->P] = tot;
+    }
     if (written) *written = tot;
     if (tot > cap) return fail(ctx, CROP_E_CAPACITY, "output capacity below the entry count");
     const bool outer = ctx->in.mode == Mode::Outer;
@@ -1223,15 +1280,17 @@ crop_status crop_read_partition(crop_ctx *ctx, uint32_t p, uint32_t *i, uint32_t
     CK(hipStreamSynchronize(ctx->stream));
     CK(hipMemcpy(bs.data(), ctx->bin_size.p, pl.NB * 4, hipMemcpyDeviceToHost));
     CK(hipMemcpy(bo.data(), ctx->bin_off.p, (pl.NB + 1) * 4, hipMemcpyDeviceToHost));
+    const int64_t b0 = partition_bin(ctx, p);
+    const uint32_t nbins = b0 >= 0 ? pl.S : 0;
     uint64_t tot = 0;
-    for (uint32_t s = 0; s < pl.S; ++s) tot += bs[p * pl.S + s];
+    for (uint32_t s = 0; s < nbins; ++s) tot += bs[b0 + s];
     if (written) *written = tot;
     if (tot > cap) return fail(ctx, CROP_E_CAPACITY, "output capacity below the entry count");
     const bool outer = ctx->in.mode == Mode::Outer;
     const bool wide = ctx->in.wide_keys;
     uint64_t w = 0;
-    for (uint32_t s = 0; s < pl.S; ++s) {
-        uint32_t b = p * pl.S + s, n = bs[b], src = bo[b];
+    for (uint32_t s = 0; s < nbins; ++s) {
+        uint32_t b = (uint32_t)b0 + s, n = bs[b], src = bo[b];
         if (!n) continue;
         if (wide) {
             std::vector<uint64_t> k(n);

@@ -47,7 +47,9 @@ struct OpChunk {
 // Resolved routing configuration of a run.
 struct RoutePlan {
     uint32_t S = 1;          // routing bins per partition
-    uint32_t NB = 1;         // routing bins in total (P * S)
+    uint32_t NB = 1;         // routing bins of the run (P * S, or the owned ones)
+    uint64_t NBall = 1;      // bins of the whole hash space (P * S)
+    uint32_t bin0 = 0;       // first bin of the run (owned partitions: p_begin * S)
     uint32_t n_chunks = 0;   // enumeration workgroups
     uint32_t R = 256;        // vectors per chunk (transactions)
     uint32_t max_items = 0;  // largest number of staged entries in a chunk
@@ -170,6 +172,7 @@ struct crop_ctx {
     bool timed = false;
 
     uint32_t P = 1;
+    uint32_t own_p0 = 0, own_p1 = 0;  // owned partitions [own_p0, own_p1); 0, 0: all
     uint64_t seed = 0x243F6A8885A308D3ull;
     crop::HashParams hp{};
     uint32_t ss_counters = 1u << 14;  // counters per partition

@@ -31,6 +31,7 @@ namespace {
 // for its last chunk), which bounds its run in each bin.
 struct ChunkView {
     uint32_t r0, r1, NB;
+    BinMap bm;
     uint32_t *row;
     const uint32_t *nxt;
 };
@@ -38,6 +39,7 @@ struct ChunkView {
 // A single stream: chunk c holds rows [c R, c R + R).
 struct SingleChunks {
     uint32_t T, R, NB, n_chunks;
+    BinMap bm;
     uint32_t *cnt;
     const uint32_t *bin_off;
     __device__ ChunkView view(uint32_t c) const
@@ -46,6 +48,7 @@ struct SingleChunks {
         v.r0 = c * R;
         v.r1 = min(v.r0 + R, T);
         v.NB = NB;
+        v.bm = bm;
         v.row = cnt + (size_t)c * NB;
         v.nxt = c + 1 < n_chunks ? v.row + NB : bin_off + 1;
         return v;
@@ -67,6 +70,7 @@ struct BatchChunks {
         v.r0 = crow[c];
         v.r1 = crow[c + 1];
         v.NB = S.NB;
+        v.bm = BinMap{S.NB, 0};
         v.row = cnt + S.cnt_base + (size_t)(c - S.chunk0) * S.NB;
         v.nxt = c + 1 < S.chunk0 + S.n_chunks ? v.row + S.NB : bin_off + S.bin_base + 1;
         return v;
@@ -90,7 +94,8 @@ k_tx_count(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
     for (uint32_t b = threadIdx.x; b < NB; b += BS) hist[b] = 0;
     const uint32_t m = stage_tx<BS>(off, items, cv.r0, cv.r1, hp, L);
     enum_tx<BS>(m, L, hp, [&](uint32_t, uint32_t, uint32_t h) {
-        atomicAdd(&hist[interval_of(h, NB)], 1u);
+        const uint32_t bin = cv.bm.local(h);
+        if (bin < NB) atomicAdd(&hist[bin], 1u);
     });
     __syncthreads();
     for (uint32_t b = threadIdx.x; b < NB; b += BS) cv.row[b] = hist[b];
@@ -160,8 +165,8 @@ k_tx_scatter(const uint32_t *__restrict__ off, const uint32_t *__restrict__ item
         const uint32_t s0 = lstart[b0];
         const bool whole = b0 == 0 && b1 == NB;
         enum_tx<BS>(m, L, hp, [&](uint32_t x, uint32_t y, uint32_t h) {
-            const uint32_t bin = interval_of(h, NB);
-            if (!whole && (bin < b0 || bin >= b1)) return;
+            const uint32_t bin = cv.bm.local(h);
+            if (bin >= NB || (!whole && (bin < b0 || bin >= b1))) return;
             const uint32_t p = atomicAdd(&lcur[bin], 1u);
             const KeyT key = pack_key<KeyT>(x, y);
             if (direct)
@@ -174,7 +179,7 @@ k_tx_scatter(const uint32_t *__restrict__ off, const uint32_t *__restrict__ item
             const uint32_t n = lstart[b1] - s0;
             for (uint32_t i = threadIdx.x; i < n; i += BS) {
                 const KeyT key = stage[i];
-                keys[i + s0 + delta[bin_of_key(key, hp, NB)]] = key;
+                keys[i + s0 + delta[bin_of_key(key, hp, cv.bm.NBall) - cv.bm.bin0]] = key;
             }
         }
         __syncthreads();
@@ -198,8 +203,8 @@ __device__ inline void chunk_range(uint32_t w, uint32_t n_wg, uint32_t n_chunks,
 template <int BS>
 __global__ void __launch_bounds__(BS)
 k_tx_count_ranges(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
-                  HashParams hp, uint32_t NB, uint32_t max_items, uint32_t T, uint32_t R,
-                  uint32_t n_chunks, uint32_t *__restrict__ cnt)
+                  HashParams hp, uint32_t NB, BinMap bm, uint32_t max_items, uint32_t T,
+                  uint32_t R, uint32_t n_chunks, uint32_t *__restrict__ cnt)
 {
     extern __shared__ uint32_t smem[];
     uint32_t *hist = smem;
@@ -213,7 +218,8 @@ k_tx_count_ranges(const uint32_t *__restrict__ off, const uint32_t *__restrict__
         const uint32_t r0 = c * R, r1 = min(r0 + R, T);
         const uint32_t m = stage_tx<BS>(off, items, r0, r1, hp, L);
         enum_tx<BS>(m, L, hp, [&](uint32_t, uint32_t, uint32_t h) {
-            atomicAdd(&hist[interval_of(h, NB)], 1u);
+            const uint32_t bin = bm.local(h);
+            if (bin < NB) atomicAdd(&hist[bin], 1u);
         });
     }
     __syncthreads();
@@ -230,8 +236,8 @@ k_tx_count_ranges(const uint32_t *__restrict__ off, const uint32_t *__restrict__
 template <int BS, class KeyT>
 __global__ void __launch_bounds__(BS)
 k_tx_scatter_ranges(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
-                    HashParams hp, uint32_t NB, uint32_t max_items, uint32_t T, uint32_t R,
-                    uint32_t n_chunks, const uint32_t *__restrict__ cur,
+                    HashParams hp, uint32_t NB, BinMap bm, uint32_t max_items, uint32_t T,
+                    uint32_t R, uint32_t n_chunks, const uint32_t *__restrict__ cur,
                     KeyT *__restrict__ keys, uint32_t cap)
 {
     extern __shared__ uint32_t smem[];
@@ -255,7 +261,8 @@ k_tx_scatter_ranges(const uint32_t *__restrict__ off, const uint32_t *__restrict
         const uint32_t r0 = c * R, r1 = min(r0 + R, T);
         const uint32_t m = stage_tx<BS>(off, items, r0, r1, hp, L);  // ends with a barrier
         enum_tx<BS>(m, L, hp, [&](uint32_t, uint32_t, uint32_t h) {
-            atomicAdd(&lstart[interval_of(h, NB)], 1u);
+            const uint32_t bin = bm.local(h);
+            if (bin < NB) atomicAdd(&lstart[bin], 1u);
         });
         __syncthreads();
         lds_exclusive_scan<BS>(lstart, NB, s_tmp);
@@ -284,8 +291,8 @@ k_tx_scatter_ranges(const uint32_t *__restrict__ off, const uint32_t *__restrict
             const uint32_t s0 = lstart[b0];
             const bool whole = b0 == 0 && b1 == NB;
             enum_tx<BS>(m, L, hp, [&](uint32_t x, uint32_t y, uint32_t h) {
-                const uint32_t bin = interval_of(h, NB);
-                if (!whole && (bin < b0 || bin >= b1)) return;
+                const uint32_t bin = bm.local(h);
+                if (bin >= NB || (!whole && (bin < b0 || bin >= b1))) return;
                 const uint32_t p = atomicAdd(&lpos[bin], 1u);
                 const KeyT key = pack_key<KeyT>(x, y);
                 if (direct)
@@ -298,7 +305,7 @@ k_tx_scatter_ranges(const uint32_t *__restrict__ off, const uint32_t *__restrict
                 const uint32_t n = lstart[b1] - s0;
                 for (uint32_t i = threadIdx.x; i < n; i += BS) {
                     const KeyT key = stage[i];
-                    const uint32_t bin = bin_of_key(key, hp, NB);
+                    const uint32_t bin = bin_of_key(key, hp, bm.NBall) - bm.bin0;
                     keys[gcur[bin] + (i + s0 - lstart[bin])] = key;
                 }
             }
@@ -311,7 +318,8 @@ k_tx_scatter_ranges(const uint32_t *__restrict__ off, const uint32_t *__restrict
 
 template <int BS>
 __global__ void __launch_bounds__(BS)
-k_op_count(OpArgs a, HashParams hp, uint32_t NB, uint32_t max_a, uint32_t *__restrict__ cnt)
+k_op_count(OpArgs a, HashParams hp, uint32_t NB, BinMap bm, uint32_t max_a,
+           uint32_t *__restrict__ cnt)
 {
     extern __shared__ uint32_t smem[];
     uint32_t *s_ai, *s_ha, *s_bs, *s_wp, *s_tmp;
@@ -324,7 +332,8 @@ k_op_count(OpArgs a, HashParams hp, uint32_t NB, uint32_t max_a, uint32_t *__res
                                      s_ha, s_av, s_bs, s_wp, s_tmp, &m);
     walk_op<BS>(Tc, m, s_ai, s_ha, s_av, s_bs, s_wp, a.b_idx, a.b_val, hp,
                 [&](uint32_t, uint32_t, uint32_t h, float) {
-                    atomicAdd(&hist[interval_of(h, NB)], 1u);
+                    const uint32_t bin = bm.local(h);
+                    if (bin < NB) atomicAdd(&hist[bin], 1u);
                 });
     __syncthreads();
     uint32_t *row = cnt + (size_t)chunk * NB;
@@ -333,7 +342,7 @@ k_op_count(OpArgs a, HashParams hp, uint32_t NB, uint32_t max_a, uint32_t *__res
 
 template <int BS>
 __global__ void __launch_bounds__(BS)
-k_op_scatter(OpArgs a, HashParams hp, uint32_t NB, uint32_t max_a,
+k_op_scatter(OpArgs a, HashParams hp, uint32_t NB, BinMap bm, uint32_t max_a,
              const uint32_t *__restrict__ cur, uint64_t *__restrict__ keys,
              float *__restrict__ vals)
 {
@@ -349,7 +358,9 @@ k_op_scatter(OpArgs a, HashParams hp, uint32_t NB, uint32_t max_a,
                                      s_ha, s_av, s_bs, s_wp, s_tmp, &m);
     walk_op<BS>(Tc, m, s_ai, s_ha, s_av, s_bs, s_wp, a.b_idx, a.b_val, hp,
                 [&](uint32_t i, uint32_t j, uint32_t h, float v) {
-                    uint32_t p = atomicAdd(&pos[interval_of(h, NB)], 1u);
+                    const uint32_t bin = bm.local(h);
+                    if (bin >= NB) return;
+                    const uint32_t p = atomicAdd(&pos[bin], 1u);
                     keys[p] = ((uint64_t)i << 32) | j;
                     vals[p] = v;
                 });
@@ -597,10 +608,12 @@ static size_t op_smem_bytes(uint32_t NB, uint32_t max_a, uint32_t BS)
     return sizeof(uint32_t) * ((size_t)NB + 5 * (size_t)max_a + 1 + BS / kWave + 1);
 }
 
+static BinMap bin_map(const RoutePlan &pl) { return BinMap{pl.NBall, pl.bin0}; }
+
 static SingleChunks single_chunks(const crop_ctx *c, uint32_t *cnt)
 {
     const RoutePlan &pl = c->plan;
-    return SingleChunks{(uint32_t)c->in.T, pl.R, pl.NB, pl.n_chunks, cnt,
+    return SingleChunks{(uint32_t)c->in.T, pl.R, pl.NB, pl.n_chunks, bin_map(pl), cnt,
                         c->bin_off.as<uint32_t>()};
 }
 
@@ -635,8 +648,8 @@ hipError_t launch_tx_count_ranges(const crop_ctx *c, uint32_t *cnt, hipStream_t 
     const RoutePlan &pl = c->plan;
     size_t sm = tx_count_smem_bytes(pl.NB, pl.max_items);
     hipLaunchKernelGGL(k_tx_count_ranges<1024>, dim3(pl.n_wg), dim3(1024), sm, s, c->in.off,
-                       c->in.items, c->hp, pl.NB, pl.max_items, (uint32_t)c->in.T, pl.R,
-                       pl.n_chunks, cnt);
+                       c->in.items, c->hp, pl.NB, bin_map(pl), pl.max_items, (uint32_t)c->in.T,
+                       pl.R, pl.n_chunks, cnt);
     return hipGetLastError();
 }
 
@@ -648,12 +661,12 @@ hipError_t launch_tx_scatter_ranges(const crop_ctx *c, const uint32_t *cur, void
     size_t sm = tx_scatter_smem_bytes(pl.NB, pl.max_items, pl.stage_cap, wide);
     if (wide)
         hipLaunchKernelGGL((k_tx_scatter_ranges<1024, uint64_t>), dim3(pl.n_wg), dim3(1024), sm,
-                           s, c->in.off, c->in.items, c->hp, pl.NB, pl.max_items,
+                           s, c->in.off, c->in.items, c->hp, pl.NB, bin_map(pl), pl.max_items,
                            (uint32_t)c->in.T, pl.R, pl.n_chunks, cur,
                            static_cast<uint64_t *>(keys), pl.stage_cap);
     else
         hipLaunchKernelGGL((k_tx_scatter_ranges<1024, uint32_t>), dim3(pl.n_wg), dim3(1024), sm,
-                           s, c->in.off, c->in.items, c->hp, pl.NB, pl.max_items,
+                           s, c->in.off, c->in.items, c->hp, pl.NB, bin_map(pl), pl.max_items,
                            (uint32_t)c->in.T, pl.R, pl.n_chunks, cur,
                            static_cast<uint32_t *>(keys), pl.stage_cap);
     return hipGetLastError();
@@ -707,7 +720,7 @@ hipError_t launch_op_count(const crop_ctx *c, uint32_t *cnt, hipStream_t s)
     const RoutePlan &pl = c->plan;
     size_t sm = op_smem_bytes(pl.NB, pl.max_items, 256);
     hipLaunchKernelGGL(k_op_count<256>, dim3(pl.n_chunks), dim3(256), sm, s, op_args(c), c->hp,
-                       pl.NB, pl.max_items, cnt);
+                       pl.NB, bin_map(pl), pl.max_items, cnt);
     return hipGetLastError();
 }
 
@@ -717,7 +730,7 @@ hipError_t launch_op_scatter(const crop_ctx *c, const uint32_t *cur, void *keys,
     const RoutePlan &pl = c->plan;
     size_t sm = op_smem_bytes(pl.NB, pl.max_items, 256);
     hipLaunchKernelGGL(k_op_scatter<256>, dim3(pl.n_chunks), dim3(256), sm, s, op_args(c), c->hp,
-                       pl.NB, pl.max_items, cur, static_cast<uint64_t *>(keys), vals);
+                       pl.NB, bin_map(pl), pl.max_items, cur, static_cast<uint64_t *>(keys), vals);
     return hipGetLastError();
 }
 

@@ -262,3 +262,87 @@ def test_outer_heavy_vector(crop, ctx):
                                np.array([0, 2000], np.uint32), bi,
                                (rng.uniform(2000) - 0.5).astype(np.float32), n, n)
     compare_outer(crop, ctx, op, 4)
+
+
+# ------------------------------------------------------------------ owned partitions
+
+@pytest.mark.parametrize("P,p0,p1,S", [(16, 3, 7, 0), (16, 0, 1, 2), (16, 15, 16, 0), (8, 0, 8, 0),
+                                      (1024, 512, 640, 0)])
+def test_owned_partitions_match_interval_oracle(crop, ctx, P, p0, p1, S):
+    """Exact run restricted to the owned partitions [p0, p1): the oracle's
+    result over the hash interval of those partitions (Lemma 1's owner set);
+    the other partitions read back empty."""
+    st = datagen.config_small()
+    crop.crop_set_partitions(ctx, P)
+    crop.crop_set_seed(ctx, SEED)
+    crop.crop_set_owned_partitions(ctx, p0, p1)
+    crop.crop_set_tuning(ctx, bins_per_partition=S)
+    crop.crop_load_transactions(ctx, st.off, st.items, st.n)
+    crop.crop_run_exact(ctx)
+    q, _ = oracle.partition_interval(p0, P)
+    r = oracle.partition_interval(p1 - 1, P)[1]
+    ref = oracle.tx_exact(st.off, st.items, P, SEED, q, r)
+    sizes, terms = crop.crop_result_sizes(ctx, P)
+    assert np.array_equal(sizes, ref["part_sizes"])
+    assert np.array_equal(terms, ref["part_terms"])
+    assert sizes[:p0].sum() == 0 and sizes[p1:].sum() == 0
+    i, j, c, part_off = crop.crop_read_all(ctx, P)
+    start = np.concatenate([[0], np.cumsum(ref["part_sizes"].astype(np.int64))])
+    for p in range(P):
+        a, b = int(part_off[p]), int(part_off[p + 1])
+        g = sort_xyc(i[a:b], j[a:b], c[a:b])
+        o = (ref["x"][start[p]:start[p + 1]], ref["y"][start[p]:start[p + 1]],
+             ref["cnt"][start[p]:start[p + 1]])
+        for u, v in zip(g, o):
+            assert np.array_equal(u, v), f"partition {p}"
+    if p1 > p0:
+        pi, pj, pc = crop.crop_read_partition(ctx, p0, int(sizes[p0]) + 1)
+        assert pi.shape[0] == sizes[p0]
+    e = crop.crop_read_partition(ctx, (p1 % P), 10) if p1 < P else None
+    if e is not None:
+        assert e[0].shape[0] == 0
+
+
+def test_owned_shards_union_is_full_result(crop, ctx):
+    """Eight owners of P/8 partitions each (one GPU's share at eight GPUs)
+    together give exactly the full result."""
+    st = datagen.tiny_transactions(17, T=2500, n=400, cap=24, mean_len=8.0)
+    P = 64
+    full = None
+    crop.crop_set_partitions(ctx, P)
+    crop.crop_set_seed(ctx, SEED)
+    crop.crop_load_transactions(ctx, st.off, st.items, st.n)
+    crop.crop_run_exact(ctx)
+    full = sort_xyc(*crop.crop_read_all(ctx, P)[:3])
+    parts = []
+    for g in range(8):
+        crop.crop_set_owned_partitions(ctx, 8 * g, 8 * g + 8)
+        crop.crop_run_exact(ctx)
+        parts.append(crop.crop_read_all(ctx, P)[:3])
+    got = sort_xyc(*(np.concatenate([p[k] for p in parts]) for k in range(3)))
+    for u, v in zip(got, full):
+        assert np.array_equal(u, v)
+
+
+def test_owned_partitions_outer_and_rejections(crop, ctx):
+    op = datagen.tiny_outer(9, K=200, n_rows=50, n_cols=40, max_nnz=10)
+    P, p0, p1 = 8, 2, 5
+    crop.crop_set_partitions(ctx, P)
+    crop.crop_set_seed(ctx, SEED)
+    crop.crop_set_owned_partitions(ctx, p0, p1)
+    crop.crop_load_outer(ctx, op.a_off, op.a_idx, op.a_val, op.b_off, op.b_idx, op.b_val,
+                         op.n_rows, op.n_cols)
+    crop.crop_run_exact(ctx)
+    q, _ = oracle.partition_interval(p0, P)
+    r = oracle.partition_interval(p1 - 1, P)[1]
+    ref = oracle.op_exact(op, P, SEED, q, r)
+    sizes, _ = crop.crop_result_sizes(ctx, P)
+    assert np.array_equal(sizes, ref["part_sizes"])
+    with pytest.raises(crop.CropError):
+        crop.crop_run_topk(ctx, 10)
+    with pytest.raises(crop.CropError):
+        crop.crop_set_owned_partitions(ctx, 5, 5)
+    with pytest.raises(crop.CropError):
+        crop.crop_set_owned_partitions(ctx, 2, P + 1)
+    crop.crop_set_partitions(ctx, P)        # resets the owned range
+    crop.crop_run_topk(ctx, 10)
