@@ -52,6 +52,8 @@ def parse():
                          "whole stream also gives the recall and equality checks")
     ap.add_argument("--learned", action="store_true",
                     help="run the learned-seeding comparison instead of the exact bench")
+    ap.add_argument("--accuracy", action="store_true",
+                    help="synthetic analogs of the paper's accuracy experiments")
     ap.add_argument("--shards", type=int, default=0,
                     help="time each of G owned-partition shares of the exact run")
     ap.add_argument("--batched", action="store_true",
@@ -360,6 +362,97 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def run_accuracy(args):
+    """Synthetic analogs of the paper's accuracy experiments on the
+    1M-transaction stream (Section 7.3):
+    * bounds ratio: mean lower/upper bound of the reported top 100 against the
+      number of buckets, two counters per bucket (Figure 2b);
+    * counters per bucket at a fixed total of counters: reported pairs with
+      lower >= 90% of upper until the 100th that is not (Figure 3, left);
+    * recall of the top 10,000 with 10,000 counters per partition on P
+      partitions (Table 2);
+    * Count-Sketch, median of 11 instances, against Space-Saving at equal
+      counters: estimate / support for the true top 3,000 (Figure 3, right)."""
+    import numpy as np
+    import torch
+    import datagen
+    import oracle
+    import paper_1210_0461_amd as crop
+    st = datagen.config_large()
+    t0 = time.perf_counter()
+    ref = oracle.tx_exact(st.off, st.items, 1, SEED)
+    rk, rc = sorted_pairs(ref["x"], ref["y"], ref["cnt"])
+    print(f"# oracle {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    def exact_of(keys):
+        pos = np.minimum(np.searchsorted(rk, keys), rk.shape[0] - 1)
+        return np.where(rk[pos] == keys, rc[pos], 0)
+
+    ctx = crop.crop_create(0)
+    crop.crop_set_stream(ctx, torch.cuda.current_stream())
+    crop.crop_set_seed(ctx, SEED)
+    crop.crop_load_transactions(ctx, st.off, st.items, st.n)
+    out = {"experiment": "accuracy analogs on the 1M-transaction stream", "terms": int(ref["n_terms"])}
+    try:
+        def topk(P, C, ell, K):
+            crop.crop_set_partitions(ctx, P)
+            crop.crop_set_summary(ctx, C, ell)
+            crop.crop_run_topk(ctx, K)
+            i, j, up, lo, _ = crop.crop_read_topk(ctx, K)
+            keys = (i.astype(np.uint64) << np.uint64(32)) | j.astype(np.uint64)
+            return keys, up, lo
+
+        rows = []
+        for lb in range(8, 21, 2):
+            B = 1 << lb
+            keys, up, lo = topk(1, 2 * B, 2, 100)
+            rows.append({"buckets": B, "mean_lower_over_upper": float(np.mean(lo / up))})
+        out["bounds_ratio_vs_buckets"] = rows
+
+        rows = []
+        total = 1 << 17
+        for ell in (2, 4, 8, 12, 16, 24):
+            C = total // ell * ell
+            keys, up, lo = topk(1, C, ell, 20000)
+            good = lo >= 0.9 * up
+            bad_pos = np.flatnonzero(~good)
+            cut = bad_pos[99] if bad_pos.shape[0] >= 100 else good.shape[0]
+            rows.append({"ell": ell, "counters": C, "good_before_100th_bad": int(good[:cut].sum())})
+        out["good_estimates_vs_ell"] = rows
+
+        rows = []
+        _, cK = top_keys(rk, rc, 10000)
+        for P in (1, 2, 4, 8, 16, 32):
+            keys, up, lo = topk(P, 10000, 2, 10000)
+            rec, _ = recall_vs(rk, rc, keys, 10000)
+            rows.append({"P": P, "counters": 10000 * P, "recall_top10000": rec})
+        out["recall_vs_P"] = rows
+
+        # Count-Sketch vs Space-Saving at 100,000 counters in total
+        true_top, _ = top_keys(rk, rc, 3000)
+        f = exact_of(true_top).astype(np.float64)
+        crop.crop_set_partitions(ctx, 1)
+        B = 100000 // 11
+        crop.crop_run_countsketch(ctx, B, 11)
+        qx = torch.from_numpy((true_top >> np.uint64(32)).astype(np.uint32).view(np.int32)).cuda()
+        qy = torch.from_numpy((true_top & np.uint64(0xFFFFFFFF)).astype(np.uint32).view(np.int32)).cuda()
+        est = torch.empty(3000, dtype=torch.float64, device="cuda")
+        crop.crop_countsketch_estimate(ctx, qx, qy, est)
+        r_cs = est.cpu().numpy() / f
+        keys, up, lo = topk(1, 100000, 2, 100000)
+        pos = {int(k): q for q, k in enumerate(keys)}
+        r_ss = np.array([up[pos[int(k)]] / v if int(k) in pos else 0.0 for k, v in zip(true_top, f)])
+        q = lambda a: [round(float(x), 4) for x in np.quantile(a, [0.05, 0.5, 0.95])]
+        out["countsketch_vs_spacesaving_top3000"] = {
+            "counters": 100000, "cs_instances": 11, "cs_buckets": B,
+            "cs_ratio_q05_q50_q95": q(r_cs), "cs_within_factor_2": float(np.mean((r_cs > 0.5) & (r_cs < 2))),
+            "ss_ratio_q05_q50_q95": q(r_ss), "ss_reported": int(np.sum(r_ss > 0)),
+            "ss_within_factor_2": float(np.mean((r_ss > 0.5) & (r_ss < 2)))}
+    finally:
+        crop.crop_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
 def run_shards(args):
     """One GPU's share of a G-GPU run: the exact path owning P/G partitions of
     the 1M-transaction stream (every term enumerated, 1/G routed and kept),
@@ -437,6 +530,9 @@ def main():
         return
     if args.shards:
         run_shards(args)
+        return
+    if args.accuracy:
+        run_accuracy(args)
         return
     import numpy as np
     import torch
