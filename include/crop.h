@@ -170,6 +170,25 @@ crop_status crop_run_topk(crop_ctx *ctx, uint32_t K);
 crop_status crop_run_topk_seeded(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
                                  const uint32_t *sy, uint64_t ns, uint32_t r_max);
 
+/* Amplification (Section 6, Theorem 2 and its proof): `instances` independent
+ * CRoP runs, instance i with the hash functions of seed + i (1 <= instances
+ * <= 15), each with its own Space-Saving summaries of the configured size.
+ * An entry is reported when at least min_votes instances (1 <= min_votes <=
+ * instances; the paper's rule is at least half, e.g. 6 of 11) monitor it
+ * in the summary of its bucket.  A reported entry's bounds intersect the
+ * reporting instances' bounds: upper = their least count, lower = their
+ * largest count - overestimation; outer products also get the median of
+ * their signed sums (mean of the two middle values for an even number).
+ * The top-K over the reported entries ranks as crop_run_topk does.  Read
+ * the result with crop_read_topk and crop_read_topk_votes;
+ * crop_read_summary returns the instances' slots one instance after the
+ * other (instances * P * B * ell slots).  Device memory: the summaries of
+ * every instance plus 14 bytes per slot for the combined entries.
+ * Errors: CROP_E_ARG for instances or min_votes out of range, else as
+ * crop_run_topk. */
+crop_status crop_run_topk_amplified(crop_ctx *ctx, uint32_t K, uint32_t instances,
+                                    uint32_t min_votes);
+
 /* ---- readback (synchronizes the context stream) ------------------------ */
 
 /* Per-partition distinct-entry counts and term counts of the last exact run
@@ -195,6 +214,11 @@ crop_status crop_read_all(crop_ctx *ctx, crop_mem where, uint32_t *i, uint32_t *
  * products, the signed sum since admission (NULL allowed). */
 crop_status crop_read_topk(crop_ctx *ctx, uint32_t *i, uint32_t *j, double *upper,
                            double *lower, double *value, uint64_t cap, uint64_t *written);
+
+/* Number of instances that reported each entry of crop_read_topk, in the
+ * same order (host array of capacity cap; 1 for single-instance runs). */
+crop_status crop_read_topk_votes(crop_ctx *ctx, uint32_t *votes, uint64_t cap,
+                                 uint64_t *written);
 
 /* Every Space-Saving slot of the last top-K run (P*B*ell slots, bucket
  * major) into host arrays: entry, count, overestimation, signed sum (outer

@@ -297,6 +297,49 @@ def ss_bounds(summary, qx, qy, seed: int):
     return up, lo
 
 
+def amplified_report(summaries, min_votes: int):
+    """Majority reporting over t independent instances (Section 6, the proof
+    of Theorem 2: run t copies with independent hash functions and report the
+    entries that at least half of them report).  An instance reports an entry
+    when one of its summaries monitors it.  Every instance's [count - err,
+    count] holds the entry's true weight (Section 4), so a reported entry gets
+    the intersection of its reporting instances' intervals; its value is the
+    median of their signed sums (mean of the two middle ones for an even
+    number; outer products only).
+
+    summaries: list of t summaries as returned by tx_spacesaving /
+    op_spacesaving (instance i built with its own seed).  Returns a dict of
+    arrays sorted by packed key: x, y, votes, upper, lower, value.  Lower
+    bounds are taken as count - err in the precision of the summary's
+    counters: fp64 differences for integer counts, fp32 differences clamped
+    at 0 for fp32 counters (fp32=True in the summary dict)."""
+    per = {}
+    for s in summaries:
+        fp32 = bool(s.get("fp32", False))
+        for q in np.flatnonzero(np.asarray(s["used"])):
+            key = (int(s["x"][q]) << 32) | int(s["y"][q])
+            c = float(s["cnt"][q])
+            if fp32:
+                lo = float(max(np.float32(c) - np.float32(s["err"][q]), np.float32(0.0)))
+            else:
+                lo = c - float(s["err"][q])
+            v = float(s["val"][q]) if "val" in s else 0.0
+            per.setdefault(key, []).append((c, lo, v))
+    keys = sorted(k for k, r in per.items() if len(r) >= min_votes)
+    out = dict(x=np.array([k >> 32 for k in keys], np.uint32),
+               y=np.array([k & 0xFFFFFFFF for k in keys], np.uint32),
+               votes=np.array([len(per[k]) for k in keys], np.int64),
+               upper=np.array([min(r[0] for r in per[k]) for k in keys], np.float64),
+               lower=np.array([max(r[1] for r in per[k]) for k in keys], np.float64))
+    val = []
+    for k in keys:
+        vs = sorted(r[2] for r in per[k])
+        n = len(vs)
+        val.append(vs[n // 2] if n % 2 else 0.5 * (vs[n // 2 - 1] + vs[n // 2]))
+    out["value"] = np.array(val, np.float64)
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Count-Sketch, one estimator per bucket (Section 4; Figure 1).
 

@@ -96,6 +96,8 @@ _SIGS = {
 _SIGS.update({
     "crop_run_topk": ([_vp, _u32], _i32),
     "crop_run_topk_seeded": ([_vp, _u32, _vp, _vp, _u64, _u32], _i32),
+    "crop_run_topk_amplified": ([_vp, _u32, _u32, _u32], _i32),
+    "crop_read_topk_votes": ([_vp, _vp, _u64, _pu64], _i32),
     "crop_read_topk": ([_vp, _vp, _vp, _vp, _vp, _vp, _u64, _pu64], _i32),
     "crop_read_summary": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64, _pu64], _i32),
     "crop_run_countsketch": ([_vp, _u32, _u32], _i32),
@@ -289,6 +291,21 @@ def crop_run_topk_seeded(ctx, K: int, sx, sy, r_max: int) -> None:
     px, _ = _ptr(sx)
     py, _ = _ptr(sy)
     _check(ctx, _lib.crop_run_topk_seeded(ctx, K, px, py, _len(sx), r_max))
+
+
+def crop_run_topk_amplified(ctx, K: int, instances: int, min_votes: int = 0) -> None:
+    """Majority reporting over `instances` CRoP runs (seeds seed, seed+1, ...);
+    min_votes 0 means at least half: (instances + 1) // 2."""
+    if min_votes == 0:
+        min_votes = (instances + 1) // 2
+    _check(ctx, _lib.crop_run_topk_amplified(ctx, K, instances, min_votes))
+
+
+def crop_read_topk_votes(ctx, cap: int):
+    v = np.zeros(max(cap, 1), np.uint32)
+    w = _u64(0)
+    _check(ctx, _lib.crop_read_topk_votes(ctx, v.ctypes.data, cap, ctypes.byref(w)))
+    return v[:w.value]
 
 
 def crop_result_sizes(ctx, P: int):

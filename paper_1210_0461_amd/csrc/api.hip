@@ -331,12 +331,29 @@ crop_status ensure_ss_buffers(crop_ctx *ctx, uint64_t nslots, uint32_t K, uint32
     ctx->ss.nslots = nslots;
     // top-K: st (8) + hist (256) + pinned counter | cand | sel | outputs
     const size_t kk = std::max<uint32_t>(K, 1);
-    CK(ctx->topk_buf.ensure(2048 + 2 * a4 + kk * 32 + ns + 256));
+    CK(ctx->topk_buf.ensure(2048 + 2 * a4 + kk * 36 + ns + 256));
+    return CROP_OK;
+}
+
+// Combined entries of an amplified run, one per slot of the t summaries:
+// upper bound, lower bound, value, used flag and votes.
+crop_status ensure_amp_buffers(crop_ctx *ctx, uint64_t nslots, SsState *A, uint8_t **votes)
+{
+    const size_t a4 = (nslots * 4 + 255) / 256 * 256, a1 = (nslots + 255) / 256 * 256;
+    CK(ctx->amp_buf.ensure(3 * a4 + 2 * a1));
+    char *p = static_cast<char *>(ctx->amp_buf.p);
+    A->key = ctx->ss.key;
+    A->cnt = reinterpret_cast<uint32_t *>(p);
+    A->err = reinterpret_cast<uint32_t *>(p + a4);
+    A->val = reinterpret_cast<float *>(p + 2 * a4);
+    A->flag = reinterpret_cast<uint8_t *>(p + 3 * a4);
+    A->nslots = nslots;
+    *votes = reinterpret_cast<uint8_t *>(p + 3 * a4 + a1);
     return CROP_OK;
 }
 
 struct TopkViews {
-    uint32_t *st, *hist, *n_pinned, *cand, *sel, *oi, *oj;
+    uint32_t *st, *hist, *n_pinned, *cand, *sel, *oi, *oj, *ovotes;
     double *ou, *ol, *ov;
     uint8_t *dup;
 };
@@ -359,7 +376,8 @@ TopkViews topk_views(crop_ctx *ctx, uint32_t K)
     v.ov = v.ol + kk;
     v.oi = reinterpret_cast<uint32_t *>(v.ov + kk);
     v.oj = v.oi + kk;
-    v.dup = reinterpret_cast<uint8_t *>(v.oj + kk);
+    v.ovotes = v.oj + kk;
+    v.dup = reinterpret_cast<uint8_t *>(v.ovotes + kk);
     return v;
 }
 
@@ -455,7 +473,7 @@ void crop_destroy(crop_ctx *ctx)
                       &ctx->vals, &ctx->out_cnt, &ctx->spill, &ctx->counter, &ctx->ss_state,
                       &ctx->topk_buf, &ctx->scratch, &ctx->learn_ws, &ctx->in.d_op_chunks,
                       &bt.d_crow, &bt.d_cstream, &bt.d_streams, &bt.d_bin_stream, &bt.tot,
-                      &bt.tiles, &ctx->cs_buf})
+                      &bt.tiles, &ctx->cs_buf, &ctx->amp_buf})
         b->release();
     for (DevBuf &b : ctx->in.own) b.release();
     for (StageRec &r : ctx->ring)
@@ -743,8 +761,13 @@ crop_status crop_run_exact(crop_ctx *ctx)
     return CROP_OK;
 }
 
+// One top-K run: t = 1 is a single CRoP instance (optionally seeded); t > 1
+// runs t instances with the hash functions of seed, seed + 1, ..., each into
+// its own summaries, and reports the entries monitored by at least
+// min_votes of them.
 static crop_status run_topk_impl(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
-                                 const uint32_t *sy, uint64_t ns, uint32_t r_max)
+                                 const uint32_t *sy, uint64_t ns, uint32_t r_max,
+                                 uint32_t t = 1, uint32_t min_votes = 1)
 {
     if (!ctx) return CROP_E_ARG;
     if (ctx->in.mode == Mode::None) return fail(ctx, CROP_E_STATE, "no input loaded");
@@ -774,14 +797,24 @@ static crop_status run_topk_impl(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
     st = ensure_route_buffers(ctx, ctx->in.wide_keys ? 8 : 4, outer);
     if (st != CROP_OK) return st;
     const uint64_t nslots = PB * ctx->ss_ell;
-    if (nslots >= (1ull << 32))
+    if (nslots * t >= (1ull << 32))
         return fail(ctx, CROP_E_UNSUPPORTED, "more than 2^32 summary slots");
-    st = ensure_ss_buffers(ctx, nslots, K, (uint32_t)ns);
+    st = ensure_ss_buffers(ctx, nslots * t, K, (uint32_t)ns);
     if (st != CROP_OK) return st;
+    SsState amp{};
+    uint8_t *votes = nullptr;
+    if (t > 1) {
+        st = ensure_amp_buffers(ctx, nslots * t, &amp, &votes);
+        if (st != CROP_OK) return st;
+    }
     const TopkViews tv = topk_views(ctx, K);
     const RoutePlan &pl = ctx->plan;
     hipStream_t s = ctx->stream;
     uint32_t *cnt = ctx->cnt_mat.as<uint32_t>();
+    CsParams ip{};
+    ip.t = t;
+    ip.PB = PB;
+    for (uint32_t i = 0; i < t; ++i) ip.hp[i] = make_hash_params(ctx->seed + i);
     st = run_begin(ctx);
     if (st != CROP_OK) return st;
     CK(launch_ss_clear(ctx->ss, s));
@@ -790,24 +823,46 @@ static crop_status run_topk_impl(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
         CK(launch_ss_pin(ctx->ss, sx, sy, (uint32_t)ns, tv.dup, r_max, ctx->hp, PB, ctx->ss_ell,
                          tv.n_pinned, s));
     STAGE("init");
-    if (pl.n_chunks) CK(outer ? launch_op_count(ctx, cnt, s)
-                              : pl.n_wg ? launch_tx_count_ranges(ctx, cnt, s)
-                                        : launch_tx_count(ctx, cnt, s));
-    STAGE("count");
-    CK(launch_scan_counts(cnt, pl.n_wg ? pl.n_wg : pl.n_chunks, pl.NB, pl.G,
-                          ctx->part_buf.as<uint32_t>(),
-                          ctx->bin_off.as<uint32_t>(), ctx->counter.as<uint32_t>(), s));
-    CK(launch_bin_order(pl.NB, ctx->bin_off.as<uint32_t>(), ctx->bin_order.as<uint32_t>(), s));
-    STAGE("scan");
-    if (pl.n_chunks)
-        CK(outer ? launch_op_scatter(ctx, cnt, ctx->keys.p, ctx->vals.as<float>(), s)
-                 : pl.n_wg ? launch_tx_scatter_ranges(ctx, cnt, ctx->keys.p, s)
-                           : launch_tx_scatter(ctx, cnt, ctx->keys.p, s));
-    STAGE("scatter");
-    CK(launch_ss_bins(ctx, ctx->ss, nbk, PB, s));
-    STAGE("summaries");
-    CK(launch_topk(ctx->ss, K, outer, ctx->topk_rank == CROP_RANK_LOWER, tv.st, tv.hist, tv.cand, tv.sel, tv.oi, tv.oj, tv.ou,
-                   tv.ol, tv.ov, s));
+    // instance i routes and summarises with its own hash functions; the
+    // kernels take the parameters by value at launch
+    for (uint32_t i = 0; i < t; ++i) {
+        ctx->hp = ip.hp[i];
+        SsState Si = ctx->ss;
+        Si.key += i * nslots;
+        Si.cnt += i * nslots;
+        Si.err += i * nslots;
+        Si.val += i * nslots;
+        Si.flag += i * nslots;
+        Si.nslots = nslots;
+        if (pl.n_chunks) CK(outer ? launch_op_count(ctx, cnt, s)
+                                  : pl.n_wg ? launch_tx_count_ranges(ctx, cnt, s)
+                                            : launch_tx_count(ctx, cnt, s));
+        if (i == 0) STAGE("count");
+        CK(launch_scan_counts(cnt, pl.n_wg ? pl.n_wg : pl.n_chunks, pl.NB, pl.G,
+                              ctx->part_buf.as<uint32_t>(),
+                              ctx->bin_off.as<uint32_t>(), ctx->counter.as<uint32_t>(), s));
+        CK(launch_bin_order(pl.NB, ctx->bin_off.as<uint32_t>(), ctx->bin_order.as<uint32_t>(),
+                            s));
+        if (i == 0) STAGE("scan");
+        if (pl.n_chunks)
+            CK(outer ? launch_op_scatter(ctx, cnt, ctx->keys.p, ctx->vals.as<float>(), s)
+                     : pl.n_wg ? launch_tx_scatter_ranges(ctx, cnt, ctx->keys.p, s)
+                               : launch_tx_scatter(ctx, cnt, ctx->keys.p, s));
+        if (i == 0) STAGE("scatter");
+        CK(launch_ss_bins(ctx, Si, nbk, PB, s));
+        if (i == 0) STAGE("summaries");
+    }
+    ctx->hp = ip.hp[0];
+    const bool by_lower = ctx->topk_rank == CROP_RANK_LOWER;
+    if (t > 1) {
+        CK(launch_amp_combine(ip, ctx->ss, ctx->ss_ell, nslots, min_votes, outer, amp, votes, s));
+        STAGE("majority");
+        CK(launch_topk(amp, K, outer, by_lower, true, votes, tv.st, tv.hist, tv.cand, tv.sel,
+                       tv.oi, tv.oj, tv.ou, tv.ol, tv.ov, tv.ovotes, s));
+    } else {
+        CK(launch_topk(ctx->ss, K, outer, by_lower, false, nullptr, tv.st, tv.hist, tv.cand,
+                       tv.sel, tv.oi, tv.oj, tv.ou, tv.ol, tv.ov, tv.ovotes, s));
+    }
     STAGE("topk");
     st = run_end(ctx);
     if (st != CROP_OK) return st;
@@ -815,6 +870,7 @@ static crop_status run_topk_impl(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
     ctx->topk_K = K;
     ctx->ss_buckets = PB;
     ctx->topk_outer = outer ? 1 : 0;
+    ctx->topk_instances = t;
     return CROP_OK;
 }
 
@@ -827,6 +883,33 @@ crop_status crop_run_topk_seeded(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
                                  const uint32_t *sy, uint64_t ns, uint32_t r_max)
 {
     return run_topk_impl(ctx, K, sx, sy, ns, r_max);
+}
+
+crop_status crop_run_topk_amplified(crop_ctx *ctx, uint32_t K, uint32_t instances,
+                                    uint32_t min_votes)
+{
+    if (!ctx) return CROP_E_ARG;
+    if (instances < 1 || instances > kCsMaxInstances)
+        return fail(ctx, CROP_E_ARG, "instances must be 1..15");
+    if (min_votes < 1 || min_votes > instances)
+        return fail(ctx, CROP_E_ARG, "min_votes must be 1..instances");
+    return run_topk_impl(ctx, K, nullptr, nullptr, 0, 0, instances, min_votes);
+}
+
+crop_status crop_read_topk_votes(crop_ctx *ctx, uint32_t *votes, uint64_t cap, uint64_t *written)
+{
+    if (!ctx || !votes) return CROP_E_ARG;
+    if (ctx->result != Result::TopK) return fail(ctx, CROP_E_STATE, "no top-K result");
+    DeviceGuard g(ctx->device);
+    const TopkViews tv = topk_views(ctx, ctx->topk_K);
+    uint32_t stv[8];
+    CK(hipStreamSynchronize(ctx->stream));
+    CK(hipMemcpy(stv, tv.st, sizeof(stv), hipMemcpyDeviceToHost));
+    const uint64_t n = stv[5];
+    if (written) *written = n;
+    if (n > cap) return fail(ctx, CROP_E_CAPACITY, "output capacity below K");
+    if (n) CK(hipMemcpy(votes, tv.ovotes, n * 4, hipMemcpyDeviceToHost));
+    return CROP_OK;
 }
 
 crop_status crop_read_topk(crop_ctx *ctx, uint32_t *i, uint32_t *j, double *upper,

@@ -196,6 +196,8 @@ struct crop_ctx {
     crop::SsState ss;          // views into ss_state
     uint64_t ss_buckets = 0;   // P * B of the last top-K run
     uint32_t topk_outer = 0;   // the last top-K run was on outer products
+    uint32_t topk_instances = 1;  // ... and ran this many instances
+    crop::DevBuf amp_buf;      // combined entries of an amplified run
 
     // profiling: per-stage events of the last kStageRing runs
     bool profiling = false;
@@ -262,10 +264,13 @@ uint32_t ss_block_threads(uint32_t nbk, uint32_t ell);
 hipError_t launch_ss_bins(const crop_ctx *c, const SsState &S, uint32_t nbk, uint64_t PB,
                           hipStream_t s);
 hipError_t launch_zero32(uint32_t *p, uint32_t n, hipStream_t s);
-hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, bool by_lower, uint32_t *st,
-                       uint32_t *hist,
-                       uint32_t *cand, uint32_t *sel, uint32_t *oi, uint32_t *oj, double *ou,
-                       double *ol, double *ov, hipStream_t s);
+hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, bool by_lower, bool err_is_lower,
+                       const uint8_t *votes, uint32_t *st, uint32_t *hist, uint32_t *cand,
+                       uint32_t *sel, uint32_t *oi, uint32_t *oj, double *ou, double *ol,
+                       double *ov, uint32_t *ovotes, hipStream_t s);
+hipError_t launch_amp_combine(const CsParams &ip, const SsState &S, uint32_t ell, uint64_t nslots,
+                              uint32_t min_votes, bool outer, const SsState &A, uint8_t *votes,
+                              hipStream_t s);
 
 size_t tx_count_smem_bytes(uint32_t NB, uint32_t max_items);
 

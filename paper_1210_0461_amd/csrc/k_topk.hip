@@ -452,19 +452,27 @@ __device__ inline uint32_t count_shift(const uint32_t *st)
     return st[7] ? (uint32_t)__clz(st[7]) : 0u;
 }
 
+// Lower bound of a summary slot: count - overestimation (fp32 difference for
+// outer products, never negative), as an order-preserving 32-bit word.
+__device__ inline uint32_t lower_of(uint32_t c, uint32_t e, bool fp)
+{
+    if (!fp) return c - e;
+    return __float_as_uint(fmaxf(__uint_as_float(c) - __uint_as_float(e), 0.0f));
+}
+
 // The ranked value of a slot as an order-preserving 32-bit word: the count
-// (upper bound) or, when ranking by guaranteed count, count - overestimation
-// (lower bound; fp32 difference for outer products, never negative).
+// (upper bound) or, when ranking by guaranteed count, the lower bound.  With
+// err_is_lower the err array holds the lower bound itself (combined entries
+// of an amplified run).
 struct RankBy {
     const uint32_t *cnt, *err;
-    bool lower, fp;
+    bool lower, fp, err_is_lower;
     __device__ uint32_t operator()(uint64_t i) const
     {
         const uint32_t c = cnt[i];
         if (!lower) return c;
-        const uint32_t e = err[i];
-        if (!fp) return c - e;
-        return __float_as_uint(fmaxf(__uint_as_float(c) - __uint_as_float(e), 0.0f));
+        if (err_is_lower) return err[i];
+        return lower_of(c, err[i], fp);
     }
 };
 
@@ -602,9 +610,10 @@ k_topk_collect(const uint64_t *__restrict__ key, RankBy rv,
 __global__ void __launch_bounds__(256)
 k_topk_rank(const uint64_t *__restrict__ key, RankBy rv, const uint32_t *__restrict__ cnt,
             const uint32_t *__restrict__ err, const float *__restrict__ val, bool outer,
-            const uint32_t *__restrict__ sel, const uint32_t *__restrict__ st,
-            uint32_t *__restrict__ oi, uint32_t *__restrict__ oj, double *__restrict__ ou,
-            double *__restrict__ ol, double *__restrict__ ov)
+            const uint8_t *__restrict__ votes, const uint32_t *__restrict__ sel,
+            const uint32_t *__restrict__ st, uint32_t *__restrict__ oi, uint32_t *__restrict__ oj,
+            double *__restrict__ ou, double *__restrict__ ol, double *__restrict__ ov,
+            uint32_t *__restrict__ ovotes)
 {
     __shared__ Comp tile[256];
     const uint32_t m = st[5];
@@ -637,7 +646,85 @@ k_topk_rank(const uint64_t *__restrict__ key, RankBy rv, const uint32_t *__restr
         ov[rank] = c;
     }
     ou[rank] = c;
-    ol[rank] = c - e;
+    ol[rank] = rv.err_is_lower ? e : c - e;
+    ovotes[rank] = votes ? votes[i] : 1u;
+}
+
+// Majority reporting over t independent instances (Section 6, proof of
+// Theorem 2): an entry counts as reported by instance j when j's summaries
+// monitor it, i.e. it sits in one of the ell slots of its bucket under j's
+// hash functions.  Every monitored slot looks its entry up in the other
+// instances' buckets; the lowest instance that monitors the entry owns it,
+// so each entry is combined once.  Entries with at least min_votes votes get
+// the intersection of the reporting instances' bounds (every instance's
+// [lower, upper] holds the true weight, Section 4), so upper = the least
+// count and lower = the largest lower bound; outer products also get the
+// median of the reporting instances' signed sums (mean of the two middle
+// values for an even number of votes).
+template <bool OUTER>
+__global__ void __launch_bounds__(256)
+k_amp_combine(CsParams ip, uint32_t ell, uint64_t ns, uint32_t min_votes,
+              const uint64_t *__restrict__ key, const uint32_t *__restrict__ cnt,
+              const uint32_t *__restrict__ err, const float *__restrict__ val,
+              const uint8_t *__restrict__ flag, uint32_t *__restrict__ up,
+              uint32_t *__restrict__ lo, float *__restrict__ mv, uint8_t *__restrict__ oflag,
+              uint8_t *__restrict__ votes)
+{
+    const uint64_t total = ns * ip.t;
+    for (uint64_t g = (uint64_t)blockIdx.x * 256 + threadIdx.x; g < total;
+         g += (uint64_t)gridDim.x * 256) {
+        oflag[g] = 0;
+        if (!(flag[g] & kUsed)) continue;
+        const uint32_t inst = (uint32_t)(g / ns);
+        const uint64_t k = key[g];
+        const uint32_t x = (uint32_t)(k >> 32), y = (uint32_t)k;
+        uint32_t v = 0, u = 0xFFFFFFFFu, l = 0;
+        float sv[kCsMaxInstances];
+        bool own = true;
+        for (uint32_t j = 0; j < ip.t && own; ++j) {
+            uint64_t q = g;
+            if (j != inst) {
+                const uint64_t b = interval_of(hash_a(ip.hp[j], x) + hash_b(ip.hp[j], y), ip.PB);
+                const uint64_t base = (uint64_t)j * ns + b * ell;
+                q = ~0ull;
+                for (uint32_t r = 0; r < ell; ++r)
+                    if ((flag[base + r] & kUsed) && key[base + r] == k) {
+                        q = base + r;
+                        break;
+                    }
+                if (q == ~0ull) continue;
+                if (j < inst) {
+                    own = false;
+                    break;
+                }
+            }
+            const uint32_t c = cnt[q];
+            u = min(u, c);
+            l = max(l, lower_of(c, err[q], OUTER));
+            if (OUTER) {
+                // insertion into the sorted prefix sv[0..v)
+                const float w = val[q];
+                uint32_t p = v;
+                while (p > 0 && sv[p - 1] > w) {
+                    sv[p] = sv[p - 1];
+                    --p;
+                }
+                sv[p] = w;
+            }
+            ++v;
+        }
+        if (!own || v < min_votes) continue;
+        up[g] = u;
+        lo[g] = l;
+        if (OUTER) {
+            const uint32_t h = v / 2;
+            mv[g] = (v & 1u) ? sv[h] : 0.5f * (sv[h - 1] + sv[h]);
+        } else {
+            mv[g] = 0.0f;
+        }
+        votes[g] = (uint8_t)v;
+        oflag[g] = kUsed;
+    }
 }
 
 }  // namespace
@@ -739,12 +826,13 @@ hipError_t launch_ss_bins(const crop_ctx *c, const SsState &S, uint32_t nbk, uin
 
 // Top-K over the summary slots; st (8 words) and hist (256 words) must be
 // zero on entry; cand and sel hold up to nslots indices.
-hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, bool by_lower, uint32_t *st,
-                       uint32_t *hist, uint32_t *cand, uint32_t *sel, uint32_t *oi, uint32_t *oj,
-                       double *ou, double *ol, double *ov, hipStream_t s)
+hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, bool by_lower, bool err_is_lower,
+                       const uint8_t *votes, uint32_t *st, uint32_t *hist, uint32_t *cand,
+                       uint32_t *sel, uint32_t *oi, uint32_t *oj, double *ou, double *ol,
+                       double *ov, uint32_t *ovotes, hipStream_t s)
 {
     const uint32_t g = grid_for(S.nslots);
-    const RankBy rv{S.cnt, S.err, by_lower, outer};
+    const RankBy rv{S.cnt, S.err, by_lower, outer, err_is_lower};
     hipLaunchKernelGGL(k_topk_max, dim3(g), dim3(256), 0, s, rv, S.flag, S.nslots, st);
     for (uint32_t pass = 0; pass < 12; ++pass) {
         hipLaunchKernelGGL(k_topk_hist, dim3(g), dim3(256), 0, s, S.key, rv, S.flag, S.nslots,
@@ -757,7 +845,25 @@ hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, bool by_lower, 
     hipLaunchKernelGGL(k_topk_collect, dim3(g), dim3(256), 0, s, S.key, rv, cand, st, sel);
     const uint32_t gr = (K + 255) / 256 ? (K + 255) / 256 : 1;
     hipLaunchKernelGGL(k_topk_rank, dim3(gr), dim3(256), 0, s, S.key, rv, S.cnt, S.err, S.val,
-                       outer, sel, st, oi, oj, ou, ol, ov);
+                       outer, votes, sel, st, oi, oj, ou, ol, ov, ovotes);
+    return hipGetLastError();
+}
+
+// Combined entries of t instances' summaries S (instance i at slots
+// [i * nslots, (i + 1) * nslots)) into A (same indexing, keys shared with S).
+hipError_t launch_amp_combine(const CsParams &ip, const SsState &S, uint32_t ell, uint64_t nslots,
+                              uint32_t min_votes, bool outer, const SsState &A, uint8_t *votes,
+                              hipStream_t s)
+{
+    const uint32_t g = grid_for(nslots * ip.t, 8192);
+    if (outer)
+        hipLaunchKernelGGL(k_amp_combine<true>, dim3(g), dim3(256), 0, s, ip, ell, nslots,
+                           min_votes, S.key, S.cnt, S.err, S.val, S.flag, A.cnt, A.err, A.val,
+                           A.flag, votes);
+    else
+        hipLaunchKernelGGL(k_amp_combine<false>, dim3(g), dim3(256), 0, s, ip, ell, nslots,
+                           min_votes, S.key, S.cnt, S.err, S.val, S.flag, A.cnt, A.err, A.val,
+                           A.flag, votes);
     return hipGetLastError();
 }
 

@@ -254,3 +254,80 @@ def test_topk_ties_and_recall():
     assert oracle.recall_at_k([10, 60, 50, 40], keys, w, 4) == 0.75
     assert oracle.recall_at_k([60, 10, 50, 30], keys, w, 4) == 1.0
     assert oracle.recall_at_k([], keys, w, 4) == 0.0
+
+
+# ---------------------------------------------------------------------------
+# Majority reporting over t instances (Section 6, Theorem 2 and its proof).
+
+def _summary(entries, fp32=False):
+    """A one-bucket summary from (x, y, count, err, value) tuples."""
+    x, y, c, e, v = (np.array(col) for col in zip(*entries))
+    return dict(x=x.astype(np.uint32), y=y.astype(np.uint32), cnt=c.astype(np.float64),
+                err=e.astype(np.float64), val=v.astype(np.float64),
+                used=np.ones(len(entries), bool), fp32=fp32)
+
+
+def test_amplified_report_by_hand():
+    s0 = _summary([(1, 2, 10, 2, -1.0), (3, 4, 5, 0, 1.0), (5, 6, 3, 3, 7.0)])
+    s1 = _summary([(1, 2, 9, 0, 4.0), (5, 6, 4, 1, -2.0)])
+    s2 = _summary([(1, 2, 12, 4, 2.0), (7, 8, 2, 0, 9.0), (3, 4, 6, 2, 3.0)])
+    r = oracle.amplified_report([s0, s1, s2], 2)
+    # (1,2): three votes, upper min(10, 9, 12) = 9, lower max(8, 9, 8) = 9,
+    # value median(-1, 4, 2) = 2; (3,4): two votes, upper 5, lower max(5, 4)
+    # = 5, value mean(1, 3) = 2; (5,6): upper 3, lower max(0, 3) = 3, value
+    # mean(7, -2) = 2.5; (7,8) has one vote and is not reported
+    assert r["x"].tolist() == [1, 3, 5] and r["y"].tolist() == [2, 4, 6]
+    assert r["votes"].tolist() == [3, 2, 2]
+    assert r["upper"].tolist() == [9, 5, 3]
+    assert r["lower"].tolist() == [9, 5, 3]
+    assert r["value"].tolist() == [2.0, 2.0, 2.5]
+    r1 = oracle.amplified_report([s0, s1, s2], 1)
+    assert r1["x"].tolist() == [1, 3, 5, 7] and r1["votes"].tolist() == [3, 2, 2, 1]
+    assert oracle.amplified_report([s0, s1, s2], 3)["x"].tolist() == [1]
+    # fp32 counters: lower = max(fp32(c - e), 0)
+    f = oracle.amplified_report([_summary([(1, 2, 1.0, 1.0 + 2 ** -20, 0.0)], fp32=True)], 1)
+    assert f["lower"].tolist() == [0.0]
+
+
+def test_amplified_single_instance_is_the_summary():
+    st = datagen.config_small()
+    s = oracle.tx_spacesaving(st.off, st.items, SEED, 2, 16, 4)
+    r = oracle.amplified_report([s], 1)
+    u = s["used"]
+    keys = oracle.pack_keys(s["x"][u], s["y"][u])
+    order = np.argsort(keys)
+    assert np.array_equal(oracle.pack_keys(r["x"], r["y"]), keys[order])
+    assert np.array_equal(r["upper"], s["cnt"][u][order])
+    assert np.array_equal(r["lower"], (s["cnt"] - s["err"])[u][order])
+    assert np.all(r["votes"] == 1)
+
+
+@pytest.mark.parametrize("t,min_votes", [(5, 3), (4, 2), (3, 3)])
+def test_amplified_reports_every_guaranteed_entry(t, min_votes):
+    """An entry heavier than m_b / ell in its bucket of instance i is
+    monitored there (Section 4).  Entries with at least min_votes such
+    instances are reported; every reported interval holds the exact count."""
+    st = datagen.config_small()
+    exact, r = exact_lookup(st)
+    P, B, ell = 2, 512, 4
+    seeds = [(SEED + i) & 0xFFFFFFFFFFFFFFFF for i in range(t)]
+    sums = [oracle.tx_spacesaving(st.off, st.items, sd, P, B, ell) for sd in seeds]
+    rep = oracle.amplified_report(sums, min_votes)
+    keys = oracle.pack_keys(r["x"], r["y"])
+    f = r["cnt"].astype(np.float64)
+    guaranteed = np.zeros(keys.shape[0], np.int64)
+    for sd in seeds:
+        _, _, h, _ = oracle.hash_many(sd, r["x"], r["y"])
+        b = oracle.bucket_of(h, P, B).astype(np.int64)
+        m_b = np.bincount(b, weights=f, minlength=P * B)
+        guaranteed += f > m_b[b] / ell
+    rk = oracle.pack_keys(rep["x"], rep["y"])
+    assert np.all(np.isin(keys[guaranteed >= min_votes], rk))
+    assert (guaranteed >= min_votes).sum() > 10
+    pos = np.searchsorted(keys, rk)
+    assert np.array_equal(keys[pos], rk)
+    assert np.all(rep["lower"] <= f[pos]) and np.all(f[pos] <= rep["upper"])
+    assert np.all(rep["votes"] >= min_votes)
+    # every vote is one monitored slot: reported * min_votes <= slots in use
+    assert int(rep["votes"].sum()) <= sum(int(s["used"].sum()) for s in sums)
+    assert rk.shape[0] * min_votes <= sum(int(s["used"].sum()) for s in sums)
