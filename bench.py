@@ -91,25 +91,31 @@ def source_digest(*names):
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(kernel, digest, launches_bytes):
+def traffic_from_profiles(kernel, digest):
     """HBM bytes of one launch of `kernel` from the committed rocprofv3 PMC
     summary (FETCH_SIZE + WRITE_SIZE, KiB per dispatch, scaled by the copy
-    kernel calibration), or None when absent or taken on other sources."""
+    kernel calibration), or None when absent or taken on other sources.
+    Lines read: `source_digest = D`, `fetch_scale = F`, `write_scale = W`
+    and `traffic <kernel> fetch_kib=A write_kib=B`."""
     path = os.path.join(ROOT, "profiles", "pmc_traffic_large1M.txt")
     if not os.path.exists(path):
         return None
-    rec = {}
+    rec, per = {}, {}
     for line in open(path):
         line = line.strip()
         if not line or line.startswith("#"):
             continue
+        if line.startswith("traffic "):
+            parts = line.split()
+            per[parts[1]] = dict(kv.split("=") for kv in parts[2:])
+            continue
         k, _, v = line.partition("=")
         rec[k.strip()] = v.strip()
-    if rec.get("kernel") != kernel or rec.get("source_digest") != digest:
+    if rec.get("source_digest") != digest or kernel not in per:
         return None
-    fetch = float(rec["fetch_kib"]) * 1024 * float(rec["fetch_scale"])
-    write = float(rec["write_kib"]) * 1024 * float(rec["write_scale"])
-    return fetch + write
+    fetch = float(per[kernel]["fetch_kib"]) * 1024 * float(rec["fetch_scale"])
+    write = float(per[kernel]["write_kib"]) * 1024 * float(rec["write_scale"])
+    return round(fetch + write)
 
 
 def cpu_baseline(st, n_rows):
@@ -613,12 +619,12 @@ def main():
     alg_bytes = in_bytes + out_bytes
     per_term = alg_bytes / terms
     kernel_names = {"count": "k_tx_count", "scan": "k_colsum/k_colbase/k_colapply",
-                    "scatter": "k_tx_scatter", "aggregate": "k_aggregate"}
+                    "scatter": "k_tx_scatter", "aggregate": "k_aggregate_flat"}
     dom = max(stage_ms, key=stage_ms.get)
     dom_ms = stage_ms[dom]
     achieved = per_term * terms / (dom_ms * 1e-3) / 1e9
     digest = source_digest("k_route.hip", "k_exact.hip", "crop_device.hpp")
-    traffic = traffic_from_profiles(kernel_names[dom], digest, None)
+    traffic = traffic_from_profiles(kernel_names[dom], digest)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "kernel": kernel_names[dom],
