@@ -132,6 +132,17 @@ k_tx_scatter(const uint32_t *__restrict__ off, const uint32_t *__restrict__ item
     const uint32_t NB = cv.NB;
     const uint32_t *row = cv.row;
     const uint32_t *nxt = cv.nxt;
+    if (cap == 0) {
+        // No staging: the bin cursors start at the chunk's global write
+        // positions, so a term's LDS atomic returns its slot in HBM.
+        for (uint32_t b = threadIdx.x; b < NB; b += BS) lcur[b] = row[b];
+        const uint32_t m = stage_tx<BS>(off, items, cv.r0, cv.r1, hp, L);  // ends with a barrier
+        enum_tx<BS>(m, L, hp, [&](uint32_t x, uint32_t y, uint32_t h) {
+            const uint32_t bin = cv.bm.local(h);
+            if (bin < NB) keys[atomicAdd(&lcur[bin], 1u)] = pack_key<KeyT>(x, y);
+        });
+        return;
+    }
     for (uint32_t b = threadIdx.x; b < NB; b += BS) lstart[b] = nxt[b] - row[b];
     __syncthreads();
     lds_exclusive_scan<BS>(lstart, NB, s_tmp);
@@ -144,10 +155,7 @@ k_tx_scatter(const uint32_t *__restrict__ off, const uint32_t *__restrict__ item
     if (Tc == 0) return;
 
     for (uint32_t b0 = 0; b0 < NB;) {
-        if (threadIdx.x == 0 && cap == 0) {
-            s_direct = 1u;  // no staging: every term goes straight to its slot
-            s_b1 = NB;
-        } else if (threadIdx.x == 0) {
+        if (threadIdx.x == 0) {
             // last b1 in [b0, NB] with lstart[b1] - lstart[b0] <= cap (lstart is
             // non-decreasing); an empty window means bin b0 alone exceeds cap
             const uint32_t lim = lstart[b0] + cap;
