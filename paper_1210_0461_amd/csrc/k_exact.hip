@@ -309,6 +309,32 @@ __device__ inline void packed_dump(const uint64_t *tab, uint32_t *keys_out, uint
     }
 }
 
+// After the table's key set is frozen: spilled entries whose key is in the
+// table add their weight there; the others stay in the spill list, which is
+// compacted in place (a batch is read before any entry is rewritten, and
+// the kept entries never outnumber the entries read).  Afterwards the spill
+// list and the table hold disjoint keys.
+template <int BS, int LOG2S>
+__device__ void packed_absorb_spill(uint64_t *tab, Spilled<uint32_t, uint32_t> *spill,
+                                    uint32_t k0, uint32_t *s_nspill_p)
+{
+    constexpr uint32_t MASK = (1u << LOG2S) - 1;
+    uint32_t &s_nspill = *s_nspill_p;
+    const uint32_t n = s_nspill;
+    __syncthreads();
+    if (threadIdx.x == 0) s_nspill = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < n; base += BS) {
+        const uint32_t i = base + threadIdx.x;
+        Spilled<uint32_t, uint32_t> e{kEmpty32, 0u};
+        if (i < n) e = spill[k0 + i];
+        __syncthreads();
+        if (i < n && packed_add<MASK, LOG2S>(tab, e.key, e.w, false) == kAbsent)
+            spill[k0 + atomicAdd(&s_nspill, 1u)] = e;
+        __syncthreads();
+    }
+}
+
 // Further rounds over a bin's spilled (key, weight) pairs until none is
 // left: each round fills the emptied table up to cap_soft and dumps it.
 template <int BS, int LOG2S>
@@ -546,14 +572,16 @@ k_aggregate_packed(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ 
     }
 }
 
-// Flat variant of the packed aggregation: U keys per thread per batch, the U
-// home slots read together, hits added without waiting for anything,
-// only collisions and new keys going on to probe; one barrier per batch.  The
-// table's occupancy for the insert decision is the sum of the per-batch
-// insert counts of all earlier batches (a ring of three counters: batch q
-// adds into ring[q % 3], zeroes ring[(q + 1) % 3] and reads ring[(q - 1) % 3]
-// after the barrier that ended batch q - 1), so every thread takes the same
-// decision without a second barrier.
+// Flat variant of the packed aggregation: every wavefront walks its own
+// batches of the bin (64 U keys: U per lane), reads the U home slots
+// together, adds hits without waiting for anything and sends only
+// collisions and new keys on to probe.  There is no barrier between
+// batches: a wavefront decides whether it may insert from the workgroup's
+// insert counter, read before each batch and raised by the batch's inserts
+// right after it.  A wavefront has at most one batch whose inserts are not
+// yet counted, so when the last batch allowed to insert read at most
+// cap_soft, the table never holds more than cap_soft + (BS / 64) * 64 U =
+// cap_soft + BS U keys.
 template <int BS, int LOG2S, int U>
 __global__ void __launch_bounds__(BS)
 k_aggregate_flat(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ keys,
@@ -563,13 +591,15 @@ k_aggregate_flat(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ ke
 {
     constexpr uint32_t S = 1u << LOG2S;
     constexpr uint32_t MASK = S - 1;
+    constexpr uint32_t NW = BS / kWave;       // wavefronts
+    constexpr uint32_t WB = kWave * U;        // keys of one wavefront batch
     static_assert(S % BS == 0, "table size must be a multiple of the block size");
     static_assert(S > BS * U, "a batch must fit in the table");
     __shared__ uint64_t tab[S];
-    __shared__ uint32_t s_ring[3];
     __shared__ uint32_t s_occ, s_nout, s_nspill, s_bin;
     __shared__ int s_insert;
     const uint32_t lane = lane_id();
+    const uint32_t wave = threadIdx.x / kWave;
 
     for (;;) {
         if (threadIdx.x == 0) {
@@ -582,27 +612,26 @@ k_aggregate_flat(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ ke
         const uint32_t k0 = bin_off[b], k1 = bin_off[b + 1];
         for (uint32_t s = threadIdx.x; s < S; s += BS) tab[s] = kFreeSlot;
         if (threadIdx.x == 0) {
-            s_ring[0] = s_ring[1] = s_ring[2] = 0;
+            s_occ = 0;
             s_nout = 0;
             s_nspill = 0;
         }
         const uint32_t last = k1 - 1;  // read only when the bin is not empty
+        uint32_t base = k0 + wave * WB;
         uint32_t cur[U] = {};
-        if (k1 > k0) {
+        if (base < k1) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) cur[u] = keys[min(k0 + u * BS + threadIdx.x, last)];
+            for (int u = 0; u < U; ++u) cur[u] = keys[min(base + u * kWave + lane, last)];
         }
-        lds_barrier();
-        uint32_t occ = 0;  // inserts of the batches before the previous one
-        uint32_t q = 0;
-        for (uint32_t base = k0; base < k1; base += BS * U, ++q) {
+        __syncthreads();
+        for (; base < k1; base += NW * WB) {
+            const uint32_t nb = base + NW * WB;
             uint32_t nx[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                nx[u] = keys[min(base + BS * U + u * BS + threadIdx.x, last)];
-            if (q) occ += s_ring[(q + 2) % 3];  // the previous batch's inserts
-            if (threadIdx.x == 0) s_ring[(q + 1) % 3] = 0;
-            const bool ins = occ <= cap_soft;  // at most cap_soft + BS * U keys in the table
+            for (int u = 0; u < U; ++u) nx[u] = keys[min(nb + u * kWave + lane, last)];
+            const bool ins =
+                __hip_atomic_load(&s_occ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <=
+                cap_soft;
             uint64_t v[U];
             uint32_t hs[U];
 #pragma unroll
@@ -613,7 +642,7 @@ k_aggregate_flat(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ ke
             uint32_t pend = 0;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const bool valid = base + u * BS + threadIdx.x < k1;
+                const bool valid = base + u * kWave + lane < k1;
                 if (!valid) continue;
                 if ((uint32_t)v[u] == cur[u])
                     atomicAdd(count_word(&tab[hs[u]]), 1u);
@@ -682,12 +711,13 @@ k_aggregate_flat(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ ke
             uint32_t tot = n_new;
 #pragma unroll
             for (int d = 32; d >= 1; d >>= 1) tot += __shfl_xor(tot, d, kWave);
-            if (lane == 0 && tot) atomicAdd(&s_ring[q % 3], tot);
-            lds_barrier();
+            if (lane == 0 && tot) atomicAdd(&s_occ, tot);
 #pragma unroll
             for (int u = 0; u < U; ++u) cur[u] = nx[u];
         }
         __syncthreads();  // keys of the bin are consumed; the spill list is complete
+        // a wavefront may have spilled a key that a slower one inserted
+        packed_absorb_spill<BS, LOG2S>(tab, spill, k0, &s_nspill);
         packed_dump<BS, LOG2S>(tab, keys + k0, w_out + k0, &s_nout);
         __syncthreads();
         packed_spill_rounds<BS, LOG2S>(tab, spill, k0, keys, w_out, cap_soft, &s_occ, &s_nout,
