@@ -241,7 +241,10 @@ crop_status crop_last_run_ms(crop_ctx *ctx, float *ms);
  * sign hash; w = 1 for transactions, a_k(i) b_k(j) for outer products).
  * `instances` (1..15) independent sketches use the hash parameters of
  * seed + i.  Counters are int32 for transactions (exact), fp32 for outer
- * products.  P * B <= 2^32. */
+ * products.  P * B <= 2^32.  Each instance's terms are routed into bins of
+ * whole buckets and summed per bin on chip when B has a suitable divisor
+ * (bins_per_partition of crop_set_tuning picks it when it divides B); else
+ * every term adds to its counter with a device atomic. */
 crop_status crop_run_countsketch(crop_ctx *ctx, uint32_t buckets_per_partition,
                                  uint32_t instances);
 /* Median over the instances of s_i(e) * C_i[bucket_i(e)] for each query pair

@@ -990,8 +990,39 @@ crop_status crop_run_countsketch(crop_ctx *ctx, uint32_t buckets_per_partition,
     DeviceGuard g(ctx->device);
     ctx->result = Result::None;
     const bool outer = ctx->in.mode == Mode::Outer;
-    crop_status st = outer ? plan_outer(ctx) : plan_tx(ctx);
+    // Routed when the partition's buckets split into S bins (S divides B)
+    // that give at least kCsMinBins bins of at most kCsMaxBinBuckets
+    // buckets each; S is the divisor closest to the exact path's terms per
+    // bin (the largest at or below it, else the smallest above).
+    const uint32_t B = buckets_per_partition;
+    const uint64_t per_bin = outer ? kTermsPerBin / 16 : kTermsPerBin;
+    const uint64_t want =
+        std::max<uint64_t>(1, (ctx->in.total_terms + per_bin - 1) / per_bin / ctx->P);
+    uint32_t S = 0;
+    for (uint64_t d = 1; d * d <= B; ++d) {
+        if (B % d) continue;
+        for (uint64_t c : {d, (uint64_t)B / d}) {
+            if ((uint64_t)ctx->P * c > kMaxP || B / c > kCsMaxBinBuckets) continue;
+            const bool better = S == 0 || (c <= want ? (S > want || c > S) : (S > want && c < S));
+            if (better) S = (uint32_t)c;
+        }
+    }
+    bool routed = S != 0 && (uint64_t)ctx->P * S >= std::min<uint64_t>(kCsMinBins, PB);
+    // bins_per_partition of crop_set_tuning, when it divides B, forces the
+    // routed form with that many bins per partition
+    const uint32_t St = ctx->tune.bins_per_partition;
+    if (St && B % St == 0 && (uint64_t)ctx->P * St <= kMaxP && B / St <= kCsMaxBinBuckets) {
+        S = St;
+        routed = true;
+    }
+    crop_status st = outer ? plan_outer(ctx, routed ? S : 0) : plan_tx(ctx, routed ? S : 0);
     if (st != CROP_OK) return st;
+    if (routed) {
+        ctx->plan.log2_slots = 0;
+        ctx->plan.BS = 256;
+        st = ensure_route_buffers(ctx, ctx->in.wide_keys || outer ? 8 : 4, outer);
+        if (st != CROP_OK) return st;
+    }
     CsParams &cp = ctx->cs;
     cp.t = instances;
     cp.PB = PB;
@@ -1002,13 +1033,35 @@ crop_status crop_run_countsketch(crop_ctx *ctx, uint32_t buckets_per_partition,
     hipStream_t s = ctx->stream;
     st = run_begin(ctx);
     if (st != CROP_OK) return st;
-    CK(launch_cs_clear(ctx->cs_buf.p, words, s));
-    STAGE("clear");
-    if (outer)
-        CK(launch_cs_op(ctx, cp, ctx->cs_buf.as<float>(), s));
-    else
-        CK(launch_cs_tx(ctx, cp, ctx->cs_buf.as<int32_t>(), s));
-    STAGE("sketch");
+    if (routed) {
+        const RoutePlan &pl = ctx->plan;
+        uint32_t *cnt = ctx->cnt_mat.as<uint32_t>();
+        for (uint32_t i = 0; i < instances; ++i) {
+            ctx->hp = cp.hp[i];  // routing by this instance's hash
+            if (pl.n_chunks) CK(outer ? launch_op_count(ctx, cnt, s)
+                                      : pl.n_wg ? launch_tx_count_ranges(ctx, cnt, s)
+                                                : launch_tx_count(ctx, cnt, s));
+            CK(launch_scan_counts(cnt, pl.n_wg ? pl.n_wg : pl.n_chunks, pl.NB, pl.G,
+                                  ctx->part_buf.as<uint32_t>(), ctx->bin_off.as<uint32_t>(),
+                                  ctx->counter.as<uint32_t>(), s));
+            if (pl.n_chunks)
+                CK(outer ? launch_op_scatter(ctx, cnt, ctx->keys.p, ctx->vals.as<float>(), s)
+                         : pl.n_wg ? launch_tx_scatter_ranges(ctx, cnt, ctx->keys.p, s)
+                                   : launch_tx_scatter(ctx, cnt, ctx->keys.p, s));
+            CK(launch_cs_bins(ctx, cp.hp[i], PB, B / S, ctx->cs_buf.as<uint32_t>() + i * PB, s));
+        }
+        ctx->hp = cp.hp[0];
+        STAGE("sketch");
+    } else {
+        CK(launch_cs_clear(ctx->cs_buf.p, words, s));
+        STAGE("clear");
+        if (outer)
+            CK(launch_cs_op(ctx, cp, ctx->cs_buf.as<float>(), s));
+        else
+            CK(launch_cs_tx(ctx, cp, ctx->cs_buf.as<int32_t>(), s));
+        STAGE("sketch");
+    }
+    ctx->cs_routed = routed ? 1u : 0u;
     st = run_end(ctx);
     if (st != CROP_OK) return st;
     ctx->result = Result::CountSketch;

@@ -102,6 +102,8 @@ struct BatchDev {
 
 // Count-Sketch instances: hash parameters of instance i from seed + i.
 constexpr uint32_t kCsMaxInstances = 15;
+constexpr uint64_t kCsMinBins = 256;          // fewer routed bins: direct atomics
+constexpr uint64_t kCsMaxBinBuckets = 16384;  // counters of one bin in LDS
 struct CsParams {
     HashParams hp[kCsMaxInstances];
     uint32_t t;   // instances
@@ -193,6 +195,7 @@ struct crop_ctx {
     crop::DevBuf cs_buf;       // Count-Sketch counters [t][P * B]
     crop::CsParams cs{};       // ... of the last Count-Sketch run
     uint32_t cs_B = 0;
+    uint32_t cs_routed = 0;    // ... was routed into bins of buckets
     crop::SsState ss;          // views into ss_state
     uint64_t ss_buckets = 0;   // P * B of the last top-K run
     uint32_t topk_outer = 0;   // the last top-K run was on outer products
@@ -278,6 +281,8 @@ size_t tx_count_smem_bytes(uint32_t NB, uint32_t max_items);
 hipError_t launch_cs_clear(void *cs, uint64_t words, hipStream_t s);
 hipError_t launch_cs_tx(const crop_ctx *c, const CsParams &cp, int32_t *cs, hipStream_t s);
 hipError_t launch_cs_op(const crop_ctx *c, const CsParams &cp, float *cs, hipStream_t s);
+hipError_t launch_cs_bins(const crop_ctx *c, const HashParams &hp, uint64_t PB, uint32_t nbk,
+                          uint32_t *out, hipStream_t s);
 hipError_t launch_cs_estimate(const CsParams &cp, const void *cs, bool fp, const uint32_t *qx,
                               const uint32_t *qy, uint64_t n, double *out, hipStream_t s);
 

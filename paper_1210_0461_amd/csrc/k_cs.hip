@@ -7,9 +7,14 @@
 // their median.  Buckets nest in partitions as for Space-Saving: bucket =
 // (h * P * B) >> 32, so partition = bucket / B.
 //
-// The enumeration is the routing kernels' (crop_enum.hpp); every term adds to
-// one counter per instance with a device-scope atomic.  Transactions count
-// with int32 counters (exact); outer products with fp32.
+// Two ways to fill the counters.  Routed (the default): each instance's
+// terms are first routed with that instance's hash into bins of whole
+// buckets (the exact path's count, scan and scatter), and one workgroup per
+// bin sums the bin's signed weights in LDS and writes its buckets' counters
+// once.  Direct (when the buckets of a partition have no divisor that gives
+// enough bins): the routing kernels' enumeration (crop_enum.hpp) adds every
+// term to one counter per instance with a device-scope atomic.  Transactions
+// count with int32 counters (exact); outer products with fp32.
 #include <algorithm>
 
 #include "crop_device.hpp"
@@ -61,6 +66,44 @@ k_cs_op(OpArgs a, uint32_t max_a, CsParams cp, float *__restrict__ cs)
                         atomicAdd(&cs[(uint64_t)i * cp.PB + b], sign_of(hp, x, y) > 0 ? v : -v);
                     }
                 });
+}
+
+// Bin b holds buckets [b nbk, (b + 1) nbk) of the instance (bucket =
+// (h * PB) >> 32 and bin = (h * NB) >> 32 with PB = NB nbk nest).  Its
+// counters are summed in LDS from the bin's routed keys and written once.
+template <int BS, class KeyT, bool OUTER>
+__global__ void __launch_bounds__(BS)
+k_cs_bins(const uint32_t *__restrict__ bin_off, const KeyT *__restrict__ keys,
+          const float *__restrict__ vals, HashParams hp, uint64_t PB, uint32_t nbk, uint32_t NB,
+          uint32_t *__restrict__ out)
+{
+    extern __shared__ uint32_t acc[];
+    for (uint32_t b = blockIdx.x; b < NB; b += gridDim.x) {
+        for (uint32_t q = threadIdx.x; q < nbk; q += BS) acc[q] = 0;
+        __syncthreads();
+        const uint32_t k1 = bin_off[b + 1];
+        const uint64_t first = (uint64_t)b * nbk;
+        for (uint32_t k = bin_off[b] + threadIdx.x; k < k1; k += BS) {
+            const KeyT key = keys[k];
+            uint32_t x, y;
+            if (sizeof(KeyT) == 4) {
+                x = (uint32_t)key >> 16;
+                y = (uint32_t)key & 0xFFFFu;
+            } else {
+                x = (uint32_t)((uint64_t)key >> 32);
+                y = (uint32_t)key;
+            }
+            const uint32_t q = (uint32_t)(interval_of(hash_a(hp, x) + hash_b(hp, y), PB) - first);
+            const int sg = sign_of(hp, x, y);
+            if (OUTER)
+                atomicAdd(reinterpret_cast<float *>(&acc[q]), sg > 0 ? vals[k] : -vals[k]);
+            else
+                atomicAdd(reinterpret_cast<int32_t *>(&acc[q]), sg);
+        }
+        __syncthreads();
+        for (uint32_t q = threadIdx.x; q < nbk; q += BS) out[first + q] = acc[q];
+        __syncthreads();
+    }
 }
 
 __global__ void __launch_bounds__(256) k_cs_clear(uint32_t *__restrict__ p, uint64_t n)
@@ -145,6 +188,30 @@ hipError_t launch_cs_op(const crop_ctx *c, const CsParams &cp, float *cs, hipStr
     const size_t sm = sizeof(uint32_t) * (5 * (size_t)pl.max_items + 1 + 256 / kWave + 1);
     hipLaunchKernelGGL(k_cs_op<256>, dim3(pl.n_chunks), dim3(256), sm, s, a, pl.max_items, cp,
                        cs);
+    return hipGetLastError();
+}
+
+// One instance's counters from the routed keys of the current plan: NB bins
+// of nbk buckets each (PB = NB nbk counters at out).
+hipError_t launch_cs_bins(const crop_ctx *c, const HashParams &hp, uint64_t PB, uint32_t nbk,
+                          uint32_t *out, hipStream_t s)
+{
+    const RoutePlan &pl = c->plan;
+    const uint32_t NB = pl.NB;
+    const size_t sm = (size_t)nbk * 4;
+    const uint32_t grid = std::min<uint32_t>(NB, 8192);
+    if (c->in.mode == Mode::Outer)
+        hipLaunchKernelGGL((k_cs_bins<256, uint64_t, true>), dim3(grid), dim3(256), sm, s,
+                           c->bin_off.as<uint32_t>(), c->keys.as<uint64_t>(),
+                           c->vals.as<float>(), hp, PB, nbk, NB, out);
+    else if (c->in.wide_keys)
+        hipLaunchKernelGGL((k_cs_bins<256, uint64_t, false>), dim3(grid), dim3(256), sm, s,
+                           c->bin_off.as<uint32_t>(), c->keys.as<uint64_t>(), nullptr, hp, PB,
+                           nbk, NB, out);
+    else
+        hipLaunchKernelGGL((k_cs_bins<256, uint32_t, false>), dim3(grid), dim3(256), sm, s,
+                           c->bin_off.as<uint32_t>(), c->keys.as<uint32_t>(), nullptr, hp, PB,
+                           nbk, NB, out);
     return hipGetLastError();
 }
 

@@ -62,6 +62,27 @@ def test_tx_counters_bit_exact(crop, ctx, P, B, t):
         np.testing.assert_array_equal(got[i], oracle.tx_countsketch(st.off, st.items, sd, P, B))
 
 
+@pytest.mark.parametrize("P,B,t,S", [(8, 64, 3, 4), (1, 100, 2, 25), (3, 100, 2, 100),
+                                     (16, 4096, 5, 8), (2, 7, 1, 7)])
+def test_tx_counters_routed_bit_exact(crop, ctx, P, B, t, S):
+    """The routed form (bins of B / S buckets summed on chip) forced on small
+    inputs, including bins of one bucket and a prime bucket count."""
+    st = datagen.config_small()
+    crop.crop_set_tuning(ctx, bins_per_partition=S)
+    got = run_tx(crop, ctx, st, P, B, t)
+    for i, sd in enumerate(seeds_of(t)):
+        np.testing.assert_array_equal(got[i], oracle.tx_countsketch(st.off, st.items, sd, P, B))
+
+
+def test_tx_wide_ids_routed(crop, ctx):
+    """Item ids beyond 16 bits (64-bit routed keys)."""
+    st = datagen.tiny_transactions(31, T=400, n=150_000, zipf_s=0.6, mean_len=6, cap=20)
+    crop.crop_set_tuning(ctx, bins_per_partition=16)
+    got = run_tx(crop, ctx, st, 4, 64, 3)
+    for i, sd in enumerate(seeds_of(3)):
+        np.testing.assert_array_equal(got[i], oracle.tx_countsketch(st.off, st.items, sd, 4, 64))
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_tx_random_tiny(crop, ctx, seed):
     st = datagen.tiny_transactions(300 + seed, T=60, n=25, cap=10)
@@ -111,6 +132,22 @@ def test_outer_counters_and_estimates(crop, ctx):
     assert np.all(np.abs(got - want) <= 1e-5 * bmax)
 
 
+def test_outer_counters_routed(crop, ctx):
+    op = datagen.tiny_outer(6, K=300, n_rows=60, n_cols=50, max_nnz=12)
+    P, B, t = 4, 16, 3
+    crop.crop_set_tuning(ctx, bins_per_partition=4)
+    crop.crop_set_partitions(ctx, P)
+    crop.crop_set_seed(ctx, SEED)
+    crop.crop_load_outer(ctx, op.a_off, op.a_idx, op.a_val, op.b_off, op.b_idx, op.b_val,
+                         op.n_rows, op.n_cols)
+    crop.crop_run_countsketch(ctx, B, t)
+    for i, sd in enumerate(seeds_of(t)):
+        got = crop.crop_read_countsketch(ctx, i, P * B)
+        want = oracle.op_countsketch(op, sd, P, B)
+        bound = 1e-5 * oracle.op_bucket_abs(op, sd, P, B) + 1e-30
+        assert np.all(np.abs(got - want) <= bound), i
+
+
 def test_outer_config(crop, ctx):
     """The 100,000-product workload, P = 8, 2^13 buckets per partition,
     three instances."""
@@ -130,7 +167,8 @@ def test_outer_config(crop, ctx):
 
 def test_large_stream_full_sketch(crop, ctx):
     """The 1M-transaction stream, P = 1024, 1024 buckets per partition, three
-    instances: every counter equal to the oracle's."""
+    instances (routed into 2,048 bins): every counter equal to the
+    oracle's."""
     st = datagen.config_large()
     P, B, t = 1024, 1024, 3
     got = run_tx(crop, ctx, st, P, B, t)
