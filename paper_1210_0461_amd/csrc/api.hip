@@ -292,7 +292,6 @@ crop_status plan_ss(crop_ctx *ctx, uint32_t *nbk_out, uint64_t *PB_out)
         return fail(ctx, CROP_E_UNSUPPORTED, "P x buckets per partition exceeds 2^32");
     const bool outer = ctx->in.mode == Mode::Outer;
     const bool wide = outer || ctx->in.wide_keys;
-    const uint32_t MB = outer ? kSsBatchOuter : wide ? kSsBatchWide : kSsBatchTx;
     // Bins of nbk buckets (nbk divides B), at most kMaxP bins and within the
     // LDS budget: the largest nbk that still leaves min(kSsMinBins, P*B)
     // bins, else the smallest feasible nbk.
@@ -304,15 +303,30 @@ crop_status plan_ss(crop_ctx *ctx, uint32_t *nbk_out, uint64_t *PB_out)
         }
     std::sort(divs.begin(), divs.end());
     const uint64_t min_bins = std::min<uint64_t>(kSsMinBins, PB);
+    auto pick_for = [&](uint32_t MB) {
+        uint64_t pick = 0;
+        for (uint64_t nbk : divs) {
+            const uint64_t NB = PB / nbk;
+            if (NB > kMaxP) continue;
+            if (ss_bins_smem_bytes((uint32_t)nbk, ell, wide, outer, MB) > kSsLdsBudget) break;
+            if (!pick || NB >= min_bins) pick = nbk;
+        }
+        return pick;
+    };
+    // Packed transaction keys merge micro-batches of kSsBatchTxLarge terms
+    // when bins hold several buckets (measured faster: fewer, longer merged
+    // update lists per bucket); a bin of one bucket keeps the smaller batch,
+    // whose merge phase is shorter for its single group of lanes.
+    uint32_t MB = outer ? kSsBatchOuter : wide ? kSsBatchWide : kSsBatchTx;
     uint64_t pick = 0;
-    for (uint64_t nbk : divs) {
-        const uint64_t NB = PB / nbk;
-        if (NB > kMaxP) continue;
-        if (ss_bins_smem_bytes((uint32_t)nbk, ell, wide, outer, MB) > kSsLdsBudget) break;
-        if (!pick || NB >= min_bins) pick = nbk;
+    if (!wide) {
+        pick = pick_for(kSsBatchTxLarge);
+        if (pick > 1) MB = kSsBatchTxLarge;
     }
+    if (MB != kSsBatchTxLarge) pick = pick_for(MB);
     if (!pick)
         return fail(ctx, CROP_E_UNSUPPORTED, "Space-Saving summaries do not fit the LDS plan");
+    ctx->plan.ss_mb = MB;
     *nbk_out = (uint32_t)pick;
     *PB_out = PB;
     return CROP_OK;

@@ -687,8 +687,10 @@ k_amp_combine(CsParams ip, uint32_t ell, uint64_t ns, uint32_t min_votes,
                 const uint64_t b = interval_of(hash_a(ip.hp[j], x) + hash_b(ip.hp[j], y), ip.PB);
                 const uint64_t base = (uint64_t)j * ns + b * ell;
                 q = ~0ull;
+                // keys first: a free slot's key is 0, so its flag is read only
+                // when the entry's own key is 0 (outer products' (0, 0))
                 for (uint32_t r = 0; r < ell; ++r)
-                    if ((flag[base + r] & kUsed) && key[base + r] == k) {
+                    if (key[base + r] == k && (flag[base + r] & kUsed)) {
                         q = base + r;
                         break;
                     }
@@ -795,6 +797,14 @@ static void launch_ss_g(const crop_ctx *c, const SsState &S, uint32_t nbk, uint6
                            sm, s, c->bin_off.as<uint32_t>(), c->bin_order.as<uint32_t>(),
                            c->keys.as<uint64_t>(), nullptr,
                            pl.NB, nbk, ell, c->hp, PB, false, c->counter.as<uint32_t>(), S.key,
+                           S.cnt, S.err, S.val, S.flag);
+    } else if (pl.ss_mb == kSsBatchTxLarge) {
+        constexpr int MB = kSsBatchTxLarge;
+        const size_t sm = ss_bins_smem_bytes(nbk, ell, false, false, MB);
+        hipLaunchKernelGGL((k_ss_groups<G, uint32_t, false, MB>), dim3(grid), dim3(bs),
+                           sm, s, c->bin_off.as<uint32_t>(), c->bin_order.as<uint32_t>(),
+                           c->keys.as<uint32_t>(), nullptr,
+                           pl.NB, nbk, ell, c->hp, PB, true, c->counter.as<uint32_t>(), S.key,
                            S.cnt, S.err, S.val, S.flag);
     } else {
         constexpr int MB = kSsBatchTx;
