@@ -2,22 +2,24 @@
 //
 // A partition's exact result is the weight of every entry it owns
 // (Section 4: sum_k a_k(i) b_k(j); Section 7: pair supports).  The paper
-// contrasts its shared-nothing owners with "a large, shared data structure"
-// updated at random (Section 7.3, throughput discussion): here every routing
+// sets its shared-nothing owners against one big table that all processors
+// update at random (Section 7.3, throughput discussion): here every routing
 // bin belongs to one workgroup, whose table lives in that CU's LDS, so all
 // random updates are on-chip and no two workgroups share an entry.
 //
 // Persistent workgroups pull bins from a counter.  A bin's keys are read
-// once, coalesced; each wavefront first merges repeated copies of the same
-// key (heavy pairs land thousands of times in one bin) and then inserts with
-// linear probing: compare-and-swap claims an empty slot, an atomic add
-// accumulates.  When the table passes its fill limit the workgroup stops
-// inserting (at a barrier, so the key set is frozen) and entries that are
-// not present are spilled to HBM with their weight; after the table is
-// written out, the spilled entries are accumulated in further rounds.  The
-// table's entries and a later round's entries are disjoint, so every key is
-// written exactly once.  Output: distinct keys in place of the bin's routed
-// keys, weights in a parallel array, and the bin's entry count.
+// once, coalesced, and inserted with linear probing: compare-and-swap claims
+// an empty slot, an atomic add accumulates.  Packed 32-bit keys use 64-bit
+// slots (key and count in one word, k_aggregate_flat); 64-bit keys and fp32
+// sums use separate key and weight arrays, and each wavefront first merges
+// repeated copies of its lead key (k_aggregate).  When the table passes its
+// fill limit the workgroup stops inserting and entries that are not present
+// are spilled to HBM with their weight; once the key set is frozen (at a
+// barrier) the table is written out and the spilled entries are accumulated
+// in further rounds.  The table's entries and a later round's entries are
+// disjoint, so every key is written exactly once.  Output: distinct keys in
+// place of the bin's routed keys, weights in a parallel array, and the bin's
+// entry count.
 #include <type_traits>
 
 #include "crop_device.hpp"
@@ -380,194 +382,6 @@ __device__ void packed_spill_rounds(uint64_t *tab, Spilled<uint32_t, uint32_t> *
             __syncthreads();
         }
         packed_dump<BS, LOG2S>(tab, keys + k0, w_out + k0, s_nout);
-        __syncthreads();
-    }
-}
-
-// One persistent workgroup per CU, 16 wavefronts.  The next batch of keys
-// is loaded into registers while the current one is accumulated, and the
-// batch barriers order LDS only, so the prefetch stays in flight.
-template <int BS, int LOG2S>
-__global__ void __launch_bounds__(BS)
-k_aggregate_packed(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ keys,
-                   uint32_t *__restrict__ w_out, uint32_t *__restrict__ bin_size,
-                   Spilled<uint32_t, uint32_t> *__restrict__ spill, uint32_t NB,
-                   uint32_t *counter, uint32_t cap_soft, const uint32_t *__restrict__ order)
-{
-    constexpr uint32_t S = 1u << LOG2S;
-    constexpr uint32_t MASK = S - 1;
-    constexpr int U = 4;
-    static_assert(S % BS == 0, "table size must be a multiple of the block size");
-    // Insertion stops at the first batch boundary after the occupancy passes
-    // cap_soft, so the table never holds more than cap_soft + BS * U keys:
-    // that must leave free slots, or a probe could run forever.
-    static_assert(S > BS * U, "a batch must fit in the table");
-    __shared__ uint64_t tab[S];
-    __shared__ uint32_t s_occ, s_nout, s_nspill, s_bin;
-    __shared__ int s_insert;
-    const uint32_t lane = lane_id();
-
-    for (;;) {
-        if (threadIdx.x == 0) {
-            const uint32_t i = atomicAdd(counter, 1u);
-            s_bin = i < NB ? order[i] : NB;
-        }
-        __syncthreads();
-        const uint32_t b = s_bin;
-        if (b >= NB) break;
-        const uint32_t k0 = bin_off[b], k1 = bin_off[b + 1];
-        for (uint32_t s = threadIdx.x; s < S; s += BS) tab[s] = kFreeSlot;
-        if (threadIdx.x == 0) {
-            s_occ = 0;
-            s_nout = 0;
-            s_nspill = 0;
-            s_insert = 1;
-        }
-        // Loads are unconditional (clamped to the bin's last key) so that no
-        // value is needed right after its load; validity is checked at use.
-        const uint32_t last = k1 - 1;  // read only when the bin is not empty
-        uint32_t cur[U] = {};
-        if (k1 > k0) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) cur[u] = keys[min(k0 + u * BS + threadIdx.x, last)];
-        }
-        lds_barrier();
-
-        for (uint32_t base = k0; base < k1; base += BS * U) {
-            uint32_t nx[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u)
-                nx[u] = keys[min(base + BS * U + u * BS + threadIdx.x, last)];
-            const bool ins = s_insert != 0;
-            // Merge: lanes holding the same key as the wavefront's first lane
-            // hand their unit to it (a heavy pair fills most of its bin).
-            uint32_t wt[U];
-            uint32_t live = 0;  // bit u: key u still to be accumulated
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const bool valid = base + u * BS + threadIdx.x < k1;
-                const uint32_t lk = __builtin_amdgcn_readfirstlane(cur[u]);
-                const uint64_t same = __ballot(valid && cur[u] == lk);
-                wt[u] = 1;
-                bool keep = valid;
-                if (valid && cur[u] == lk) {
-                    if (lane == (uint32_t)(__ffsll((long long)same) - 1))
-                        wt[u] = (uint32_t)__popcll(same);
-                    else
-                        keep = false;
-                }
-                live |= (keep ? 1u : 0u) << u;
-            }
-            // Fast path: the U home slots are read together (no dependency
-            // between the reads), then a key found there takes its weight and
-            // a free home slot takes a new key.  Only the rest probe further.
-            uint32_t n_new = 0;
-            {
-                uint64_t hv[U];
-                uint32_t hs[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    hs[u] = slot_of(cur[u], LOG2S);
-                    hv[u] = tab[hs[u]];
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (!((live >> u) & 1u)) continue;
-                    const uint32_t k = (uint32_t)hv[u];
-                    if (k == cur[u]) {
-                        atomicAdd(count_word(&tab[hs[u]]), wt[u]);
-                        live &= ~(1u << u);
-                    } else if (k == kEmpty32 && ins) {
-                        const uint64_t old = atomicCAS((unsigned long long *)&tab[hs[u]],
-                                                       (unsigned long long)kFreeSlot,
-                                                       ((unsigned long long)wt[u] << 32) | cur[u]);
-                        if (old == kFreeSlot) {
-                            ++n_new;
-                            live &= ~(1u << u);
-                        } else if ((uint32_t)old == cur[u]) {
-                            atomicAdd(count_word(&tab[hs[u]]), wt[u]);
-                            live &= ~(1u << u);
-                        }
-                    }
-                }
-            }
-            // Each lane runs its U keys back to back through one probing loop:
-            // a lane that settles a key starts its next key at the next step,
-            // so a wavefront waits for the longest lane's total probe count,
-            // not for the longest probe of every key.
-            int j = 0;
-            while (j < U && !((live >> j) & 1u)) ++j;
-            uint32_t key = 0, w = 0, sl = 0;
-            if (j < U) {
-                key = cur[0];
-                w = wt[0];
-#pragma unroll
-                for (int u = 1; u < U; ++u)
-                    if (j == u) {
-                        key = cur[u];
-                        w = wt[u];
-                    }
-                sl = slot_of(key, LOG2S);
-            }
-            while (j < U) {
-                const uint64_t v = tab[sl];
-                const uint32_t k = (uint32_t)v;
-                bool settled = false;
-                if (k == key) {
-                    atomicAdd(count_word(&tab[sl]), w);
-                    settled = true;
-                } else if (k == kEmpty32) {
-                    if (!ins) {
-                        const uint32_t p = atomicAdd(&s_nspill, 1u);
-                        spill[k0 + p] = Spilled<uint32_t, uint32_t>{key, w};
-                        settled = true;
-                    } else {
-                        const uint64_t old = atomicCAS((unsigned long long *)&tab[sl],
-                                                       (unsigned long long)kFreeSlot,
-                                                       ((unsigned long long)w << 32) | key);
-                        if (old == kFreeSlot) {
-                            ++n_new;
-                            settled = true;
-                        }
-                        // otherwise the slot was just taken: look at it again
-                    }
-                } else {
-                    sl = (sl + 1) & MASK;
-                }
-                if (settled) {
-                    ++j;
-                    while (j < U && !((live >> j) & 1u)) ++j;
-                    if (j < U) {
-                        key = cur[0];
-                        w = wt[0];
-#pragma unroll
-                        for (int u = 1; u < U; ++u)
-                            if (j == u) {
-                                key = cur[u];
-                                w = wt[u];
-                            }
-                        sl = slot_of(key, LOG2S);
-                    }
-                }
-            }
-            // one occupancy update per wavefront
-            uint32_t tot = n_new;
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) tot += __shfl_xor(tot, d, kWave);
-            if (lane == 0 && tot) atomicAdd(&s_occ, tot);
-            lds_barrier();
-            if (threadIdx.x == 0 && s_occ > cap_soft) s_insert = 0;
-            lds_barrier();
-#pragma unroll
-            for (int u = 0; u < U; ++u) cur[u] = nx[u];
-        }
-        __syncthreads();  // keys of the bin are consumed; the spill list is complete
-        packed_dump<BS, LOG2S>(tab, keys + k0, w_out + k0, &s_nout);
-        __syncthreads();
-
-        packed_spill_rounds<BS, LOG2S>(tab, spill, k0, keys, w_out, cap_soft, &s_occ, &s_nout,
-                                       &s_nspill, &s_insert);
-        if (threadIdx.x == 0) bin_size[b] = s_nout;
         __syncthreads();
     }
 }
