@@ -23,6 +23,9 @@ namespace crop {
 
 namespace {
 
+// Threads of a workgroup of the unstaged scatter.
+constexpr int kScatterBS = 1024;
+
 // ---------------------------------------------------------------- chunks
 
 // One chunk of transactions as the count and scatter kernels see it: rows
@@ -101,15 +104,14 @@ k_tx_count(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
     for (uint32_t b = threadIdx.x; b < NB; b += BS) cv.row[b] = hist[b];
 }
 
-// Scatter.  Every term takes a slot of its bin's run in this chunk with an
-// LDS atomic on the bin's local cursor and, with cap == 0, is written
-// straight to that slot (the L2 merges the chunk's neighbouring keys of a
-// bin into whole lines).  With cap > 0 the chunk's terms of a window of bins
-// are put in LDS sorted by bin first and written out run by run, so
-// consecutive lanes store consecutive addresses; a window holds at most cap
-// terms, a bin with more terms than that in one chunk is written directly,
-// and windows are set by bin, a property of the term itself, so each term
-// lands in exactly one window.
+// Staged scatter (cap > 0; without staging k_tx_scatter_direct runs).
+// Every term takes a slot of its bin's run in this chunk with an LDS atomic
+// on the bin's local cursor; the chunk's terms of a window of bins are put
+// in LDS sorted by bin first and written out run by run, so consecutive
+// lanes store consecutive addresses.  A window holds at most cap terms, a
+// bin with more terms than that in one chunk is written directly, and
+// windows are set by bin, a property of the term itself, so each term lands
+// in exactly one window.
 template <int BS, class KeyT, class Chunks>
 __global__ void __launch_bounds__(BS)
 k_tx_scatter(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items, HashParams hp,
@@ -132,17 +134,6 @@ k_tx_scatter(const uint32_t *__restrict__ off, const uint32_t *__restrict__ item
     const uint32_t NB = cv.NB;
     const uint32_t *row = cv.row;
     const uint32_t *nxt = cv.nxt;
-    if (cap == 0) {
-        // No staging: the bin cursors start at the chunk's global write
-        // positions, so a term's LDS atomic returns its slot in HBM.
-        for (uint32_t b = threadIdx.x; b < NB; b += BS) lcur[b] = row[b];
-        const uint32_t m = stage_tx<BS>(off, items, cv.r0, cv.r1, hp, L);  // ends with a barrier
-        enum_tx<BS>(m, L, hp, [&](uint32_t x, uint32_t y, uint32_t h) {
-            const uint32_t bin = cv.bm.local(h);
-            if (bin < NB) keys[atomicAdd(&lcur[bin], 1u)] = pack_key<KeyT>(x, y);
-        });
-        return;
-    }
     for (uint32_t b = threadIdx.x; b < NB; b += BS) lstart[b] = nxt[b] - row[b];
     __syncthreads();
     lds_exclusive_scan<BS>(lstart, NB, s_tmp);
@@ -193,6 +184,30 @@ k_tx_scatter(const uint32_t *__restrict__ off, const uint32_t *__restrict__ item
         __syncthreads();
         b0 = b1;
     }
+}
+
+// Scatter without staging: the chunk's bin cursors start at its global
+// write positions (its row of the scanned count matrix), so a term's LDS
+// atomic returns its slot in HBM and the key is stored there.  LDS: the
+// cursors and the chunk image only.
+template <int BS, class KeyT, class Chunks>
+__global__ void __launch_bounds__(BS)
+k_tx_scatter_direct(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
+                    HashParams hp, uint32_t NBmax, uint32_t max_items, Chunks ch,
+                    KeyT *__restrict__ keys)
+{
+    extern __shared__ uint32_t smem[];
+    uint32_t *lcur = smem;  // NB: global write cursor of each bin
+    const TxLds L = tx_lds(smem, NBmax, max_items);
+    const uint32_t chunk = xcd_contiguous(blockIdx.x, gridDim.x);
+    const ChunkView cv = ch.view(chunk);
+    const uint32_t NB = cv.NB;
+    for (uint32_t b = threadIdx.x; b < NB; b += BS) lcur[b] = cv.row[b];
+    const uint32_t m = stage_tx<BS>(off, items, cv.r0, cv.r1, hp, L);  // ends with a barrier
+    enum_tx<BS>(m, L, hp, [&](uint32_t x, uint32_t y, uint32_t h) {
+        const uint32_t bin = cv.bm.local(h);
+        if (bin < NB) keys[atomicAdd(&lcur[bin], 1u)] = pack_key<KeyT>(x, y);
+    });
 }
 
 // ---- chunk ranges: one workgroup per contiguous range of chunks
@@ -640,6 +655,18 @@ hipError_t launch_tx_scatter(const crop_ctx *c, const uint32_t *cur, void *keys,
     const bool wide = c->in.wide_keys;
     size_t sm = tx_scatter_smem_bytes(pl.NB, pl.max_items, pl.stage_cap, wide);
     const SingleChunks ch = single_chunks(c, const_cast<uint32_t *>(cur));
+    if (pl.stage_cap == 0) {
+        sm = 4 * tx_lds_words(pl.NB, pl.max_items);
+        if (wide)
+            hipLaunchKernelGGL((k_tx_scatter_direct<kScatterBS, uint64_t, SingleChunks>),
+                               dim3(pl.n_chunks), dim3(kScatterBS), sm, s, c->in.off, c->in.items,
+                               c->hp, pl.NB, pl.max_items, ch, static_cast<uint64_t *>(keys));
+        else
+            hipLaunchKernelGGL((k_tx_scatter_direct<kScatterBS, uint32_t, SingleChunks>),
+                               dim3(pl.n_chunks), dim3(kScatterBS), sm, s, c->in.off, c->in.items,
+                               c->hp, pl.NB, pl.max_items, ch, static_cast<uint32_t *>(keys));
+        return hipGetLastError();
+    }
     if (wide)
         hipLaunchKernelGGL((k_tx_scatter<1024, uint64_t, SingleChunks>), dim3(pl.n_chunks),
                            dim3(1024), sm, s, c->in.off, c->in.items, c->hp, pl.NB, pl.max_items,
@@ -699,6 +726,18 @@ hipError_t launch_batch_scatter(const uint32_t *off, const uint32_t *items, cons
     if (!b.n_chunks) return hipSuccess;
     size_t sm = tx_scatter_smem_bytes(b.NBmax, b.max_items, b.stage_cap, wide);
     const BatchChunks ch{b.crow, b.cstream, b.streams, cur, bin_off};
+    if (b.stage_cap == 0) {
+        sm = 4 * tx_lds_words(b.NBmax, b.max_items);
+        if (wide)
+            hipLaunchKernelGGL((k_tx_scatter_direct<kScatterBS, uint64_t, BatchChunks>),
+                               dim3(b.n_chunks), dim3(kScatterBS), sm, s, off, items, hp, b.NBmax,
+                               b.max_items, ch, static_cast<uint64_t *>(keys));
+        else
+            hipLaunchKernelGGL((k_tx_scatter_direct<kScatterBS, uint32_t, BatchChunks>),
+                               dim3(b.n_chunks), dim3(kScatterBS), sm, s, off, items, hp, b.NBmax,
+                               b.max_items, ch, static_cast<uint32_t *>(keys));
+        return hipGetLastError();
+    }
     if (wide)
         hipLaunchKernelGGL((k_tx_scatter<1024, uint64_t, BatchChunks>), dim3(b.n_chunks),
                            dim3(1024), sm, s, off, items, hp, b.NBmax, b.max_items, ch,
