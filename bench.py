@@ -619,7 +619,7 @@ def main():
     alg_bytes = in_bytes + out_bytes
     per_term = alg_bytes / terms
     kernel_names = {"count": "k_tx_count", "scan": "k_colsum/k_colbase/k_colapply",
-                    "scatter": "k_tx_scatter", "aggregate": "k_aggregate_flat"}
+                    "scatter": "k_tx_scatter_direct", "aggregate": "k_aggregate_flat"}
     dom = max(stage_ms, key=stage_ms.get)
     dom_ms = stage_ms[dom]
     achieved = per_term * terms / (dom_ms * 1e-3) / 1e9

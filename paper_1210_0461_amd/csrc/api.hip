@@ -839,6 +839,7 @@ static crop_status run_topk_impl(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
     STAGE("init");
     // instance i routes and summarises with its own hash functions; the
     // kernels take the parameters by value at launch
+    HashGuard hg(ctx);
     for (uint32_t i = 0; i < t; ++i) {
         ctx->hp = ip.hp[i];
         SsState Si = ctx->ss;
@@ -866,7 +867,7 @@ static crop_status run_topk_impl(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
         CK(launch_ss_bins(ctx, Si, nbk, PB, s));
         if (i == 0) STAGE("summaries");
     }
-    ctx->hp = ip.hp[0];
+    ctx->hp = hg.saved;
     const bool by_lower = ctx->topk_rank == CROP_RANK_LOWER;
     if (t > 1) {
         CK(launch_amp_combine(ip, ctx->ss, ctx->ss_ell, nslots, min_votes, outer, amp, votes, s));
@@ -1050,6 +1051,7 @@ crop_status crop_run_countsketch(crop_ctx *ctx, uint32_t buckets_per_partition,
     if (routed) {
         const RoutePlan &pl = ctx->plan;
         uint32_t *cnt = ctx->cnt_mat.as<uint32_t>();
+        HashGuard hg(ctx);
         for (uint32_t i = 0; i < instances; ++i) {
             ctx->hp = cp.hp[i];  // routing by this instance's hash
             if (pl.n_chunks) CK(outer ? launch_op_count(ctx, cnt, s)
@@ -1064,7 +1066,6 @@ crop_status crop_run_countsketch(crop_ctx *ctx, uint32_t buckets_per_partition,
                                    : launch_tx_scatter(ctx, cnt, ctx->keys.p, s));
             CK(launch_cs_bins(ctx, cp.hp[i], PB, B / S, ctx->cs_buf.as<uint32_t>() + i * PB, s));
         }
-        ctx->hp = cp.hp[0];
         STAGE("sketch");
     } else {
         CK(launch_cs_clear(ctx->cs_buf.p, words, s));

@@ -29,6 +29,17 @@ crop_status hip_fail(crop_ctx *c, hipError_t e, const char *what);
         if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr);     \
     } while (0)
 
+// Restores the context's hash parameters when a loop over instances, which
+// routes with each instance's parameters in turn, ends or returns early.
+struct HashGuard {
+    crop_ctx *c;
+    HashParams saved;
+    explicit HashGuard(crop_ctx *ctx) : c(ctx), saved(ctx->hp) {}
+    ~HashGuard() { c->hp = saved; }
+    HashGuard(const HashGuard &) = delete;
+    HashGuard &operator=(const HashGuard &) = delete;
+};
+
 struct DeviceGuard {
     int prev = -1;
     explicit DeviceGuard(int dev)
