@@ -542,7 +542,7 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the path shards by hash interval across GPUs with no exchange; see DESIGN.md)",
+              "(the path shards by hash interval across GPUs with no exchange between them)",
               file=sys.stderr)
         sys.exit(2)
     if args.learned:
