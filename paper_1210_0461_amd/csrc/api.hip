@@ -345,7 +345,7 @@ crop_status ensure_ss_buffers(crop_ctx *ctx, uint64_t nslots, uint32_t K, uint32
     ctx->ss.nslots = nslots;
     // top-K: st (8) + hist (256) + pinned counter | cand | sel | outputs
     const size_t kk = std::max<uint32_t>(K, 1);
-    CK(ctx->topk_buf.ensure(2048 + 2 * a4 + kk * 36 + ns + 256));
+    CK(ctx->topk_buf.ensure(2048 + 2 * a4 + kk * 40 + ns + 256));
     return CROP_OK;
 }
 
@@ -367,7 +367,7 @@ crop_status ensure_amp_buffers(crop_ctx *ctx, uint64_t nslots, SsState *A, uint8
 }
 
 struct TopkViews {
-    uint32_t *st, *hist, *n_pinned, *cand, *sel, *oi, *oj, *ovotes;
+    uint32_t *st, *hist, *n_pinned, *cand, *sel, *oi, *oj, *ovotes, *rank;
     double *ou, *ol, *ov;
     uint8_t *dup;
 };
@@ -391,7 +391,8 @@ TopkViews topk_views(crop_ctx *ctx, uint32_t K)
     v.oi = reinterpret_cast<uint32_t *>(v.ov + kk);
     v.oj = v.oi + kk;
     v.ovotes = v.oj + kk;
-    v.dup = reinterpret_cast<uint8_t *>(v.ovotes + kk);
+    v.rank = v.ovotes + kk;
+    v.dup = reinterpret_cast<uint8_t *>(v.rank + kk);
     return v;
 }
 
@@ -873,10 +874,10 @@ static crop_status run_topk_impl(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
         CK(launch_amp_combine(ip, ctx->ss, ctx->ss_ell, nslots, min_votes, outer, amp, votes, s));
         STAGE("majority");
         CK(launch_topk(amp, K, outer, by_lower, true, votes, tv.st, tv.hist, tv.cand, tv.sel,
-                       tv.oi, tv.oj, tv.ou, tv.ol, tv.ov, tv.ovotes, s));
+                       tv.rank, tv.oi, tv.oj, tv.ou, tv.ol, tv.ov, tv.ovotes, s));
     } else {
         CK(launch_topk(ctx->ss, K, outer, by_lower, false, nullptr, tv.st, tv.hist, tv.cand,
-                       tv.sel, tv.oi, tv.oj, tv.ou, tv.ol, tv.ov, tv.ovotes, s));
+                       tv.sel, tv.rank, tv.oi, tv.oj, tv.ou, tv.ol, tv.ov, tv.ovotes, s));
     }
     STAGE("topk");
     st = run_end(ctx);

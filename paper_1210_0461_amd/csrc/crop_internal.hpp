@@ -271,8 +271,8 @@ hipError_t launch_ss_bins(const crop_ctx *c, const SsState &S, uint32_t nbk, uin
 hipError_t launch_zero32(uint32_t *p, uint32_t n, hipStream_t s);
 hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, bool by_lower, bool err_is_lower,
                        const uint8_t *votes, uint32_t *st, uint32_t *hist, uint32_t *cand,
-                       uint32_t *sel, uint32_t *oi, uint32_t *oj, double *ou, double *ol,
-                       double *ov, uint32_t *ovotes, hipStream_t s);
+                       uint32_t *sel, uint32_t *rank, uint32_t *oi, uint32_t *oj, double *ou,
+                       double *ol, double *ov, uint32_t *ovotes, hipStream_t s);
 hipError_t launch_amp_combine(const CsParams &ip, const SsState &S, uint32_t ell, uint64_t nslots,
                               uint32_t min_votes, bool outer, const SsState &A, uint8_t *votes,
                               hipStream_t s);

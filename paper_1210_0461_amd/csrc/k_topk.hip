@@ -485,12 +485,30 @@ __device__ inline Comp comp_of(const uint64_t *key, const RankBy &rv, uint64_t i
 __global__ void __launch_bounds__(256)
 k_topk_max(RankBy rv, const uint8_t *__restrict__ flag, uint64_t n, uint32_t *__restrict__ st)
 {
+    __shared__ uint32_t s_mx[256 / kWave];
     uint32_t mx = 0;
     for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n;
          i += (uint64_t)gridDim.x * 256)
         if (flag[i] & kUsed) mx = max(mx, rv(i));
     for (int d = 32; d >= 1; d >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, kWave));
-    if (lane_id() == 0 && mx) atomicMax(&st[7], mx);
+    if (lane_id() == 0) s_mx[threadIdx.x / kWave] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < 256 / kWave; ++w) mx = max(mx, s_mx[w]);
+        if (mx) atomicMax(&st[7], mx);  // one atomic per workgroup
+    }
+}
+
+// Append the lanes with `keep` to list[*count], one atomic per wavefront.
+__device__ inline void wave_append(bool keep, uint32_t value, uint32_t *count, uint32_t *list)
+{
+    const uint64_t m = __ballot(keep);
+    if (!m) return;
+    const int first = __ffsll((long long)m) - 1;
+    uint32_t base = 0;
+    if (lane_id() == (uint32_t)first) base = atomicAdd(count, (uint32_t)__popcll(m));
+    base = (uint32_t)__shfl((int)base, first, kWave);
+    if (keep) list[base + (uint32_t)__popcll(m & ((1ull << lane_id()) - 1))] = value;
 }
 
 __device__ inline uint32_t digit_of(const Comp &c, uint32_t pass)
@@ -583,11 +601,13 @@ k_topk_compact(RankBy rv, const uint8_t *__restrict__ flag, uint64_t n,
                uint32_t *__restrict__ st, uint32_t *__restrict__ cand)
 {
     const uint32_t sh = count_shift(st);
-    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+    const uint32_t lim = st[0] >> 16;
+    // whole wavefronts iterate together so the append can use ballots
+    const uint64_t n_all = (n + kWave - 1) / kWave * kWave;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n_all;
          i += (uint64_t)gridDim.x * 256) {
-        if (!(flag[i] & kUsed)) continue;
-        if (((rv(i) << sh) >> 16) < (st[0] >> 16)) continue;
-        cand[atomicAdd(&st[4], 1u)] = (uint32_t)i;
+        const bool keep = i < n && (flag[i] & kUsed) && ((rv(i) << sh) >> 16) >= lim;
+        wave_append(keep, (uint32_t)i, &st[4], cand);
     }
 }
 
@@ -599,55 +619,73 @@ k_topk_collect(const uint64_t *__restrict__ key, RankBy rv,
 {
     const uint32_t m = st[4];
     const uint32_t sh = count_shift(st);
-    for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < m; t += gridDim.x * 256) {
-        const uint32_t i = cand[t];
-        if (comp_ge(comp_of(key, rv, i, sh), st)) sel[atomicAdd(&st[5], 1u)] = i;
+    const uint32_t m_all = (m + kWave - 1) / kWave * kWave;
+    for (uint32_t t = blockIdx.x * 256 + threadIdx.x; t < m_all; t += gridDim.x * 256) {
+        const uint32_t i = t < m ? cand[t] : 0u;
+        wave_append(t < m && comp_ge(comp_of(key, rv, i, sh), st), i, &st[5], sel);
     }
 }
 
-// rank of every selected slot = number of selected slots ranking above it;
-// writes the outputs in rank order.
+// Rank of every selected slot = number of selected slots ranking above it,
+// counted tile against tile: block (bi, bj) compares the 256 selected slots
+// of tile bi with the 256 of tile bj and adds its counts to rank[] (zero on
+// entry), so the m^2 comparisons spread over the whole GPU.
 __global__ void __launch_bounds__(256)
-k_topk_rank(const uint64_t *__restrict__ key, RankBy rv, const uint32_t *__restrict__ cnt,
-            const uint32_t *__restrict__ err, const float *__restrict__ val, bool outer,
-            const uint8_t *__restrict__ votes, const uint32_t *__restrict__ sel,
-            const uint32_t *__restrict__ st, uint32_t *__restrict__ oi, uint32_t *__restrict__ oj,
-            double *__restrict__ ou, double *__restrict__ ol, double *__restrict__ ov,
-            uint32_t *__restrict__ ovotes)
+k_topk_rank_tiles(const uint64_t *__restrict__ key, RankBy rv, const uint32_t *__restrict__ sel,
+                  const uint32_t *__restrict__ st, uint32_t *__restrict__ rank)
 {
     __shared__ Comp tile[256];
     const uint32_t m = st[5];
+    const uint32_t i0 = blockIdx.x * 256;
+    if (i0 >= m) return;  // uniform over the block
     const uint32_t sh = count_shift(st);
-    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
-    Comp me{{0, 0, 0}};
-    if (t < m) me = comp_of(key, rv, sel[t], sh);
-    uint32_t rank = 0;
-    for (uint32_t b = 0; b < m; b += 256) {
+    const uint32_t t = i0 + threadIdx.x;
+    const Comp me = t < m ? comp_of(key, rv, sel[t], sh) : Comp{{0, 0, 0}};
+    // tiles bj = blockIdx.y, blockIdx.y + gridDim.y, ... (the grid's y size
+    // is capped, so a large K still launches)
+    for (uint32_t j0 = blockIdx.y * 256; j0 < m; j0 += gridDim.y * 256) {
         __syncthreads();
-        if (b + threadIdx.x < m) tile[threadIdx.x] = comp_of(key, rv, sel[b + threadIdx.x], sh);
+        if (j0 + threadIdx.x < m) tile[threadIdx.x] = comp_of(key, rv, sel[j0 + threadIdx.x], sh);
         __syncthreads();
-        const uint32_t lim = min(256u, m - b);
-        if (t < m)
-            for (uint32_t q = 0; q < lim; ++q) rank += comp_gt(tile[q], me) ? 1u : 0u;
+        if (t < m) {
+            const uint32_t lim = min(256u, m - j0);
+            uint32_t r = 0;
+            for (uint32_t q = 0; q < lim; ++q) r += comp_gt(tile[q], me) ? 1u : 0u;
+            if (r) atomicAdd(&rank[t], r);
+        }
     }
+}
+
+// Write every selected slot at its rank.
+__global__ void __launch_bounds__(256)
+k_topk_emit(const uint64_t *__restrict__ key, RankBy rv, const uint32_t *__restrict__ cnt,
+            const uint32_t *__restrict__ err, const float *__restrict__ val, bool outer,
+            const uint8_t *__restrict__ votes, const uint32_t *__restrict__ sel,
+            const uint32_t *__restrict__ st, const uint32_t *__restrict__ rank,
+            uint32_t *__restrict__ oi, uint32_t *__restrict__ oj, double *__restrict__ ou,
+            double *__restrict__ ol, double *__restrict__ ov, uint32_t *__restrict__ ovotes)
+{
+    const uint32_t m = st[5];
+    const uint32_t t = blockIdx.x * 256 + threadIdx.x;
     if (t >= m) return;
+    const uint32_t r = rank[t];
     const uint32_t i = sel[t];
     const uint64_t k = key[i];
-    oi[rank] = (uint32_t)(k >> 32);
-    oj[rank] = (uint32_t)k;
+    oi[r] = (uint32_t)(k >> 32);
+    oj[r] = (uint32_t)k;
     double c, e;
     if (outer) {
         c = (double)__uint_as_float(cnt[i]);
         e = (double)__uint_as_float(err[i]);
-        ov[rank] = (double)val[i];
+        ov[r] = (double)val[i];
     } else {
         c = (double)cnt[i];
         e = (double)err[i];
-        ov[rank] = c;
+        ov[r] = c;
     }
-    ou[rank] = c;
-    ol[rank] = rv.err_is_lower ? e : c - e;
-    ovotes[rank] = votes ? votes[i] : 1u;
+    ou[r] = c;
+    ol[r] = rv.err_is_lower ? e : c - e;
+    ovotes[r] = votes ? votes[i] : 1u;
 }
 
 // Majority reporting over t independent instances (Section 6, proof of
@@ -843,12 +881,13 @@ hipError_t launch_ss_bins(const crop_ctx *c, const SsState &S, uint32_t nbk, uin
 // zero on entry; cand and sel hold up to nslots indices.
 hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, bool by_lower, bool err_is_lower,
                        const uint8_t *votes, uint32_t *st, uint32_t *hist, uint32_t *cand,
-                       uint32_t *sel, uint32_t *oi, uint32_t *oj, double *ou, double *ol,
-                       double *ov, uint32_t *ovotes, hipStream_t s)
+                       uint32_t *sel, uint32_t *rank, uint32_t *oi, uint32_t *oj, double *ou,
+                       double *ol, double *ov, uint32_t *ovotes, hipStream_t s)
 {
     const uint32_t g = grid_for(S.nslots);
     const RankBy rv{S.cnt, S.err, by_lower, outer, err_is_lower};
-    hipLaunchKernelGGL(k_topk_max, dim3(g), dim3(256), 0, s, rv, S.flag, S.nslots, st);
+    hipLaunchKernelGGL(k_topk_max, dim3(grid_for(S.nslots, 1024)), dim3(256), 0, s, rv, S.flag,
+                       S.nslots, st);
     for (uint32_t pass = 0; pass < 12; ++pass) {
         hipLaunchKernelGGL(k_topk_hist, dim3(g), dim3(256), 0, s, S.key, rv, S.flag, S.nslots,
                            pass < 2 ? nullptr : cand, st, pass, hist);
@@ -859,8 +898,11 @@ hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, bool by_lower, 
     }
     hipLaunchKernelGGL(k_topk_collect, dim3(g), dim3(256), 0, s, S.key, rv, cand, st, sel);
     const uint32_t gr = (K + 255) / 256 ? (K + 255) / 256 : 1;
-    hipLaunchKernelGGL(k_topk_rank, dim3(gr), dim3(256), 0, s, S.key, rv, S.cnt, S.err, S.val,
-                       outer, votes, sel, st, oi, oj, ou, ol, ov, ovotes);
+    hipLaunchKernelGGL(k_zero32, dim3(grid_for(K, 1024)), dim3(256), 0, s, rank, K);
+    hipLaunchKernelGGL(k_topk_rank_tiles, dim3(gr, std::min<uint32_t>(gr, 1024)), dim3(256), 0, s,
+                       S.key, rv, sel, st, rank);
+    hipLaunchKernelGGL(k_topk_emit, dim3(gr), dim3(256), 0, s, S.key, rv, S.cnt, S.err, S.val,
+                       outer, votes, sel, st, rank, oi, oj, ou, ol, ov, ovotes);
     return hipGetLastError();
 }
 
