@@ -554,29 +554,62 @@ k_topk_hist(const uint64_t *__restrict__ key, RankBy rv,
 }
 
 // One wavefront: pick the digit of this pass and clear the histogram.
+// Walking the digits from 255 down, the pick is the first digit d >= 1 at
+// which the running count reaches the remaining rank (else 0); the new
+// remaining rank excludes the digits above d.  Lane L holds digits
+// 255 - 4L .. 252 - 4L, so a scan over lanes gives every running count.
 __global__ void __launch_bounds__(64)
 k_topk_pick(uint32_t *__restrict__ st, uint32_t *__restrict__ hist, uint32_t pass, uint32_t K)
 {
-    if (threadIdx.x != 0) return;
+    const uint32_t lane = threadIdx.x;
+    uint32_t h[4], local = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        h[q] = hist[255 - (4 * lane + q)];
+        local += h[q];
+    }
+    const uint32_t incl = wave_inclusive_scan(local);
+    uint32_t rem;
     if (pass == 0) {
-        uint32_t used = 0;
-        for (int d = 0; d < 256; ++d) used += hist[d];
-        st[6] = used;
-        st[3] = K < used ? K : used;
+        const uint32_t used = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+        rem = K < used ? K : used;
+        if (lane == 0) st[6] = used;
+    } else {
+        rem = st[3];
     }
-    uint32_t rem = st[3];
-    uint32_t cum = 0;
-    int d = 255;
+    uint32_t before[4], run = incl - local;
+    int myq = -1;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        before[q] = run;
+        const uint32_t d = 255 - (4 * lane + q);
+        if (myq < 0 && d >= 1 && run + h[q] >= rem) myq = q;
+        run += h[q];
+    }
+    uint32_t d = 255, new_rem = rem;
     if (rem > 0) {
-        for (; d > 0; --d) {
-            if (cum + hist[d] >= rem) break;
-            cum += hist[d];
+        const uint64_t m = __ballot(myq >= 0);
+        uint32_t b = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+            if (myq == q) b = before[q];
+        if (m) {
+            const int L = __ffsll((long long)m) - 1;
+            const int qL = __shfl(myq, L, kWave);
+            d = 255 - (4 * (uint32_t)L + (uint32_t)qL);
+            new_rem = rem - (uint32_t)__shfl((int)b, L, kWave);
+        } else {
+            d = 0;  // digit 0: lane 63, slot 3
+            new_rem = rem - (uint32_t)__shfl((int)before[3], kWave - 1, kWave);
         }
-        st[3] = rem - cum;
     }
-    const uint32_t w = pass >> 2, sh = 24 - 8 * (pass & 3);
-    st[w] = (st[w] & ~(0xFFu << sh)) | ((uint32_t)d << sh);
-    for (int i = 0; i < 256; ++i) hist[i] = 0;
+    if (lane == 0) {
+        st[3] = new_rem;
+        const uint32_t w = pass >> 2, sh = 24 - 8 * (pass & 3);
+        st[w] = (st[w] & ~(0xFFu << sh)) | (d << sh);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) hist[4 * lane + q] = 0;
 }
 
 __device__ inline bool comp_ge(const Comp &a, const uint32_t *t)
