@@ -195,17 +195,25 @@ template <> __device__ inline uint64_t empty_key<uint64_t>() { return kEmpty64; 
 
 // Add weight w (and signed value v) of key to the micro-batch table
 // (linear probing, at most half full, so a free slot is always reached).
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+
+// Adds (w, v) to key's entry of the merge table; returns the entry's slot
+// when this call inserted the key, else kNoSlot.
 template <class KeyT, bool OUTER>
-__device__ inline void table_add(KeyT *hk, uint32_t *hw, float *hv, uint32_t log2hs, KeyT key,
-                                 uint32_t w, float v)
+__device__ inline uint32_t table_add(KeyT *hk, uint32_t *hw, float *hv, uint32_t log2hs, KeyT key,
+                                     uint32_t w, float v)
 {
     const uint32_t mask = (1u << log2hs) - 1;
     uint32_t s = slot_of(key, log2hs);
     for (;;) {
         KeyT cur = hk[s];
+        bool inserted = false;
         if (cur == empty_key<KeyT>()) {
             cur = atomicCAS(&hk[s], empty_key<KeyT>(), key);
-            if (cur == empty_key<KeyT>()) cur = key;
+            if (cur == empty_key<KeyT>()) {
+                cur = key;
+                inserted = true;
+            }
         }
         if (cur == key) {
             if (OUTER) {
@@ -214,7 +222,7 @@ __device__ inline void table_add(KeyT *hk, uint32_t *hw, float *hv, uint32_t log
             } else {
                 atomicAdd(&hw[s], w);
             }
-            return;
+            return inserted ? s : kNoSlot;
         }
         s = (s + 1) & mask;
     }
@@ -225,7 +233,10 @@ __device__ inline void table_add(KeyT *hk, uint32_t *hw, float *hv, uint32_t log
 // bin's routed terms are read in micro-batches of MB:
 //   1. equal keys of the micro-batch are merged into one weighted update in
 //      an LDS hash table (a wave first merges the copies of its lead key);
-//   2. the merged updates are grouped by bucket with a counting sort;
+//   2. the merged updates are grouped by bucket with a counting sort; a bin
+//      of one bucket instead keeps them in the order of each key's first
+//      copy in the micro-batch, so the bucket sees its entries in stream
+//      order (routed keys keep the order of their chunks);
 //   3. a group of G lanes (G >= ell) applies one bucket's updates in order,
 //      lane j holding slot j in registers:
 //        hit    one ballot finds the monitored slot;
@@ -301,17 +312,21 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                 if (OUTER) h_v[i] = 0.0f;
             }
             for (uint32_t i = threadIdx.x; i <= nbk; i += BS) s_pos[i] = 0;
+            // one bucket: t_w[i] = merge-table slot of the key first seen at i
+            if (nbk == 1)
+                for (uint32_t i = threadIdx.x; i < MB; i += BS) t_w[i] = kNoSlot;
             __syncthreads();
             // 1. merge equal keys
             const uint32_t n_all = (n + BS - 1) / BS * BS;
             for (uint32_t i = threadIdx.x; i < n_all; i += BS) {
                 const bool valid = i < n;
                 const KeyT key = valid ? keys[base + i] : empty_key<KeyT>();
+                uint32_t first = kNoSlot;
                 if (OUTER) {
                     if (valid) {
                         const float v = vals[base + i];
-                        table_add<KeyT, true>(h_k, h_w, h_v, LOG2HS, key,
-                                              __float_as_uint(fabsf(v)), v);
+                        first = table_add<KeyT, true>(h_k, h_w, h_v, LOG2HS, key,
+                                                      __float_as_uint(fabsf(v)), v);
                     }
                 } else {
                     const uint64_t vm = __ballot(valid);
@@ -321,30 +336,60 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                     const uint64_t m = __ballot(same);
                     if (same) {
                         if (lane == (uint32_t)__ffsll((long long)m) - 1)
-                            table_add<KeyT, false>(h_k, h_w, h_v, LOG2HS, key,
-                                                   (uint32_t)__popcll(m), 0.0f);
+                            first = table_add<KeyT, false>(h_k, h_w, h_v, LOG2HS, key,
+                                                           (uint32_t)__popcll(m), 0.0f);
                     } else if (valid) {
-                        table_add<KeyT, false>(h_k, h_w, h_v, LOG2HS, key, 1u, 0.0f);
+                        first = table_add<KeyT, false>(h_k, h_w, h_v, LOG2HS, key, 1u, 0.0f);
                     }
                 }
+                // the inserting copy is one of the key's first copies: rounds
+                // of 256 positions run in order, a wave's lowest lane inserts
+                // for its copies (only waves of one round can race)
+                if (nbk == 1 && first != kNoSlot) t_w[i] = first;
             }
             __syncthreads();
             // 2. group the merged updates by bucket
-            for (uint32_t i = threadIdx.x; i < HS; i += BS) {
-                const KeyT key = h_k[i];
-                if (key == empty_key<KeyT>()) continue;
-                atomicAdd(&s_pos[(uint32_t)(bucket_of_key(key, hp, PB, narrow) - bucket0)], 1u);
-            }
-            __syncthreads();
-            lds_exclusive_scan_rt(s_pos, nbk, s_tmp);
-            for (uint32_t i = threadIdx.x; i < HS; i += BS) {
-                const KeyT key = h_k[i];
-                if (key == empty_key<KeyT>()) continue;
-                const uint32_t lb = (uint32_t)(bucket_of_key(key, hp, PB, narrow) - bucket0);
-                const uint32_t p = atomicAdd(&s_pos[lb], 1u);  // becomes the bucket's end
-                t_k[p] = key;
-                t_w[p] = h_w[i];
-                if (OUTER) t_v[p] = h_v[i];
+            if (nbk == 1) {
+                // order of first copies: compact t_w's slots in position
+                // order (every thread reads its positions before the scan's
+                // barriers and writes at or below them afterwards; the
+                // workgroup has 256 threads, see ss_block_threads)
+                constexpr uint32_t PER = MB / 256;
+                uint32_t sl[PER], cnt = 0;
+#pragma unroll
+                for (uint32_t q = 0; q < PER; ++q) {
+                    sl[q] = t_w[threadIdx.x * PER + q];
+                    cnt += sl[q] != kNoSlot ? 1u : 0u;
+                }
+                uint32_t total;
+                uint32_t p = block_exclusive_scan<256>(cnt, s_tmp, &total);
+#pragma unroll
+                for (uint32_t q = 0; q < PER; ++q) {
+                    if (sl[q] == kNoSlot) continue;
+                    t_k[p] = h_k[sl[q]];
+                    t_w[p] = h_w[sl[q]];
+                    if (OUTER) t_v[p] = h_v[sl[q]];
+                    ++p;
+                }
+                if (threadIdx.x == 0) s_pos[0] = total;  // the bucket's end
+            } else {
+                for (uint32_t i = threadIdx.x; i < HS; i += BS) {
+                    const KeyT key = h_k[i];
+                    if (key == empty_key<KeyT>()) continue;
+                    atomicAdd(&s_pos[(uint32_t)(bucket_of_key(key, hp, PB, narrow) - bucket0)],
+                              1u);
+                }
+                __syncthreads();
+                lds_exclusive_scan_rt(s_pos, nbk, s_tmp);
+                for (uint32_t i = threadIdx.x; i < HS; i += BS) {
+                    const KeyT key = h_k[i];
+                    if (key == empty_key<KeyT>()) continue;
+                    const uint32_t lb = (uint32_t)(bucket_of_key(key, hp, PB, narrow) - bucket0);
+                    const uint32_t p = atomicAdd(&s_pos[lb], 1u);  // becomes the bucket's end
+                    t_k[p] = key;
+                    t_w[p] = h_w[i];
+                    if (OUTER) t_v[p] = h_v[i];
+                }
             }
             __syncthreads();
             // 3. one group per bucket applies its updates

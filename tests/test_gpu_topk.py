@@ -121,21 +121,27 @@ def test_few_distinct_per_bucket_is_exact(crop, ctx):
 
 def test_recall_matches_sequential_oracle(crop, ctx):
     """1/8 of the small stream's distinct pairs fit: GPU recall@100 is
-    close to the sequential oracle's at equal memory."""
+    close to the sequential oracle's at equal memory.  The GPU applies a
+    bucket's updates in another order than the stream (and that order is
+    not fixed from run to run), so the recalls are compared as means over
+    four hash seeds."""
     st = datagen.config_small()
-    exact, r = exact_map(st)
     P, C, ell, K = 4, 1024, 16, 100
-    s, top = run_tx_topk(crop, ctx, st, P, C, ell, K)
-    check_invariants(s, exact, SEED)
-    ek = oracle.pack_keys(r["x"], r["y"])
-    rec_gpu = oracle.recall_at_k(oracle.pack_keys(top[0], top[1]), ek, r["cnt"], K)
-    o = oracle.tx_spacesaving(st.off, st.items, SEED, P, C // ell, ell)
-    used = o["used"]
-    okeys = oracle.pack_keys(o["x"][used], o["y"][used])
-    oi = oracle.topk(okeys, o["cnt"][used], K)
-    rec_orc = oracle.recall_at_k(okeys[oi], ek, r["cnt"], K)
-    print(f"recall@{K}: gpu {rec_gpu:.3f} oracle {rec_orc:.3f}")
-    assert rec_gpu >= rec_orc - 0.05
+    rec_gpu, rec_orc = [], []
+    for k in range(4):
+        seed = (SEED + 7919 * k) & 0xFFFFFFFFFFFFFFFF
+        exact, r = exact_map(st, seed)
+        s, top = run_tx_topk(crop, ctx, st, P, C, ell, K, seed=seed)
+        check_invariants(s, exact, seed)
+        ek = oracle.pack_keys(r["x"], r["y"])
+        rec_gpu.append(oracle.recall_at_k(oracle.pack_keys(top[0], top[1]), ek, r["cnt"], K))
+        o = oracle.tx_spacesaving(st.off, st.items, seed, P, C // ell, ell)
+        used = o["used"]
+        okeys = oracle.pack_keys(o["x"][used], o["y"][used])
+        oi = oracle.topk(okeys, o["cnt"][used], K)
+        rec_orc.append(oracle.recall_at_k(okeys[oi], ek, r["cnt"], K))
+    print(f"recall@{K}: gpu {rec_gpu} oracle {rec_orc}")
+    assert np.mean(rec_gpu) >= np.mean(rec_orc) - 0.04
 
 
 def test_seeded_pins_exact_and_placement(crop, ctx):
