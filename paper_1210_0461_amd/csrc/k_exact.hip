@@ -65,6 +65,20 @@ __device__ inline void wave_merge_unit(KeyT key, uint32_t &w)
     }
 }
 
+// One round of wave_merge_unit for 32-bit keys: lanes holding the first open
+// lane's key hand their weight to the lowest of them.
+__device__ inline void wave_merge_lead(uint32_t key, uint32_t &w)
+{
+    const bool open = w != 0;
+    const uint64_t act = __ballot(open);
+    if (act == 0) return;
+    const int leader = __ffsll((long long)act) - 1;
+    const uint32_t lk = (uint32_t)__shfl((int)key, leader, kWave);
+    const bool eq = open && key == lk;
+    const uint64_t m = __ballot(eq);
+    if (eq) w = (lane_id() == (uint32_t)leader) ? (uint32_t)__popcll(m) : 0u;
+}
+
 template <class KeyT, class W>
 struct Table {
     KeyT *k;
@@ -387,9 +401,9 @@ __device__ void packed_spill_rounds(uint64_t *tab, Spilled<uint32_t, uint32_t> *
 }
 
 // Flat variant of the packed aggregation: every wavefront walks its own
-// batches of the bin (64 U keys: U per lane), reads the U home slots
-// together, adds hits without waiting for anything and sends only
-// collisions and new keys on to probe.  There is no barrier between
+// batches of the bin (64 U keys: U per lane), merges the copies of its lead
+// key, reads the U home slots together, adds hits without waiting for
+// anything and sends only collisions and new keys on to probe.  There is no barrier between
 // batches: a wavefront decides whether it may insert from the workgroup's
 // insert counter, read before each batch and raised by the batch's inserts
 // right after it.  A wavefront has at most one batch whose inserts are not
@@ -446,6 +460,14 @@ k_aggregate_flat(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ ke
             const bool ins =
                 __hip_atomic_load(&s_occ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <=
                 cap_soft;
+            // copies of each wavefront's lead key merge into its lowest lane
+            // (a hot pair fills most of its bin; one atomic instead of many)
+            uint32_t wt[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                wt[u] = base + u * kWave + lane < k1 ? 1u : 0u;
+                wave_merge_lead(cur[u], wt[u]);
+            }
             uint64_t v[U];
             uint32_t hs[U];
 #pragma unroll
@@ -456,10 +478,9 @@ k_aggregate_flat(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ ke
             uint32_t pend = 0;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const bool valid = base + u * kWave + lane < k1;
-                if (!valid) continue;
+                if (!wt[u]) continue;
                 if ((uint32_t)v[u] == cur[u])
-                    atomicAdd(count_word(&tab[hs[u]]), 1u);
+                    atomicAdd(count_word(&tab[hs[u]]), wt[u]);
                 else
                     pend |= 1u << u;
             }
@@ -474,7 +495,7 @@ k_aggregate_flat(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ ke
                     if (((pend >> u) & 1u) && (uint32_t)v[u] == kEmpty32)
                         old[u] = atomicCAS((unsigned long long *)&tab[hs[u]],
                                            (unsigned long long)kFreeSlot,
-                                           (1ull << 32) | cur[u]);
+                                           ((uint64_t)wt[u] << 32) | cur[u]);
                 }
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
@@ -483,7 +504,7 @@ k_aggregate_flat(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ ke
                         ++n_new;
                         pend &= ~(1u << u);
                     } else if ((uint32_t)old[u] == cur[u]) {
-                        atomicAdd(count_word(&tab[hs[u]]), 1u);
+                        atomicAdd(count_word(&tab[hs[u]]), wt[u]);
                         pend &= ~(1u << u);
                     } else {
                         v[u] = old[u];  // another key took the home slot: probe on
@@ -494,23 +515,24 @@ k_aggregate_flat(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ ke
             for (int u = 0; u < U; ++u) {
                 if (!((pend >> u) & 1u)) continue;
                 const uint32_t key = cur[u];
+                const uint32_t wk = wt[u];
                 uint32_t sl = hs[u];
                 uint64_t val = v[u];
                 for (;;) {
                     const uint32_t k = (uint32_t)val;
                     if (k == key) {
-                        atomicAdd(count_word(&tab[sl]), 1u);
+                        atomicAdd(count_word(&tab[sl]), wk);
                         break;
                     }
                     if (k == kEmpty32) {
                         if (!ins) {
                             const uint32_t p = atomicAdd(&s_nspill, 1u);
-                            spill[k0 + p] = Spilled<uint32_t, uint32_t>{key, 1u};
+                            spill[k0 + p] = Spilled<uint32_t, uint32_t>{key, wk};
                             break;
                         }
                         const uint64_t old = atomicCAS((unsigned long long *)&tab[sl],
                                                        (unsigned long long)kFreeSlot,
-                                                       (1ull << 32) | key);
+                                                       ((uint64_t)wk << 32) | key);
                         if (old == kFreeSlot) {
                             ++n_new;
                             break;
