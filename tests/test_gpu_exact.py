@@ -102,6 +102,19 @@ def test_edge_cases(crop, ctx):
         compare_all_partitions(crop, ctx, st, 8)
 
 
+def test_maximum_partitions_and_top_ids(crop, ctx):
+    """P = 8192 (the largest partition count: one routing bin each), and
+    item ids just below 2^32 (64-bit keys with the high words in use)."""
+    st = datagen.tiny_transactions(41, T=400, n=300, cap=20, mean_len=8.0)
+    compare_all_partitions(crop, ctx, st, 8192)
+    top = np.uint32(0xFFFFFFFF - 400)
+    hi = datagen.Transactions(st.off.copy(), (st.items + top).astype(np.uint32),
+                              int(top) + st.n)
+    compare_all_partitions(crop, ctx, hi, 64)
+    with pytest.raises(crop.CropError):
+        crop.crop_set_partitions(ctx, 8193)
+
+
 def test_wide_keys(crop, ctx):
     # more than 2^16 item ids: 64-bit keys
     st = datagen.transactions(3000, 200_000, 0.9, 8.0, 40, datagen.Raw(77), "wide")
