@@ -29,6 +29,10 @@ namespace {
 constexpr int kScatterBS = 1024;
 constexpr int kCountBS = 512;
 
+// Row groups of the count-matrix scan: at most this many (k_colprefix keeps
+// one partial per group in registers).
+constexpr uint32_t kMaxScanGroups = 64;
+
 // ---------------------------------------------------------------- chunks
 
 // One chunk of transactions as the count and scatter kernels see it: rows
@@ -404,6 +408,7 @@ k_colsum(const uint32_t *__restrict__ cnt, uint32_t n, uint32_t NB, uint32_t row
     const uint32_t g = blockIdx.y;
     const uint32_t c0 = g * rows_per_g, c1 = min(n, c0 + rows_per_g);
     uint32_t s = 0;
+#pragma unroll 8
     for (uint32_t c = c0; c < c1; ++c) s += cnt[(size_t)c * NB + b];
     part[(size_t)g * NB + b] = s;
 }
@@ -414,11 +419,16 @@ k_colprefix(uint32_t *__restrict__ part, uint32_t NB, uint32_t G, uint32_t *__re
 {
     const uint32_t b = blockIdx.x * 256 + threadIdx.x;
     if (b >= NB) return;
+    // G <= kMaxScanGroups: every group's partial is loaded before any is
+    // rewritten, so the loads are in flight together
+    uint32_t v[kMaxScanGroups];
+#pragma unroll
+    for (uint32_t g = 0; g < kMaxScanGroups; ++g) v[g] = g < G ? part[(size_t)g * NB + b] : 0u;
     uint32_t run = 0;
-    for (uint32_t g = 0; g < G; ++g) {
-        const uint32_t v = part[(size_t)g * NB + b];
-        part[(size_t)g * NB + b] = run;
-        run += v;
+#pragma unroll
+    for (uint32_t g = 0; g < kMaxScanGroups; ++g) {
+        if (g < G) part[(size_t)g * NB + b] = run;
+        run += v[g];
     }
     tot[b] = run;
 }
@@ -483,6 +493,7 @@ k_colapply(uint32_t *__restrict__ cnt, uint32_t n, uint32_t NB, uint32_t rows_pe
     const uint32_t g = blockIdx.y;
     const uint32_t c0 = g * rows_per_g, c1 = min(n, c0 + rows_per_g);
     uint32_t run = bin_off[b] + part[(size_t)g * NB + b];
+#pragma unroll 8
     for (uint32_t c = c0; c < c1; ++c) {
         uint32_t v = cnt[(size_t)c * NB + b];
         cnt[(size_t)c * NB + b] = run;
@@ -795,6 +806,7 @@ hipError_t launch_scan_counts(uint32_t *cnt, uint32_t n_chunks, uint32_t NB, uin
                               uint32_t *part, uint32_t *bin_off, uint32_t *counter,
                               hipStream_t s)
 {
+    if (G < 1 || G > kMaxScanGroups) return hipErrorInvalidValue;
     const uint32_t rows_per_g = (n_chunks + G - 1) / G;
     dim3 grid((NB + 255) / 256, G);
     hipLaunchKernelGGL(k_colsum, grid, dim3(256), 0, s, cnt, n_chunks, NB, rows_per_g, part);
