@@ -515,6 +515,7 @@ k_bcolscan(BatchDev b, uint32_t *__restrict__ cnt, uint32_t *__restrict__ tot)
     const uint32_t lb = g - S.bin_base;
     uint32_t *col = cnt + S.cnt_base + lb;
     uint32_t run = 0;
+#pragma unroll 8
     for (uint32_t c = 0; c < S.n_chunks; ++c) {
         const uint32_t v = col[(size_t)c * S.NB];
         col[(size_t)c * S.NB] = run;
@@ -598,6 +599,7 @@ k_bapply(BatchDev b, uint32_t *__restrict__ cnt, const uint32_t *__restrict__ bi
     const BatchStreamDev S = b.streams[b.bin_stream[g]];
     uint32_t *col = cnt + S.cnt_base + (g - S.bin_base);
     const uint32_t base = bin_off[g];
+#pragma unroll 8
     for (uint32_t c = 0; c < S.n_chunks; ++c) col[(size_t)c * S.NB] += base;
 }
 
