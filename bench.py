@@ -522,6 +522,17 @@ def run_shards(args):
 
         full_ms, full_terms, full_st = timed(0, P)
         out["full"] = {"ms": round(full_ms, 4), "terms": full_terms, "stage_ms": full_st}
+        # Table 3 analog: term loads (pair occurrences) per processor when
+        # the P partitions are split into 2, 4 or 8 equal intervals, and per
+        # partition
+        _, part_terms = crop.crop_result_sizes(ctx, P)
+        part_terms = part_terms.astype(np.float64)
+        loads = {}
+        for n in (2, 4, 8, P):
+            per = part_terms.reshape(n, -1).sum(axis=1)
+            loads[str(n)] = {"mean": round(float(per.mean()), 1), "max": int(per.max()),
+                             "max_over_mean": round(float(per.max() / per.mean()), 4)}
+        out["term_loads"] = loads
         shares = []
         for g in range(G):
             ms, terms, stg = timed(g * P // G, (g + 1) * P // G)
