@@ -52,6 +52,8 @@ def parse():
                          "whole stream also gives the recall and equality checks")
     ap.add_argument("--learned", action="store_true",
                     help="run the learned-seeding comparison instead of the exact bench")
+    ap.add_argument("--outer", action="store_true",
+                    help="the outer-product workload: exact fp32 sums and top 10,000")
     ap.add_argument("--accuracy", action="store_true",
                     help="synthetic analogs of the paper's accuracy experiments")
     ap.add_argument("--shards", type=int, default=0,
@@ -476,6 +478,79 @@ def run_accuracy(args):
     print(json.dumps(out), flush=True)
 
 
+def run_outer(args):
+    """The outer-product workload (100,000 products over 200,000 rows and
+    columns, nnz per vector ~ m^-2 on [1, 2000], fp32 values; P = 8):
+    exact fp32 sums with the tolerance pass rate against the oracle's fp64
+    sums (|c32 - c64| <= 1e-5 sum |terms|), and the Space-Saving top 10,000
+    (2^16 counters per partition, 16 per bucket, weights |a b|) with its
+    recall of the exact top 10,000 by sum |a b|."""
+    import numpy as np
+    import torch
+    import datagen
+    import oracle
+    import paper_1210_0461_amd as crop
+    Pop = 8
+    op = datagen.config_outer()
+    t0 = time.perf_counter()
+    ref = oracle.op_exact(op, 1, SEED)
+    print(f"# oracle {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    rk = (ref["i"].astype(np.uint64) << np.uint64(32)) | ref["j"].astype(np.uint64)
+    o = np.argsort(rk)
+    rk, rsum, rabs = rk[o], ref["sum"][o], ref["abs"][o]
+    terms = int(ref["n_terms"])
+    ctx = crop.crop_create(0)
+    out = {"experiment": "outer products: exact fp32 sums and Space-Saving top 10,000",
+           "K": int(op.K), "terms": terms, "distinct": int(rk.shape[0]), "P": Pop}
+    try:
+        stream = torch.cuda.current_stream()
+        crop.crop_set_stream(ctx, stream)
+        crop.crop_set_partitions(ctx, Pop)
+        crop.crop_set_seed(ctx, SEED)
+        crop.crop_load_outer(ctx, op.a_off, op.a_idx, op.a_val, op.b_off, op.b_idx, op.b_val,
+                             op.n_rows, op.n_cols)
+
+        def timed(fn):
+            for _ in range(args.warmup):
+                fn()
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(args.steps):
+                fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / args.steps
+
+        ms = timed(lambda: crop.crop_run_exact(ctx))
+        i, j, v, _ = crop.crop_read_all(ctx, Pop, outer=True)
+        gk = (i.astype(np.uint64) << np.uint64(32)) | j.astype(np.uint64)
+        og = np.argsort(gk)
+        same = gk.shape[0] == rk.shape[0] and bool(np.array_equal(gk[og], rk))
+        err = np.abs(v[og].astype(np.float64) - rsum) if same else None
+        out["exact"] = {"ms": round(ms, 4), "term_updates_per_s": terms / (ms * 1e-3),
+                        "same_entries_as_oracle": same,
+                        "within_tolerance": float(np.mean(err <= 1e-5 * rabs)) if same else 0.0,
+                        "worst_err_over_abs": float(np.max(err / np.maximum(rabs, 1e-300)))
+                        if same else None}
+        crop.crop_set_summary(ctx, 1 << 16, 16)
+        K = 10000
+        ms = timed(lambda: crop.crop_run_topk(ctx, K))
+        ti, tj, up, lo, val = crop.crop_read_topk(ctx, K)
+        tk = (ti.astype(np.uint64) << np.uint64(32)) | tj.astype(np.uint64)
+        kth = np.sort(rabs)[::-1][K - 1]
+        pos = np.minimum(np.searchsorted(rk, tk), rk.shape[0] - 1)
+        exact_abs = np.where(rk[pos] == tk, rabs[pos], 0.0)
+        out["topk"] = {"ms": round(ms, 4), "term_updates_per_s": terms / (ms * 1e-3), "K": K,
+                       "recall_by_abs_weight": float(np.mean(exact_abs >= kth)),
+                       "bounds_hold": bool(np.all(lo <= exact_abs * (1 + 1e-5) + 1e-6) and
+                                           np.all(exact_abs <= up * (1 + 1e-5) + 1e-6))}
+    finally:
+        crop.crop_destroy(ctx)
+    print(json.dumps(out), flush=True)
+
+
 def run_shards(args):
     """One GPU's share of a G-GPU run: the exact path owning P/G partitions of
     the 1M-transaction stream (every term enumerated, 1/G routed and kept),
@@ -567,6 +642,9 @@ def main():
         return
     if args.accuracy:
         run_accuracy(args)
+        return
+    if args.outer:
+        run_outer(args)
         return
     import numpy as np
     import torch
