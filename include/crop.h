@@ -128,6 +128,16 @@ crop_status crop_use_own_stream(crop_ctx *ctx);
 crop_status crop_set_tuning(crop_ctx *ctx, const crop_tune *tune);
 /* The configuration the next (or last) run uses, after automatic choices. */
 crop_status crop_get_tuning(const crop_ctx *ctx, crop_tune *out);
+/* Tune exact runs of the loaded transaction stream: time routing bins per
+ * partition S in {S0-1 .. S0+2} (S0 = the automatic choice, within 8192
+ * bins) x rows per chunk in {64, 96, 128, 192, 256}, reps timed runs each
+ * after one warm-up, keep the fastest as the context's tuning (other
+ * tuning fields unchanged) and leave the exact result of a run with it.
+ * Results do not depend on the plan.  Outputs (NULL allowed): the chosen
+ * S and rows per chunk (after any halving to fit LDS) and the best time in
+ * ms.  CROP_E_STATE without a loaded transaction stream. */
+crop_status crop_autotune(crop_ctx *ctx, uint32_t reps, uint32_t *bins_per_partition,
+                          uint32_t *rows_per_chunk, float *best_ms);
 
 /* ---- input ------------------------------------------------------------- */
 

@@ -97,6 +97,7 @@ _SIGS.update({
     "crop_run_topk": ([_vp, _u32], _i32),
     "crop_run_topk_seeded": ([_vp, _u32, _vp, _vp, _u64, _u32], _i32),
     "crop_run_topk_amplified": ([_vp, _u32, _u32, _u32], _i32),
+    "crop_autotune": ([_vp, _u32, _vp, _vp, _vp], _i32),
     "crop_read_topk_votes": ([_vp, _vp, _u64, _pu64], _i32),
     "crop_read_topk": ([_vp, _vp, _vp, _vp, _vp, _vp, _u64, _pu64], _i32),
     "crop_read_summary": ([_vp, _vp, _vp, _vp, _vp, _vp, _vp, _u64, _pu64], _i32),
@@ -252,6 +253,16 @@ def crop_set_tuning(ctx, bins_per_partition=0, rows_per_chunk=0, stage_keys=0,
                     route=CROP_ROUTE_AUTO) -> None:
     t = crop_tune(bins_per_partition, rows_per_chunk, stage_keys, route)
     _check(ctx, _lib.crop_set_tuning(ctx, ctypes.byref(t)))
+
+
+def crop_autotune(ctx, reps: int = 3):
+    """Tune exact runs of the loaded stream; returns (bins_per_partition,
+    rows_per_chunk, best_ms) and keeps them as the context's tuning."""
+    S = ctypes.c_uint32(0)
+    R = ctypes.c_uint32(0)
+    ms = ctypes.c_float(0.0)
+    _check(ctx, _lib.crop_autotune(ctx, reps, ctypes.byref(S), ctypes.byref(R), ctypes.byref(ms)))
+    return S.value, R.value, float(ms.value)
 
 
 def crop_get_tuning(ctx) -> dict:

@@ -1321,6 +1321,68 @@ crop_status crop_synchronize(crop_ctx *ctx)
     return CROP_OK;
 }
 
+// Exact-run tuner for a loaded transaction stream: times routing bins per
+// partition S in {S0 - 1, S0, S0 + 1, S0 + 2} (S0 the automatic choice) x
+// rows per chunk in {64, 96, 128, 192, 256}, keeps the fastest in the
+// context's tuning and leaves the result of a run with it.
+crop_status crop_autotune(crop_ctx *ctx, uint32_t reps, uint32_t *bins_per_partition,
+                          uint32_t *rows_per_chunk, float *best_ms)
+{
+    if (!ctx) return CROP_E_ARG;
+    if (ctx->in.mode != Mode::Tx)
+        return fail(ctx, CROP_E_STATE, "the tuner needs a loaded transaction stream");
+    DeviceGuard g(ctx->device);
+    reps = std::max<uint32_t>(reps, 1);
+    const crop_tune saved = ctx->tune;
+    ctx->tune.bins_per_partition = 0;
+    ctx->tune.rows_per_chunk = 0;
+    crop_status st = plan_tx(ctx);
+    if (st != CROP_OK) {
+        ctx->tune = saved;
+        return st;
+    }
+    const uint32_t S0 = ctx->plan.S;
+    uint32_t p0, p1;
+    owned_range(ctx, &p0, &p1);
+    float best = -1.0f;
+    uint32_t bS = 0, bR = 0;
+    for (uint32_t S = S0 > 1 ? S0 - 1 : 1; S <= S0 + 2; ++S) {
+        if ((uint64_t)(p1 - p0) * S > kMaxP) break;
+        for (uint32_t R : {64u, 96u, 128u, 192u, 256u}) {
+            ctx->tune = saved;
+            ctx->tune.bins_per_partition = S;
+            ctx->tune.rows_per_chunk = R;
+            float lo = -1.0f, ms = 0.0f;
+            for (uint32_t k = 0; k <= reps; ++k) {  // the first run warms up
+                st = crop_run_exact(ctx);
+                if (st == CROP_OK) st = crop_last_run_ms(ctx, &ms);
+                if (st != CROP_OK) break;
+                if (k && (lo < 0 || ms < lo)) lo = ms;
+            }
+            if (st != CROP_OK) {
+                if (st == CROP_E_UNSUPPORTED) continue;  // a plan that does not fit
+                ctx->tune = saved;
+                return st;
+            }
+            if (best < 0 || lo < best) {
+                best = lo;
+                bS = S;
+                bR = R;
+            }
+        }
+    }
+    ctx->tune = saved;
+    if (best < 0) return fail(ctx, CROP_E_UNSUPPORTED, "no candidate plan fits this stream");
+    ctx->tune.bins_per_partition = bS;
+    ctx->tune.rows_per_chunk = bR;
+    st = crop_run_exact(ctx);
+    if (st != CROP_OK) return st;
+    if (bins_per_partition) *bins_per_partition = bS;
+    if (rows_per_chunk) *rows_per_chunk = ctx->plan.R;
+    if (best_ms) *best_ms = best;
+    return CROP_OK;
+}
+
 crop_status crop_last_run_ms(crop_ctx *ctx, float *ms)
 {
     if (!ctx || !ms) return CROP_E_ARG;

@@ -146,6 +146,39 @@ def test_tuning_does_not_change_results(crop, ctx):
         ref = cur
 
 
+def test_autotune_choice_and_invariance(crop, ctx):
+    """The exact-run tuner picks a candidate plan, keeps it as the context's
+    tuning, and the result it leaves equals the oracle's."""
+    st = datagen.tiny_transactions(9, T=4000, n=400, cap=40, mean_len=10.0)
+    P = 16
+    crop.crop_set_partitions(ctx, P)
+    crop.crop_set_seed(ctx, SEED)
+    crop.crop_load_transactions(ctx, st.off, st.items, st.n)
+    S, R, ms = crop.crop_autotune(ctx, 1)
+    assert 1 <= S <= 8192 // P and R in (64, 96, 128, 192, 256, 48, 32, 24, 16, 12, 8) and ms > 0
+    t = crop.crop_get_tuning(ctx)
+    assert t["bins_per_partition"] == S and t["rows_per_chunk"] == R
+    ref = oracle.tx_exact(st.off, st.items, P, SEED)
+    sizes, terms = crop.crop_result_sizes(ctx, P)
+    assert np.array_equal(sizes, ref["part_sizes"]) and np.array_equal(terms, ref["part_terms"])
+    i, j, c, _ = crop.crop_read_all(ctx, P)
+    got = sort_xyc(i, j, c)
+    o = np.lexsort((ref["y"], ref["x"]))
+    for u, v in zip(got, (ref["x"][o], ref["y"][o], ref["cnt"][o])):
+        assert np.array_equal(u, v)
+    # a later run with the kept tuning gives the same result
+    crop.crop_run_exact(ctx)
+    i2, j2, c2, _ = crop.crop_read_all(ctx, P)
+    for u, v in zip(sort_xyc(i2, j2, c2), got):
+        assert np.array_equal(u, v)
+    with pytest.raises(crop.CropError):
+        h = crop.crop_create(0)
+        try:
+            crop.crop_autotune(h, 1)              # nothing loaded
+        finally:
+            crop.crop_destroy(h)
+
+
 def test_invalid_input_is_rejected(crop, ctx):
     bad = [
         (np.array([0, 2, 3], np.uint32), np.array([1, 1, 2], np.uint32), 5, 0),   # repeat
