@@ -52,6 +52,8 @@ def parse():
                          "whole stream also gives the recall and equality checks")
     ap.add_argument("--learned", action="store_true",
                     help="run the learned-seeding comparison instead of the exact bench")
+    ap.add_argument("--autotune", action="store_true",
+                    help="tune the exact run's plan (crop_autotune) before timing")
     ap.add_argument("--outer", action="store_true",
                     help="the outer-product workload: exact fp32 sums and top 10,000")
     ap.add_argument("--accuracy", action="store_true",
@@ -670,6 +672,11 @@ def main():
         crop.crop_set_seed(ctx, SEED)
         crop.crop_load_transactions(ctx, off, items, st.n, own=crop.CROP_OWN_BORROW)
         crop.crop_set_profiling(ctx, True)
+        tuned = None
+        if args.autotune:
+            # before the warm-up and the timed steps, outside the timed region
+            S_t, R_t, ms_t = crop.crop_autotune(ctx, 2)
+            tuned = {"bins_per_partition": S_t, "rows_per_chunk": R_t, "best_ms": round(ms_t, 4)}
         for _ in range(args.warmup):
             crop.crop_run_exact(ctx)
         torch.cuda.synchronize(dev)
@@ -738,7 +745,8 @@ def main():
                    "transactions": st.T, "items": st.nnz, "terms": terms,
                    "distinct_pairs": distinct, "P": P, "seed": SEED,
                    "bins_per_partition": tune["bins_per_partition"],
-                   "rows_per_chunk": tune["rows_per_chunk"]},
+                   "rows_per_chunk": tune["rows_per_chunk"],
+                   "plan": "autotuned" if tuned else "automatic"},
         "roofline": roofline,
         "path_roofline": {"bound": "hbm", "achieved": round(path_gbs, 1),
                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
