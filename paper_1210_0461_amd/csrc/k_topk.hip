@@ -196,6 +196,9 @@ template <> __device__ inline uint64_t empty_key<uint64_t>() { return kEmpty64; 
 // Add weight w (and signed value v) of key to the micro-batch table
 // (linear probing, at most half full, so a free slot is always reached).
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;
+// Merge-table weight of an update already applied as a hit (merged weights
+// are counts below 2^31 or non-negative fp32 bits, never all ones).
+constexpr uint32_t kConsumed = 0xFFFFFFFFu;
 
 // Adds (w, v) to key's entry of the merge table; returns the entry's slot
 // when this call inserted the key, else kNoSlot.
@@ -233,13 +236,16 @@ __device__ inline uint32_t table_add(KeyT *hk, uint32_t *hw, float *hv, uint32_t
 // bin's routed terms are read in micro-batches of MB:
 //   1. equal keys of the micro-batch are merged into one weighted update in
 //      an LDS hash table (a wave first merges the copies of its lead key);
-//   2. the merged updates are grouped by bucket with a counting sort; a bin
-//      of one bucket instead keeps them in the order of each key's first
+//   2. a bin of one bucket takes its hits first, in parallel: every
+//      monitored slot takes the merged weight of its key, if the
+//      micro-batch has it;
+//   3. the remaining updates are grouped by bucket with a counting sort; a
+//      bin of one bucket instead keeps them in the order of each key's first
 //      copy in the micro-batch, so the bucket sees its entries in stream
 //      order (routed keys keep the order of their chunks);
-//   3. a group of G lanes (G >= ell) applies one bucket's updates in order,
+//   4. a group of G lanes (G >= ell) applies one bucket's updates in order,
 //      lane j holding slot j in registers:
-//        hit    one ballot finds the monitored slot;
+//        hit    one ballot finds the monitored slot (not needed after 2);
 //        free   the lowest free slot (ballot, first set bit);
 //        evict  minimum count over the unpinned slots by a G-lane butterfly,
 //               the lowest slot among equal minima by a ballot.
@@ -247,7 +253,7 @@ __device__ inline uint32_t table_add(KeyT *hk, uint32_t *hw, float *hv, uint32_t
 // (Section 4), which hold for any order of weighted updates.  Counts and
 // overestimations are 32-bit words: uint32 for transactions, fp32 bits for
 // outer products (non-negative fp32 bits order like the values).
-template <int G, class KeyT, bool OUTER, int MB>
+template <int G, class KeyT, bool OUTER, int MB, bool ONE>
 __global__ void __launch_bounds__(256)
 k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ order,
             const KeyT *__restrict__ keys, const float *__restrict__ vals, uint32_t NB,
@@ -313,7 +319,7 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
             }
             for (uint32_t i = threadIdx.x; i <= nbk; i += BS) s_pos[i] = 0;
             // one bucket: t_w[i] = merge-table slot of the key first seen at i
-            if (nbk == 1)
+            if (ONE)
                 for (uint32_t i = threadIdx.x; i < MB; i += BS) t_w[i] = kNoSlot;
             __syncthreads();
             // 1. merge equal keys
@@ -345,11 +351,42 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                 // the inserting copy is one of the key's first copies: rounds
                 // of 256 positions run in order, a wave's lowest lane inserts
                 // for its copies (only waves of one round can race)
-                if (nbk == 1 && first != kNoSlot) t_w[i] = first;
+                if (ONE && first != kNoSlot) t_w[i] = first;
             }
             __syncthreads();
-            // 2. group the merged updates by bucket
-            if (nbk == 1) {
+            // 2. a bin of one bucket takes its hits in one parallel step: every
+            // monitored slot looks its key up in the merge table and takes the
+            // merged weight, and the entry is marked consumed (keys are only
+            // read here, so probe chains stay intact).  A micro-batch holds
+            // each key once, so a key that is not monitored now cannot become
+            // monitored before its own update: every update left for step 4
+            // is a miss.  Any order of the updates keeps the Section 4
+            // bounds.  (Bins of many buckets would scan all their slots per
+            // micro-batch; they keep the hit test in step 4.)
+            for (uint32_t q = threadIdx.x; ONE && q < nslot; q += BS) {
+                if (!(s_f[q] & kUsed)) continue;
+                const KeyT key = s_k[q];
+                uint32_t sl = slot_of(key, LOG2HS);
+                for (;;) {
+                    const KeyT cur = h_k[sl];
+                    if (cur == key) {
+                        const uint32_t w = h_w[sl];
+                        if (OUTER) {
+                            s_c[q] = __float_as_uint(__uint_as_float(s_c[q]) + __uint_as_float(w));
+                            s_v[q] += h_v[sl];
+                        } else {
+                            s_c[q] += w;
+                        }
+                        h_w[sl] = kConsumed;
+                        break;
+                    }
+                    if (cur == empty_key<KeyT>()) break;
+                    sl = (sl + 1) & (HS - 1);
+                }
+            }
+            __syncthreads();
+            // 3. group the remaining (missed) updates by bucket
+            if constexpr (ONE) {
                 // order of first copies: compact t_w's slots in position
                 // order (every thread reads its positions before the scan's
                 // barriers and writes at or below them afterwards; the
@@ -359,6 +396,7 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
 #pragma unroll
                 for (uint32_t q = 0; q < PER; ++q) {
                     sl[q] = t_w[threadIdx.x * PER + q];
+                    if (sl[q] != kNoSlot && h_w[sl[q]] == kConsumed) sl[q] = kNoSlot;
                     cnt += sl[q] != kNoSlot ? 1u : 0u;
                 }
                 uint32_t total;
@@ -392,7 +430,8 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                 }
             }
             __syncthreads();
-            // 3. one group per bucket applies its updates
+            // 4. one group per bucket applies its updates in order; after
+            // step 2 (one-bucket bins) they are all misses
             for (uint32_t lb = group; lb < nbk; lb += n_groups) {
                 const uint32_t e1 = s_pos[lb];
                 const uint32_t e0 = lb ? s_pos[lb - 1] : 0;
@@ -416,20 +455,24 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                         if (OUTER) nv = t_v[p + 1];
                     }
                     const bool used = (f & kUsed) != 0;
-                    const bool hit = real && used && k == key;
-                    const auto hg = group_bits<G>(__builtin_amdgcn_ballot_w64(hit), gsh);
-                    const auto fg = group_bits<G>(__builtin_amdgcn_ballot_w64(real && !used), gsh);
-                    // hit: the monitored slot takes the weight
-                    if (hit) {
-                        if (OUTER) {
-                            c = __float_as_uint(__uint_as_float(c) + __uint_as_float(w));
-                            v += val;
-                        } else {
-                            c += w;
+                    bool missed = true;  // uniform over the group
+                    if constexpr (!ONE) {
+                        const bool hit = real && used && k == key;
+                        const auto hg = group_bits<G>(__builtin_amdgcn_ballot_w64(hit), gsh);
+                        // hit: the monitored slot takes the weight
+                        if (hit) {
+                            if (OUTER) {
+                                c = __float_as_uint(__uint_as_float(c) + __uint_as_float(w));
+                                v += val;
+                            } else {
+                                c += w;
+                            }
                         }
+                        missed = !hg;
                     }
+                    const auto fg = group_bits<G>(__builtin_amdgcn_ballot_w64(real && !used), gsh);
                     // free: the lowest free slot takes the entry
-                    if (!hg && fg && j == lowest_bit(fg)) {
+                    if (missed && fg && j == lowest_bit(fg)) {
                         k = key;
                         c = w;
                         e = 0u;
@@ -437,7 +480,7 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                         f = kUsed;
                     }
                     // evict: the lowest unpinned slot of minimum count
-                    const bool need = !hg && !fg;  // uniform over the group
+                    const bool need = missed && !fg;  // uniform over the group
                     if (__builtin_amdgcn_ballot_w64(need)) {
                         const bool cand = need && real && !(f & kPinned);
                         const uint32_t mine = cand ? c : 0xFFFFFFFFu;
@@ -898,44 +941,45 @@ uint32_t ss_block_threads(uint32_t nbk, uint32_t ell)
     return 256u;
 }
 
+// One launch of the summary kernel: bins of one bucket take the ONE variant.
+template <int G, class KeyT, bool OUTER, int MB>
+static void launch_ss_k(const crop_ctx *c, const SsState &S, uint32_t nbk, uint64_t PB,
+                        uint32_t grid, uint32_t bs, bool narrow, const KeyT *keys,
+                        const float *vals, hipStream_t s)
+{
+    const RoutePlan &pl = c->plan;
+    const uint32_t ell = c->ss_ell;
+    const size_t sm = ss_bins_smem_bytes(nbk, ell, sizeof(KeyT) == 8, OUTER, MB);
+    if (nbk == 1)
+        hipLaunchKernelGGL((k_ss_groups<G, KeyT, OUTER, MB, true>), dim3(grid), dim3(bs), sm, s,
+                           c->bin_off.as<uint32_t>(), c->bin_order.as<uint32_t>(), keys, vals,
+                           pl.NB, nbk, ell, c->hp, PB, narrow, c->counter.as<uint32_t>(), S.key,
+                           S.cnt, S.err, S.val, S.flag);
+    else
+        hipLaunchKernelGGL((k_ss_groups<G, KeyT, OUTER, MB, false>), dim3(grid), dim3(bs), sm, s,
+                           c->bin_off.as<uint32_t>(), c->bin_order.as<uint32_t>(), keys, vals,
+                           pl.NB, nbk, ell, c->hp, PB, narrow, c->counter.as<uint32_t>(), S.key,
+                           S.cnt, S.err, S.val, S.flag);
+}
+
 template <int G>
 static void launch_ss_g(const crop_ctx *c, const SsState &S, uint32_t nbk, uint64_t PB,
                         uint32_t grid, uint32_t bs, hipStream_t s)
 {
     const RoutePlan &pl = c->plan;
-    const uint32_t ell = c->ss_ell;
-    if (c->in.mode == Mode::Outer) {
-        constexpr int MB = kSsBatchOuter;
-        const size_t sm = ss_bins_smem_bytes(nbk, ell, true, true, MB);
-        hipLaunchKernelGGL((k_ss_groups<G, uint64_t, true, MB>), dim3(grid), dim3(bs), sm,
-                           s, c->bin_off.as<uint32_t>(), c->bin_order.as<uint32_t>(),
-                           c->keys.as<uint64_t>(), c->vals.as<float>(), pl.NB, nbk, ell, c->hp, PB, false,
-                           c->counter.as<uint32_t>(), S.key, S.cnt, S.err, S.val, S.flag);
-    } else if (c->in.wide_keys) {
-        constexpr int MB = kSsBatchWide;
-        const size_t sm = ss_bins_smem_bytes(nbk, ell, true, false, MB);
-        hipLaunchKernelGGL((k_ss_groups<G, uint64_t, false, MB>), dim3(grid), dim3(bs),
-                           sm, s, c->bin_off.as<uint32_t>(), c->bin_order.as<uint32_t>(),
-                           c->keys.as<uint64_t>(), nullptr,
-                           pl.NB, nbk, ell, c->hp, PB, false, c->counter.as<uint32_t>(), S.key,
-                           S.cnt, S.err, S.val, S.flag);
-    } else if (pl.ss_mb == kSsBatchTxLarge) {
-        constexpr int MB = kSsBatchTxLarge;
-        const size_t sm = ss_bins_smem_bytes(nbk, ell, false, false, MB);
-        hipLaunchKernelGGL((k_ss_groups<G, uint32_t, false, MB>), dim3(grid), dim3(bs),
-                           sm, s, c->bin_off.as<uint32_t>(), c->bin_order.as<uint32_t>(),
-                           c->keys.as<uint32_t>(), nullptr,
-                           pl.NB, nbk, ell, c->hp, PB, true, c->counter.as<uint32_t>(), S.key,
-                           S.cnt, S.err, S.val, S.flag);
-    } else {
-        constexpr int MB = kSsBatchTx;
-        const size_t sm = ss_bins_smem_bytes(nbk, ell, false, false, MB);
-        hipLaunchKernelGGL((k_ss_groups<G, uint32_t, false, MB>), dim3(grid), dim3(bs),
-                           sm, s, c->bin_off.as<uint32_t>(), c->bin_order.as<uint32_t>(),
-                           c->keys.as<uint32_t>(), nullptr,
-                           pl.NB, nbk, ell, c->hp, PB, true, c->counter.as<uint32_t>(), S.key,
-                           S.cnt, S.err, S.val, S.flag);
-    }
+    if (c->in.mode == Mode::Outer)
+        launch_ss_k<G, uint64_t, true, kSsBatchOuter>(c, S, nbk, PB, grid, bs, false,
+                                                       c->keys.as<uint64_t>(),
+                                                       c->vals.as<float>(), s);
+    else if (c->in.wide_keys)
+        launch_ss_k<G, uint64_t, false, kSsBatchWide>(c, S, nbk, PB, grid, bs, false,
+                                                       c->keys.as<uint64_t>(), nullptr, s);
+    else if (pl.ss_mb == kSsBatchTxLarge)
+        launch_ss_k<G, uint32_t, false, kSsBatchTxLarge>(c, S, nbk, PB, grid, bs, true,
+                                                          c->keys.as<uint32_t>(), nullptr, s);
+    else
+        launch_ss_k<G, uint32_t, false, kSsBatchTx>(c, S, nbk, PB, grid, bs, true,
+                                                     c->keys.as<uint32_t>(), nullptr, s);
 }
 
 hipError_t launch_ss_bins(const crop_ctx *c, const SsState &S, uint32_t nbk, uint64_t PB,
