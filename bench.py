@@ -486,7 +486,7 @@ def run_outer(args):
     exact fp32 sums with the tolerance pass rate against the oracle's fp64
     sums (|c32 - c64| <= 1e-5 sum |terms|), and the Space-Saving top 10,000
     (2^16 counters per partition, 16 per bucket, weights |a b|) with its
-    recall of the exact top 10,000 by sum |a b|."""
+    recall of the exact top 10,000 by sum |a b| and by |sum a b|."""
     import numpy as np
     import torch
     import datagen
@@ -542,10 +542,14 @@ def run_outer(args):
         ti, tj, up, lo, val = crop.crop_read_topk(ctx, K)
         tk = (ti.astype(np.uint64) << np.uint64(32)) | tj.astype(np.uint64)
         kth = np.sort(rabs)[::-1][K - 1]
+        kth_c = np.sort(np.abs(rsum))[::-1][K - 1]
         pos = np.minimum(np.searchsorted(rk, tk), rk.shape[0] - 1)
-        exact_abs = np.where(rk[pos] == tk, rabs[pos], 0.0)
+        found = rk[pos] == tk
+        exact_abs = np.where(found, rabs[pos], 0.0)
+        exact_c = np.where(found, np.abs(rsum[pos]), 0.0)
         out["topk"] = {"ms": round(ms, 4), "term_updates_per_s": terms / (ms * 1e-3), "K": K,
                        "recall_by_abs_weight": float(np.mean(exact_abs >= kth)),
+                       "recall_by_abs_sum": float(np.mean(exact_c >= kth_c)),
                        "bounds_hold": bool(np.all(lo <= exact_abs * (1 + 1e-5) + 1e-6) and
                                            np.all(exact_abs <= up * (1 + 1e-5) + 1e-6))}
     finally:
