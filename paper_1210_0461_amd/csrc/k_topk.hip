@@ -164,10 +164,12 @@ __host__ __device__ inline SsLayout ss_layout(uint32_t nbk, uint32_t ell, uint32
 template <int G>
 __device__ inline uint32_t group_min(uint32_t v)
 {
-    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0xB1, 0xF, 0xF, false));
-    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x4E, 0xF, 0xF, false));
-    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x124, 0xF, 0xF, false));
-    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x128, 0xF, 0xF, false));
+    // old = all ones, the identity of the minimum, lets the compiler fold
+    // each move into the min (a lane with no valid source keeps its value)
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0xB1, 0xF, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0x4E, 0xF, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0x124, 0xF, 0xF, false));
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp(-1, (int)v, 0x128, 0xF, 0xF, false));
     if (G >= 32) v = min(v, (uint32_t)__shfl_xor((int)v, 16, kWave));
     if (G >= 64) v = min(v, (uint32_t)__shfl_xor((int)v, 32, kWave));
     return v;
@@ -248,7 +250,11 @@ __device__ inline uint32_t table_add(KeyT *hk, uint32_t *hw, float *hv, uint32_t
 //        hit    one ballot finds the monitored slot (not needed after 2);
 //        free   the lowest free slot (ballot, first set bit);
 //        evict  minimum count over the unpinned slots by a G-lane butterfly,
-//               the lowest slot among equal minima by a ballot.
+//               the lowest slot among equal minima by a ballot;
+//      with transaction counts small enough, one G-lane minimum over packed
+//      (kind, count, slot) offers takes all three decisions without a ballot
+//      (the ballots' round trips through scalar registers set the pace of
+//      the serial chain).
 // Merging and reordering a bucket's updates keeps Space-Saving's bounds
 // (Section 4), which hold for any order of weighted updates.  Counts and
 // overestimations are 32-bit words: uint32 for transactions, fp32 bits for
@@ -432,9 +438,19 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
             __syncthreads();
             // 4. one group per bucket applies its updates in order; after
             // step 2 (one-bucket bins) they are all misses
-            for (uint32_t lb = group; lb < nbk; lb += n_groups) {
-                const uint32_t e1 = s_pos[lb];
-                const uint32_t e0 = lb ? s_pos[lb - 1] : 0;
+            // A bin of one bucket has a single chain of updates; workgroups
+            // run it on different wavefronts (blockIdx mod 4) so that the
+            // chains of the workgroups sharing a CU spread over its SIMDs.
+            const uint32_t g_one = ONE ? (blockIdx.x & 3u) * (uint32_t)(kWave / G) : 0u;
+            for (uint32_t lb = group - g_one; lb < nbk; lb += n_groups) {
+                uint32_t e1 = s_pos[lb];
+                uint32_t e0 = lb ? s_pos[lb - 1] : 0;
+                if constexpr (ONE) {
+                    // a bin of one bucket has one active group, lanes [0, G)
+                    // of one wavefront: its bounds are wave-uniform
+                    e1 = __builtin_amdgcn_readfirstlane(e1);
+                    e0 = __builtin_amdgcn_readfirstlane(e0);
+                }
                 if (e0 == e1) continue;  // uniform over the group
                 const uint32_t sidx = lb * ell + j;
                 KeyT k = real ? s_k[sidx] : (KeyT)0;
@@ -442,18 +458,7 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                 uint32_t e = real ? s_e[sidx] : 0u;
                 float v = (OUTER && real) ? s_v[sidx] : 0.0f;
                 uint8_t f = real ? s_f[sidx] : (uint8_t)0;
-                KeyT nk = t_k[e0];
-                uint32_t nw = t_w[e0];
-                float nv = OUTER ? t_v[e0] : 0.0f;
-                for (uint32_t p = e0; p < e1; ++p) {
-                    const KeyT key = nk;
-                    const uint32_t w = nw;
-                    const float val = nv;
-                    if (p + 1 < e1) {  // prefetch the next update
-                        nk = t_k[p + 1];
-                        nw = t_w[p + 1];
-                        if (OUTER) nv = t_v[p + 1];
-                    }
+                auto step = [&](const KeyT key, const uint32_t w, const float val) {
                     const bool used = (f & kUsed) != 0;
                     bool missed = true;  // uniform over the group
                     if constexpr (!ONE) {
@@ -494,6 +499,92 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                             k = key;
                             v = val;
                         }
+                    }
+                };
+                // Transaction counts: while every count of the bucket stays
+                // below 2^(30 - log2 G) - 1 (counts grow by at most the
+                // micro-batch's n terms), one minimum over packed words
+                // decides an update without ballots.  Lane j offers
+                //   j                               if its slot holds the key,
+                //   2^30 | j                        if its slot is free,
+                //   2^31 | count << log2 G | j      if it may be evicted,
+                //   all ones                        otherwise (pinned, padding);
+                // the smallest offer is the hit, else the lowest free slot,
+                // else the lowest slot of minimum count, as in step.
+                constexpr uint32_t LOGG = G == 16 ? 4u : G == 32 ? 5u : 6u;
+                constexpr uint32_t kPackLim = 1u << (30 - LOGG);
+                bool pack = false;
+                if constexpr (!OUTER) {
+                    const uint32_t cmax = ~group_min<G>(real ? ~c : 0xFFFFFFFFu);
+                    pack = cmax < kPackLim - 1 && n < kPackLim - 1 - cmax;
+                    if constexpr (ONE) pack = __builtin_amdgcn_readfirstlane((int)pack) != 0;
+                }
+                auto step_packed = [&](const KeyT key, const uint32_t w) {
+                    const bool used = (f & kUsed) != 0;
+                    uint32_t mine = (real && used && !(f & kPinned))
+                                        ? 0x80000000u | (c << LOGG) | j
+                                        : 0xFFFFFFFFu;
+                    mine = (real && !used) ? 0x40000000u | j : mine;
+                    if constexpr (!ONE) mine = (real && used && k == key) ? j : mine;
+                    const uint32_t mn = group_min<G>(mine);
+                    const bool win = mine == mn && mine != 0xFFFFFFFFu;
+                    const bool hit = mn < 0x40000000u;
+                    const bool fr = !hit && mn < 0x80000000u;
+                    e = (win && !hit) ? (fr ? 0u : c) : e;
+                    k = (win && !hit) ? key : k;
+                    c = win ? (fr ? w : c + w) : c;
+                    f = win ? (uint8_t)(f | kUsed) : f;
+                };
+                if constexpr (ONE) {
+                    // G updates per LDS load: lane j holds update p0 + j and
+                    // each update is broadcast from its lane in turn, so the
+                    // serial chain waits on LDS once per G updates
+                    for (uint32_t p0 = e0; p0 < e1; p0 += G) {
+                        const uint32_t q = p0 + j;
+                        const KeyT bk = q < e1 ? t_k[q] : (KeyT)0;
+                        const uint32_t bw = q < e1 ? t_w[q] : 0u;
+                        const float bv = (OUTER && q < e1) ? t_v[q] : 0.0f;
+                        const uint32_t cnt = min((uint32_t)G, e1 - p0);
+                        for (uint32_t i = 0; i < cnt; ++i) {
+                            KeyT key;
+                            if constexpr (sizeof(KeyT) == 8) {
+                                const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane(
+                                    (int)(uint32_t)bk, (int)i);
+                                const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane(
+                                    (int)(uint32_t)((uint64_t)bk >> 32), (int)i);
+                                key = (KeyT)(((uint64_t)hi << 32) | lo);
+                            } else {
+                                key = (KeyT)(uint32_t)__builtin_amdgcn_readlane((int)bk, (int)i);
+                            }
+                            const uint32_t w =
+                                (uint32_t)__builtin_amdgcn_readlane((int)bw, (int)i);
+                            float val = 0.0f;
+                            if (OUTER)
+                                val = __int_as_float(
+                                    __builtin_amdgcn_readlane(__float_as_int(bv), (int)i));
+                            if (pack)
+                                step_packed(key, w);
+                            else
+                                step(key, w, val);
+                        }
+                    }
+                } else {
+                    KeyT nk = t_k[e0];
+                    uint32_t nw = t_w[e0];
+                    float nv = OUTER ? t_v[e0] : 0.0f;
+                    for (uint32_t p = e0; p < e1; ++p) {
+                        const KeyT key = nk;
+                        const uint32_t w = nw;
+                        const float val = nv;
+                        if (p + 1 < e1) {  // prefetch the next update
+                            nk = t_k[p + 1];
+                            nw = t_w[p + 1];
+                            if (OUTER) nv = t_v[p + 1];
+                        }
+                        if (pack)
+                            step_packed(key, w);
+                        else
+                            step(key, w, val);
                     }
                 }
                 if (real) {
