@@ -287,7 +287,7 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
     float *t_v = reinterpret_cast<float *>(sm + Lo.tv);
     uint32_t *s_pos = reinterpret_cast<uint32_t *>(sm + Lo.pos);
     __shared__ uint32_t s_tmp[256 / kWave + 1];
-    __shared__ uint32_t s_bin;
+    __shared__ uint32_t s_bin, s_cmax;
 
     const uint32_t BS = blockDim.x;
     const uint32_t nslot = nbk * ell;
@@ -298,7 +298,10 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
     const bool real = j < ell;
 
     for (;;) {
-        if (threadIdx.x == 0) s_bin = atomicAdd(counter, 1u);
+        if (threadIdx.x == 0) {
+            s_bin = atomicAdd(counter, 1u);
+            s_cmax = 0;
+        }
         __syncthreads();
         const uint32_t q = s_bin;
         if (q >= NB) break;
@@ -309,7 +312,9 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
             // seeded slots carry a 64-bit pair key; narrow runs compare packed keys
             s_k[s] = narrow ? (KeyT)(((uint32_t)(g >> 32) << 16) | (uint32_t)(g & 0xFFFFu))
                             : (KeyT)g;
-            s_c[s] = g_cnt[g0 + s];
+            const uint32_t cnt = g_cnt[g0 + s];
+            s_c[s] = cnt;
+            if (!OUTER && cnt) atomicMax(&s_cmax, cnt);
             s_e[s] = g_err[g0 + s];
             if (OUTER) s_v[s] = g_val[g0 + s];
             s_f[s] = g_flag[g0 + s];
@@ -501,10 +506,11 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                         }
                     }
                 };
-                // Transaction counts: while every count of the bucket stays
-                // below 2^(30 - log2 G) - 1 (counts grow by at most the
-                // micro-batch's n terms), one minimum over packed words
-                // decides an update without ballots.  Lane j offers
+                // Transaction counts: while every count of the bin stays
+                // below 2^(30 - log2 G) - 1 (a count is at most the bin's
+                // largest initial count plus its k1 - k0 terms of unit
+                // weight), one minimum over packed words decides an update
+                // without ballots.  Lane j offers
                 //   j                               if its slot holds the key,
                 //   2^30 | j                        if its slot is free,
                 //   2^31 | count << log2 G | j      if it may be evicted,
@@ -513,12 +519,8 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                 // else the lowest slot of minimum count, as in step.
                 constexpr uint32_t LOGG = G == 16 ? 4u : G == 32 ? 5u : 6u;
                 constexpr uint32_t kPackLim = 1u << (30 - LOGG);
-                bool pack = false;
-                if constexpr (!OUTER) {
-                    const uint32_t cmax = ~group_min<G>(real ? ~c : 0xFFFFFFFFu);
-                    pack = cmax < kPackLim - 1 && n < kPackLim - 1 - cmax;
-                    if constexpr (ONE) pack = __builtin_amdgcn_readfirstlane((int)pack) != 0;
-                }
+                const uint32_t cmax0 = __builtin_amdgcn_readfirstlane(s_cmax);  // uniform
+                const bool pack = !OUTER && (uint64_t)cmax0 + (k1 - k0) < kPackLim - 1;
                 auto step_packed = [&](const KeyT key, const uint32_t w) {
                     const bool used = (f & kUsed) != 0;
                     uint32_t mine = (real && used && !(f & kPinned))
