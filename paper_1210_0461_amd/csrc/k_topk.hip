@@ -321,8 +321,25 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
         }
         const uint32_t k0 = bin_off[b], k1 = bin_off[b + 1];
         const uint64_t bucket0 = (uint64_t)b * nbk;
-        for (uint32_t base = k0; base < k1; base += MB) {
+        // The keys (and values) of a micro-batch, MB / 256 per thread, are
+        // loaded while the previous micro-batch is applied, so their HBM
+        // latency overlaps the serial work.
+        constexpr uint32_t PT = MB / 256;
+        KeyT kk[PT];
+        float vv[PT];
+        auto load_batch = [&](uint32_t b0) {
+            const uint32_t m = b0 < k1 ? min((uint32_t)MB, k1 - b0) : 0u;
+#pragma unroll
+            for (uint32_t q = 0; q < PT; ++q) {
+                const uint32_t i = threadIdx.x + q * 256;
+                kk[q] = i < m ? keys[b0 + i] : empty_key<KeyT>();
+                vv[q] = (OUTER && i < m) ? vals[b0 + i] : 0.0f;
+            }
+        };
+        load_batch(k0);
+        for (uint32_t base = k0; base < k1;) {
             const uint32_t n = min((uint32_t)MB, k1 - base);
+            const uint32_t next = base + n;  // <= k1: no wrap-around
             for (uint32_t i = threadIdx.x; i < HS; i += BS) {
                 h_k[i] = empty_key<KeyT>();
                 h_w[i] = 0u;
@@ -333,15 +350,17 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
             if (ONE)
                 for (uint32_t i = threadIdx.x; i < MB; i += BS) t_w[i] = kNoSlot;
             __syncthreads();
-            // 1. merge equal keys
-            const uint32_t n_all = (n + BS - 1) / BS * BS;
-            for (uint32_t i = threadIdx.x; i < n_all; i += BS) {
+            // 1. merge equal keys (kk, vv hold this micro-batch)
+#pragma unroll
+            for (uint32_t q = 0; q < PT; ++q) {
+                if (q * 256 >= n) break;  // uniform
+                const uint32_t i = threadIdx.x + q * 256;
                 const bool valid = i < n;
-                const KeyT key = valid ? keys[base + i] : empty_key<KeyT>();
+                const KeyT key = kk[q];
                 uint32_t first = kNoSlot;
                 if (OUTER) {
                     if (valid) {
-                        const float v = vals[base + i];
+                        const float v = vv[q];
                         first = table_add<KeyT, true>(h_k, h_w, h_v, LOG2HS, key,
                                                       __float_as_uint(fabsf(v)), v);
                     }
@@ -364,6 +383,7 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                 // for its copies (only waves of one round can race)
                 if (ONE && first != kNoSlot) t_w[i] = first;
             }
+            load_batch(next);  // the next micro-batch, used after step 4
             __syncthreads();
             // 2. a bin of one bucket takes its hits in one parallel step: every
             // monitored slot looks its key up in the merge table and takes the
@@ -598,6 +618,7 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                 }
             }
             __syncthreads();
+            base = next;
         }
         for (uint32_t s = threadIdx.x; s < nslot; s += BS) {
             uint64_t g;
