@@ -260,7 +260,7 @@ __device__ inline uint32_t table_add(KeyT *hk, uint32_t *hw, float *hv, uint32_t
 // overestimations are 32-bit words: uint32 for transactions, fp32 bits for
 // outer products (non-negative fp32 bits order like the values).
 template <int G, class KeyT, bool OUTER, int MB, bool ONE>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(ONE ? 256 : 512)
 k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ order,
             const KeyT *__restrict__ keys, const float *__restrict__ vals, uint32_t NB,
             uint32_t nbk, uint32_t ell, HashParams hp, uint64_t PB, bool narrow,
@@ -286,10 +286,13 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
     uint32_t *t_w = reinterpret_cast<uint32_t *>(sm + Lo.tw);
     float *t_v = reinterpret_cast<float *>(sm + Lo.tv);
     uint32_t *s_pos = reinterpret_cast<uint32_t *>(sm + Lo.pos);
-    __shared__ uint32_t s_tmp[256 / kWave + 1];
+    __shared__ uint32_t s_tmp[512 / kWave + 1];
     __shared__ uint32_t s_bin, s_cmax;
 
-    const uint32_t BS = blockDim.x;
+    // Bins of one bucket run 256 threads (one chain; the merge and grouping
+    // phases still use every lane), bins of several buckets 512 (twice the
+    // wavefronts per CU for the latency-bound merge, grouping and chains).
+    constexpr uint32_t BS = ONE ? 256u : 512u;
     const uint32_t nslot = nbk * ell;
     const uint32_t lane = lane_id();
     const uint32_t j = lane & (G - 1);  // slot held by this lane
@@ -321,17 +324,18 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
         }
         const uint32_t k0 = bin_off[b], k1 = bin_off[b + 1];
         const uint64_t bucket0 = (uint64_t)b * nbk;
-        // The keys (and values) of a micro-batch, MB / 256 per thread, are
+        // The keys (and values) of a micro-batch, MB / BS per thread, are
         // loaded while the previous micro-batch is applied, so their HBM
         // latency overlaps the serial work.
-        constexpr uint32_t PT = MB / 256;
+        constexpr uint32_t PT = MB / BS;
+        static_assert(PT * BS == MB, "micro-batch is a multiple of the block");
         KeyT kk[PT];
         float vv[PT];
         auto load_batch = [&](uint32_t b0) {
             const uint32_t m = b0 < k1 ? min((uint32_t)MB, k1 - b0) : 0u;
 #pragma unroll
             for (uint32_t q = 0; q < PT; ++q) {
-                const uint32_t i = threadIdx.x + q * 256;
+                const uint32_t i = threadIdx.x + q * BS;
                 kk[q] = i < m ? keys[b0 + i] : empty_key<KeyT>();
                 vv[q] = (OUTER && i < m) ? vals[b0 + i] : 0.0f;
             }
@@ -353,8 +357,8 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
             // 1. merge equal keys (kk, vv hold this micro-batch)
 #pragma unroll
             for (uint32_t q = 0; q < PT; ++q) {
-                if (q * 256 >= n) break;  // uniform
-                const uint32_t i = threadIdx.x + q * 256;
+                if (q * BS >= n) break;  // uniform
+                const uint32_t i = threadIdx.x + q * BS;
                 const bool valid = i < n;
                 const KeyT key = kk[q];
                 uint32_t first = kNoSlot;
@@ -1050,9 +1054,8 @@ uint32_t ss_group_width(uint32_t ell) { return ell <= 16 ? 16u : ell <= 32 ? 32u
 // sized to the bin's groups: P = 1 with 1,024 buckets 26 -> 18 ms).
 uint32_t ss_block_threads(uint32_t nbk, uint32_t ell)
 {
-    (void)nbk;
     (void)ell;
-    return 256u;
+    return nbk == 1 ? 256u : 512u;  // as k_ss_groups' BS for ONE and not ONE
 }
 
 // One launch of the summary kernel: bins of one bucket take the ONE variant.
