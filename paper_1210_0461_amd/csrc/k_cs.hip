@@ -81,24 +81,40 @@ k_cs_bins(const uint32_t *__restrict__ bin_off, const KeyT *__restrict__ keys,
     for (uint32_t b = blockIdx.x; b < NB; b += gridDim.x) {
         for (uint32_t q = threadIdx.x; q < nbk; q += BS) acc[q] = 0;
         __syncthreads();
-        const uint32_t k1 = bin_off[b + 1];
+        const uint64_t k1 = bin_off[b + 1];
         const uint64_t first = (uint64_t)b * nbk;
-        for (uint32_t k = bin_off[b] + threadIdx.x; k < k1; k += BS) {
-            const KeyT key = keys[k];
-            uint32_t x, y;
-            if (sizeof(KeyT) == 4) {
-                x = (uint32_t)key >> 16;
-                y = (uint32_t)key & 0xFFFFu;
-            } else {
-                x = (uint32_t)((uint64_t)key >> 32);
-                y = (uint32_t)key;
+        // U keys per thread are loaded before any is summed, so their
+        // latencies overlap
+        constexpr int U = 4;
+        for (uint64_t k = bin_off[b] + threadIdx.x; k < k1; k += (uint64_t)U * BS) {
+            KeyT kv[U];
+            float vv[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const uint64_t i = k + (uint64_t)u * BS;
+                kv[u] = i < k1 ? keys[i] : (KeyT)0;
+                vv[u] = (OUTER && i < k1) ? vals[i] : 0.0f;
             }
-            const uint32_t q = (uint32_t)(interval_of(hash_a(hp, x) + hash_b(hp, y), PB) - first);
-            const int sg = sign_of(hp, x, y);
-            if (OUTER)
-                atomicAdd(reinterpret_cast<float *>(&acc[q]), sg > 0 ? vals[k] : -vals[k]);
-            else
-                atomicAdd(reinterpret_cast<int32_t *>(&acc[q]), sg);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (k + (uint64_t)u * BS >= k1) break;
+                const KeyT key = kv[u];
+                uint32_t x, y;
+                if (sizeof(KeyT) == 4) {
+                    x = (uint32_t)key >> 16;
+                    y = (uint32_t)key & 0xFFFFu;
+                } else {
+                    x = (uint32_t)((uint64_t)key >> 32);
+                    y = (uint32_t)key;
+                }
+                const uint32_t q =
+                    (uint32_t)(interval_of(hash_a(hp, x) + hash_b(hp, y), PB) - first);
+                const int sg = sign_of(hp, x, y);
+                if (OUTER)
+                    atomicAdd(reinterpret_cast<float *>(&acc[q]), sg > 0 ? vv[u] : -vv[u]);
+                else
+                    atomicAdd(reinterpret_cast<int32_t *>(&acc[q]), sg);
+            }
         }
         __syncthreads();
         for (uint32_t q = threadIdx.x; q < nbk; q += BS) out[first + q] = acc[q];
