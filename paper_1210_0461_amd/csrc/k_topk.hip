@@ -965,12 +965,19 @@ k_amp_combine(CsParams ip, uint32_t ell, uint64_t ns, uint32_t min_votes,
                 const uint64_t base = (uint64_t)j * ns + b * ell;
                 q = ~0ull;
                 // keys first: a free slot's key is 0, so its flag is read only
-                // when the entry's own key is 0 (outer products' (0, 0))
-                for (uint32_t r = 0; r < ell; ++r)
-                    if (key[base + r] == k && (flag[base + r] & kUsed)) {
-                        q = base + r;
-                        break;
-                    }
+                // when the entry's own key is 0 (outer products' (0, 0)).  The
+                // keys are loaded eight at a time before any is compared, so
+                // the loads of a bucket overlap.
+                for (uint32_t r0 = 0; r0 < ell && q == ~0ull; r0 += 8) {
+                    uint64_t kb[8];
+#pragma unroll
+                    for (uint32_t t = 0; t < 8; ++t)
+                        kb[t] = r0 + t < ell ? key[base + r0 + t] : ~k;
+#pragma unroll
+                    for (uint32_t t = 0; t < 8; ++t)
+                        if (q == ~0ull && kb[t] == k && (flag[base + r0 + t] & kUsed))
+                            q = base + r0 + t;
+                }
                 if (q == ~0ull) continue;
                 if (j < inst) {
                     own = false;
