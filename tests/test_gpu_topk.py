@@ -206,3 +206,44 @@ def test_outer_config_topk_recall(crop, ctx):
     rec_abs = oracle.recall_at_k(oracle.pack_keys(top[0], top[1]), ek, ex["abs"], K)
     print(f"outer top-{K}: recall by |sum| {rec:.4f}, by sum|terms| {rec_abs:.4f}")
     assert rec_abs > 0.9
+
+
+def test_bucket_with_more_than_2_pow_26_terms(crop, ctx):
+    """A single bucket (P = 1, 16 counters, ell = 16) fed 67.6M terms: more
+    than 2^26 - 1, so the update step cannot pack counts with slot indices
+    and takes the ballot form.  Nine of every ten transactions are
+    {0, ..., 5} (15 pairs), the tenth is {6, 7, 8} (3 pairs): 18 distinct
+    pairs compete for 16 slots, every micro-batch evicts, and the exact
+    supports are known in closed form."""
+    import types
+    T = 4_900_000
+    light = (np.arange(T) % 10) == 9
+    lens = np.where(light, 3, 6).astype(np.int64)
+    off = np.zeros(T + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    items = np.empty(int(off[-1]), np.uint32)
+    heavy_rows = np.flatnonzero(~light)
+    light_rows = np.flatnonzero(light)
+    for c in range(6):
+        items[off[heavy_rows] + c] = c
+    for c in range(3):
+        items[off[light_rows] + c] = 6 + c
+    st = types.SimpleNamespace(off=off.astype(np.uint32), items=items, n=9)
+    terms = 15 * len(heavy_rows) + 3 * len(light_rows)
+    assert terms > (1 << 26)
+    exact = {}
+    for a in range(6):
+        for b in range(a + 1, 6):
+            exact[int(oracle.pack_keys(np.array([a]), np.array([b]))[0])] = float(len(heavy_rows))
+    for a in range(6, 9):
+        for b in range(a + 1, 9):
+            exact[int(oracle.pack_keys(np.array([a]), np.array([b]))[0])] = float(len(light_rows))
+    s, top = run_tx_topk(crop, ctx, st, 1, 16, 16, 16)
+    check_invariants(s, exact, SEED)
+    assert float(np.asarray(s["cnt"])[s["used"]].sum()) == float(terms)
+    # the 15 heavy pairs hold more than m / ell each and must be monitored
+    mon = set(oracle.pack_keys(s["x"][s["used"]], s["y"][s["used"]]).tolist())
+    for k, f in exact.items():
+        if f == len(heavy_rows):
+            assert k in mon
+    check_topk_is_summary_topk(s, top, 16)
