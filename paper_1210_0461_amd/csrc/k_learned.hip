@@ -32,6 +32,23 @@ constexpr int kH = 64;       // hidden width
 constexpr int oW1 = 0, oB1 = kH * kIn, oW2 = oB1 + kH, oB2 = oW2 + kH * kH, oW3 = oB2 + kH,
               oB3 = oW3 + kH, kParams = oB3 + 1;
 static_assert(kParams == 6337, "parameter layout");
+// The training kernels keep the weights in LDS with rows of W1 and W2 padded
+// by one word (strides kIn + 1 and kH + 1), so that the lanes of a wavefront,
+// which read one row each, hit different LDS banks.  lds_of maps a
+// parameter index to its padded LDS position.
+constexpr int kW1S = kIn + 1, kW2S = kH + 1;
+constexpr int lW1 = 0, lB1 = kH * kW1S, lW2 = lB1 + kH, lB2 = lW2 + kH * kW2S, lW3 = lB2 + kH,
+              lB3 = lW3 + kH, kLdsParams = lB3 + 1;
+__device__ inline uint32_t lds_of(uint32_t p)
+{
+    if (p < (uint32_t)oB1) return lW1 + (p / kIn) * kW1S + p % kIn;
+    if (p < (uint32_t)oW2) return lB1 + (p - oB1);
+    if (p < (uint32_t)oB2) {
+        const uint32_t q = p - oW2;
+        return lW2 + (q / kH) * kW2S + q % kH;
+    }
+    return lB2 + (p - oB2);  // b2, w3, b3 keep their order
+}
 
 // ---------------------------------------------------------------- features
 
@@ -254,14 +271,14 @@ __device__ void mlp_batch(const MlpLds &L, uint32_t nb, float inv_n, const float
                           const uint32_t *idx, bool apply, float *gstage, float *m, float *v,
                           float lr, float bc1, float bc2, float *sse)
 {
-    const float *W1 = L.W + oW1, *b1 = L.W + oB1, *W2 = L.W + oW2, *b2 = L.W + oB2,
-                *w3 = L.W + oW3;
-    const float b3 = L.W[oB3];
+    const float *W1 = L.W + lW1, *b1 = L.W + lB1, *W2 = L.W + lW2, *b2 = L.W + lB2,
+                *w3 = L.W + lW3;
+    const float b3 = L.W[lB3];
     // layer 1
     for (uint32_t e = threadIdx.x; e < nb * kH; e += BS) {
         const uint32_t s = e / kH, i = e % kH;
         float a = b1[i];
-        for (int k = 0; k < kIn; ++k) a = fmaf(W1[i * kIn + k], L.Zs[s * kIn + k], a);
+        for (int k = 0; k < kIn; ++k) a = fmaf(W1[i * kW1S + k], L.Zs[s * kIn + k], a);
         L.H1[s * kH + i] = fmaxf(a, 0.0f);
     }
     __syncthreads();
@@ -269,7 +286,7 @@ __device__ void mlp_batch(const MlpLds &L, uint32_t nb, float inv_n, const float
     for (uint32_t e = threadIdx.x; e < nb * kH; e += BS) {
         const uint32_t s = e / kH, i = e % kH;
         float a = b2[i];
-        for (int k = 0; k < kH; ++k) a = fmaf(W2[i * kH + k], L.H1[s * kH + k], a);
+        for (int k = 0; k < kH; ++k) a = fmaf(W2[i * kW2S + k], L.H1[s * kH + k], a);
         L.H2[s * kH + i] = fmaxf(a, 0.0f);
     }
     __syncthreads();
@@ -282,11 +299,13 @@ __device__ void mlp_batch(const MlpLds &L, uint32_t nb, float inv_n, const float
         L.g[s] = 2.0f * r * inv_n;
         part += r * r;
     }
-    if (threadIdx.x < BS) L.red[threadIdx.x] = part;
+#pragma unroll
+    for (int d = kWave / 2; d >= 1; d >>= 1) part += __shfl_xor(part, d, kWave);
+    if (lane_id() == 0) L.red[threadIdx.x / kWave] = part;
     __syncthreads();
     if (threadIdx.x == 0) {
         float t = 0.0f;
-        for (int k = 0; k < BS; ++k) t += L.red[k];
+        for (int k = 0; k < BS / kWave; ++k) t += L.red[k];
         *sse = t;
     }
     // gradients of w3, b3 (need H2), then G2 = g * w3 * [H2 > 0]
@@ -325,7 +344,7 @@ __device__ void mlp_batch(const MlpLds &L, uint32_t nb, float inv_n, const float
     for (uint32_t e = threadIdx.x; e < nb * kH; e += BS) {
         const uint32_t s = e / kH, k = e % kH;
         float acc = 0.0f;
-        for (int i = 0; i < kH; ++i) acc = fmaf(L.G2[s * kH + i], W2[i * kH + k], acc);
+        for (int i = 0; i < kH; ++i) acc = fmaf(L.G2[s * kH + i], W2[i * kW2S + k], acc);
         G1[e] = L.H1[e] > 0.0f ? acc : 0.0f;
     }
     __syncthreads();
@@ -350,7 +369,7 @@ __device__ void mlp_batch(const MlpLds &L, uint32_t nb, float inv_n, const float
             const float vp = 0.999f * v[p] + 0.001f * gr * gr;
             m[p] = mp;
             v[p] = vp;
-            L.W[p] -= lr * (mp / bc1) / (sqrtf(vp / bc2) + 1e-8f);
+            L.W[lds_of(p)] -= lr * (mp / bc1) / (sqrtf(vp / bc2) + 1e-8f);
         }
         __syncthreads();
     }
@@ -360,7 +379,7 @@ __device__ inline MlpLds mlp_lds(float *smem)
 {
     MlpLds L;
     L.W = smem;
-    L.Zs = L.W + ((kParams + 3) & ~3);
+    L.Zs = L.W + ((kLdsParams + 3) & ~3);
     L.H1 = L.Zs + kBatch * kIn;
     L.H2 = L.H1 + kBatch * kH;
     L.G2 = L.H2 + kBatch * kH;
@@ -369,9 +388,9 @@ __device__ inline MlpLds mlp_lds(float *smem)
     return L;
 }
 
-constexpr int kMlpBS = 256;
+constexpr int kMlpBS = 1024;  // one workgroup: as many wavefronts as a CU takes
 constexpr size_t kMlpSmem =
-    sizeof(float) * (((kParams + 3) & ~3) + kBatch * kIn + 3 * kBatch * kH + kBatch + kMlpBS);
+    sizeof(float) * (((kLdsParams + 3) & ~3) + kBatch * kIn + 3 * kBatch * kH + kBatch + kMlpBS);
 
 // Persistent single workgroup: n_steps Adam steps over consecutive slices of
 // `order` (batch indices into Z/y), weights kept in LDS; Adam moments in
@@ -386,7 +405,7 @@ k_mlp_train(float *__restrict__ params, float *__restrict__ m, float *__restrict
     const MlpLds L = mlp_lds(smem_f);
     __shared__ uint32_t s_idx[kBatch];
     __shared__ float s_sse;
-    for (uint32_t p = threadIdx.x; p < kParams; p += kMlpBS) L.W[p] = params[p];
+    for (uint32_t p = threadIdx.x; p < kParams; p += kMlpBS) L.W[lds_of(p)] = params[p];
     __syncthreads();
     const uint64_t n_steps = n_order / batch;
     float last = 0.0f;
@@ -404,7 +423,7 @@ k_mlp_train(float *__restrict__ params, float *__restrict__ m, float *__restrict
                           &s_sse);
         last = s_sse;
     }
-    for (uint32_t p = threadIdx.x; p < kParams; p += kMlpBS) params[p] = L.W[p];
+    for (uint32_t p = threadIdx.x; p < kParams; p += kMlpBS) params[p] = L.W[lds_of(p)];
     if (threadIdx.x == 0 && loss_out) *loss_out = last / (float)batch;
 }
 
@@ -418,7 +437,7 @@ k_mlp_grad(const float *__restrict__ params, const float *__restrict__ Z,
     const MlpLds L = mlp_lds(smem_f);
     __shared__ uint32_t s_idx[kBatch];
     __shared__ float s_sse;
-    for (uint32_t p = threadIdx.x; p < kParams; p += kMlpBS) L.W[p] = params[p];
+    for (uint32_t p = threadIdx.x; p < kParams; p += kMlpBS) L.W[lds_of(p)] = params[p];
     for (uint32_t s = threadIdx.x; s < N; s += kMlpBS) s_idx[s] = s;
     for (uint32_t e = threadIdx.x; e < N * kIn; e += kMlpBS) L.Zs[e] = Z[e];
     __syncthreads();
