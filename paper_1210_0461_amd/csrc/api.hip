@@ -354,9 +354,11 @@ crop_status ensure_ss_buffers(crop_ctx *ctx, uint64_t nslots, uint32_t K, uint32
 crop_status ensure_amp_buffers(crop_ctx *ctx, uint64_t nslots, SsState *A, uint8_t **votes)
 {
     const size_t a4 = (nslots * 4 + 255) / 256 * 256, a1 = (nslots + 255) / 256 * 256;
-    CK(ctx->amp_buf.ensure(3 * a4 + 2 * a1));
+    CK(ctx->amp_buf.ensure(4 * a4 + 2 * a1));
     char *p = static_cast<char *>(ctx->amp_buf.p);
     A->key = ctx->ss.key;
+    // packed keys of the t summaries (narrow runs), for the combine's lookups
+    A->key32 = reinterpret_cast<uint32_t *>(p + 3 * a4 + 2 * a1);
     A->cnt = reinterpret_cast<uint32_t *>(p);
     A->err = reinterpret_cast<uint32_t *>(p + a4);
     A->val = reinterpret_cast<float *>(p + 2 * a4);
@@ -850,6 +852,8 @@ static crop_status run_topk_impl(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
         Si.val += i * nslots;
         Si.flag += i * nslots;
         Si.nslots = nslots;
+        const bool narrow = !outer && !ctx->in.wide_keys;
+        Si.key32 = (t > 1 && narrow) ? amp.key32 + i * nslots : nullptr;
         if (pl.n_chunks) CK(outer ? launch_op_count(ctx, cnt, s)
                                   : pl.n_wg ? launch_tx_count_ranges(ctx, cnt, s)
                                             : launch_tx_count(ctx, cnt, s));
@@ -871,7 +875,10 @@ static crop_status run_topk_impl(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
     ctx->hp = hg.saved;
     const bool by_lower = ctx->topk_rank == CROP_RANK_LOWER;
     if (t > 1) {
-        CK(launch_amp_combine(ip, ctx->ss, ctx->ss_ell, nslots, min_votes, outer, amp, votes, s));
+        SsState S = ctx->ss;
+        S.key32 = amp.key32;
+        CK(launch_amp_combine(ip, S, ctx->ss_ell, nslots, min_votes, outer,
+                              !outer && !ctx->in.wide_keys, amp, votes, s));
         STAGE("majority");
         CK(launch_topk(amp, K, outer, by_lower, true, votes, tv.st, tv.hist, tv.cand, tv.sel,
                        tv.rank, tv.oi, tv.oj, tv.ou, tv.ol, tv.ov, tv.ovotes, s));

@@ -117,6 +117,9 @@ struct CsParams {
 // used, bit 1 = pinned.
 struct SsState {
     uint64_t *key = nullptr;
+    // optional copy of the used slots' keys packed as (x << 16) | y (0 for a
+    // free slot), written by the summary kernel of a narrow run when set
+    uint32_t *key32 = nullptr;
     uint32_t *cnt = nullptr;
     uint32_t *err = nullptr;
     float *val = nullptr;
@@ -274,8 +277,8 @@ hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, bool by_lower, 
                        uint32_t *sel, uint32_t *rank, uint32_t *oi, uint32_t *oj, double *ou,
                        double *ol, double *ov, uint32_t *ovotes, hipStream_t s);
 hipError_t launch_amp_combine(const CsParams &ip, const SsState &S, uint32_t ell, uint64_t nslots,
-                              uint32_t min_votes, bool outer, const SsState &A, uint8_t *votes,
-                              hipStream_t s);
+                              uint32_t min_votes, bool outer, bool narrow, const SsState &A,
+                              uint8_t *votes, hipStream_t s);
 
 size_t tx_count_smem_bytes(uint32_t NB, uint32_t max_items);
 

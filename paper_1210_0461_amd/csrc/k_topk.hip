@@ -265,7 +265,8 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
             const KeyT *__restrict__ keys, const float *__restrict__ vals, uint32_t NB,
             uint32_t nbk, uint32_t ell, HashParams hp, uint64_t PB, bool narrow,
             uint32_t *counter, uint64_t *__restrict__ g_key, uint32_t *__restrict__ g_cnt,
-            uint32_t *__restrict__ g_err, float *__restrict__ g_val, uint8_t *__restrict__ g_flag)
+            uint32_t *__restrict__ g_err, float *__restrict__ g_val, uint8_t *__restrict__ g_flag,
+            uint32_t *__restrict__ g_key32)
 {
     static_assert(G == 16 || G == 32 || G == 64, "group width");
     static_assert((MB & (MB - 1)) == 0, "micro-batch is a power of two");
@@ -633,6 +634,8 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                 g = (uint64_t)s_k[s];
             }
             g_key[g0 + s] = (s_f[s] & kUsed) ? g : 0;
+            if constexpr (sizeof(KeyT) == 4)
+                if (g_key32) g_key32[g0 + s] = (s_f[s] & kUsed) ? (uint32_t)s_k[s] : 0u;
             g_cnt[g0 + s] = s_c[s];
             g_err[g0 + s] = s_e[s];
             if (OUTER) g_val[g0 + s] = s_v[s];
@@ -941,7 +944,8 @@ k_topk_emit(const uint64_t *__restrict__ key, RankBy rv, const uint32_t *__restr
 template <bool OUTER>
 __global__ void __launch_bounds__(256)
 k_amp_combine(CsParams ip, uint32_t ell, uint64_t ns, uint32_t min_votes,
-              const uint64_t *__restrict__ key, const uint32_t *__restrict__ cnt,
+              const uint64_t *__restrict__ key, const uint32_t *__restrict__ key32,
+              const uint32_t *__restrict__ cnt,
               const uint32_t *__restrict__ err, const float *__restrict__ val,
               const uint8_t *__restrict__ flag, uint32_t *__restrict__ up,
               uint32_t *__restrict__ lo, float *__restrict__ mv, uint8_t *__restrict__ oflag,
@@ -953,8 +957,17 @@ k_amp_combine(CsParams ip, uint32_t ell, uint64_t ns, uint32_t min_votes,
         oflag[g] = 0;
         if (!(flag[g] & kUsed)) continue;
         const uint32_t inst = (uint32_t)(g / ns);
-        const uint64_t k = key[g];
-        const uint32_t x = (uint32_t)(k >> 32), y = (uint32_t)k;
+        uint32_t x, y;
+        if (key32) {
+            const uint32_t p32 = key32[g];
+            x = p32 >> 16;
+            y = p32 & 0xFFFFu;
+        } else {
+            const uint64_t k64 = key[g];
+            x = (uint32_t)(k64 >> 32);
+            y = (uint32_t)k64;
+        }
+        const uint64_t k = ((uint64_t)x << 32) | y;
         uint32_t v = 0, u = 0xFFFFFFFFu, l = 0;
         float sv[kCsMaxInstances];
         bool own = true;
@@ -967,16 +980,48 @@ k_amp_combine(CsParams ip, uint32_t ell, uint64_t ns, uint32_t min_votes,
                 // keys first: a free slot's key is 0, so its flag is read only
                 // when the entry's own key is 0 (outer products' (0, 0)).  The
                 // keys are loaded eight at a time before any is compared, so
-                // the loads of a bucket overlap.
-                for (uint32_t r0 = 0; r0 < ell && q == ~0ull; r0 += 8) {
-                    uint64_t kb[8];
+                // the loads of a bucket overlap; narrow runs compare the
+                // packed 32-bit copies (half the bytes per bucket).
+                if (key32 && (ell & 3u) == 0) {
+                    // 16-byte loads: one request per four keys (base and r0
+                    // are multiples of four when ell is)
+                    const uint32_t k32 = (x << 16) | y;
+                    for (uint32_t r0 = 0; r0 < ell && q == ~0ull; r0 += 8) {
+                        uint4 kb[2];
+                        kb[0] = *reinterpret_cast<const uint4 *>(key32 + base + r0);
+                        kb[1] = r0 + 4 < ell
+                                    ? *reinterpret_cast<const uint4 *>(key32 + base + r0 + 4)
+                                    : make_uint4(~k32, ~k32, ~k32, ~k32);
+                        const uint32_t kw[8] = {kb[0].x, kb[0].y, kb[0].z, kb[0].w,
+                                                kb[1].x, kb[1].y, kb[1].z, kb[1].w};
 #pragma unroll
-                    for (uint32_t t = 0; t < 8; ++t)
-                        kb[t] = r0 + t < ell ? key[base + r0 + t] : ~k;
+                        for (uint32_t t = 0; t < 8; ++t)
+                            if (q == ~0ull && kw[t] == k32 && (flag[base + r0 + t] & kUsed))
+                                q = base + r0 + t;
+                    }
+                } else if (key32) {
+                    const uint32_t k32 = (x << 16) | y;
+                    for (uint32_t r0 = 0; r0 < ell && q == ~0ull; r0 += 8) {
+                        uint32_t kb[8];
 #pragma unroll
-                    for (uint32_t t = 0; t < 8; ++t)
-                        if (q == ~0ull && kb[t] == k && (flag[base + r0 + t] & kUsed))
-                            q = base + r0 + t;
+                        for (uint32_t t = 0; t < 8; ++t)
+                            kb[t] = r0 + t < ell ? key32[base + r0 + t] : ~k32;
+#pragma unroll
+                        for (uint32_t t = 0; t < 8; ++t)
+                            if (q == ~0ull && kb[t] == k32 && (flag[base + r0 + t] & kUsed))
+                                q = base + r0 + t;
+                    }
+                } else {
+                    for (uint32_t r0 = 0; r0 < ell && q == ~0ull; r0 += 8) {
+                        uint64_t kb[8];
+#pragma unroll
+                        for (uint32_t t = 0; t < 8; ++t)
+                            kb[t] = r0 + t < ell ? key[base + r0 + t] : ~k;
+#pragma unroll
+                        for (uint32_t t = 0; t < 8; ++t)
+                            if (q == ~0ull && kb[t] == k && (flag[base + r0 + t] & kUsed))
+                                q = base + r0 + t;
+                    }
                 }
                 if (q == ~0ull) continue;
                 if (j < inst) {
@@ -1078,12 +1123,12 @@ static void launch_ss_k(const crop_ctx *c, const SsState &S, uint32_t nbk, uint6
         hipLaunchKernelGGL((k_ss_groups<G, KeyT, OUTER, MB, true>), dim3(grid), dim3(bs), sm, s,
                            c->bin_off.as<uint32_t>(), c->bin_order.as<uint32_t>(), keys, vals,
                            pl.NB, nbk, ell, c->hp, PB, narrow, c->counter.as<uint32_t>(), S.key,
-                           S.cnt, S.err, S.val, S.flag);
+                           S.cnt, S.err, S.val, S.flag, S.key32);
     else
         hipLaunchKernelGGL((k_ss_groups<G, KeyT, OUTER, MB, false>), dim3(grid), dim3(bs), sm, s,
                            c->bin_off.as<uint32_t>(), c->bin_order.as<uint32_t>(), keys, vals,
                            pl.NB, nbk, ell, c->hp, PB, narrow, c->counter.as<uint32_t>(), S.key,
-                           S.cnt, S.err, S.val, S.flag);
+                           S.cnt, S.err, S.val, S.flag, S.key32);
 }
 
 template <int G>
@@ -1155,18 +1200,19 @@ hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, bool by_lower, 
 // Combined entries of t instances' summaries S (instance i at slots
 // [i * nslots, (i + 1) * nslots)) into A (same indexing, keys shared with S).
 hipError_t launch_amp_combine(const CsParams &ip, const SsState &S, uint32_t ell, uint64_t nslots,
-                              uint32_t min_votes, bool outer, const SsState &A, uint8_t *votes,
-                              hipStream_t s)
+                              uint32_t min_votes, bool outer, bool narrow, const SsState &A,
+                              uint8_t *votes, hipStream_t s)
 {
+    const uint32_t *k32 = narrow ? S.key32 : nullptr;
     const uint32_t g = grid_for(nslots * ip.t, 8192);
     if (outer)
         hipLaunchKernelGGL(k_amp_combine<true>, dim3(g), dim3(256), 0, s, ip, ell, nslots,
-                           min_votes, S.key, S.cnt, S.err, S.val, S.flag, A.cnt, A.err, A.val,
-                           A.flag, votes);
+                           min_votes, S.key, k32, S.cnt, S.err, S.val, S.flag, A.cnt, A.err,
+                           A.val, A.flag, votes);
     else
         hipLaunchKernelGGL(k_amp_combine<false>, dim3(g), dim3(256), 0, s, ip, ell, nslots,
-                           min_votes, S.key, S.cnt, S.err, S.val, S.flag, A.cnt, A.err, A.val,
-                           A.flag, votes);
+                           min_votes, S.key, k32, S.cnt, S.err, S.val, S.flag, A.cnt, A.err,
+                           A.val, A.flag, votes);
     return hipGetLastError();
 }
 
