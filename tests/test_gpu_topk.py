@@ -247,3 +247,15 @@ def test_bucket_with_more_than_2_pow_26_terms(crop, ctx):
         if f == len(heavy_rows):
             assert k in mon
     check_topk_is_summary_topk(s, top, 16)
+
+
+@pytest.mark.parametrize("P,C,ell", [(1, 64, 16), (2, 96, 2), (8, 8192, 16)])
+def test_wide_item_ids(crop, ctx, P, C, ell):
+    """More than 2^16 item ids: the summaries hold 64-bit keys.  The first
+    two settings give bins of one bucket, the last bins of two buckets."""
+    st = datagen.transactions(3000, 200_000, 0.9, 8.0, 40, datagen.Raw(78), "wide")
+    K = 50
+    s, top = run_tx_topk(crop, ctx, st, P, C, ell, K)
+    exact, _ = exact_map(st)
+    check_invariants(s, exact, SEED)
+    check_topk_is_summary_topk(s, top, K)
