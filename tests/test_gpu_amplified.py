@@ -147,6 +147,30 @@ def test_small_config_invariants_and_majority(crop, ctx, t, m):
     assert np.all(np.isin(keys[g >= m], rep))
 
 
+@pytest.mark.parametrize("C,ell,wide", [(2048, 2, False), (1536, 6, False), (2048, 4, True)])
+def test_bucket_widths_and_wide_ids(crop, ctx, C, ell, wide):
+    """Bucket widths that are not a multiple of four (the combine compares
+    packed keys one at a time) and more than 2^16 item ids (64-bit keys)."""
+    if wide:
+        st = datagen.transactions(3000, 200_000, 0.9, 8.0, 40, datagen.Raw(79), "wide")
+    else:
+        st = datagen.config_small()
+    keys, f, _ = exact_tx(st)
+    P, t, m, K = 2, 5, 3, 100000
+    sums, top, votes = run_amp(crop, ctx, st, P, C, ell, K, t, m)
+    exact = dict(zip(keys.tolist(), f.tolist()))
+    seeds = seeds_of(t)
+    for s, sd in zip(sums, seeds):
+        check_invariants(s, exact, sd)
+    rep = check_report(top, votes, sums, m, K)
+    got = pack(top[0], top[1])
+    pos = np.minimum(np.searchsorted(keys, got), keys.shape[0] - 1)
+    assert np.array_equal(keys[pos], got)
+    assert np.all(top[3] <= f[pos]) and np.all(f[pos] <= top[2])
+    g = guaranteed_votes(keys, f, seeds, P, C // ell, ell)
+    assert np.all(np.isin(keys[g >= m], rep))
+
+
 def test_exact_regime_equals_oracle(crop, ctx):
     """At most ell distinct entries per bucket: every summary is exact, so
     the GPU report equals the oracle's majority report of its own
