@@ -1100,10 +1100,11 @@ size_t ss_bins_smem_bytes(uint32_t nbk, uint32_t ell, bool wide_key, bool outer,
 
 uint32_t ss_group_width(uint32_t ell) { return ell <= 16 ? 16u : ell <= 32 ? 32u : 64u; }
 
-// 256 threads whatever the number of buckets of a bin: the merge and
-// grouping phases use every lane, and a bin of fewer buckets than groups
-// leaves only the update phase partly idle (measured faster than workgroups
-// sized to the bin's groups: P = 1 with 1,024 buckets 26 -> 18 ms).
+// Workgroup size of the summary kernel, whatever the group width: 256
+// threads for bins of one bucket (the merge and grouping phases use every
+// lane while one group runs the chain; measured faster than workgroups sized
+// to the bin's groups and than 512 threads), 512 for bins of several
+// buckets (twice the wavefronts per CU for the latency-bound phases).
 uint32_t ss_block_threads(uint32_t nbk, uint32_t ell)
 {
     (void)ell;
