@@ -566,53 +566,64 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                     // G updates per LDS load: lane j holds update p0 + j and
                     // each update is broadcast from its lane in turn, so the
                     // serial chain waits on LDS once per G updates
-                    for (uint32_t p0 = e0; p0 < e1; p0 += G) {
-                        const uint32_t q = p0 + j;
-                        const KeyT bk = q < e1 ? t_k[q] : (KeyT)0;
-                        const uint32_t bw = q < e1 ? t_w[q] : 0u;
-                        const float bv = (OUTER && q < e1) ? t_v[q] : 0.0f;
-                        const uint32_t cnt = min((uint32_t)G, e1 - p0);
-                        for (uint32_t i = 0; i < cnt; ++i) {
-                            KeyT key;
-                            if constexpr (sizeof(KeyT) == 8) {
-                                const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane(
-                                    (int)(uint32_t)bk, (int)i);
-                                const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane(
-                                    (int)(uint32_t)((uint64_t)bk >> 32), (int)i);
-                                key = (KeyT)(((uint64_t)hi << 32) | lo);
-                            } else {
-                                key = (KeyT)(uint32_t)__builtin_amdgcn_readlane((int)bk, (int)i);
+                    // (the trip count is read into a scalar register and the
+                    // two update forms get loops of their own, so the loop
+                    // control stays scalar)
+                    auto chain = [&](auto apply) {
+                        for (uint32_t p0 = e0; p0 < e1; p0 += G) {
+                            const uint32_t q = p0 + j;
+                            const KeyT bk = q < e1 ? t_k[q] : (KeyT)0;
+                            const uint32_t bw = q < e1 ? t_w[q] : 0u;
+                            const float bv = (OUTER && q < e1) ? t_v[q] : 0.0f;
+                            const uint32_t cnt = (uint32_t)__builtin_amdgcn_readfirstlane(
+                                (int)min((uint32_t)G, e1 - p0));
+                            for (uint32_t i = 0; i < cnt; ++i) {
+                                KeyT key;
+                                if constexpr (sizeof(KeyT) == 8) {
+                                    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane(
+                                        (int)(uint32_t)bk, (int)i);
+                                    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane(
+                                        (int)(uint32_t)((uint64_t)bk >> 32), (int)i);
+                                    key = (KeyT)(((uint64_t)hi << 32) | lo);
+                                } else {
+                                    key = (KeyT)(uint32_t)__builtin_amdgcn_readlane((int)bk,
+                                                                                    (int)i);
+                                }
+                                const uint32_t w =
+                                    (uint32_t)__builtin_amdgcn_readlane((int)bw, (int)i);
+                                float val = 0.0f;
+                                if (OUTER)
+                                    val = __int_as_float(
+                                        __builtin_amdgcn_readlane(__float_as_int(bv), (int)i));
+                                apply(key, w, val);
                             }
-                            const uint32_t w =
-                                (uint32_t)__builtin_amdgcn_readlane((int)bw, (int)i);
-                            float val = 0.0f;
-                            if (OUTER)
-                                val = __int_as_float(
-                                    __builtin_amdgcn_readlane(__float_as_int(bv), (int)i));
-                            if (pack)
-                                step_packed(key, w);
-                            else
-                                step(key, w, val);
                         }
-                    }
+                    };
+                    if (pack)
+                        chain([&](KeyT key, uint32_t w, float) { step_packed(key, w); });
+                    else
+                        chain([&](KeyT key, uint32_t w, float val) { step(key, w, val); });
                 } else {
-                    KeyT nk = t_k[e0];
-                    uint32_t nw = t_w[e0];
-                    float nv = OUTER ? t_v[e0] : 0.0f;
-                    for (uint32_t p = e0; p < e1; ++p) {
-                        const KeyT key = nk;
-                        const uint32_t w = nw;
-                        const float val = nv;
-                        if (p + 1 < e1) {  // prefetch the next update
-                            nk = t_k[p + 1];
-                            nw = t_w[p + 1];
-                            if (OUTER) nv = t_v[p + 1];
+                    auto chain = [&](auto apply) {
+                        KeyT nk = t_k[e0];
+                        uint32_t nw = t_w[e0];
+                        float nv = OUTER ? t_v[e0] : 0.0f;
+                        for (uint32_t p = e0; p < e1; ++p) {
+                            const KeyT key = nk;
+                            const uint32_t w = nw;
+                            const float val = nv;
+                            if (p + 1 < e1) {  // prefetch the next update
+                                nk = t_k[p + 1];
+                                nw = t_w[p + 1];
+                                if (OUTER) nv = t_v[p + 1];
+                            }
+                            apply(key, w, val);
                         }
-                        if (pack)
-                            step_packed(key, w);
-                        else
-                            step(key, w, val);
-                    }
+                    };
+                    if (pack)
+                        chain([&](KeyT key, uint32_t w, float) { step_packed(key, w); });
+                    else
+                        chain([&](KeyT key, uint32_t w, float val) { step(key, w, val); });
                 }
                 if (real) {
                     s_k[sidx] = k;
