@@ -546,20 +546,27 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                 constexpr uint32_t kPackLim = 1u << (30 - LOGG);
                 const uint32_t cmax0 = __builtin_amdgcn_readfirstlane(s_cmax);  // uniform
                 const bool pack = !OUTER && (uint64_t)cmax0 + (k1 - k0) < kPackLim - 1;
+                // (written as chains of single-condition selects: conditions
+                // joined with && become scalar mask operations whose round
+                // trips through scalar registers slow the serial chain)
+                const uint32_t notreal = real ? 0u : 0xFFFFFFFFu;
                 auto step_packed = [&](const KeyT key, const uint32_t w) {
-                    const bool used = (f & kUsed) != 0;
-                    uint32_t mine = (real && used && !(f & kPinned))
-                                        ? 0x80000000u | (c << LOGG) | j
-                                        : 0xFFFFFFFFu;
-                    mine = (real && !used) ? 0x40000000u | j : mine;
-                    if constexpr (!ONE) mine = (real && used && k == key) ? j : mine;
+                    const uint32_t offer_used =
+                        (f & kPinned) ? 0xFFFFFFFFu : (0x80000000u | (c << LOGG) | j);
+                    uint32_t mine = (f & kUsed) ? offer_used : (0x40000000u | j);
+                    if constexpr (!ONE) mine = (k == key) ? ((f & kUsed) ? j : mine) : mine;
+                    mine |= notreal;
                     const uint32_t mn = group_min<G>(mine);
-                    const bool win = mine == mn && mine != 0xFFFFFFFFu;
-                    const bool hit = mn < 0x40000000u;
-                    const bool fr = !hit && mn < 0x80000000u;
-                    e = (win && !hit) ? (fr ? 0u : c) : e;
-                    k = (win && !hit) ? key : k;
-                    c = win ? (fr ? w : c + w) : c;
+                    // the winner offered the minimum; nobody wins when every
+                    // offer is all ones (then mn + 1 wraps to 0)
+                    const uint32_t tag = mine == mn ? mn + 1u : 0u;
+                    const bool win = tag != 0u;
+                    const uint32_t kind = mn >> 30;  // 0 hit, 1 free slot, 2 or 3 evict
+                    const uint32_t cw = kind == 1u ? w : c + w;
+                    const uint32_t ew = kind == 1u ? 0u : c;
+                    e = win ? (kind == 0u ? e : ew) : e;
+                    k = win ? (kind == 0u ? k : key) : k;
+                    c = win ? cw : c;
                     f = win ? (uint8_t)(f | kUsed) : f;
                 };
                 if constexpr (ONE) {
