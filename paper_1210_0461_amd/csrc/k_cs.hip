@@ -217,15 +217,15 @@ hipError_t launch_cs_bins(const crop_ctx *c, const HashParams &hp, uint64_t PB, 
     const size_t sm = (size_t)nbk * 4;
     const uint32_t grid = std::min<uint32_t>(NB, 8192);
     if (c->in.mode == Mode::Outer)
-        hipLaunchKernelGGL((k_cs_bins<256, uint64_t, true>), dim3(grid), dim3(256), sm, s,
+        hipLaunchKernelGGL((k_cs_bins<512, uint64_t, true>), dim3(grid), dim3(512), sm, s,
                            c->bin_off.as<uint32_t>(), c->keys.as<uint64_t>(),
                            c->vals.as<float>(), hp, PB, nbk, NB, out);
     else if (c->in.wide_keys)
-        hipLaunchKernelGGL((k_cs_bins<256, uint64_t, false>), dim3(grid), dim3(256), sm, s,
+        hipLaunchKernelGGL((k_cs_bins<512, uint64_t, false>), dim3(grid), dim3(512), sm, s,
                            c->bin_off.as<uint32_t>(), c->keys.as<uint64_t>(), nullptr, hp, PB,
                            nbk, NB, out);
     else
-        hipLaunchKernelGGL((k_cs_bins<256, uint32_t, false>), dim3(grid), dim3(256), sm, s,
+        hipLaunchKernelGGL((k_cs_bins<512, uint32_t, false>), dim3(grid), dim3(512), sm, s,
                            c->bin_off.as<uint32_t>(), c->keys.as<uint32_t>(), nullptr, hp, PB,
                            nbk, NB, out);
     return hipGetLastError();
