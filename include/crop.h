@@ -176,7 +176,10 @@ crop_status crop_run_topk(crop_ctx *ctx, uint32_t K);
 /* As crop_run_topk, with learned seeding: seeds (device arrays sx, sy of ns
  * transaction pairs x < y, highest priority first) are pinned into their
  * buckets before the stream, at most r_max per bucket (r_max < ell), in the
- * given order.  A pinned slot is never evicted, so its count is exact. */
+ * given order.  A pinned slot is never evicted, so its count is exact.
+ * The seeds are checked on the device first (this call synchronizes once
+ * for that): a pair without x < y < n_items returns CROP_E_INPUT with the
+ * first offending seed in crop_last_error_index, and nothing runs. */
 crop_status crop_run_topk_seeded(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
                                  const uint32_t *sy, uint64_t ns, uint32_t r_max);
 
@@ -236,6 +239,15 @@ crop_status crop_read_topk_votes(crop_ctx *ctx, uint32_t *votes, uint64_t cap,
 crop_status crop_read_summary(crop_ctx *ctx, uint32_t *i, uint32_t *j, double *cnt,
                               double *err, double *value, uint8_t *flags, uint64_t cap,
                               uint64_t *written);
+
+/* The consistent hash of query pairs under the context's seed and P
+ * (Section 5: every processor can compute the owner of any entry from the
+ * broadcast hash description): h[q] = (h_a(qx[q]) + h_b(qy[q])) mod 2^32 and
+ * part[q] = (h[q] * P) >> 32.  qx, qy, h, part are device arrays of n
+ * elements; h or part may be NULL.  Any 32-bit ids are accepted.
+ * Asynchronous on the context stream. */
+crop_status crop_hash_pairs(crop_ctx *ctx, const uint32_t *qx, const uint32_t *qy, uint64_t n,
+                            uint32_t *h, uint32_t *part);
 
 /* Wait for all work enqueued by this context. */
 crop_status crop_synchronize(crop_ctx *ctx);

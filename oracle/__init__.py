@@ -270,33 +270,6 @@ def op_spacesaving(op, seed: int, P: int, B: int, ell: int):
                 cnt=cnt, err=err, val=val, ell=ell, P=P, B=B)
 
 
-def ss_bounds(summary, qx, qy, seed: int):
-    """Upper and lower bound of each queried entry (Section 4): the counter
-    if monitored, else the minimum counter of its (full) bucket as the upper
-    bound and 0 as the lower bound; an unfilled bucket gives 0 and 0."""
-    prm_P, prm_B, ell = summary["P"], summary["B"], summary["ell"]
-    _, _, h, _ = hash_many(seed, qx, qy, 1)
-    bk = bucket_of(h, prm_P, prm_B).astype(np.int64)
-    kx = summary["x"].reshape(-1, ell)
-    ky = summary["y"].reshape(-1, ell)
-    used = summary["used"].reshape(-1, ell)
-    pinned = summary["pinned"].reshape(-1, ell)
-    cnt = summary["cnt"].reshape(-1, ell)
-    err = summary["err"].reshape(-1, ell)
-    up = np.zeros(len(bk))
-    lo = np.zeros(len(bk))
-    for n, b in enumerate(bk):
-        hit = used[b] & (kx[b] == qx[n]) & (ky[b] == qy[n])
-        if hit.any():
-            s = int(np.flatnonzero(hit)[0])
-            up[n] = cnt[b, s]
-            lo[n] = cnt[b, s] - err[b, s]
-        elif used[b].all():
-            free = ~pinned[b]
-            up[n] = cnt[b][free].min() if free.any() else 0.0
-    return up, lo
-
-
 def amplified_report(summaries, min_votes: int):
     """Majority reporting over t independent instances (Section 6, the proof
     of Theorem 2: run t copies with independent hash functions and report the

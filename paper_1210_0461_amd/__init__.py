@@ -125,6 +125,7 @@ _SIGS.update({
     "crop_mlp_loss": ([_vp, _vp, _vp], _i32),
     "crop_mlp_score": ([_vp, _vp, _vp, _u64, _vp], _i32),
     "crop_select_seeds": ([_vp, _vp, _vp, _vp, _u64, _u32, _vp, _vp], _i32),
+    "crop_hash_pairs": ([_vp, _vp, _vp, _u64, _vp, _vp], _i32),
 })
 
 # Entry points bound only when the loaded library exports them.
@@ -566,6 +567,13 @@ def crop_select_seeds(ctx, score, cx, cy, R: int, sx, sy) -> None:
     _check(ctx, _lib.crop_select_seeds(ctx, _dev(score, "score"), _dev(cx, "cx"),
                                        _dev(cy, "cy"), _len(score), R, _dev(sx, "sx"),
                                        _dev(sy, "sy")))
+
+
+def crop_hash_pairs(ctx, qx, qy, h=None, part=None) -> None:
+    """h[q], part[q] of the pairs (qx[q], qy[q]); device tensors, either
+    output may be None."""
+    _check(ctx, _lib.crop_hash_pairs(ctx, _dev(qx, "qx"), _dev(qy, "qy"), _len(qx),
+                                     _dev(h, "h"), _dev(part, "part")))
 
 
 def crop_synchronize(ctx) -> None:

@@ -53,6 +53,22 @@ crop_status validate_on_device(crop_ctx *ctx, const uint32_t *v_off, uint64_t K,
     return CROP_OK;
 }
 
+// First query pair breaking x < y < n_items, or -1 (synchronizes).
+crop_status check_pairs_on_device(crop_ctx *ctx, const uint32_t *qx, const uint32_t *qy,
+                                  uint64_t n, uint32_t n_items, int64_t *bad_out)
+{
+    CK(ctx->scratch.ensure(64));
+    auto *bad = ctx->scratch.as<unsigned long long>();
+    unsigned long long init = ~0ull;
+    CK(hipMemcpyAsync(bad, &init, sizeof(init), hipMemcpyHostToDevice, ctx->stream));
+    CK(launch_check_pairs(qx, qy, n, n_items, bad, ctx->stream));
+    unsigned long long got = 0;
+    CK(hipMemcpyAsync(&got, bad, sizeof(got), hipMemcpyDeviceToHost, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    *bad_out = got == ~0ull ? -1 : (int64_t)got;
+    return CROP_OK;
+}
+
 crop_status check_offsets(crop_ctx *ctx, const std::vector<uint32_t> &off, uint64_t nnz,
                           const char *name)
 {
@@ -183,6 +199,8 @@ crop_status plan_tx(crop_ctx *ctx, uint32_t S_force = 0)
         pl.n_wg = (uint32_t)std::min<uint64_t>(pl.n_chunks, (uint64_t)cus * per_cu);
     }
     pl.G = std::max<uint32_t>(1, std::min<uint32_t>(64, pl.n_wg ? pl.n_wg / 16 : pl.n_chunks));
+    if (!tx_launch_layouts_ok(pl.NB, pl.max_items, pl.stage_cap, in.wide_keys))
+        return fail(ctx, CROP_E_UNSUPPORTED, "chunk image does not fit its LDS layout");
     return CROP_OK;
 }
 
@@ -521,6 +539,7 @@ crop_status crop_set_seed(crop_ctx *ctx, uint64_t seed)
     ctx->seed = seed;
     ctx->hp = make_hash_params(seed);
     ctx->result = Result::None;
+    batch_invalidate_graph(ctx);  // a captured batch graph holds the old parameters
     return CROP_OK;
 }
 
@@ -801,6 +820,18 @@ static crop_status run_topk_impl(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
         return fail(ctx, CROP_E_ARG, "r_max must be below the slots per bucket");
     DeviceGuard g(ctx->device);
     ctx->result = Result::None;
+    if (ns) {
+        // a seed must be a pair the stream can hold: a key outside x < y <
+        // n_items would be pinned where no term ever reaches it
+        int64_t bad = -1;
+        crop_status cs = check_pairs_on_device(ctx, sx, sy, ns, ctx->in.n_items, &bad);
+        if (cs != CROP_OK) return cs;
+        if (bad >= 0) {
+            ctx->err_index = bad;
+            return fail(ctx, CROP_E_INPUT,
+                        "seed " + std::to_string(bad) + ": need x < y < n_items");
+        }
+    }
     uint32_t nbk = 0;
     uint64_t PB = 0;
     crop_status st = plan_ss(ctx, &nbk, &PB);
@@ -1317,6 +1348,15 @@ crop_status crop_select_seeds(crop_ctx *ctx, const float *score, const uint32_t 
     if (R > n) return fail(ctx, CROP_E_ARG, "R exceeds the candidate count");
     DeviceGuard g(ctx->device);
     CK(launch_select_seeds(score, cx, cy, (uint32_t)n, R, sx, sy, ctx->stream));
+    return CROP_OK;
+}
+
+crop_status crop_hash_pairs(crop_ctx *ctx, const uint32_t *qx, const uint32_t *qy, uint64_t n,
+                            uint32_t *h, uint32_t *part)
+{
+    if (!ctx || (n && (!qx || !qy))) return CROP_E_ARG;
+    DeviceGuard g(ctx->device);
+    CK(launch_hash_pairs(qx, qy, n, ctx->hp, ctx->P, h, part, ctx->stream));
     return CROP_OK;
 }
 

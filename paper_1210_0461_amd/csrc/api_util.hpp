@@ -91,10 +91,13 @@ inline hipError_t place(const T *src, size_t n, crop_mem where, crop_own own, De
 uint64_t tx_terms_of(const std::vector<uint32_t> &off);
 crop_status validate_on_device(crop_ctx *ctx, const uint32_t *v_off, uint64_t K,
                                const uint32_t *idx, uint64_t nnz, uint32_t n, int64_t *bad_out);
+crop_status check_pairs_on_device(crop_ctx *ctx, const uint32_t *qx, const uint32_t *qy,
+                                  uint64_t n, uint32_t n_items, int64_t *bad_out);
 crop_status check_offsets(crop_ctx *ctx, const std::vector<uint32_t> &off, uint64_t nnz,
                           const char *name);
 void reset_input(crop_ctx *ctx);
 void reset_batch(crop_ctx *ctx);
+void batch_invalidate_graph(crop_ctx *ctx);
 crop_status ensure_route_buffers(crop_ctx *ctx, size_t key_bytes, bool sums);
 crop_status require_exact(crop_ctx *ctx);
 crop_status run_begin(crop_ctx *ctx);

@@ -120,7 +120,8 @@ crop_status plan_batch(crop_ctx *ctx, uint32_t tpb, uint32_t R)
         for (uint32_t k = 0; k < b.P[s]; ++k) bin_stream[b.bin_base[s] + k] = s;
     }
     const uint32_t stage_cap = 0;  // direct scatter writes (as for single streams)
-    if (tx_scatter_smem_bytes(NBmax, mi, 0, in.wide_keys) > kStageBudget)
+    if (tx_scatter_smem_bytes(NBmax, mi, 0, in.wide_keys) > kStageBudget ||
+        !tx_launch_layouts_ok(NBmax, mi, stage_cap, in.wide_keys))
         return fail(ctx, CROP_E_UNSUPPORTED, "routing bins and chunk do not fit in LDS");
     CK(b.d_crow.ensure(crow.size() * 4));
     CK(b.d_cstream.ensure(std::max<size_t>(cstream.size(), 1) * 4));
@@ -213,6 +214,10 @@ crop_status timed_eager_run(crop_ctx *ctx, float *ms)
 }
 
 }  // namespace
+
+// The captured graph holds the kernels' arguments by value (the hash
+// parameters among them): a change of any of them must capture again.
+void batch_invalidate_graph(crop_ctx *ctx) { drop_graph(ctx->batch); }
 
 void reset_batch(crop_ctx *ctx)
 {

@@ -13,6 +13,7 @@
 #include "crop_device.hpp"
 #include "crop_hash.hpp"
 #include "crop_internal.hpp"
+#include "crop_layout.hpp"
 
 namespace crop {
 
@@ -84,26 +85,6 @@ __device__ inline void enum_tx(uint32_t m, const TxLds &L, const HashParams &hp,
     }
 }
 
-// LDS layout of a chunk image after `lead` words, in 32-bit words: xh (two
-// words per entry, 8-byte aligned), then w and perm (u16 each, both padded to
-// an even count so that bucket stays 4-byte aligned for its atomics), then
-// the 64 bucket words.
-struct TxLayout {
-    size_t xh, w, perm, bucket, end;  // word offsets
-};
-
-__host__ __device__ inline TxLayout tx_layout(uint32_t lead, uint32_t max_items)
-{
-    TxLayout t;
-    const size_t half = (max_items + 1) / 2;  // words of one padded u16 array
-    t.xh = (lead + 1) & ~1u;
-    t.w = t.xh + 2 * (size_t)max_items;
-    t.perm = t.w + half;
-    t.bucket = t.perm + half;
-    t.end = t.bucket + 64;
-    return t;
-}
-
 __device__ inline TxLds tx_lds(uint32_t *smem, uint32_t lead, uint32_t max_items)
 {
     const TxLayout t = tx_layout(lead, max_items);
@@ -113,11 +94,6 @@ __device__ inline TxLds tx_lds(uint32_t *smem, uint32_t lead, uint32_t max_items
     L.perm = reinterpret_cast<uint16_t *>(smem + t.perm);
     L.bucket = smem + t.bucket;
     return L;
-}
-
-__host__ __device__ inline size_t tx_lds_words(uint32_t lead, uint32_t max_items)
-{
-    return tx_layout(lead, max_items).end;
 }
 
 template <class KeyT>

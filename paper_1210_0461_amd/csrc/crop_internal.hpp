@@ -226,6 +226,13 @@ hipError_t launch_validate_outer(const uint32_t *v_off, uint64_t K, const uint32
                                  uint64_t nnz, uint32_t n, unsigned long long *bad,
                                  hipStream_t s);
 
+// *bad <- min(*bad, first q whose pair breaks x < y < n_items).
+hipError_t launch_check_pairs(const uint32_t *qx, const uint32_t *qy, uint64_t n,
+                              uint32_t n_items, unsigned long long *bad, hipStream_t s);
+hipError_t launch_hash_pairs(const uint32_t *qx, const uint32_t *qy, uint64_t n,
+                             const HashParams &hp, uint32_t P, uint32_t *h, uint32_t *part,
+                             hipStream_t s);
+
 hipError_t launch_tx_count(const crop_ctx *c, uint32_t *cnt, hipStream_t s);
 // Range kernels: n_wg workgroups, each over a contiguous range of chunks;
 // the count matrix is [n_wg x NB].
@@ -281,6 +288,7 @@ hipError_t launch_amp_combine(const CsParams &ip, const SsState &S, uint32_t ell
                               uint8_t *votes, hipStream_t s);
 
 size_t tx_count_smem_bytes(uint32_t NB, uint32_t max_items);
+bool tx_launch_layouts_ok(uint32_t NB, uint32_t max_items, uint32_t cap, bool wide);
 
 // Count-Sketch (k_cs.hip).
 hipError_t launch_cs_clear(void *cs, uint64_t words, hipStream_t s);

@@ -1,0 +1,59 @@
+// LDS layout of a staged chunk of transactions, shared by the device code
+// (crop_enum.hpp) and the host's launch checks.  Plain C++: it also builds
+// with a host compiler, so its alignment and bounds can be tested without a
+// GPU.
+#pragma once
+#include <stddef.h>
+#include <stdint.h>
+
+#ifndef __HIPCC__
+#ifndef __host__
+#define __host__
+#endif
+#ifndef __device__
+#define __device__
+#endif
+#endif
+
+namespace crop {
+
+// Word offsets of a chunk image placed after `lead` 32-bit words: xh (two
+// words per entry, 8-byte aligned for its 64-bit LDS loads), then w and perm
+// (u16 each, each padded to an even count of u16 so the next array starts on
+// a word), then the 64 bucket words that take 32-bit LDS atomics.
+struct TxLayout {
+    size_t xh, w, perm, bucket, end;
+};
+
+__host__ __device__ inline TxLayout tx_layout(uint32_t lead, uint32_t max_items)
+{
+    TxLayout t;
+    const size_t half = ((size_t)max_items + 1) / 2;  // words of one padded u16 array
+    t.xh = ((size_t)lead + 1) & ~(size_t)1;
+    t.w = t.xh + 2 * (size_t)max_items;
+    t.perm = t.w + half;
+    t.bucket = t.perm + half;
+    t.end = t.bucket + 64;
+    return t;
+}
+
+__host__ __device__ inline size_t tx_lds_words(uint32_t lead, uint32_t max_items)
+{
+    return tx_layout(lead, max_items).end;
+}
+
+// The properties the kernels rely on, checked on the host before a launch
+// with `smem_bytes` of dynamic LDS: 64-bit alignment of xh, no overlap of
+// the arrays (each at least as long as its entries need), and the whole
+// image inside the dynamic allocation.
+__host__ __device__ inline bool tx_layout_ok(uint32_t lead, uint32_t max_items, size_t smem_bytes)
+{
+    const TxLayout t = tx_layout(lead, max_items);
+    if (t.xh % 2 != 0 || t.xh < lead) return false;
+    if (t.w < t.xh + 2 * (size_t)max_items) return false;
+    if (2 * (t.perm - t.w) < max_items || 2 * (t.bucket - t.perm) < max_items) return false;
+    if (t.end != t.bucket + 64) return false;
+    return 4 * t.end <= smem_bytes;
+}
+
+}  // namespace crop

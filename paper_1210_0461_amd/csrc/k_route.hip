@@ -15,6 +15,8 @@
 // staged LDS data, while its key costs HBM traffic.
 //
 // The enumeration inside a chunk is in crop_enum.hpp.
+#include <algorithm>
+
 #include "crop_device.hpp"
 #include "crop_enum.hpp"
 #include "crop_internal.hpp"
@@ -627,6 +629,32 @@ k_validate_csr(const uint32_t *__restrict__ v_off, uint64_t K, const uint32_t *_
     }
 }
 
+// bad <- min over q of q where pair (qx[q], qy[q]) breaks x < y < n.
+__global__ void __launch_bounds__(256)
+k_check_pairs(const uint32_t *__restrict__ qx, const uint32_t *__restrict__ qy, uint64_t n,
+              uint32_t n_items, unsigned long long *bad)
+{
+    for (uint64_t q = (uint64_t)blockIdx.x * 256 + threadIdx.x; q < n;
+         q += (uint64_t)gridDim.x * 256) {
+        const uint32_t x = qx[q], y = qy[q];
+        if (!(x < y && y < n_items)) atomicMin(bad, (unsigned long long)q);
+    }
+}
+
+// Consistent hash of query pairs: h[q] = h_a(qx[q]) + h_b(qy[q]) mod 2^32 and
+// part[q] = (h[q] P) >> 32 (either output may be null).
+__global__ void __launch_bounds__(256)
+k_hash_pairs(const uint32_t *__restrict__ qx, const uint32_t *__restrict__ qy, uint64_t n,
+             HashParams hp, uint32_t P, uint32_t *__restrict__ h, uint32_t *__restrict__ part)
+{
+    for (uint64_t q = (uint64_t)blockIdx.x * 256 + threadIdx.x; q < n;
+         q += (uint64_t)gridDim.x * 256) {
+        const uint32_t v = hash_a(hp, qx[q]) + hash_b(hp, qy[q]);
+        if (h) h[q] = v;
+        if (part) part[q] = interval_of(v, P);
+    }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
@@ -640,6 +668,21 @@ size_t tx_scatter_smem_bytes(uint32_t NB, uint32_t max_items, uint32_t cap, bool
 {
     size_t w = (tx_lds_words(3 * NB + 1, max_items) + 1) & ~(size_t)1;
     return 4 * w + (size_t)cap * (wide ? 8 : 4);
+}
+
+// Every chunk image the transaction kernels place in LDS (count, direct and
+// staged scatter) is aligned, disjoint and inside the dynamic LDS of its
+// launch, and that LDS fits a CU.
+bool tx_launch_layouts_ok(uint32_t NB, uint32_t max_items, uint32_t cap, bool wide)
+{
+    const size_t count = tx_count_smem_bytes(NB, max_items);
+    const size_t direct = 4 * tx_lds_words(NB, max_items);
+    const size_t staged = tx_scatter_smem_bytes(NB, max_items, cap, wide);
+    if (!tx_layout_ok(NB, max_items, count) || !tx_layout_ok(NB, max_items, direct) ||
+        !tx_layout_ok(3 * NB + 1, max_items, staged))
+        return false;
+    const size_t cu = 160 * 1024;
+    return count <= cu && direct <= cu && (cap == 0 || staged <= cu);
 }
 
 static size_t op_smem_bytes(uint32_t NB, uint32_t max_a, uint32_t BS)
@@ -845,6 +888,27 @@ hipError_t launch_validate_tx(const uint32_t *off, uint64_t T, const uint32_t *i
     if (blocks == 0) blocks = 1;
     hipLaunchKernelGGL(k_validate_csr, dim3((uint32_t)blocks), dim3(256), 0, s, off, T, items,
                        nnz, n_items, bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_check_pairs(const uint32_t *qx, const uint32_t *qy, uint64_t n,
+                              uint32_t n_items, unsigned long long *bad, hipStream_t s)
+{
+    if (!n) return hipSuccess;
+    const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_check_pairs, dim3((uint32_t)blocks), dim3(256), 0, s, qx, qy, n, n_items,
+                       bad);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash_pairs(const uint32_t *qx, const uint32_t *qy, uint64_t n,
+                             const HashParams &hp, uint32_t P, uint32_t *h, uint32_t *part,
+                             hipStream_t s)
+{
+    if (!n) return hipSuccess;
+    const uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_hash_pairs, dim3((uint32_t)blocks), dim3(256), 0, s, qx, qy, n, hp, P,
+                       h, part);
     return hipGetLastError();
 }
 

@@ -213,3 +213,22 @@ def test_full_batched_config_sampled(crop, ctx):
         sizes, terms = crop.crop_batch_result_sizes(ctx, k)
         assert int(terms.sum()) == want
         assert crop.crop_batch_info(ctx, k)["terms"] == want
+
+
+def test_seed_change_recaptures_graph(crop, ctx):
+    """The captured graph holds the hash parameters by value: after
+    crop_set_seed a replay must partition by the new seed's hash, the same
+    as the oracle under that seed."""
+    streams = small_batch()[3:9]
+    tx, off, items, n = make_batch(streams)
+    crop.crop_load_batch(ctx, tx, off, items, n)
+    crop.crop_batch_set_graph(ctx, True)
+    crop.crop_batch_set_plan(ctx, 2000, 64)
+    crop.crop_run_exact_batched(ctx)          # captures with SEED
+    for k, st in enumerate(streams):
+        check_stream(crop, ctx, k, st, SEED)
+    new_seed = 0x9E3779B97F4A7C15
+    crop.crop_set_seed(ctx, new_seed)
+    crop.crop_run_exact_batched(ctx)          # must not replay the old capture
+    for k, st in enumerate(streams):
+        check_stream(crop, ctx, k, st, new_seed)

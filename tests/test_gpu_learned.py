@@ -364,6 +364,29 @@ def test_mlp_train_rejects_bad_index(crop, ctx, torch):
         crop.crop_mlp_destroy(mlp)
 
 
+def test_seeded_run_rejects_invalid_seed_pairs(crop, ctx, torch):
+    """Seeds must be pairs x < y < n_items: an unordered pair, a diagonal
+    pair or an id beyond the stream's items is reported with its index and
+    nothing runs; valid seeds still run afterwards."""
+    st = datagen.config_small()
+    load(crop, ctx, st, 8)
+    crop.crop_set_summary(ctx, 256, 8)
+    good_x = np.array([1, 2, 3, 4], np.int32)
+    good_y = np.array([5, 6, 7, 8], np.int32)
+    for k, (x, y) in enumerate([(9, 3), (7, 7), (2, st.n), (0, 1 << 20)]):
+        sx = good_x.copy()
+        sy = good_y.copy()
+        sx[2], sy[2] = x, y
+        with pytest.raises(crop.CropError) as e:
+            crop.crop_run_topk_seeded(ctx, 10, torch.from_numpy(sx).cuda(),
+                                      torch.from_numpy(sy).cuda(), 4)
+        assert e.value.status == -3 and e.value.index == 2, (k, e.value)
+    crop.crop_run_topk_seeded(ctx, 10, torch.from_numpy(good_x).cuda(),
+                              torch.from_numpy(good_y).cuda(), 4)
+    s = crop.crop_read_summary(ctx, 8 * 256)
+    assert int(s["pinned"].sum()) == 4
+
+
 def test_seeding_gain_over_plain_summary(crop, ctx, torch):
     """What the trained network adds at equal memory: six training streams
     and one held-out stream of 200,000 transactions (like the 1M-transaction
