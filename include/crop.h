@@ -97,8 +97,13 @@ int crop_abi_version(void);
 
 /* ---- parameters -------------------------------------------------------- */
 
-/* Number of owners P, 1 <= P <= 8192 (Section 6, Theorem 1: owners hold
- * disjoint equal intervals of the hash space). */
+/* Number of owners P, 1 <= P <= 2^20 (Section 6, Theorem 1: owners hold
+ * disjoint equal intervals of the hash space; the paper's own runs used about
+ * 2^20 buckets, Table 4).  Up to 8192 owned partitions each get one or more
+ * routing bins of their own; beyond that a routing bin holds 2^g consecutive
+ * partitions and each partition's entries are told apart by its hash when
+ * the results are read.  Either way partition p owns exactly the hash values
+ * h with floor(h P / 2^32) = p. */
 crop_status crop_set_partitions(crop_ctx *ctx, uint32_t P);
 /* 64-bit seed of the hash functions (Section 5: the hash description is
  * broadcast before the computation). */
@@ -235,7 +240,9 @@ crop_status crop_read_topk_votes(crop_ctx *ctx, uint32_t *votes, uint64_t cap,
 
 /* Every Space-Saving slot of the last top-K run (P*B*ell slots, bucket
  * major) into host arrays: entry, count, overestimation, signed sum (outer
- * products; else 0) and flags (bit 0 used, bit 1 pinned). */
+ * products; else 0) and flags (bit 0 used, bit 1 pinned).  With P above 8192
+ * the slots are padded to whole routing bins of 2^g partitions: the count
+ * (*written) is then rounded up and the extra slots, at the end, are unused. */
 crop_status crop_read_summary(crop_ctx *ctx, uint32_t *i, uint32_t *j, double *cnt,
                               double *err, double *value, uint8_t *flags, uint64_t cap,
                               uint64_t *written);
@@ -381,6 +388,63 @@ crop_status crop_mlp_score(crop_ctx *ctx, const crop_mlp *mlp, const float *Z, u
 crop_status crop_select_seeds(crop_ctx *ctx, const float *score, const uint32_t *cx,
                               const uint32_t *cy, uint64_t n, uint32_t R, uint32_t *sx,
                               uint32_t *sy);
+
+/* The predictor as one object: training and scoring composed from the calls
+ * above.  A training stream is a CSR transaction stream as for
+ * crop_load_transactions; the arrays of every stream of a set live in
+ * `where` (device arrays are borrowed for the call, host arrays copied). */
+typedef struct crop_stream_ref {
+    const uint32_t *off;   /* T + 1 offsets */
+    uint64_t T;
+    const uint32_t *items; /* nnz item ids, strictly increasing per row */
+    uint64_t nnz;
+    uint32_t n_items;
+} crop_stream_ref;
+typedef struct crop_train_set {
+    const crop_stream_ref *streams;
+    uint32_t n_streams;
+    crop_mem where;
+} crop_train_set;
+/* Zero fields take the defaults in brackets. */
+typedef struct crop_train_opts {
+    uint32_t top_items;    /* M: candidates are the pairs of the M items most
+                              frequent in a stream's prefix [256]            */
+    uint32_t epochs;       /* passes over the samples [4]                    */
+    uint32_t batch;        /* Adam minibatch, <= 128 [128]                   */
+    float lr;              /* Adam learning rate [1e-3]                      */
+    uint64_t shuffle_seed; /* SplitMix64 seed of the minibatch order (one
+                              Fisher-Yates permutation per epoch) and of the
+                              default initial weights                        */
+    const float *init;     /* host, 6337 initial weights in crop_mlp_create's
+                              order, or NULL: He-uniform +-sqrt(6/fan_in),
+                              zero biases                                    */
+} crop_train_opts;
+typedef struct crop_predictor crop_predictor;
+
+/* Train a predictor: for each training stream an exact run under the
+ * context's seed and P gives the labels log1p(support) of the candidate
+ * pairs of its prefix (crop_item_features over the first ceil(T/20)
+ * transactions, crop_top_item_pairs with M = top_items, crop_lookup_exact,
+ * crop_pair_inputs); then crop_mlp_train over all samples.  The work runs on
+ * a private context of the same GPU: the caller's loaded input, results and
+ * stream are left as they were (this call synchronizes the caller's stream
+ * first).  *out owns its device weights until crop_predictor_free.
+ * Errors: CROP_E_ARG for an empty set or bad options, CROP_E_INPUT for an
+ * invalid stream (crop_last_error_index: the offending transaction of that
+ * stream), else as the calls it makes. */
+crop_status crop_predictor_train(crop_ctx *ctx, const crop_train_set *set,
+                                 const crop_train_opts *opts, crop_predictor **out);
+/* Seeds for the loaded transaction stream: features and candidate pairs of
+ * its prefix, bf16 scores (crop_mlp_score) and the R best candidates, in rank
+ * order, into device arrays sx, sy of capacity R, for crop_run_topk_seeded.
+ * *n_seeds (may be NULL) receives min(R, M(M-1)/2).  Synchronizes. */
+crop_status crop_predictor_score(crop_ctx *ctx, const crop_predictor *pred, uint32_t R,
+                                 uint32_t *sx, uint32_t *sy, uint64_t *n_seeds);
+/* The trained weights (host array of 6337 floats, crop_mlp_create's order)
+ * and the mean loss of the last training minibatch (may be NULL). */
+crop_status crop_predictor_params(crop_ctx *ctx, const crop_predictor *pred, float *out,
+                                  float *last_loss);
+void crop_predictor_free(crop_predictor *pred);
 
 /* Profiling: when enabled, every run also records one HIP event after each
  * of its stages (kernels or kernel groups) on the context stream, kept for

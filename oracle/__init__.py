@@ -84,6 +84,42 @@ def lib():
     return L
 
 
+_cpu = None
+
+
+def cpu_lib():
+    """The paper's method on the host (oracle/crop_cpu.c): the benchmark's
+    multi-core CPU baseline, not a checker."""
+    global _cpu
+    if _cpu is not None:
+        return _cpu
+    path = os.path.join(_HERE, "libcropcpu.so")
+    src = os.path.join(_HERE, "crop_cpu.c")
+    if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(src):
+        _build.build_cpu()
+    L = ctypes.CDLL(path)
+    L.cpu_crop_tx.argtypes = [_u32p, _u64, _u32p, _u32, _u64, _u32, ctypes.c_void_p,
+                              ctypes.c_void_p, ctypes.POINTER(_u64)]
+    L.cpu_crop_tx.restype = ctypes.c_int
+    _cpu = L
+    return L
+
+
+def cpu_crop_tx(off, items, P: int, seed: int, n_threads: int):
+    """Run the paper's multi-threaded method (each of n_threads owners reads
+    every transaction, sorts it by h_b and enumerates only the pairs of its
+    hash interval, Lemma 1).  Returns (part_sizes, part_terms, distinct)."""
+    off = _c(off, np.uint32)
+    ps = np.zeros(P, np.uint64)
+    pt = np.zeros(P, np.uint64)
+    d = _u64(0)
+    rc = cpu_lib().cpu_crop_tx(off, off.shape[0] - 1, _c(items, np.uint32), P, seed, n_threads,
+                               ps.ctypes.data, pt.ctypes.data, ctypes.byref(d))
+    if rc != 0:
+        raise RuntimeError("cpu_crop_tx ran out of memory")
+    return ps, pt, int(d.value)
+
+
 def _c(a, dt):
     return np.ascontiguousarray(a, dtype=dt)
 

@@ -38,6 +38,22 @@ class CropError(RuntimeError):
         self.index = index
 
 
+class crop_stream_ref(ctypes.Structure):
+    _fields_ = [("off", ctypes.c_void_p), ("T", ctypes.c_uint64), ("items", ctypes.c_void_p),
+                ("nnz", ctypes.c_uint64), ("n_items", ctypes.c_uint32)]
+
+
+class crop_train_set(ctypes.Structure):
+    _fields_ = [("streams", ctypes.POINTER(crop_stream_ref)), ("n_streams", ctypes.c_uint32),
+                ("where", ctypes.c_int)]
+
+
+class crop_train_opts(ctypes.Structure):
+    _fields_ = [("top_items", ctypes.c_uint32), ("epochs", ctypes.c_uint32),
+                ("batch", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("shuffle_seed", ctypes.c_uint64), ("init", ctypes.c_void_p)]
+
+
 class crop_tune(ctypes.Structure):
     _fields_ = [("bins_per_partition", ctypes.c_uint32), ("rows_per_chunk", ctypes.c_uint32),
                 ("stage_keys", ctypes.c_uint32), ("route", ctypes.c_uint32)]
@@ -126,6 +142,10 @@ _SIGS.update({
     "crop_mlp_score": ([_vp, _vp, _vp, _u64, _vp], _i32),
     "crop_select_seeds": ([_vp, _vp, _vp, _vp, _u64, _u32, _vp, _vp], _i32),
     "crop_hash_pairs": ([_vp, _vp, _vp, _u64, _vp, _vp], _i32),
+    "crop_predictor_train": ([_vp, _vp, _vp, ctypes.POINTER(_vp)], _i32),
+    "crop_predictor_score": ([_vp, _vp, _u32, _vp, _vp, _pu64], _i32),
+    "crop_predictor_params": ([_vp, _vp, _vp, ctypes.POINTER(ctypes.c_float)], _i32),
+    "crop_predictor_free": ([_vp], None),
 })
 
 # Entry points bound only when the loaded library exports them.
@@ -574,6 +594,53 @@ def crop_hash_pairs(ctx, qx, qy, h=None, part=None) -> None:
     output may be None."""
     _check(ctx, _lib.crop_hash_pairs(ctx, _dev(qx, "qx"), _dev(qy, "qy"), _len(qx),
                                      _dev(h, "h"), _dev(part, "part")))
+
+
+def crop_predictor_train(ctx, streams, top_items: int = 0, epochs: int = 0, batch: int = 0,
+                         lr: float = 0.0, shuffle_seed: int = 0, init=None):
+    """Train a predictor on `streams`, a list of (off, items, n_items) with the
+    arrays all numpy (host) or all torch device tensors; returns the handle."""
+    refs = (crop_stream_ref * len(streams))()
+    where = None
+    keep = []
+    for k, (off, items, n) in enumerate(streams):
+        po, wo = _ptr(off)
+        pi, wi = _ptr(items)
+        if where is None:
+            where = wo
+        if wo != where or (len(items) and wi != where):
+            raise ValueError("every training array must be host or every one device")
+        keep += [off, items]
+        refs[k] = crop_stream_ref(po, _len(off) - 1, pi, _len(items), int(n))
+    tset = crop_train_set(refs, len(streams), CROP_MEM_HOST if where is None else where)
+    w = None if init is None else np.ascontiguousarray(init, np.float32)
+    opts = crop_train_opts(top_items, epochs, batch, lr, shuffle_seed,
+                           None if w is None else w.ctypes.data)
+    out = _vp()
+    _check(ctx, _lib.crop_predictor_train(ctx, ctypes.byref(tset), ctypes.byref(opts),
+                                          ctypes.byref(out)))
+    return out.value
+
+
+def crop_predictor_score(ctx, pred, R: int, sx, sy) -> int:
+    """Seeds of the loaded stream into device tensors sx, sy (capacity R);
+    returns how many were written."""
+    n = _u64(0)
+    _check(ctx, _lib.crop_predictor_score(ctx, pred, R, _dev(sx, "sx"), _dev(sy, "sy"),
+                                          ctypes.byref(n)))
+    return int(n.value)
+
+
+def crop_predictor_params(ctx, pred):
+    """(weights [MLP_PARAMS], mean loss of the last training minibatch)."""
+    out = np.zeros(MLP_PARAMS, np.float32)
+    loss = ctypes.c_float(0.0)
+    _check(ctx, _lib.crop_predictor_params(ctx, pred, out.ctypes.data, ctypes.byref(loss)))
+    return out, float(loss.value)
+
+
+def crop_predictor_free(pred) -> None:
+    _lib.crop_predictor_free(pred)
 
 
 def crop_synchronize(ctx) -> None:

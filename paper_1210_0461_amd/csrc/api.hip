@@ -111,10 +111,18 @@ static void owned_range(const crop_ctx *ctx, uint32_t *p0, uint32_t *p1)
     *p1 = all ? ctx->P : ctx->own_p1;
 }
 
-// Bins of the run: P * S over the hash space, of which the owned partitions'
-// S bins each are kept.  S aims at kTermsPerBin routed terms per bin, and
-// the kept bins must fit the count kernels' LDS histogram (kMaxP words).
-static crop_status plan_bins(crop_ctx *ctx, uint32_t S, uint64_t terms_per_bin)
+// Bins spanned by the owned partitions [p0, p1) when a bin groups 2^g.
+static uint64_t grouped_span(uint32_t p0, uint32_t p1, uint32_t g)
+{
+    return (uint64_t)((p1 - 1) >> g) - (p0 >> g) + 1;
+}
+
+// Bins of the run.  Up to kMaxP kept bins (the count kernels' LDS histogram):
+// S bins per partition (M = P * S) while the owned partitions times S fit,
+// S chosen for about terms_per_bin routed terms per bin; beyond that (P above
+// 8192) one bin holds 2^g consecutive partitions (M = P), g the smallest that
+// fits.  g_req >= 0 asks for that grouping with one bin per 2^g partitions.
+static crop_status plan_bins(crop_ctx *ctx, uint32_t S, uint64_t terms_per_bin, int g_req = -1)
 {
     Input &in = ctx->in;
     RoutePlan &pl = ctx->plan;
@@ -122,28 +130,43 @@ static crop_status plan_bins(crop_ctx *ctx, uint32_t S, uint64_t terms_per_bin)
     uint32_t p0, p1;
     owned_range(ctx, &p0, &p1);
     const uint32_t Pown = p1 - p0;
-    if (S == 0) {
+    if (g_req < 0 && S == 0) {
         const uint64_t want = (in.total_terms + terms_per_bin - 1) / terms_per_bin;
         S = (uint32_t)std::max<uint64_t>(1, (want + P - 1) / P);
         while (S > 1 && (uint64_t)Pown * S > kMaxP) --S;
     }
-    if ((uint64_t)Pown * S > kMaxP)
+    if (g_req < 0 && (uint64_t)Pown * S <= kMaxP) {
+        if ((uint64_t)P * S > (1ull << 32))
+            return fail(ctx, CROP_E_UNSUPPORTED, "partitions x bins_per_partition exceeds 2^32");
+        pl.S = S;
+        pl.g = 0;
+        pl.M = (uint64_t)P * S;
+        pl.u0 = p0 * S;
+        pl.nu = Pown * S;
+        pl.NB = Pown * S;
+        return CROP_OK;
+    }
+    if (g_req < 0 && S > 1)
         return fail(ctx, CROP_E_UNSUPPORTED, "owned partitions x bins_per_partition exceeds 8192");
-    if ((uint64_t)P * S > (1ull << 32))
-        return fail(ctx, CROP_E_UNSUPPORTED, "partitions x bins_per_partition exceeds 2^32");
-    pl.S = S;
-    pl.NB = Pown * S;
-    pl.NBall = (uint64_t)P * S;
-    pl.bin0 = p0 * S;
+    uint32_t g = g_req < 0 ? 0u : (uint32_t)g_req;
+    while (grouped_span(p0, p1, g) > kMaxP) ++g;
+    if (g > kMaxGroupLog2)
+        return fail(ctx, CROP_E_UNSUPPORTED, "too many partitions per routing bin");
+    pl.S = 1;
+    pl.g = g;
+    pl.M = P;
+    pl.u0 = p0;
+    pl.nu = Pown;
+    pl.NB = (uint32_t)grouped_span(p0, p1, g);
     return CROP_OK;
 }
 
-crop_status plan_tx(crop_ctx *ctx, uint32_t S_force = 0)
+crop_status plan_tx(crop_ctx *ctx, uint32_t S_force = 0, int g_req = -1)
 {
     Input &in = ctx->in;
     RoutePlan &pl = ctx->plan;
     crop_status st = plan_bins(ctx, S_force ? S_force : ctx->tune.bins_per_partition,
-                               kTermsPerBin);
+                               kTermsPerBin, g_req);
     if (st != CROP_OK) return st;
     const size_t hist_bytes = (size_t)pl.NB * 4;
     // 128 transactions per chunk: about 11,000 terms at ten items per
@@ -204,14 +227,14 @@ crop_status plan_tx(crop_ctx *ctx, uint32_t S_force = 0)
     return CROP_OK;
 }
 
-crop_status plan_outer(crop_ctx *ctx, uint32_t S_force = 0)
+crop_status plan_outer(crop_ctx *ctx, uint32_t S_force = 0, int g_req = -1)
 {
     Input &in = ctx->in;
     RoutePlan &pl = ctx->plan;
     // outer-product entries rarely repeat and fp32 sums use 8192-slot
     // tables: aim at about 2000 routed terms per bin
     crop_status st = plan_bins(ctx, S_force ? S_force : ctx->tune.bins_per_partition,
-                               kTermsPerBin / 16);
+                               kTermsPerBin / 16, g_req);
     if (st != CROP_OK) return st;
     pl.max_items = in.op_max_a;
     pl.n_chunks = (uint32_t)in.op_chunks.size();
@@ -280,14 +303,20 @@ crop_status ensure_route_buffers(crop_ctx *ctx, size_t key_bytes, bool sums)
         CK(ctx->out_cnt.ensure(nt * 4));
     CK(ctx->spill.ensure(nt * spill_entry_bytes(ctx->in.wide_keys, sums)));
     CK(ctx->counter.ensure(64));
+    if (pl.g) CK(ctx->part_stats.ensure((size_t)ctx->P * 8));
     return CROP_OK;
 }
 
-// First local bin of partition p in the last run, or -1 when p is not owned.
+// First local bin of partition p in the last run, or -1 when p is not owned
+// (with grouped bins, the one bin p shares with its neighbours).
 static int64_t partition_bin(const crop_ctx *ctx, uint32_t p)
 {
     const RoutePlan &pl = ctx->plan;
-    const uint32_t p0 = pl.bin0 / pl.S, p1 = p0 + pl.NB / pl.S;
+    if (pl.g) {
+        if (p < pl.u0 || p - pl.u0 >= pl.nu) return -1;
+        return (int64_t)(p >> pl.g) - (pl.u0 >> pl.g);
+    }
+    const uint32_t p0 = pl.u0 / pl.S, p1 = p0 + pl.nu / pl.S;
     return (p >= p0 && p < p1) ? (int64_t)(p - p0) * pl.S : -1;
 }
 
@@ -300,8 +329,11 @@ crop_status require_exact(crop_ctx *ctx)
 
 // Space-Saving routing: bins hold whole groups of nbk buckets (nbk divides
 // the B buckets of a partition), the bucket summaries of a bin must fit in
-// LDS, and there should be enough bins to occupy the GPU.
-crop_status plan_ss(crop_ctx *ctx, uint32_t *nbk_out, uint64_t *PB_out)
+// LDS, and there should be enough bins to occupy the GPU.  When no divisor
+// keeps the bins within kMaxP (P above 8192), a bin holds the B buckets of
+// 2^g consecutive partitions instead (*g_out = g; else -1); the last bin may
+// then be partial, and the summary state is padded to whole bins.
+crop_status plan_ss(crop_ctx *ctx, uint32_t *nbk_out, uint64_t *PB_out, int *g_out)
 {
     const uint32_t P = ctx->P, ell = ctx->ss_ell;
     const uint64_t B = ctx->ss_counters / ell;
@@ -342,8 +374,19 @@ crop_status plan_ss(crop_ctx *ctx, uint32_t *nbk_out, uint64_t *PB_out)
         if (pick > 1) MB = kSsBatchTxLarge;
     }
     if (MB != kSsBatchTxLarge) pick = pick_for(MB);
-    if (!pick)
-        return fail(ctx, CROP_E_UNSUPPORTED, "Space-Saving summaries do not fit the LDS plan");
+    *g_out = -1;
+    if (!pick) {
+        // grouped bins: the smallest g with ceil(P / 2^g) <= kMaxP
+        uint32_t g = 0;
+        while (((uint64_t)P + (1ull << g) - 1) >> g > kMaxP) ++g;
+        const uint64_t nbk = B << g;
+        MB = outer ? kSsBatchOuter : wide ? kSsBatchWide : kSsBatchTx;
+        if (g == 0 || g > kMaxGroupLog2 || nbk > (1ull << 20) ||
+            ss_bins_smem_bytes((uint32_t)nbk, ell, wide, outer, MB) > kSsLdsBudget)
+            return fail(ctx, CROP_E_UNSUPPORTED, "Space-Saving summaries do not fit the LDS plan");
+        pick = nbk;
+        *g_out = (int)g;
+    }
     ctx->plan.ss_mb = MB;
     *nbk_out = (uint32_t)pick;
     *PB_out = PB;
@@ -526,7 +569,8 @@ int64_t crop_last_error_index(const crop_ctx *ctx) { return ctx ? ctx->err_index
 crop_status crop_set_partitions(crop_ctx *ctx, uint32_t P)
 {
     if (!ctx) return CROP_E_ARG;
-    if (P < 1 || P > kMaxP) return fail(ctx, CROP_E_UNSUPPORTED, "P must be in [1, 8192]");
+    if (P < 1 || P > kMaxPartitions)
+        return fail(ctx, CROP_E_UNSUPPORTED, "P must be in [1, 2^20]");
     ctx->P = P;
     ctx->own_p0 = ctx->own_p1 = 0;  // a new partition count owns all partitions again
     ctx->result = Result::None;
@@ -789,8 +833,19 @@ crop_status crop_run_exact(crop_ctx *ctx)
                  : pl.n_wg ? launch_tx_scatter_ranges(ctx, cnt, ctx->keys.p, s)
                            : launch_tx_scatter(ctx, cnt, ctx->keys.p, s));
     STAGE("scatter");
+    // grouped bins: per-partition terms from the routed keys (outer products;
+    // for transactions they are the sums of the supports, taken below)
+    uint32_t *ps_n = ctx->part_stats.as<uint32_t>(), *ps_w = ps_n + (pl.g ? ctx->P : 0);
+    if (pl.g) {
+        CK(launch_zero32(ps_n, 2 * ctx->P, s));
+        if (outer) CK(launch_part_stats(ctx, true, ps_w, nullptr, s));
+    }
     CK(outer ? launch_aggregate_sums(ctx, s) : launch_aggregate_counts(ctx, s));
     STAGE("aggregate");
+    if (pl.g) {
+        CK(launch_part_stats(ctx, false, ps_n, outer ? nullptr : ps_w, s));
+        STAGE("partitions");
+    }
     st = run_end(ctx);
     if (st != CROP_OK) return st;
     ctx->result = Result::Exact;
@@ -834,17 +889,21 @@ static crop_status run_topk_impl(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
     }
     uint32_t nbk = 0;
     uint64_t PB = 0;
-    crop_status st = plan_ss(ctx, &nbk, &PB);
+    int g_ss = -1;
+    crop_status st = plan_ss(ctx, &nbk, &PB, &g_ss);
     if (st != CROP_OK) return st;
-    const uint32_t S = (uint32_t)(PB / ctx->P / nbk);
+    const uint32_t S = g_ss < 0 ? (uint32_t)(PB / ctx->P / nbk) : 1u;
     const bool outer = ctx->in.mode == Mode::Outer;
-    st = outer ? plan_outer(ctx, S) : plan_tx(ctx, S);
+    st = outer ? plan_outer(ctx, S, g_ss) : plan_tx(ctx, S, g_ss);
     if (st != CROP_OK) return st;
+    if (g_ss >= 0 && ctx->plan.g != (uint32_t)g_ss)
+        return fail(ctx, CROP_E_UNSUPPORTED, "Space-Saving bins do not match the routing bins");
     ctx->plan.log2_slots = 0;
     ctx->plan.BS = 256;
     st = ensure_route_buffers(ctx, ctx->in.wide_keys ? 8 : 4, outer);
     if (st != CROP_OK) return st;
-    const uint64_t nslots = PB * ctx->ss_ell;
+    // grouped bins: the state covers whole bins (the last one may be partial)
+    const uint64_t nslots = (g_ss < 0 ? PB : (uint64_t)ctx->plan.NB * nbk) * ctx->ss_ell;
     if (nslots * t >= (1ull << 32))
         return fail(ctx, CROP_E_UNSUPPORTED, "more than 2^32 summary slots");
     st = ensure_ss_buffers(ctx, nslots * t, K, (uint32_t)ns);
@@ -1393,8 +1452,11 @@ crop_status crop_autotune(crop_ctx *ctx, uint32_t reps, uint32_t *bins_per_parti
     owned_range(ctx, &p0, &p1);
     float best = -1.0f;
     uint32_t bS = 0, bR = 0;
-    for (uint32_t S = S0 > 1 ? S0 - 1 : 1; S <= S0 + 2; ++S) {
-        if ((uint64_t)(p1 - p0) * S > kMaxP) break;
+    // grouped bins (P above the bin limit) have one bin per 2^g partitions:
+    // only the rows per chunk are tuned
+    const uint32_t S_hi = ctx->plan.g ? 1u : S0 + 2;
+    for (uint32_t S = S0 > 1 ? S0 - 1 : 1; S <= S_hi; ++S) {
+        if (ctx->plan.g == 0 && (uint64_t)(p1 - p0) * S > kMaxP) break;
         for (uint32_t R : {64u, 96u, 128u, 192u, 256u}) {
             ctx->tune = saved;
             ctx->tune.bins_per_partition = S;
@@ -1442,6 +1504,61 @@ crop_status crop_last_run_ms(crop_ctx *ctx, float *ms)
 
 // ============================================================== readback
 
+namespace {
+
+// Partition p of a run with grouped bins: its bin is gathered by partition
+// into scratch and p's slice is copied out.
+crop_status read_partition_grouped(crop_ctx *ctx, uint32_t p, uint32_t *i, uint32_t *j,
+                                   uint32_t *count, float *value, uint64_t cap,
+                                   uint64_t *written)
+{
+    const RoutePlan &pl = ctx->plan;
+    CK(hipStreamSynchronize(ctx->stream));
+    const int64_t b = partition_bin(ctx, p);
+    if (b < 0) {
+        if (written) *written = 0;
+        return CROP_OK;
+    }
+    const uint32_t G = 1u << pl.g;
+    const uint32_t first = (uint32_t)((b + (pl.u0 >> pl.g)) << pl.g);
+    std::vector<uint32_t> ps(G, 0), dst(G, 0);
+    const uint32_t last = std::min<uint32_t>(first + G, ctx->P);
+    CK(hipMemcpy(ps.data(), ctx->part_stats.as<uint32_t>() + first, (last - first) * 4,
+                 hipMemcpyDeviceToHost));
+    uint32_t bs = 0;
+    CK(hipMemcpy(&bs, ctx->bin_size.as<uint32_t>() + b, 4, hipMemcpyDeviceToHost));
+    uint64_t run = 0;
+    for (uint32_t k = 0; k < G; ++k) {
+        dst[k] = (uint32_t)run;
+        run += ps[k];
+    }
+    const uint64_t tot = ps[p - first];
+    if (written) *written = tot;
+    if (tot > cap) return fail(ctx, CROP_E_CAPACITY, "output capacity below the entry count");
+    const size_t n = std::max<uint32_t>(bs, 1);
+    const size_t head = ((size_t)G * 4 + 255) / 256 * 256;
+    CK(ctx->scratch.ensure(head + 16 * n));
+    uint32_t *d_dst = ctx->scratch.as<uint32_t>();
+    uint32_t *oi = reinterpret_cast<uint32_t *>(reinterpret_cast<char *>(d_dst) + head);
+    uint32_t *oj = oi + n, *oc = oj + n;
+    float *ov = reinterpret_cast<float *>(oc + n);
+    const bool outer = ctx->in.mode == Mode::Outer;
+    CK(hipMemcpyAsync(d_dst, dst.data(), G * 4, hipMemcpyHostToDevice, ctx->stream));
+    CK(launch_gather_grouped(ctx, (uint32_t)b, 1, d_dst, first, oi, oj, outer ? nullptr : oc,
+                             outer ? ov : nullptr, ctx->stream));
+    CK(hipStreamSynchronize(ctx->stream));
+    const uint32_t at = dst[p - first];
+    if (tot) {
+        CK(hipMemcpy(i, oi + at, tot * 4, hipMemcpyDeviceToHost));
+        CK(hipMemcpy(j, oj + at, tot * 4, hipMemcpyDeviceToHost));
+        if (count && !outer) CK(hipMemcpy(count, oc + at, tot * 4, hipMemcpyDeviceToHost));
+        if (value && outer) CK(hipMemcpy(value, ov + at, tot * 4, hipMemcpyDeviceToHost));
+    }
+    return CROP_OK;
+}
+
+}  // namespace
+
 crop_status crop_result_sizes(crop_ctx *ctx, uint64_t *sizes, uint64_t *terms)
 {
     if (!ctx) return CROP_E_ARG;
@@ -1449,8 +1566,17 @@ crop_status crop_result_sizes(crop_ctx *ctx, uint64_t *sizes, uint64_t *terms)
     if (st != CROP_OK) return st;
     DeviceGuard g(ctx->device);
     const RoutePlan &pl = ctx->plan;
-    std::vector<uint32_t> bs(pl.NB), bo(pl.NB + 1);
     CK(hipStreamSynchronize(ctx->stream));
+    if (pl.g) {
+        std::vector<uint32_t> v(2 * (size_t)ctx->P);
+        CK(hipMemcpy(v.data(), ctx->part_stats.p, v.size() * 4, hipMemcpyDeviceToHost));
+        for (uint32_t p = 0; p < ctx->P; ++p) {
+            if (sizes) sizes[p] = v[p];
+            if (terms) terms[p] = v[ctx->P + p];
+        }
+        return CROP_OK;
+    }
+    std::vector<uint32_t> bs(pl.NB), bo(pl.NB + 1);
     CK(hipMemcpy(bs.data(), ctx->bin_size.p, pl.NB * 4, hipMemcpyDeviceToHost));
     CK(hipMemcpy(bo.data(), ctx->bin_off.p, (pl.NB + 1) * 4, hipMemcpyDeviceToHost));
     for (uint32_t p = 0; p < ctx->P; ++p) {
@@ -1478,13 +1604,25 @@ crop_status crop_read_all(crop_ctx *ctx, crop_mem where, uint32_t *i, uint32_t *
     std::vector<uint32_t> bs(pl.NB);
     CK(hipStreamSynchronize(ctx->stream));
     CK(hipMemcpy(bs.data(), ctx->bin_size.p, pl.NB * 4, hipMemcpyDeviceToHost));
-    std::vector<uint32_t> dst(pl.NB);
+    std::vector<uint32_t> dst(pl.g ? ctx->P : pl.NB);
     uint64_t tot = 0;
-    for (uint32_t b = 0; b < pl.NB; ++b) {
-        dst[b] = (uint32_t)tot;
-        tot += bs[b];
+    if (pl.g) {
+        // grouped bins: partition starts from the per-partition sizes
+        std::vector<uint32_t> ps(ctx->P);
+        CK(hipMemcpy(ps.data(), ctx->part_stats.p, ps.size() * 4, hipMemcpyDeviceToHost));
+        for (uint32_t p = 0; p < ctx->P; ++p) {
+            dst[p] = (uint32_t)tot;
+            if (part_off) part_off[p] = tot;
+            tot += ps[p];
+        }
+        if (part_off) part_off[ctx->P] = tot;
+    } else {
+        for (uint32_t b = 0; b < pl.NB; ++b) {
+            dst[b] = (uint32_t)tot;
+            tot += bs[b];
+        }
     }
-    if (part_off) {
+    if (part_off && !pl.g) {
         // partitions outside the owned range are empty
         uint64_t run = 0;
         for (uint32_t p = 0; p < ctx->P; ++p) {
@@ -1503,10 +1641,10 @@ crop_status crop_read_all(crop_ctx *ctx, crop_mem where, uint32_t *i, uint32_t *
     // scratch layout: dst offsets, then (host readback only) four arrays of n
     // words starting at the next 256-byte boundary
     const size_t n = std::max<uint64_t>(tot, 1);
-    const size_t head = ((size_t)pl.NB * 4 + 255) / 256 * 256;
+    const size_t head = (dst.size() * 4 + 255) / 256 * 256;
     CK(ctx->scratch.ensure(head + (where == CROP_MEM_HOST ? 16 * n : 0)));
     uint32_t *d_dst = ctx->scratch.as<uint32_t>();
-    CK(hipMemcpyAsync(d_dst, dst.data(), pl.NB * 4, hipMemcpyHostToDevice, ctx->stream));
+    CK(hipMemcpyAsync(d_dst, dst.data(), dst.size() * 4, hipMemcpyHostToDevice, ctx->stream));
     uint32_t *oi = i, *oj = j, *oc = count;
     float *ov = value;
     if (where == CROP_MEM_HOST) {
@@ -1516,8 +1654,12 @@ crop_status crop_read_all(crop_ctx *ctx, crop_mem where, uint32_t *i, uint32_t *
         oc = count ? oj + n : nullptr;
         ov = value ? reinterpret_cast<float *>(oj + 2 * n) : nullptr;
     }
-    CK(launch_gather_result(ctx, 0, pl.NB, d_dst, oi, oj, outer ? nullptr : oc,
-                            outer ? ov : nullptr, ctx->stream));
+    if (pl.g)
+        CK(launch_gather_grouped(ctx, 0, pl.NB, d_dst, 0, oi, oj, outer ? nullptr : oc,
+                                 outer ? ov : nullptr, ctx->stream));
+    else
+        CK(launch_gather_result(ctx, 0, pl.NB, d_dst, oi, oj, outer ? nullptr : oc,
+                                outer ? ov : nullptr, ctx->stream));
     if (where == CROP_MEM_HOST) {
         CK(hipMemcpyAsync(i, oi, tot * 4, hipMemcpyDeviceToHost, ctx->stream));
         CK(hipMemcpyAsync(j, oj, tot * 4, hipMemcpyDeviceToHost, ctx->stream));
@@ -1537,6 +1679,7 @@ crop_status crop_read_partition(crop_ctx *ctx, uint32_t p, uint32_t *i, uint32_t
     if (p >= ctx->P) return fail(ctx, CROP_E_ARG, "partition index out of range");
     DeviceGuard g(ctx->device);
     const RoutePlan &pl = ctx->plan;
+    if (pl.g) return read_partition_grouped(ctx, p, i, j, count, value, cap, written);
     std::vector<uint32_t> bs(pl.NB), bo(pl.NB + 1);
     CK(hipStreamSynchronize(ctx->stream));
     CK(hipMemcpy(bs.data(), ctx->bin_size.p, pl.NB * 4, hipMemcpyDeviceToHost));

@@ -12,7 +12,9 @@
 
 namespace crop {
 
-constexpr uint32_t kMaxP = 8192;
+constexpr uint32_t kMaxP = 8192;             // routing bins of one run (LDS histogram)
+constexpr uint32_t kMaxPartitions = 1u << 20; // owners P
+constexpr uint32_t kMaxGroupLog2 = 10;        // at most 1024 partitions in one bin
 constexpr uint64_t kTermsPerBin = 30000;   // routed terms per bin the auto plan aims at
 constexpr size_t kLdsBudget = 64 * 1024;   // enumeration kernels' staging budget
 constexpr size_t kStageBudget = 150 * 1024; // scatter kernel: dynamic LDS in total

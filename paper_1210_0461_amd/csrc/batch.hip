@@ -156,8 +156,10 @@ crop_status plan_batch(crop_ctx *ctx, uint32_t tpb, uint32_t R)
     pl = RoutePlan{};
     pl.S = 1;
     pl.NB = (uint32_t)NBtot;
-    pl.NBall = NBtot;
-    pl.bin0 = 0;
+    pl.M = NBtot;
+    pl.u0 = 0;
+    pl.nu = (uint32_t)NBtot;
+    pl.g = 0;
     pl.n_chunks = n_chunks;
     pl.R = R;
     pl.max_items = mi;

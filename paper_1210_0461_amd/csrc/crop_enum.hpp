@@ -103,30 +103,6 @@ __device__ inline KeyT pack_key(uint32_t x, uint32_t y)
     return (KeyT)(((uint64_t)x << 32) | y);
 }
 
-// Routing bins of a run: NBall equal intervals of the hash space, of which
-// the run keeps [bin0, bin0 + NB) (all of them unless the context owns only
-// some partitions).  local() is the kept bin of hash value h, or a value
-// >= NB for a term outside the kept range.
-struct BinMap {
-    uint64_t NBall;
-    uint32_t bin0;
-    __device__ uint32_t local(uint32_t h) const { return interval_of(h, NBall) - bin0; }
-};
-
-template <class KeyT>
-__device__ inline uint32_t bin_of_key(KeyT key, const HashParams &hp, uint64_t NB)
-{
-    uint32_t x, y;
-    if (sizeof(KeyT) == 4) {
-        x = (uint32_t)key >> 16;
-        y = (uint32_t)key & 0xFFFFu;
-    } else {
-        x = (uint32_t)((uint64_t)key >> 32);
-        y = (uint32_t)key;
-    }
-    return interval_of(hash_a(hp, x) + hash_b(hp, y), NB);
-}
-
 // ---- outer products
 
 // Stage the a-entries [a_lo, a_hi) of vectors k0..k1-1: s_ai = index,

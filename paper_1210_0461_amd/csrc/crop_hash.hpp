@@ -78,4 +78,36 @@ __host__ __device__ inline int sign_of(const HashParams &p, uint32_t i, uint32_t
     return (g >> 31) ? -1 : 1;
 }
 
+// Routing bins of a run.  A hash value h maps to u = floor(h M / 2^32)
+// (M = partitions x bins per partition, or partitions alone when a bin groups
+// 2^g of them); the run keeps u in [u0, u0 + nu) -- its owned partitions --
+// and local() is the kept bin (u >> g) - (u0 >> g), or kNoBin for a term
+// outside the kept range.  Partition p = floor(h P / 2^32) nests in its bins
+// because every bin boundary is a partition boundary (nested floors).
+constexpr uint32_t kNoBin = 0xFFFFFFFFu;
+
+struct BinMap {
+    uint64_t M;
+    uint32_t u0, nu, g;
+    __host__ __device__ uint32_t local(uint32_t h) const
+    {
+        const uint32_t u = interval_of(h, M);
+        return u - u0 < nu ? (u >> g) - (u0 >> g) : kNoBin;
+    }
+};
+
+template <class KeyT>
+__host__ __device__ inline uint32_t hash_of_key(KeyT key, const HashParams &hp)
+{
+    uint32_t x, y;
+    if (sizeof(KeyT) == 4) {
+        x = (uint32_t)key >> 16;
+        y = (uint32_t)key & 0xFFFFu;
+    } else {
+        x = (uint32_t)((uint64_t)key >> 32);
+        y = (uint32_t)key;
+    }
+    return hash_a(hp, x) + hash_b(hp, y);
+}
+
 }  // namespace crop

@@ -46,10 +46,15 @@ struct OpChunk {
 
 // Resolved routing configuration of a run.
 struct RoutePlan {
-    uint32_t S = 1;          // routing bins per partition
-    uint32_t NB = 1;         // routing bins of the run (P * S, or the owned ones)
-    uint64_t NBall = 1;      // bins of the whole hash space (P * S)
-    uint32_t bin0 = 0;       // first bin of the run (owned partitions: p_begin * S)
+    // Bins: a hash value h maps to u = floor(h M / 2^32) with M = P * S (S
+    // bins per partition) or M = P (bins that group 2^g partitions); the run
+    // keeps u in [u0, u0 + nu) (the owned partitions) and routes u to bin
+    // (u >> g) - (u0 >> g).
+    uint32_t S = 1;          // routing bins per partition (1 when g > 0)
+    uint32_t NB = 1;         // routing bins of the run
+    uint64_t M = 1;          // P * S
+    uint32_t u0 = 0, nu = 1; // kept range of u
+    uint32_t g = 0;          // log2 of the partitions grouped in one bin
     uint32_t n_chunks = 0;   // enumeration workgroups
     uint32_t R = 256;        // vectors per chunk (transactions)
     uint32_t max_items = 0;  // largest number of staged entries in a chunk
@@ -195,6 +200,7 @@ struct crop_ctx {
     crop::DevBuf cnt_mat, part_buf, bin_off, bin_size, bin_order, keys, vals, out_cnt, spill,
         counter;
     crop::DevBuf ss_state, topk_buf, scratch, learn_ws;
+    crop::DevBuf part_stats;   // grouped bins: entries and terms of each partition
     crop::BatchState batch;    // batched streams
     crop::DevBuf cs_buf;       // Count-Sketch counters [t][P * B]
     crop::CsParams cs{};       // ... of the last Count-Sketch run
@@ -219,6 +225,7 @@ struct crop_ctx {
 namespace crop {
 
 // ---- launchers (kernels live in the .hip files) ---------------------------
+BinMap bin_map(const RoutePlan &pl);
 hipError_t launch_validate_tx(const uint32_t *off, uint64_t T, const uint32_t *items,
                               uint64_t nnz, uint32_t n_items, unsigned long long *bad,
                               hipStream_t s);
@@ -322,6 +329,17 @@ hipError_t launch_select_seeds(const float *score, const uint32_t *cx, const uin
 hipError_t launch_max_index(const uint32_t *idx, uint64_t n, uint32_t *out, hipStream_t s);
 int mlp_param_count();
 int mlp_batch_max();
+
+// Grouped bins: entries (out_n) and weights (out_w: counts, or terms when
+// `routed`, over the routed keys before aggregation) of every kept partition.
+hipError_t launch_part_stats(const crop_ctx *c, bool routed, uint32_t *out_n, uint32_t *out_w,
+                             hipStream_t s);
+// Grouped bins [bin0, bin0 + n_bins) to partition-contiguous arrays;
+// partition p starts at dst[p - dst_p0].
+hipError_t launch_gather_grouped(const crop_ctx *c, uint32_t bin0, uint32_t n_bins,
+                                 const uint32_t *dst, uint32_t dst_p0, uint32_t *out_i,
+                                 uint32_t *out_j, uint32_t *out_cnt, float *out_val,
+                                 hipStream_t s);
 
 // Gather the bin-segmented exact result into partition-contiguous arrays.
 hipError_t launch_gather_result(const crop_ctx *c, uint32_t bin0, uint32_t n_bins,

@@ -209,7 +209,7 @@ k_pairs(const uint32_t *__restrict__ top, uint32_t M, uint32_t *__restrict__ cx,
 template <class KeyT>
 __global__ void __launch_bounds__(256)
 k_lookup(const uint32_t *__restrict__ qx, const uint32_t *__restrict__ qy, uint64_t n,
-         HashParams hp, uint64_t NBall, uint32_t bin0, uint32_t NB,
+         HashParams hp, BinMap bm, uint32_t NB,
          const uint32_t *__restrict__ bin_off,
          const uint32_t *__restrict__ bin_size, const KeyT *__restrict__ keys,
          const uint32_t *__restrict__ cnt, uint32_t *__restrict__ out)
@@ -219,7 +219,7 @@ k_lookup(const uint32_t *__restrict__ qx, const uint32_t *__restrict__ qy, uint6
     if (q >= n) return;
     const uint32_t x = qx[q], y = qy[q];
     // the query's bin of the run (a pair outside the owned partitions: none)
-    const uint32_t b = interval_of(hash_a(hp, x) + hash_b(hp, y), NBall) - bin0;
+    const uint32_t b = bm.local(hash_a(hp, x) + hash_b(hp, y));
     const KeyT key = sizeof(KeyT) == 4 ? (KeyT)((x << 16) | y) : (KeyT)(((uint64_t)x << 32) | y);
     const uint32_t s0 = b < NB ? bin_off[b] : 0, ns = b < NB ? bin_size[b] : 0;
     uint32_t found = 0;
@@ -580,13 +580,13 @@ hipError_t launch_lookup(const crop_ctx *c, const uint32_t *qx, const uint32_t *
     const uint64_t blocks = (n * kWave + 255) / 256;
     if (c->in.wide_keys)
         hipLaunchKernelGGL((k_lookup<uint64_t>), dim3((uint32_t)blocks), dim3(256), 0, s, qx, qy, n,
-                           c->hp, c->plan.NBall, c->plan.bin0, c->plan.NB,
+                           c->hp, bin_map(c->plan), c->plan.NB,
                            c->bin_off.as<uint32_t>(),
                            c->bin_size.as<uint32_t>(), c->keys.as<uint64_t>(),
                            c->out_cnt.as<uint32_t>(), out);
     else
         hipLaunchKernelGGL((k_lookup<uint32_t>), dim3((uint32_t)blocks), dim3(256), 0, s, qx, qy, n,
-                           c->hp, c->plan.NBall, c->plan.bin0, c->plan.NB,
+                           c->hp, bin_map(c->plan), c->plan.NB,
                            c->bin_off.as<uint32_t>(),
                            c->bin_size.as<uint32_t>(), c->keys.as<uint32_t>(),
                            c->out_cnt.as<uint32_t>(), out);

@@ -82,7 +82,7 @@ struct BatchChunks {
         v.r0 = crow[c];
         v.r1 = crow[c + 1];
         v.NB = S.NB;
-        v.bm = BinMap{S.NB, 0};
+        v.bm = BinMap{S.NB, 0, S.NB, 0};
         v.row = cnt + S.cnt_base + (size_t)(c - S.chunk0) * S.NB;
         v.nxt = c + 1 < S.chunk0 + S.n_chunks ? v.row + S.NB : bin_off + S.bin_base + 1;
         return v;
@@ -187,7 +187,7 @@ k_tx_scatter(const uint32_t *__restrict__ off, const uint32_t *__restrict__ item
             const uint32_t n = lstart[b1] - s0;
             for (uint32_t i = threadIdx.x; i < n; i += BS) {
                 const KeyT key = stage[i];
-                keys[i + s0 + delta[bin_of_key(key, hp, cv.bm.NBall) - cv.bm.bin0]] = key;
+                keys[i + s0 + delta[cv.bm.local(hash_of_key(key, hp))]] = key;
             }
         }
         __syncthreads();
@@ -337,7 +337,7 @@ k_tx_scatter_ranges(const uint32_t *__restrict__ off, const uint32_t *__restrict
                 const uint32_t n = lstart[b1] - s0;
                 for (uint32_t i = threadIdx.x; i < n; i += BS) {
                     const KeyT key = stage[i];
-                    const uint32_t bin = bin_of_key(key, hp, bm.NBall) - bm.bin0;
+                    const uint32_t bin = bm.local(hash_of_key(key, hp));
                     keys[gcur[bin] + (i + s0 - lstart[bin])] = key;
                 }
             }
@@ -690,7 +690,7 @@ static size_t op_smem_bytes(uint32_t NB, uint32_t max_a, uint32_t BS)
     return sizeof(uint32_t) * ((size_t)NB + 5 * (size_t)max_a + 1 + BS / kWave + 1);
 }
 
-static BinMap bin_map(const RoutePlan &pl) { return BinMap{pl.NBall, pl.bin0}; }
+BinMap bin_map(const RoutePlan &pl) { return BinMap{pl.M, pl.u0, pl.nu, pl.g}; }
 
 static SingleChunks single_chunks(const crop_ctx *c, uint32_t *cnt)
 {

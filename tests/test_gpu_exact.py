@@ -49,6 +49,14 @@ def compare_all_partitions(crop, ctx, st, P, seed=SEED, **tune):
     assert np.array_equal(terms, ref["part_terms"]), "terms per partition"
     assert np.array_equal(sizes, ref["part_sizes"]), "entries per partition"
     i, j, c, part_off = crop.crop_read_all(ctx, P)
+    if P > 4096:
+        # vectorised: label every entry with the partition read_all put it
+        # in, sort by (partition, x, y) as the oracle does, compare whole
+        lab = np.repeat(np.arange(P), np.diff(part_off.astype(np.int64)))
+        o = np.lexsort((j, i, lab))
+        assert np.array_equal(i[o], ref["x"]) and np.array_equal(j[o], ref["y"])
+        assert np.array_equal(c[o], ref["cnt"])
+        return sizes
     start = np.concatenate([[0], np.cumsum(ref["part_sizes"].astype(np.int64))])
     for p in range(P):
         a, b = int(part_off[p]), int(part_off[p + 1])
@@ -112,7 +120,58 @@ def test_maximum_partitions_and_top_ids(crop, ctx):
                               int(top) + st.n)
     compare_all_partitions(crop, ctx, hi, 64)
     with pytest.raises(crop.CropError):
-        crop.crop_set_partitions(ctx, 8193)
+        crop.crop_set_partitions(ctx, (1 << 20) + 1)
+
+
+@pytest.mark.parametrize("P", [8193, 65537, 1 << 20])
+def test_grouped_partitions_on_small_config(crop, ctx, P):
+    """More partitions than routing bins (Section 6, Theorem 1 with P up to
+    2^20, the order of the paper's own runs in Table 4): a bin holds 2^g
+    consecutive partitions, and per-partition sizes, terms and entry sets
+    still equal the oracle's for the 2,000-transaction workload."""
+    st = datagen.config_small()
+    sizes = compare_all_partitions(crop, ctx, st, P)
+    assert (sizes > 0).sum() > min(P, 20000) // 4
+    # single partitions read back alone equal their slice of read_all
+    i, j, c, part_off = crop.crop_read_all(ctx, P)
+    for p in [0, 1, P // 2, P - 1] + list(np.flatnonzero(sizes)[:5]):
+        n = int(sizes[p])
+        pi, pj, pc = crop.crop_read_partition(ctx, int(p), max(n, 1))
+        a, b = int(part_off[p]), int(part_off[p + 1])
+        assert b - a == n == len(pi)
+        for u, v in zip(sort_xyc(pi, pj, pc), sort_xyc(i[a:b], j[a:b], c[a:b])):
+            assert np.array_equal(u, v)
+
+
+@pytest.mark.parametrize("P", [65537, 1 << 20])
+def test_grouped_partitions_owned_range(crop, ctx, P):
+    """An owned range of a grouped run: the range's bins cut partitions at
+    both ends, the others read back empty."""
+    st = datagen.config_small()
+    p0, p1 = P // 3 + 5, P // 3 + 5 + P // 7
+    crop.crop_set_partitions(ctx, P)
+    crop.crop_set_seed(ctx, SEED)
+    crop.crop_set_owned_partitions(ctx, p0, p1)
+    crop.crop_load_transactions(ctx, st.off, st.items, st.n)
+    crop.crop_run_exact(ctx)
+    sizes, terms = crop.crop_result_sizes(ctx, P)
+    ref = oracle.tx_exact(st.off, st.items, P, SEED)
+    want_s = ref["part_sizes"].copy()
+    want_t = ref["part_terms"].copy()
+    want_s[:p0] = 0
+    want_s[p1:] = 0
+    want_t[:p0] = 0
+    want_t[p1:] = 0
+    np.testing.assert_array_equal(sizes, want_s)
+    np.testing.assert_array_equal(terms, want_t)
+    i, j, c, part_off = crop.crop_read_all(ctx, P)
+    lab = np.repeat(np.arange(P), np.diff(part_off.astype(np.int64)))
+    o = np.lexsort((j, i, lab))
+    start = np.concatenate([[0], np.cumsum(ref["part_sizes"].astype(np.int64))])
+    a, b = start[p0], start[p1]
+    np.testing.assert_array_equal(i[o], ref["x"][a:b])
+    np.testing.assert_array_equal(j[o], ref["y"][a:b])
+    np.testing.assert_array_equal(c[o], ref["cnt"][a:b])
 
 
 def test_wide_keys(crop, ctx):
@@ -265,6 +324,13 @@ def compare_outer(crop, ctx, op, P, seed=SEED, **tune):
     assert np.array_equal(terms, ref["part_terms"])
     assert np.array_equal(sizes, ref["part_sizes"])
     i, j, v, part_off = crop.crop_read_all(ctx, P, outer=True)
+    if P > 4096:
+        lab = np.repeat(np.arange(P), np.diff(part_off.astype(np.int64)))
+        o = np.lexsort((j, i, lab))
+        assert np.array_equal(i[o], ref["i"]) and np.array_equal(j[o], ref["j"])
+        err = np.abs(v[o].astype(np.float64) - ref["sum"])
+        assert np.all(err <= 1e-5 * ref["abs"])
+        return float(np.max(err / np.maximum(ref["abs"], 1e-300))) if len(err) else 0.0
     start = np.concatenate([[0], np.cumsum(ref["part_sizes"].astype(np.int64))])
     worst = 0.0
     for p in range(P):
@@ -288,6 +354,14 @@ def compare_outer(crop, ctx, op, P, seed=SEED, **tune):
 def test_outer_tiny(crop, ctx, seed):
     op = datagen.tiny_outer(seed, K=40 + seed, n_rows=50, n_cols=60, max_nnz=20)
     compare_outer(crop, ctx, op, [1, 4, 8, 3, 16, 2][seed], seed=seed + 11)
+
+
+@pytest.mark.parametrize("P", [65537, 1 << 20])
+def test_outer_grouped_partitions(crop, ctx, P):
+    """fp32 sums with more partitions than routing bins: per-partition terms
+    (from the routed terms) and entries (from the sums) equal the oracle's."""
+    op = datagen.tiny_outer(5, K=300, n_rows=400, n_cols=300, max_nnz=30)
+    compare_outer(crop, ctx, op, P, seed=77)
 
 
 def test_outer_config(crop, ctx):

@@ -440,3 +440,78 @@ def test_seeding_gain_over_plain_summary(crop, ctx, torch):
         assert res["seeded"]["gap"] <= res["plain"]["gap"]
     finally:
         crop.crop_mlp_destroy(mlp)
+
+
+def _fisher_yates_order(seed, n, epochs):
+    """The predictor's minibatch order, restated: one Fisher-Yates
+    permutation per epoch driven by SplitMix64, j = (word * (i + 1)) >> 64."""
+    m64 = (1 << 64) - 1
+    s = seed & m64
+    out = []
+    for _ in range(epochs):
+        p = list(range(n))
+        for i in range(n - 1, 0, -1):
+            s = (s + 0x9E3779B97F4A7C15) & m64
+            z = s
+            z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & m64
+            z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & m64
+            z ^= z >> 31
+            j = (z * (i + 1)) >> 64
+            p[i], p[j] = p[j], p[i]
+        out += p
+    return np.array(out, np.int32)
+
+
+def test_predictor_object_matches_stepwise_calls(crop, ctx, torch):
+    """crop_predictor_train / score / free give exactly what the step-wise
+    calls give with the same inputs: the same trained weights (labels from
+    exact runs, the same minibatch order) and the same seeds."""
+    from paper_1210_0461_amd import seeding
+    streams = [datagen.transactions(20000, 3000, 1.1, 10.0, 64, datagen.Raw(7100 + k), f"p{k}")
+               for k in range(3)]
+    M, epochs, bs, lr, sseed = 64, 2, 128, 3e-3, 99
+    init = seeding.flat_init(datagen.mlp_init_weights(17))
+    crop.crop_set_partitions(ctx, 16)
+    crop.crop_set_seed(ctx, SEED)
+    held = datagen.transactions(20000, 3000, 1.1, 10.0, 64, datagen.Raw(7200), "held")
+    crop.crop_load_transactions(ctx, held.off, held.items, held.n)
+    pred = crop.crop_predictor_train(ctx, [(s.off, s.items, s.n) for s in streams],
+                                     top_items=M, epochs=epochs, batch=bs, lr=lr,
+                                     shuffle_seed=sseed, init=init)
+    try:
+        # the caller's loaded stream is untouched: an exact run still works on it
+        crop.crop_run_exact(ctx)
+        w_obj, loss_obj = crop.crop_predictor_params(ctx, pred)
+        # step-wise
+        Zs, ys = [], []
+        for s in streams:
+            crop.crop_load_transactions(ctx, s.off, s.items, s.n)
+            Z, y, _, _, _ = seeding.training_pairs(ctx, s.T, s.n, M)
+            Zs.append(Z)
+            ys.append(y)
+        Z = torch.cat(Zs)
+        y = torch.cat(ys)
+        order = torch.from_numpy(_fisher_yates_order(sseed, Z.shape[0], epochs)).cuda()
+        mlp = crop.crop_mlp_create(ctx, init)
+        try:
+            crop.crop_mlp_train(ctx, mlp, Z, y, order, bs, lr)
+            w_step = crop.crop_mlp_params(ctx, mlp)
+            np.testing.assert_array_equal(w_obj, w_step)
+            assert loss_obj == crop.crop_mlp_loss(ctx, mlp)
+            crop.crop_load_transactions(ctx, held.off, held.items, held.n)
+            R = 50
+            sx = torch.zeros(R, dtype=torch.int32, device="cuda")
+            sy = torch.zeros(R, dtype=torch.int32, device="cuda")
+            n = crop.crop_predictor_score(ctx, pred, R, sx, sy)
+            assert n == R
+            tx, ty, _ = seeding.predict_seeds(ctx, mlp, held.T, held.n, M, R)
+            torch.cuda.synchronize()
+            np.testing.assert_array_equal(sx.cpu().numpy(), tx.cpu().numpy())
+            np.testing.assert_array_equal(sy.cpu().numpy(), ty.cpu().numpy())
+            assert np.all(sx.cpu().numpy() < sy.cpu().numpy())
+        finally:
+            crop.crop_mlp_destroy(mlp)
+    finally:
+        crop.crop_predictor_free(pred)
+    with pytest.raises(crop.CropError):
+        crop.crop_predictor_train(ctx, [], top_items=M)

@@ -259,3 +259,27 @@ def test_wide_item_ids(crop, ctx, P, C, ell):
     exact, _ = exact_map(st)
     check_invariants(s, exact, SEED)
     check_topk_is_summary_topk(s, top, K)
+
+
+@pytest.mark.parametrize("P,C,ell", [(65537, 16, 16), (1 << 20, 4, 4)])
+def test_grouped_partitions_invariants_and_topk(crop, ctx, P, C, ell):
+    """P above the routing-bin limit: one bin holds the buckets of 2^g
+    consecutive partitions (the last bin partly), and every bucket still
+    satisfies the Section 4 invariants with the oracle's exact counts; the
+    state is padded to whole bins and the padding stays unused."""
+    st = datagen.config_small()
+    exact, _ = exact_map(st)
+    crop.crop_set_partitions(ctx, P)
+    crop.crop_set_seed(ctx, SEED)
+    crop.crop_set_summary(ctx, C, ell)
+    crop.crop_load_transactions(ctx, st.off, st.items, st.n)
+    crop.crop_run_topk(ctx, 100)
+    real = P * C
+    s = crop.crop_read_summary(ctx, real + (1 << 16) * C)
+    assert real <= len(s["x"]) < real + 8192 * C
+    assert not s["used"][real:].any()
+    s = {k: v[:real] for k, v in s.items()}
+    s.update(P=P, B=C // ell, ell=ell)
+    check_invariants(s, exact, SEED)
+    top = crop.crop_read_topk(ctx, 100)
+    check_topk_is_summary_topk(s, top, 100)

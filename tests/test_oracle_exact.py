@@ -176,3 +176,18 @@ def test_outer_config_term_count():
     La = np.diff(op.a_off.astype(np.int64))
     Lb = np.diff(op.b_off.astype(np.int64))
     assert oracle.op_num_terms(op.a_off, op.b_off) == int((La * Lb).sum())
+
+
+@pytest.mark.parametrize("P,threads", [(1, 1), (8, 3), (1024, 8), (7, 7)])
+def test_cpu_crop_baseline_matches_oracle(P, threads):
+    """The host run of the paper's method (the benchmark's multi-core
+    baseline: owners enumerate their hash interval through the h_b-sorted
+    windows of Lemma 1, wrap included) gives the oracle's per-partition
+    sizes and terms."""
+    for st in (datagen.config_small(), datagen.tiny_transactions(5, T=300, n=50, cap=30)):
+        seed = 0x243F6A8885A308D3
+        ps, pt, d = oracle.cpu_crop_tx(st.off, st.items, P, seed, threads)
+        r = oracle.tx_exact(st.off, st.items, P, seed)
+        np.testing.assert_array_equal(ps, r["part_sizes"])
+        np.testing.assert_array_equal(pt, r["part_terms"])
+        assert d == len(r["x"])
