@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define CROP_ABI_VERSION 2
+#define CROP_ABI_VERSION 3
 
 typedef enum crop_status {
     CROP_OK = 0,
@@ -72,7 +72,14 @@ typedef struct crop_tune {
                                     its slot; >= 1024 stages up to that many
                                     keys per window in LDS, sorted by bin     */
     uint32_t route;              /* transactions: CROP_ROUTE_*                */
+    uint32_t window;             /* owned shares: CROP_WINDOW_*               */
 } crop_tune;
+
+/* How an exact run that owns at most half of the hash space finds its terms:
+ * through h_b-bucketed windows of every transaction (Section 5, Lemma 1: the
+ * owner's entries without enumerating the others; the default), or by
+ * enumerating every term and keeping the owned ones. */
+enum { CROP_WINDOW_AUTO = 0, CROP_WINDOW_OFF = 1 };
 
 /* How the routing offsets of a transaction stream are built: one count row
  * per chunk (a [chunk x bin] matrix), or one row per workgroup that walks a

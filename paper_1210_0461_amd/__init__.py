@@ -56,7 +56,8 @@ class crop_train_opts(ctypes.Structure):
 
 class crop_tune(ctypes.Structure):
     _fields_ = [("bins_per_partition", ctypes.c_uint32), ("rows_per_chunk", ctypes.c_uint32),
-                ("stage_keys", ctypes.c_uint32), ("route", ctypes.c_uint32)]
+                ("stage_keys", ctypes.c_uint32), ("route", ctypes.c_uint32),
+                ("window", ctypes.c_uint32)]
 
 
 # torch ships its own HIP runtime under the same soname (libamdhip64.so.7).
@@ -268,11 +269,13 @@ def crop_use_own_stream(ctx) -> None:
 CROP_ROUTE_AUTO = 0
 CROP_ROUTE_CHUNKS = 1
 CROP_ROUTE_RANGES = 2
+CROP_WINDOW_AUTO = 0
+CROP_WINDOW_OFF = 1
 
 
 def crop_set_tuning(ctx, bins_per_partition=0, rows_per_chunk=0, stage_keys=0,
-                    route=CROP_ROUTE_AUTO) -> None:
-    t = crop_tune(bins_per_partition, rows_per_chunk, stage_keys, route)
+                    route=CROP_ROUTE_AUTO, window=0) -> None:
+    t = crop_tune(bins_per_partition, rows_per_chunk, stage_keys, route, window)
     _check(ctx, _lib.crop_set_tuning(ctx, ctypes.byref(t)))
 
 

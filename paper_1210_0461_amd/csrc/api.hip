@@ -161,6 +161,27 @@ static crop_status plan_bins(crop_ctx *ctx, uint32_t S, uint64_t terms_per_bin, 
     return CROP_OK;
 }
 
+// An owned share of at most half the hash space enumerates through h_b
+// windows (Lemma 1) instead of every term: the owned interval is [q, r) with
+// q = ceil(u0 2^32 / M), r = ceil((u0 + nu) 2^32 / M), and the bucket bits
+// make a bucket about a quarter of the window (at most 32 per row).
+static void plan_window(crop_ctx *ctx)
+{
+    RoutePlan &pl = ctx->plan;
+    pl.win_kb = pl.win_q = pl.win_W = 0;
+    if (ctx->tune.window == CROP_WINDOW_OFF || pl.n_wg || pl.stage_cap) return;
+    const uint64_t q = (((uint64_t)pl.u0 << 32) + pl.M - 1) / pl.M;
+    const uint64_t r = ((((uint64_t)pl.u0 + pl.nu) << 32) + pl.M - 1) / pl.M;
+    const uint64_t W = r - q;
+    if (W == 0 || W > (1ull << 31)) return;
+    uint32_t kb = 2;
+    while (kb < 5 && (1ull << (32 - kb)) > W / 4) ++kb;
+    if (!tx_win_layout_ok(pl.NB, pl.R, kb, pl.max_items)) return;
+    pl.win_kb = kb;
+    pl.win_q = (uint32_t)q;
+    pl.win_W = (uint32_t)W;
+}
+
 crop_status plan_tx(crop_ctx *ctx, uint32_t S_force = 0, int g_req = -1)
 {
     Input &in = ctx->in;
@@ -224,6 +245,7 @@ crop_status plan_tx(crop_ctx *ctx, uint32_t S_force = 0, int g_req = -1)
     pl.G = std::max<uint32_t>(1, std::min<uint32_t>(64, pl.n_wg ? pl.n_wg / 16 : pl.n_chunks));
     if (!tx_launch_layouts_ok(pl.NB, pl.max_items, pl.stage_cap, in.wide_keys))
         return fail(ctx, CROP_E_UNSUPPORTED, "chunk image does not fit its LDS layout");
+    plan_window(ctx);
     return CROP_OK;
 }
 
@@ -647,6 +669,8 @@ crop_status crop_set_tuning(crop_ctx *ctx, const crop_tune *t)
         return fail(ctx, CROP_E_ARG, "route must be CROP_ROUTE_AUTO, _CHUNKS or _RANGES");
     if (t->stage_keys && t->stage_keys < 1024)
         return fail(ctx, CROP_E_ARG, "stage_keys must be 0 (automatic) or at least 1024");
+    if (t->window > CROP_WINDOW_OFF)
+        return fail(ctx, CROP_E_ARG, "window must be CROP_WINDOW_AUTO or CROP_WINDOW_OFF");
     ctx->tune = *t;
     return CROP_OK;
 }
@@ -691,6 +715,7 @@ crop_status crop_get_tuning(const crop_ctx *ctx, crop_tune *out)
     out->rows_per_chunk = ctx->plan.R;
     out->stage_keys = ctx->plan.stage_cap;
     out->route = ctx->plan.n_wg ? CROP_ROUTE_RANGES : CROP_ROUTE_CHUNKS;
+    out->window = ctx->plan.win_kb ? CROP_WINDOW_AUTO : CROP_WINDOW_OFF;
     return CROP_OK;
 }
 
@@ -821,6 +846,7 @@ crop_status crop_run_exact(crop_ctx *ctx)
     if (st != CROP_OK) return st;
     if (pl.n_chunks) CK(outer ? launch_op_count(ctx, cnt, s)
                               : pl.n_wg ? launch_tx_count_ranges(ctx, cnt, s)
+                              : pl.win_kb ? launch_tx_count_win(ctx, cnt, s)
                                         : launch_tx_count(ctx, cnt, s));
     STAGE("count");
     CK(launch_scan_counts(cnt, pl.n_wg ? pl.n_wg : pl.n_chunks, pl.NB, pl.G,
@@ -831,6 +857,7 @@ crop_status crop_run_exact(crop_ctx *ctx)
     if (pl.n_chunks)
         CK(outer ? launch_op_scatter(ctx, cnt, ctx->keys.p, ctx->vals.as<float>(), s)
                  : pl.n_wg ? launch_tx_scatter_ranges(ctx, cnt, ctx->keys.p, s)
+                 : pl.win_kb ? launch_tx_scatter_win(ctx, cnt, ctx->keys.p, s)
                            : launch_tx_scatter(ctx, cnt, ctx->keys.p, s));
     STAGE("scatter");
     // grouped bins: per-partition terms from the routed keys (outer products;

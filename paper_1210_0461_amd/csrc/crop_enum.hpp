@@ -103,6 +103,104 @@ __device__ inline KeyT pack_key(uint32_t x, uint32_t y)
     return (KeyT)(((uint64_t)x << 32) | y);
 }
 
+// ---- an owner's terms through hash-bucketed windows (Lemma 1)
+//
+// The owner of the hash interval [q, q + W) needs, for each item x of a
+// transaction, the partners y with (h_a(x) + h_b(y)) mod 2^32 in it, i.e.
+// with h_b(y) in the window [q - h_a(x), q - h_a(x) + W) mod 2^32: one arc of
+// the circular h_b order, two runs of a sorted list where it wraps (Section
+// 5, proof of Lemma 1).  Each transaction of the chunk is bucket-sorted by
+// the top kb bits of h_b (the hash-and-bucket step of Figure 1; a counting
+// sort over (row, bucket)), an entry visits only the buckets its window
+// covers, and the exact window test and y > x pick the owner's pairs.
+// Requires W <= 2^31, so the two runs of a wrapping window never share a
+// bucket.
+struct WinLds {
+    uint32_t *hist;  // (rows << kb) + 1: exclusive starts, then (after placement) ends
+    uint2 *yh;       // (item, h_b) in (row, bucket) order
+    uint16_t *row;   // chunk row of each sorted entry
+};
+
+__device__ inline WinLds win_lds(uint32_t *smem, uint32_t lead, uint32_t rows, uint32_t kb,
+                                 uint32_t max_items)
+{
+    const WinLayout t = win_layout(lead, rows, kb, max_items);
+    WinLds L;
+    L.hist = smem + t.hist;
+    L.yh = reinterpret_cast<uint2 *>(smem + t.yh);
+    L.row = reinterpret_cast<uint16_t *>(smem + t.row);
+    return L;
+}
+
+// Stage rows [r0, r1) bucket-sorted; returns the number of entries.  After
+// the call hist[i] holds the end of (row, bucket) slot i, so slot i spans
+// [i ? hist[i - 1] : 0, hist[i]).
+template <int BS>
+__device__ inline uint32_t stage_tx_win(const uint32_t *__restrict__ off,
+                                        const uint32_t *__restrict__ items, uint32_t r0,
+                                        uint32_t r1, uint32_t kb, const HashParams &hp,
+                                        const WinLds &L, uint32_t *s_tmp)
+{
+    const uint32_t p0 = off[r0];
+    const uint32_t m = off[r1] - p0;
+    const uint32_t nh = (r1 - r0) << kb;
+    const uint32_t sh = 32 - kb;
+    for (uint32_t i = threadIdx.x; i <= nh; i += BS) L.hist[i] = 0;
+    __syncthreads();
+    for (uint32_t r = r0 + threadIdx.x; r < r1; r += BS) {
+        const uint32_t base = (r - r0) << kb;
+        for (uint32_t k = off[r]; k < off[r + 1]; ++k)
+            atomicAdd(&L.hist[base + (hash_b(hp, items[k]) >> sh)], 1u);
+    }
+    __syncthreads();
+    lds_exclusive_scan<BS>(L.hist, nh, s_tmp);
+    for (uint32_t r = r0 + threadIdx.x; r < r1; r += BS) {
+        const uint32_t base = (r - r0) << kb;
+        for (uint32_t k = off[r]; k < off[r + 1]; ++k) {
+            const uint32_t y = items[k], hb = hash_b(hp, y);
+            const uint32_t pos = atomicAdd(&L.hist[base + (hb >> sh)], 1u);
+            L.yh[pos] = make_uint2(y, hb);
+            L.row[pos] = (uint16_t)(r - r0);
+        }
+    }
+    __syncthreads();
+    return m;
+}
+
+// visit(x, y, h) for every pair x < y of the staged chunk whose hash lies in
+// [q, q + W).
+template <int BS, class Visit>
+__device__ inline void enum_tx_win(uint32_t m, uint32_t kb, uint32_t q, uint32_t W,
+                                   const WinLds &L, const HashParams &hp, Visit visit)
+{
+    const uint32_t sh = 32 - kb;
+    auto start = [&](uint32_t i) { return i ? L.hist[i - 1] : 0u; };
+    for (uint32_t j = threadIdx.x; j < m; j += BS) {
+        const uint32_t x = L.yh[j].x;
+        const uint32_t base = (uint32_t)L.row[j] << kb;
+        const uint32_t ha = hash_a(hp, x);
+        const uint32_t lo = q - ha;                 // window [lo, lo + W) mod 2^32
+        const uint32_t last = lo + (W - 1);
+        const uint32_t b0 = lo >> sh, b1 = last >> sh;
+        uint32_t a0 = start(base + b0), e0, a1 = 0, e1 = 0;
+        if (b1 >= b0 && last >= lo) {
+            e0 = start(base + b1 + 1);
+        } else {                                    // wraps past 2^32: two runs
+            e0 = start(base + (1u << kb));
+            a1 = start(base);
+            e1 = start(base + b1 + 1);
+        }
+        for (uint32_t i = a0; i < e0; ++i) {
+            const uint2 yh = L.yh[i];
+            if (yh.x > x && yh.y - lo < W) visit(x, yh.x, ha + yh.y);
+        }
+        for (uint32_t i = a1; i < e1; ++i) {
+            const uint2 yh = L.yh[i];
+            if (yh.x > x && yh.y - lo < W) visit(x, yh.x, ha + yh.y);
+        }
+    }
+}
+
 // ---- outer products
 
 // Stage the a-entries [a_lo, a_hi) of vectors k0..k1-1: s_ai = index,

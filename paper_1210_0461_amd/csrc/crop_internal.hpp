@@ -62,6 +62,9 @@ struct RoutePlan {
     uint32_t G = 1;          // row groups of the count-matrix scan
     uint32_t n_wg = 0;       // transactions: workgroups of the range kernels
                              // (0: one count row per chunk)
+    // windowed enumeration of an owned share (Lemma 1): the owned hash
+    // interval [win_q, win_q + win_W) and the h_b bucket bits (0: off)
+    uint32_t win_kb = 0, win_q = 0, win_W = 0;
     uint32_t log2_slots = 14;
     uint32_t BS = 256;
     uint32_t ss_mb = 0;      // Space-Saving micro-batch of the last top-K plan
@@ -241,6 +244,12 @@ hipError_t launch_hash_pairs(const uint32_t *qx, const uint32_t *qy, uint64_t n,
                              hipStream_t s);
 
 hipError_t launch_tx_count(const crop_ctx *c, uint32_t *cnt, hipStream_t s);
+// Owned shares with windowed enumeration (plan.win_kb > 0).
+size_t tx_win_smem_bytes(uint32_t NB, uint32_t R, uint32_t kb, uint32_t max_items);
+bool tx_win_layout_ok(uint32_t NB, uint32_t R, uint32_t kb, uint32_t max_items);
+hipError_t launch_tx_count_win(const crop_ctx *c, uint32_t *cnt, hipStream_t s);
+hipError_t launch_tx_scatter_win(const crop_ctx *c, const uint32_t *cur, void *keys,
+                                 hipStream_t s);
 // Range kernels: n_wg workgroups, each over a contiguous range of chunks;
 // the count matrix is [n_wg x NB].
 hipError_t launch_tx_count_ranges(const crop_ctx *c, uint32_t *cnt, hipStream_t s);

@@ -56,4 +56,37 @@ __host__ __device__ inline bool tx_layout_ok(uint32_t lead, uint32_t max_items, 
     return 4 * t.end <= smem_bytes;
 }
 
+// LDS image of a chunk for windowed enumeration (an owner's share of the
+// hash space), after `lead` 32-bit words: hist, the (rows << kb) + 1
+// exclusive starts of every (row, h_b bucket); yh, (item, h_b) of each entry
+// in (row, bucket) order, 8-byte aligned; row, the chunk row of each sorted
+// entry (u16, padded to a whole word).
+struct WinLayout {
+    size_t hist, yh, row, end;
+};
+
+__host__ __device__ inline WinLayout win_layout(uint32_t lead, uint32_t rows, uint32_t kb,
+                                                uint32_t max_items)
+{
+    WinLayout t;
+    t.hist = lead;
+    const size_t nh = ((size_t)rows << kb) + 1;
+    t.yh = (t.hist + nh + 1) & ~(size_t)1;
+    t.row = t.yh + 2 * (size_t)max_items;
+    t.end = t.row + ((size_t)max_items + 1) / 2;
+    return t;
+}
+
+__host__ __device__ inline bool win_layout_ok(uint32_t lead, uint32_t rows, uint32_t kb,
+                                              uint32_t max_items, size_t smem_bytes)
+{
+    const WinLayout t = win_layout(lead, rows, kb, max_items);
+    if (t.hist < lead || t.yh % 2 != 0) return false;
+    if (t.yh < t.hist + ((size_t)rows << kb) + 1) return false;
+    if (t.row < t.yh + 2 * (size_t)max_items) return false;
+    if (2 * (t.end - t.row) < max_items) return false;
+    if (rows > 65535 || max_items > 65535) return false;  // u16 rows and positions
+    return 4 * t.end <= smem_bytes;
+}
+
 }  // namespace crop

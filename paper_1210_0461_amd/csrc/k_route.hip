@@ -219,6 +219,58 @@ k_tx_scatter_direct(const uint32_t *__restrict__ off, const uint32_t *__restrict
     });
 }
 
+// ---- an owner's share: windowed enumeration (one chunk per workgroup)
+//
+// The count and scatter of a run that owns the hash interval [q, q + W)
+// with W <= 2^31: each chunk is bucket-sorted by h_b and every entry walks
+// only its window (enum_tx_win), so the enumeration costs the owner's terms
+// plus the window searches instead of every term of the stream.
+
+template <int BS>
+__global__ void __launch_bounds__(BS)
+k_tx_count_win(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items, HashParams hp,
+               uint32_t NB, BinMap bm, uint32_t max_items, uint32_t T, uint32_t R, uint32_t kb,
+               uint32_t q, uint32_t W, uint32_t *__restrict__ cnt)
+{
+    extern __shared__ uint32_t smem[];
+    __shared__ uint32_t s_tmp[BS / kWave + 1];
+    uint32_t *hist = smem;
+    const WinLds L = win_lds(smem, NB, R, kb, max_items);
+    const uint32_t chunk = xcd_contiguous(blockIdx.x, gridDim.x);
+    const uint32_t r0 = chunk * R, r1 = min(r0 + R, T);
+    for (uint32_t b = threadIdx.x; b < NB; b += BS) hist[b] = 0;
+    const uint32_t m = stage_tx_win<BS>(off, items, r0, r1, kb, hp, L, s_tmp);
+    enum_tx_win<BS>(m, kb, q, W, L, hp, [&](uint32_t, uint32_t, uint32_t h) {
+        const uint32_t bin = bm.local(h);
+        if (bin < NB) atomicAdd(&hist[bin], 1u);
+    });
+    __syncthreads();
+    uint32_t *row = cnt + (size_t)chunk * NB;
+    for (uint32_t b = threadIdx.x; b < NB; b += BS) row[b] = hist[b];
+}
+
+template <int BS, class KeyT>
+__global__ void __launch_bounds__(BS)
+k_tx_scatter_win(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
+                 HashParams hp, uint32_t NB, BinMap bm, uint32_t max_items, uint32_t T,
+                 uint32_t R, uint32_t kb, uint32_t q, uint32_t W,
+                 const uint32_t *__restrict__ cur, KeyT *__restrict__ keys)
+{
+    extern __shared__ uint32_t smem[];
+    __shared__ uint32_t s_tmp[BS / kWave + 1];
+    uint32_t *lcur = smem;
+    const WinLds L = win_lds(smem, NB, R, kb, max_items);
+    const uint32_t chunk = xcd_contiguous(blockIdx.x, gridDim.x);
+    const uint32_t r0 = chunk * R, r1 = min(r0 + R, T);
+    const uint32_t *row = cur + (size_t)chunk * NB;
+    for (uint32_t b = threadIdx.x; b < NB; b += BS) lcur[b] = row[b];
+    const uint32_t m = stage_tx_win<BS>(off, items, r0, r1, kb, hp, L, s_tmp);
+    enum_tx_win<BS>(m, kb, q, W, L, hp, [&](uint32_t x, uint32_t y, uint32_t h) {
+        const uint32_t bin = bm.local(h);
+        if (bin < NB) keys[atomicAdd(&lcur[bin], 1u)] = pack_key<KeyT>(x, y);
+    });
+}
+
 // ---- chunk ranges: one workgroup per contiguous range of chunks
 
 // The range of chunks of workgroup w when n_chunks chunks are split over
@@ -735,6 +787,45 @@ hipError_t launch_tx_scatter(const crop_ctx *c, const uint32_t *cur, void *keys,
         hipLaunchKernelGGL((k_tx_scatter<1024, uint32_t, SingleChunks>), dim3(pl.n_chunks),
                            dim3(1024), sm, s, c->in.off, c->in.items, c->hp, pl.NB, pl.max_items,
                            ch, static_cast<uint32_t *>(keys), pl.stage_cap);
+    return hipGetLastError();
+}
+
+size_t tx_win_smem_bytes(uint32_t NB, uint32_t R, uint32_t kb, uint32_t max_items)
+{
+    return 4 * win_layout(NB, R, kb, max_items).end;
+}
+
+bool tx_win_layout_ok(uint32_t NB, uint32_t R, uint32_t kb, uint32_t max_items)
+{
+    const size_t sm = tx_win_smem_bytes(NB, R, kb, max_items);
+    return sm <= 160 * 1024 && win_layout_ok(NB, R, kb, max_items, sm);
+}
+
+hipError_t launch_tx_count_win(const crop_ctx *c, uint32_t *cnt, hipStream_t s)
+{
+    const RoutePlan &pl = c->plan;
+    const size_t sm = tx_win_smem_bytes(pl.NB, pl.R, pl.win_kb, pl.max_items);
+    hipLaunchKernelGGL(k_tx_count_win<kCountBS>, dim3(pl.n_chunks), dim3(kCountBS), sm, s,
+                       c->in.off, c->in.items, c->hp, pl.NB, bin_map(pl), pl.max_items,
+                       (uint32_t)c->in.T, pl.R, pl.win_kb, pl.win_q, pl.win_W, cnt);
+    return hipGetLastError();
+}
+
+hipError_t launch_tx_scatter_win(const crop_ctx *c, const uint32_t *cur, void *keys,
+                                 hipStream_t s)
+{
+    const RoutePlan &pl = c->plan;
+    const size_t sm = tx_win_smem_bytes(pl.NB, pl.R, pl.win_kb, pl.max_items);
+    if (c->in.wide_keys)
+        hipLaunchKernelGGL((k_tx_scatter_win<kScatterBS, uint64_t>), dim3(pl.n_chunks),
+                           dim3(kScatterBS), sm, s, c->in.off, c->in.items, c->hp, pl.NB,
+                           bin_map(pl), pl.max_items, (uint32_t)c->in.T, pl.R, pl.win_kb,
+                           pl.win_q, pl.win_W, cur, static_cast<uint64_t *>(keys));
+    else
+        hipLaunchKernelGGL((k_tx_scatter_win<kScatterBS, uint32_t>), dim3(pl.n_chunks),
+                           dim3(kScatterBS), sm, s, c->in.off, c->in.items, c->hp, pl.NB,
+                           bin_map(pl), pl.max_items, (uint32_t)c->in.T, pl.R, pl.win_kb,
+                           pl.win_q, pl.win_W, cur, static_cast<uint32_t *>(keys));
     return hipGetLastError();
 }
 

@@ -386,17 +386,21 @@ def test_outer_heavy_vector(crop, ctx):
 
 # ------------------------------------------------------------------ owned partitions
 
+@pytest.mark.parametrize("window", [0, 1])
 @pytest.mark.parametrize("P,p0,p1,S", [(16, 3, 7, 0), (16, 0, 1, 2), (16, 15, 16, 0), (8, 0, 8, 0),
-                                      (1024, 512, 640, 0)])
-def test_owned_partitions_match_interval_oracle(crop, ctx, P, p0, p1, S):
+                                      (1024, 512, 640, 0), (8, 0, 4, 0), (8, 4, 8, 0),
+                                      (8, 2, 7, 0)])
+def test_owned_partitions_match_interval_oracle(crop, ctx, P, p0, p1, S, window):
     """Exact run restricted to the owned partitions [p0, p1): the oracle's
     result over the hash interval of those partitions (Lemma 1's owner set);
-    the other partitions read back empty."""
+    the other partitions read back empty.  window 0 walks the h_b windows of
+    each transaction (shares of at most half the hash space), window 1
+    enumerates every term and keeps the owned ones."""
     st = datagen.config_small()
     crop.crop_set_partitions(ctx, P)
     crop.crop_set_seed(ctx, SEED)
     crop.crop_set_owned_partitions(ctx, p0, p1)
-    crop.crop_set_tuning(ctx, bins_per_partition=S)
+    crop.crop_set_tuning(ctx, bins_per_partition=S, window=window)
     crop.crop_load_transactions(ctx, st.off, st.items, st.n)
     crop.crop_run_exact(ctx)
     q, _ = oracle.partition_interval(p0, P)
@@ -421,6 +425,52 @@ def test_owned_partitions_match_interval_oracle(crop, ctx, P, p0, p1, S):
     e = crop.crop_read_partition(ctx, (p1 % P), 10) if p1 < P else None
     if e is not None:
         assert e[0].shape[0] == 0
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_windowed_share_equals_interval_oracle_on_random_streams(crop, ctx, seed):
+    """Lemma 1's windowed enumeration against the interval oracle on random
+    tiny streams and random owner intervals.  A share's window wraps past
+    2^32 for the items x with (q - h_a(x)) mod 2^32 + W > 2^32 (two runs of
+    the sorted h_b order); the larger shares here have many such items, and
+    the windowed and the enumerate-all paths must give the same sets."""
+    st = datagen.tiny_transactions(900 + seed, T=120 + 37 * seed, n=60 + 11 * seed, cap=40,
+                                   mean_len=9.0)
+    r = datagen.Raw(1000 + seed)
+    P = [2, 8, 64, 1000, 4096][seed % 5]
+    span = max(1, min(P // 2, int(r.randint(1, 1, max(1, P // 2))[0])))
+    p0 = int(r.randint(1, 0, P - span)[0])
+    p1 = p0 + span
+    hseed = 0x1234567 + 31 * seed
+    crop.crop_set_partitions(ctx, P)
+    crop.crop_set_seed(ctx, hseed)
+    crop.crop_set_owned_partitions(ctx, p0, p1)
+    crop.crop_load_transactions(ctx, st.off, st.items, st.n)
+    q = oracle.partition_interval(p0, P)[0]
+    rr = oracle.partition_interval(p1 - 1, P)[1]
+    ref = oracle.tx_exact(st.off, st.items, P, hseed, q, rr)
+    got = []
+    for window in (0, 1):
+        crop.crop_set_tuning(ctx, window=window)
+        crop.crop_run_exact(ctx)
+        assert crop.crop_get_tuning(ctx)["window"] == window
+        sizes, terms = crop.crop_result_sizes(ctx, P)
+        np.testing.assert_array_equal(sizes, ref["part_sizes"])
+        np.testing.assert_array_equal(terms, ref["part_terms"])
+        i, j, c, part_off = crop.crop_read_all(ctx, P)
+        lab = np.repeat(np.arange(P), np.diff(part_off.astype(np.int64)))
+        o = np.lexsort((j, i, lab))
+        np.testing.assert_array_equal(i[o], ref["x"])
+        np.testing.assert_array_equal(j[o], ref["y"])
+        np.testing.assert_array_equal(c[o], ref["cnt"])
+        got.append((i[o], j[o], c[o]))
+    # shares whose windows wrap: some item of the stream has h_a within W
+    # of the top of the hash space measured from q
+    ha, _, _, _ = oracle.hash_many(hseed, np.unique(st.items), np.unique(st.items))
+    W = rr - q
+    wraps = ((q - ha.astype(np.int64)) % (1 << 32)) + W > (1 << 32)
+    if ha.shape[0] * W > 8 * (1 << 32):   # more than 8 wrapping items expected
+        assert wraps.any()
 
 
 def test_owned_shards_union_is_full_result(crop, ctx):
