@@ -191,7 +191,7 @@ struct crop_ctx {
     crop::HashParams hp{};
     uint32_t ss_counters = 1u << 14;  // counters per partition
     uint32_t ss_ell = 16;             // counters per bucket
-    int topk_rank = CROP_RANK_UPPER;  // top-K order
+    int topk_rank = CROP_RANK_LOWER;  // top-K order
     crop_tune tune{};                 // user request (0 = auto)
     crop::RoutePlan plan{};
 

@@ -111,7 +111,7 @@ def guaranteed_votes(keys, f, seeds, P, B, ell):
     return g
 
 
-def check_report(top, votes, sums, m, K, by_lower=False, outer=False):
+def check_report(top, votes, sums, m, K, by_lower=True, outer=False):
     """The top-K is the first K of the majority combination of the GPU's own
     summaries by (rank value desc, key asc)."""
     uk, v, up, lo = majority_of(sums, m, outer)
@@ -213,13 +213,15 @@ def test_single_instance_equals_plain_topk(crop, ctx):
         assert np.all(res[3] <= f[pos]) and np.all(f[pos] <= res[2])
 
 
-def test_rank_by_lower_bound(crop, ctx):
+def test_rank_by_upper_bound(crop, ctx):
+    """The report ordered by upper bound on request (the default is the
+    lower bound)."""
     st = datagen.config_small()
-    crop.crop_set_topk_rank(ctx, crop.CROP_RANK_LOWER)
+    crop.crop_set_topk_rank(ctx, crop.CROP_RANK_UPPER)
     t, m, K = 5, 3, 500
     sums, top, votes = run_amp(crop, ctx, st, 2, 1024, 8, K, t, m)
-    check_report(top, votes, sums, m, K, by_lower=True)
-    assert np.all(np.diff(top[3]) <= 0)
+    check_report(top, votes, sums, m, K, by_lower=False)
+    assert np.all(np.diff(top[2]) <= 0)
 
 
 def test_outer_products(crop, ctx):
