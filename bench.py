@@ -11,10 +11,13 @@ kernels).  The metric is term-updates per second (pair occurrences per
 second).
 
 Printed: one JSON line with the throughput, the roofline of the dominant
-kernel (HIP events on the library's stream over the timed steps), and the
-CPU oracle timed on the same stream (single-threaded, about half a minute),
-whose result also gives the recall@1000 of the GPU's exact top 1000 and a
-whole-result equality check.
+kernel (HIP events on the library's stream over the timed steps), the CPU
+oracle timed on the same stream (single-threaded, about half a minute; its
+result also gives a whole-result equality check), the paper's own method on
+the host cores (multi-threaded, median of 3), and the top-1000 recall of the
+Space-Saving summaries, plain and learned-seeded at equal memory, on a
+held-out stream (the learned-seeding workload: 20 training streams of 1M
+transactions, seeds 5000-5019, held-out seed 5100).
 
 --batched times the 256-stream batched workload (one tuned plan replayed as
 a captured HIP graph).  --learned runs the learned-seeding comparison: an MLP trained on
@@ -46,7 +49,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true",
-                    help="skip the CPU oracle leg (profiling runs)")
+                    help="skip the CPU legs: the oracle and the host CRoP (profiling runs)")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="skip the learned-seeding leg of the default line (profiling runs)")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000,
                     help="transactions of the stream the CPU oracle is timed on; the "
                          "whole stream also gives the recall and equality checks")
@@ -134,6 +139,124 @@ def cpu_baseline(st, n_rows):
             "sample": f"first {sample.T} transactions of the 1M stream "
                       f"({r['n_terms']} terms), P={P}, {dt:.2f} s single-threaded",
             "seconds": round(dt, 3)}, r, sample.T
+
+
+def host_cpu():
+    """Model name, physical cores of the host and the threads this process
+    may use (its affinity mask, at most 16: the CPU share a GPU gets)."""
+    model, cores = "unknown", set()
+    try:
+        phys = core = None
+        for line in open("/proc/cpuinfo"):
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k == "model name" and model == "unknown":
+                model = v
+            elif k == "physical id":
+                phys = v
+            elif k == "core id":
+                core = v
+            elif not k and phys is not None:
+                cores.add((phys, core))
+                phys = core = None
+    except OSError:
+        pass
+    threads = min(16, len(os.sched_getaffinity(0)))
+    return model, len(cores) or None, threads
+
+
+def cpu_crop_baseline(st, terms, reps=3):
+    """The paper's method on the host (multi-threaded CRoP: every owner thread
+    reads the whole stream, sorts each transaction by h_b and enumerates only
+    the pairs of its hash interval, Lemma 1, into a private table), timed as
+    the median of `reps` runs on the whole stream.  Context beside the GPU
+    figure, not a target; the oracle stays the checker."""
+    import numpy as np
+    import oracle
+    model, phys, threads = host_cpu()
+    times, res = [], None
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        res = oracle.cpu_crop_tx(st.off, st.items, P, SEED, threads)
+        times.append(time.perf_counter() - t0)
+    med = sorted(times)[len(times) // 2]
+    sizes, part_terms, distinct = res
+    return {"value": terms / med, "unit": "term-updates/s", "threads": threads,
+            "cpu_model": model, "physical_cores": phys, "kind": "paper's method (CRoP), "
+            "owner threads with Lemma 1 windows", "seconds_median_of_3": round(med, 3),
+            "seconds": [round(t, 3) for t in times],
+            "sample": f"whole stream ({terms} terms), P={P}"}, sizes, part_terms
+
+
+def learned_leg(streams, steps=3):
+    """Learned seeding at its stated size on the default line: a predictor
+    trained on the exact supports of 20 training streams (crop_predictor_*)
+    seeds the Space-Saving summaries of the held-out stream with its 1,000
+    best pairs (r_max 4); top-1000 recall and largest count error against
+    the oracle's exact supports, plain vs seeded at equal memory, in the
+    library's default report order, for one partition of 16,384 counters
+    and 1,024 partitions of 2^14 counters (16 per bucket)."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_1210_0461_amd as crop
+    K = 1000
+    off, items, n = streams[-1]
+    t0 = time.perf_counter()
+    ref = oracle.tx_exact(off, items, 1, SEED)
+    rk, rc = sorted_pairs(ref["x"], ref["y"], ref["cnt"])
+    oracle_s = time.perf_counter() - t0
+    terms = int(ref["n_terms"])
+    ctx = crop.crop_create(0)
+    out = {"train_streams": len(streams) - 1, "K": K, "top_items": 256, "epochs": 4,
+           "r_max": 4, "oracle_seconds": round(oracle_s, 2)}
+    try:
+        crop.crop_set_stream(ctx, torch.cuda.current_stream())
+        crop.crop_set_seed(ctx, SEED)
+        crop.crop_set_partitions(ctx, P)
+        t0 = time.perf_counter()
+        pred = crop.crop_predictor_train(ctx, streams[:-1], top_items=256, epochs=4, batch=128,
+                                         lr=1e-3, shuffle_seed=6000)
+        torch.cuda.synchronize()
+        out["train_seconds"] = round(time.perf_counter() - t0, 2)
+        try:
+            crop.crop_load_transactions(ctx, off, items, n)
+            sx = torch.zeros(K, dtype=torch.int32, device="cuda")
+            sy = torch.zeros(K, dtype=torch.int32, device="cuda")
+            crop.crop_predictor_score(ctx, pred, K, sx, sy)
+            ev0 = torch.cuda.Event(enable_timing=True)
+            ev1 = torch.cuda.Event(enable_timing=True)
+            for Pr, C in ((1, 16384), (1024, 1 << 14)):
+                crop.crop_set_partitions(ctx, Pr)
+                crop.crop_set_summary(ctx, C, 16)
+                row = {}
+                for mode in ("plain", "seeded"):
+                    def once():
+                        if mode == "plain":
+                            crop.crop_run_topk(ctx, K)
+                        else:
+                            crop.crop_run_topk_seeded(ctx, K, sx, sy, 4)
+                    once()
+                    torch.cuda.synchronize()
+                    ev0.record()
+                    for _ in range(steps):
+                        once()
+                    ev1.record()
+                    torch.cuda.synchronize()
+                    ms = ev0.elapsed_time(ev1) / steps
+                    i, j, up, lo, _ = crop.crop_read_topk(ctx, K)
+                    rep = (i.astype(np.uint64) << np.uint64(32)) | j.astype(np.uint64)
+                    rec, exact = recall_vs(rk, rc, rep, K)
+                    row[mode] = {"recall_at_1000": rec,
+                                 "max_count_error": float((up - exact).max()) if up.size else 0.0,
+                                 "max_lower_bound_gap": float((exact - lo).max()) if lo.size else 0.0,
+                                 "ms": round(ms, 4), "term_updates_per_s": terms / (ms * 1e-3)}
+                out[f"P{Pr}_C{C}"] = row
+        finally:
+            crop.crop_predictor_free(pred)
+    finally:
+        crop.crop_destroy(ctx)
+    return out
 
 
 def sorted_pairs(x, y, c):
@@ -657,6 +780,15 @@ def main():
     import datagen
     import paper_1210_0461_amd as crop
 
+    learned_streams = None
+    if not args.no_learned:
+        import multiprocessing as mp
+        t_gen = time.perf_counter()
+        # generated in worker processes before this process touches the GPU
+        with mp.get_context("fork").Pool(min(8, os.cpu_count() or 1)) as pool:
+            learned_streams = pool.map(_gen_learned, list(range(20)) + [-1])
+        print(f"# generated 21 learned-seeding streams in {time.perf_counter() - t_gen:.1f} s",
+              file=sys.stderr, flush=True)
     t_gen = time.perf_counter()
     st = datagen.config_large()
     print(f"# generated {st.T} transactions, {st.nnz} items in "
@@ -747,7 +879,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "exact pair supports, 1M transactions over 50k items, "
                                "Zipf s=1.1, Geom(mean 10) lengths capped at 64, P=1024",
-                   "transactions": st.T, "items": st.nnz, "terms": terms,
+                   "transactions": st.T, "n_items": st.n, "nnz": st.nnz, "terms": terms,
                    "distinct_pairs": distinct, "P": P, "seed": SEED,
                    "bins_per_partition": tune["bins_per_partition"],
                    "rows_per_chunk": tune["rows_per_chunk"],
@@ -758,9 +890,15 @@ def main():
                           "frac": round(path_gbs / HBM_PEAK_GBS, 4),
                           "alg_bytes": alg_bytes},
         "stage_ms": {k: round(v, 4) for k, v in stage_ms.items()},
-        "recall_top1000": None,
+        "recall_top1000": {},
     }
+    if traffic:
+        roofline["kernel_traffic_gbs"] = round(traffic / (dom_ms * 1e-3) / 1e9, 1)
     if not args.no_cpu_baseline:
+        crop_cpu, cpu_sizes, cpu_terms = cpu_crop_baseline(st, terms)
+        crop_cpu["same_partition_sizes_as_gpu"] = bool(
+            np.array_equal(cpu_sizes, sizes) and np.array_equal(cpu_terms, part_terms))
+        out["cpu_crop"] = crop_cpu
         base, ref, rows = cpu_baseline(st, args.cpu_sample)
         out["cpu_baseline"] = base
         if rows == st.T:
@@ -769,9 +907,15 @@ def main():
             rk, rc = sorted_pairs(ref["x"], ref["y"], ref["cnt"])
             gk, gcnt = sorted_pairs(gx, gy, gc)
             top, _ = top_keys(gk, gcnt, 1000)
-            out["recall_top1000"], _ = recall_vs(rk, rc, top, 1000)
+            out["recall_top1000"]["exact_path"], _ = recall_vs(rk, rc, top, 1000)
             out["exact_match_vs_oracle"] = bool(np.array_equal(rk, gk) and
                                                 np.array_equal(rc, gcnt))
+    if learned_streams is not None:
+        lt = learned_leg(learned_streams)
+        out["learned_top1000"] = lt
+        for key in ("P1_C16384", "P1024_C16384"):
+            for mode in ("plain", "seeded"):
+                out["recall_top1000"][f"summary_{mode}_{key}"] = lt[key][mode]["recall_at_1000"]
     print(json.dumps(out), flush=True)
 
 
