@@ -851,12 +851,13 @@ def main():
     alg_bytes = in_bytes + out_bytes
     per_term = alg_bytes / terms
     kernel_names = {"count": "k_tx_count", "scan": "k_colsum/k_colbase/k_colapply",
-                    "scatter": "k_tx_scatter_direct", "aggregate": "k_aggregate_flat"}
+                    "scatter": "k_tx_scatter_direct", "aggregate": "k_aggregate_flat",
+                    "route": "k_sb_route", "headers": "k_sb_headers", "collect": "k_sb_collect"}
     dom = max(stage_ms, key=stage_ms.get)
     dom_ms = stage_ms[dom]
     achieved = per_term * terms / (dom_ms * 1e-3) / 1e9
-    digest = source_digest("k_route.hip", "k_exact.hip", "crop_device.hpp", "crop_enum.hpp",
-                           "crop_hash.hpp")
+    digest = source_digest("k_route.hip", "k_sbroute.hip", "k_exact.hip", "crop_device.hpp",
+                           "crop_enum.hpp", "crop_hash.hpp", "crop_runs.hpp")
     traffic = traffic_from_profiles(kernel_names[dom], digest)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -44,7 +44,7 @@
 extern "C" {
 #endif
 
-#define CROP_ABI_VERSION 3
+#define CROP_ABI_VERSION 4
 
 typedef enum crop_status {
     CROP_OK = 0,
@@ -73,6 +73,8 @@ typedef struct crop_tune {
                                     keys per window in LDS, sorted by bin     */
     uint32_t route;              /* transactions: CROP_ROUTE_*                */
     uint32_t window;             /* owned shares: CROP_WINDOW_*               */
+    uint32_t region_terms;       /* region route: terms per sub-batch, 16384
+                                    or 24576 (largest that fits when 0)       */
 } crop_tune;
 
 /* How an exact run that owns at most half of the hash space finds its terms:
@@ -81,10 +83,17 @@ typedef struct crop_tune {
  * enumerating every term and keeping the owned ones. */
 enum { CROP_WINDOW_AUTO = 0, CROP_WINDOW_OFF = 1 };
 
-/* How the routing offsets of a transaction stream are built: one count row
- * per chunk (a [chunk x bin] matrix), or one row per workgroup that walks a
- * contiguous range of chunks and keeps its bin cursors in LDS. */
-enum { CROP_ROUTE_AUTO = 0, CROP_ROUTE_CHUNKS = 1, CROP_ROUTE_RANGES = 2 };
+/* How the terms of a transaction stream reach their routing bins.  REGIONS
+ * (what AUTO takes for exact runs of streams with fewer than 2^16 items,
+ * whose keys pack into 32 bits, when every transaction fits a sub-batch and
+ * no owned share enumerates through windows): each workgroup sorts the
+ * terms of a sub-batch of consecutive transactions by bin in LDS and writes
+ * them as one contiguous region with a row of bin starts, and a bin is read
+ * back as one run per region; no count pass.  CHUNKS: a count pass builds a
+ * [chunk x bin] matrix of offsets and a second enumeration writes every key
+ * to its offset.  RANGES: as CHUNKS with one count row per workgroup that
+ * walks a contiguous range of chunks. */
+enum { CROP_ROUTE_AUTO = 0, CROP_ROUTE_CHUNKS = 1, CROP_ROUTE_RANGES = 2, CROP_ROUTE_REGIONS = 3 };
 
 /* ---- context ----------------------------------------------------------- */
 
@@ -148,12 +157,15 @@ crop_status crop_set_tuning(crop_ctx *ctx, const crop_tune *tune);
 crop_status crop_get_tuning(const crop_ctx *ctx, crop_tune *out);
 /* Tune exact runs of the loaded transaction stream: time routing bins per
  * partition S in {S0-1 .. S0+2} (S0 = the automatic choice, within 8192
- * bins) x rows per chunk in {64, 96, 128, 192, 256}, reps timed runs each
- * after one warm-up, keep the fastest as the context's tuning (other
- * tuning fields unchanged) and leave the exact result of a run with it.
- * Results do not depend on the plan.  Outputs (NULL allowed): the chosen
- * S and rows per chunk (after any halving to fit LDS) and the best time in
- * ms.  CROP_E_STATE without a loaded transaction stream. */
+ * bins) x, on the region route, terms per sub-batch in {16384, 24576},
+ * otherwise rows per chunk in {64, 96,
+ * 128, 192, 256}; reps timed runs each after one warm-up, keep the fastest
+ * as the context's tuning (other tuning fields unchanged) and leave the
+ * exact result of a run with it.  Results do not depend on the plan.
+ * Outputs (NULL allowed): the chosen S, the rows per chunk (after any
+ * halving to fit LDS; 0 on the region route, whose choice crop_get_tuning
+ * reports as region_terms) and the best time in ms.  CROP_E_STATE without a
+ * loaded transaction stream. */
 crop_status crop_autotune(crop_ctx *ctx, uint32_t reps, uint32_t *bins_per_partition,
                           uint32_t *rows_per_chunk, float *best_ms);
 

@@ -57,7 +57,7 @@ class crop_train_opts(ctypes.Structure):
 class crop_tune(ctypes.Structure):
     _fields_ = [("bins_per_partition", ctypes.c_uint32), ("rows_per_chunk", ctypes.c_uint32),
                 ("stage_keys", ctypes.c_uint32), ("route", ctypes.c_uint32),
-                ("window", ctypes.c_uint32)]
+                ("window", ctypes.c_uint32), ("region_terms", ctypes.c_uint32)]
 
 
 # torch ships its own HIP runtime under the same soname (libamdhip64.so.7).
@@ -269,19 +269,22 @@ def crop_use_own_stream(ctx) -> None:
 CROP_ROUTE_AUTO = 0
 CROP_ROUTE_CHUNKS = 1
 CROP_ROUTE_RANGES = 2
+CROP_ROUTE_REGIONS = 3
 CROP_WINDOW_AUTO = 0
 CROP_WINDOW_OFF = 1
 
 
 def crop_set_tuning(ctx, bins_per_partition=0, rows_per_chunk=0, stage_keys=0,
-                    route=CROP_ROUTE_AUTO, window=0) -> None:
-    t = crop_tune(bins_per_partition, rows_per_chunk, stage_keys, route, window)
+                    route=CROP_ROUTE_AUTO, window=0, region_terms=0) -> None:
+    t = crop_tune(bins_per_partition, rows_per_chunk, stage_keys, route, window, region_terms)
     _check(ctx, _lib.crop_set_tuning(ctx, ctypes.byref(t)))
 
 
 def crop_autotune(ctx, reps: int = 3):
     """Tune exact runs of the loaded stream; returns (bins_per_partition,
-    rows_per_chunk, best_ms) and keeps them as the context's tuning."""
+    rows_per_chunk, best_ms) and keeps them as the context's tuning
+    (rows_per_chunk is 0 on the region route, whose terms per sub-batch
+    crop_get_tuning reports)."""
     S = ctypes.c_uint32(0)
     R = ctypes.c_uint32(0)
     ms = ctypes.c_float(0.0)

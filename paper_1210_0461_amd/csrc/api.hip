@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "api_util.hpp"
+#include "crop_layout.hpp"
 
 using namespace crop;
 
@@ -96,6 +97,7 @@ void reset_input(crop_ctx *ctx)
     in.total_terms = 0;
     in.h_off.clear();
     in.h_b_off.clear();
+    ctx->sb.valid = false;
     in.op_chunks.clear();
     reset_batch(ctx);
     ctx->result = Result::None;
@@ -186,6 +188,7 @@ crop_status plan_tx(crop_ctx *ctx, uint32_t S_force = 0, int g_req = -1)
 {
     Input &in = ctx->in;
     RoutePlan &pl = ctx->plan;
+    pl.regions = false;
     crop_status st = plan_bins(ctx, S_force ? S_force : ctx->tune.bins_per_partition,
                                kTermsPerBin, g_req);
     if (st != CROP_OK) return st;
@@ -249,10 +252,131 @@ crop_status plan_tx(crop_ctx *ctx, uint32_t S_force = 0, int g_req = -1)
     return CROP_OK;
 }
 
+// ---- region route plan
+
+// Caps of a sub-batch for NB bins (packed keys): the terms (route threads x
+// Q, Q in {24, 16}), items and rows in proportion (about ten items and 45
+// terms per transaction of the 1M-transaction stream: a sub-batch is cut by
+// its terms, rarely by the others); the largest that fits the LDS budget.
+static bool sb_caps(uint32_t NB, uint32_t key_bytes, uint32_t want, uint32_t *S, uint32_t *I,
+                    uint32_t *R)
+{
+    static const uint32_t qs[] = {24, 16};
+    for (int k = 0; k < 2; ++k) {
+        const uint32_t terms = sb_threads() * qs[k];
+        if (want && terms != want) continue;
+        const uint32_t items = terms / 8, rows = terms / 24;
+        const size_t sm = sb_route_smem_bytes(NB, rows, items, terms, key_bytes);
+        if (sm <= kStageBudget && sb_layout_ok(NB, rows, items, terms, key_bytes, sm)) {
+            *S = terms;
+            *I = items;
+            *R = rows;
+            return true;
+        }
+    }
+    return false;
+}
+
+// Sub-batches of the loaded stream for these caps (greedy over the rows,
+// kept until the next load); false when one transaction alone exceeds them.
+// The row and term boundaries go to the device once per plan.
+static crop_status plan_sb_rows(crop_ctx *ctx, uint32_t S, uint32_t I, uint32_t R, bool *ok)
+{
+    SbPlan &sp = ctx->sb;
+    *ok = true;
+    if (sp.valid && sp.max_terms == S && sp.max_items == I && sp.max_rows == R) return CROP_OK;
+    sp.valid = false;
+    sp.row.assign(1, 0);
+    sp.term.assign(1, 0);
+    const std::vector<uint32_t> &off = ctx->in.h_off;
+    const uint64_t T = ctx->in.T;
+    // region bases: the term prefix with each region rounded up to four
+    // keys, so that every region starts on 16 bytes
+    uint64_t base = 0;
+    uint32_t ct = 0, ci = 0, cr = 0;
+    for (uint64_t t = 0; t < T; ++t) {
+        const uint32_t L = off[t + 1] - off[t];
+        const uint64_t n = L ? (uint64_t)L * (L - 1) / 2 : 0;
+        if (n > S || L > I) {
+            *ok = false;
+            return CROP_OK;
+        }
+        if (cr && (ct + n > S || ci + L > I || cr + 1 > R)) {
+            base += (ct + 3) & ~3u;
+            sp.row.push_back((uint32_t)t);
+            sp.term.push_back((uint32_t)base);
+            ct = ci = cr = 0;
+        }
+        ct += (uint32_t)n;
+        ci += L;
+        cr += 1;
+    }
+    if (T) {
+        base += (ct + 3) & ~3u;
+        sp.row.push_back((uint32_t)T);
+        sp.term.push_back((uint32_t)base);
+    }
+    if (base >= (1ull << 32)) {
+        *ok = false;
+        return CROP_OK;
+    }
+    sp.n_sub = (uint32_t)sp.row.size() - 1;
+    sp.max_terms = S;
+    sp.max_items = I;
+    sp.max_rows = R;
+    CK(ctx->sb_row.ensure(sp.row.size() * 4));
+    CK(ctx->sb_term.ensure(sp.term.size() * 4));
+    CK(hipMemcpy(ctx->sb_row.p, sp.row.data(), sp.row.size() * 4, hipMemcpyHostToDevice));
+    CK(hipMemcpy(ctx->sb_term.p, sp.term.data(), sp.term.size() * 4, hipMemcpyHostToDevice));
+    sp.valid = true;
+    return CROP_OK;
+}
+
+// The region route for an exact run of the loaded transaction stream, when
+// the tuning allows it (route AUTO or REGIONS, no staged scatter), no owned
+// share of at most half the hash space enumerates through windows instead,
+// and every transaction fits a sub-batch.  *ok false: plan_tx decides.
+static crop_status plan_regions(crop_ctx *ctx, bool *ok)
+{
+    *ok = false;
+    const crop_tune &tu = ctx->tune;
+    if (ctx->in.mode != Mode::Tx || ctx->in.wide_keys) return CROP_OK;
+    if (tu.route != CROP_ROUTE_AUTO && tu.route != CROP_ROUTE_REGIONS) return CROP_OK;
+    if (tu.stage_keys) return CROP_OK;
+    crop_status st = plan_bins(ctx, tu.bins_per_partition, kTermsPerBin);
+    if (st != CROP_OK) return st;
+    RoutePlan &pl = ctx->plan;
+    if (tu.window != CROP_WINDOW_OFF && tu.route == CROP_ROUTE_AUTO) {
+        const uint64_t q = (((uint64_t)pl.u0 << 32) + pl.M - 1) / pl.M;
+        const uint64_t r = ((((uint64_t)pl.u0 + pl.nu) << 32) + pl.M - 1) / pl.M;
+        if (r - q <= (1ull << 31)) return CROP_OK;
+    }
+    uint32_t S, I, R;
+    const uint32_t kb = ctx->in.wide_keys ? 8 : 4;
+    if (!sb_caps(pl.NB, kb, tu.region_terms, &S, &I, &R)) return CROP_OK;
+    bool fits = false;
+    st = plan_sb_rows(ctx, S, I, R, &fits);
+    if (st != CROP_OK || !fits) return st;
+    SbPlan &sp = ctx->sb;
+    sp.hdr_stride = (pl.NB + 1 + 63) & ~63u;
+    sp.hdrT_stride = (sp.n_sub + 63) & ~63u;
+    pl.regions = true;
+    pl.n_chunks = 0;
+    pl.R = 0;
+    pl.max_items = 0;
+    pl.stage_cap = 0;
+    pl.n_wg = 0;
+    pl.G = 1;
+    pl.win_kb = pl.win_q = pl.win_W = 0;
+    *ok = true;
+    return CROP_OK;
+}
+
 crop_status plan_outer(crop_ctx *ctx, uint32_t S_force = 0, int g_req = -1)
 {
     Input &in = ctx->in;
     RoutePlan &pl = ctx->plan;
+    pl.regions = false;
     // outer-product entries rarely repeat and fp32 sums use 8192-slot
     // tables: aim at about 2000 routed terms per bin
     crop_status st = plan_bins(ctx, S_force ? S_force : ctx->tune.bins_per_partition,
@@ -326,6 +450,21 @@ crop_status ensure_route_buffers(crop_ctx *ctx, size_t key_bytes, bool sums)
     CK(ctx->spill.ensure(nt * spill_entry_bytes(ctx->in.wide_keys, sums)));
     CK(ctx->counter.ensure(64));
     if (pl.g) CK(ctx->part_stats.ensure((size_t)ctx->P * 8));
+    return CROP_OK;
+}
+
+// Region route: the routed array (the padded regions of every sub-batch;
+// terms an owned share drops leave gaps), the sub-batches' bin-start rows
+// and their transpose.
+crop_status ensure_region_buffers(crop_ctx *ctx)
+{
+    const SbPlan &sp = ctx->sb;
+    const size_t kb = ctx->in.wide_keys ? 8 : 4;
+    // the padded regions, and one more 16-byte group past the last
+    CK(ctx->routed.ensure((sp.term.empty() ? 0 : (size_t)sp.term.back()) * kb + 64));
+    CK(ctx->sb_hdr.ensure((size_t)sp.n_sub * sp.hdr_stride * 2));
+    CK(ctx->sb_hdrT.ensure(((size_t)ctx->plan.NB + 1) * sp.hdrT_stride * 2));
+    CK(ctx->sb_tsum.ensure((((size_t)sp.n_sub + 63) / 64) * ((size_t)ctx->plan.NB + 1) * 4));
     return CROP_OK;
 }
 
@@ -665,12 +804,14 @@ crop_status crop_set_tuning(crop_ctx *ctx, const crop_tune *t)
         ctx->tune = crop_tune{};
         return CROP_OK;
     }
-    if (t->route > CROP_ROUTE_RANGES)
-        return fail(ctx, CROP_E_ARG, "route must be CROP_ROUTE_AUTO, _CHUNKS or _RANGES");
+    if (t->route > CROP_ROUTE_REGIONS)
+        return fail(ctx, CROP_E_ARG, "route must be CROP_ROUTE_AUTO, _CHUNKS, _RANGES or _REGIONS");
     if (t->stage_keys && t->stage_keys < 1024)
         return fail(ctx, CROP_E_ARG, "stage_keys must be 0 (automatic) or at least 1024");
     if (t->window > CROP_WINDOW_OFF)
         return fail(ctx, CROP_E_ARG, "window must be CROP_WINDOW_AUTO or CROP_WINDOW_OFF");
+    if (t->region_terms && t->region_terms != 16384 && t->region_terms != 24576)
+        return fail(ctx, CROP_E_ARG, "region_terms must be 0, 16384 or 24576");
     ctx->tune = *t;
     return CROP_OK;
 }
@@ -714,8 +855,11 @@ crop_status crop_get_tuning(const crop_ctx *ctx, crop_tune *out)
     out->bins_per_partition = ctx->plan.S;
     out->rows_per_chunk = ctx->plan.R;
     out->stage_keys = ctx->plan.stage_cap;
-    out->route = ctx->plan.n_wg ? CROP_ROUTE_RANGES : CROP_ROUTE_CHUNKS;
+    out->route = ctx->plan.regions ? CROP_ROUTE_REGIONS
+                 : ctx->plan.n_wg      ? CROP_ROUTE_RANGES
+                                       : CROP_ROUTE_CHUNKS;
     out->window = ctx->plan.win_kb ? CROP_WINDOW_AUTO : CROP_WINDOW_OFF;
+    out->region_terms = ctx->plan.regions ? ctx->sb.max_terms : 0;
     return CROP_OK;
 }
 
@@ -833,33 +977,52 @@ crop_status crop_run_exact(crop_ctx *ctx)
     DeviceGuard g(ctx->device);
     ctx->result = Result::None;
     const bool outer = ctx->in.mode == Mode::Outer;
-    crop_status st = outer ? plan_outer(ctx) : plan_tx(ctx);
+    bool regions = false;
+    crop_status st = outer ? plan_outer(ctx) : plan_regions(ctx, &regions);
     if (st != CROP_OK) return st;
+    if (!outer && !regions) {
+        st = plan_tx(ctx);
+        if (st != CROP_OK) return st;
+    }
     ctx->plan.log2_slots = (outer || ctx->in.wide_keys) ? 13 : 14;
     ctx->plan.BS = 256;
     st = ensure_route_buffers(ctx, ctx->in.wide_keys ? 8 : 4, outer);
+    if (st == CROP_OK && regions) st = ensure_region_buffers(ctx);
     if (st != CROP_OK) return st;
     const RoutePlan &pl = ctx->plan;
     hipStream_t s = ctx->stream;
     uint32_t *cnt = ctx->cnt_mat.as<uint32_t>();
     st = run_begin(ctx);
     if (st != CROP_OK) return st;
-    if (pl.n_chunks) CK(outer ? launch_op_count(ctx, cnt, s)
-                              : pl.n_wg ? launch_tx_count_ranges(ctx, cnt, s)
-                              : pl.win_kb ? launch_tx_count_win(ctx, cnt, s)
-                                        : launch_tx_count(ctx, cnt, s));
-    STAGE("count");
-    CK(launch_scan_counts(cnt, pl.n_wg ? pl.n_wg : pl.n_chunks, pl.NB, pl.G,
-                          ctx->part_buf.as<uint32_t>(),
-                          ctx->bin_off.as<uint32_t>(), ctx->counter.as<uint32_t>(), s));
-    CK(launch_bin_order(pl.NB, ctx->bin_off.as<uint32_t>(), ctx->bin_order.as<uint32_t>(), s));
-    STAGE("scan");
-    if (pl.n_chunks)
-        CK(outer ? launch_op_scatter(ctx, cnt, ctx->keys.p, ctx->vals.as<float>(), s)
-                 : pl.n_wg ? launch_tx_scatter_ranges(ctx, cnt, ctx->keys.p, s)
-                 : pl.win_kb ? launch_tx_scatter_win(ctx, cnt, ctx->keys.p, s)
-                           : launch_tx_scatter(ctx, cnt, ctx->keys.p, s));
-    STAGE("scatter");
+    if (regions) {
+        if (ctx->sb.n_sub) CK(launch_sb_route(ctx, s));
+        STAGE("route");
+        CK(launch_sb_headers(ctx, s));
+        CK(launch_zero32(ctx->counter.as<uint32_t>(), 2, s));
+        CK(launch_bin_order(pl.NB, ctx->bin_off.as<uint32_t>(), ctx->bin_order.as<uint32_t>(),
+                            s));
+        STAGE("headers");
+        CK(launch_sb_collect(ctx, ctx->keys.p, s));
+        STAGE("collect");
+    } else {
+        if (pl.n_chunks) CK(outer ? launch_op_count(ctx, cnt, s)
+                                  : pl.n_wg ? launch_tx_count_ranges(ctx, cnt, s)
+                                  : pl.win_kb ? launch_tx_count_win(ctx, cnt, s)
+                                            : launch_tx_count(ctx, cnt, s));
+        STAGE("count");
+        CK(launch_scan_counts(cnt, pl.n_wg ? pl.n_wg : pl.n_chunks, pl.NB, pl.G,
+                              ctx->part_buf.as<uint32_t>(),
+                              ctx->bin_off.as<uint32_t>(), ctx->counter.as<uint32_t>(), s));
+        CK(launch_bin_order(pl.NB, ctx->bin_off.as<uint32_t>(), ctx->bin_order.as<uint32_t>(),
+                            s));
+        STAGE("scan");
+        if (pl.n_chunks)
+            CK(outer ? launch_op_scatter(ctx, cnt, ctx->keys.p, ctx->vals.as<float>(), s)
+                     : pl.n_wg ? launch_tx_scatter_ranges(ctx, cnt, ctx->keys.p, s)
+                     : pl.win_kb ? launch_tx_scatter_win(ctx, cnt, ctx->keys.p, s)
+                               : launch_tx_scatter(ctx, cnt, ctx->keys.p, s));
+        STAGE("scatter");
+    }
     // grouped bins: per-partition terms from the routed keys (outer products;
     // for transactions they are the sums of the supports, taken below)
     uint32_t *ps_n = ctx->part_stats.as<uint32_t>(), *ps_w = ps_n + (pl.g ? ctx->P : 0);
@@ -1469,12 +1632,22 @@ crop_status crop_autotune(crop_ctx *ctx, uint32_t reps, uint32_t *bins_per_parti
     const crop_tune saved = ctx->tune;
     ctx->tune.bins_per_partition = 0;
     ctx->tune.rows_per_chunk = 0;
-    crop_status st = plan_tx(ctx);
+    ctx->tune.region_terms = 0;
+    bool regions = false;
+    crop_status st = plan_regions(ctx, &regions);
+    if (st == CROP_OK && !regions) st = plan_tx(ctx);
     if (st != CROP_OK) {
         ctx->tune = saved;
         return st;
     }
     const uint32_t S0 = ctx->plan.S;
+    // the second axis: terms per sub-batch on the region route, else rows
+    // per chunk
+    std::vector<uint32_t> second;
+    if (regions)
+        second = {16384u, 24576u};
+    else
+        second = {64u, 96u, 128u, 192u, 256u};
     uint32_t p0, p1;
     owned_range(ctx, &p0, &p1);
     float best = -1.0f;
@@ -1484,10 +1657,13 @@ crop_status crop_autotune(crop_ctx *ctx, uint32_t reps, uint32_t *bins_per_parti
     const uint32_t S_hi = ctx->plan.g ? 1u : S0 + 2;
     for (uint32_t S = S0 > 1 ? S0 - 1 : 1; S <= S_hi; ++S) {
         if (ctx->plan.g == 0 && (uint64_t)(p1 - p0) * S > kMaxP) break;
-        for (uint32_t R : {64u, 96u, 128u, 192u, 256u}) {
+        for (uint32_t R : second) {
             ctx->tune = saved;
             ctx->tune.bins_per_partition = S;
-            ctx->tune.rows_per_chunk = R;
+            if (regions)
+                ctx->tune.region_terms = R;
+            else
+                ctx->tune.rows_per_chunk = R;
             float lo = -1.0f, ms = 0.0f;
             for (uint32_t k = 0; k <= reps; ++k) {  // the first run warms up
                 st = crop_run_exact(ctx);
@@ -1510,7 +1686,10 @@ crop_status crop_autotune(crop_ctx *ctx, uint32_t reps, uint32_t *bins_per_parti
     ctx->tune = saved;
     if (best < 0) return fail(ctx, CROP_E_UNSUPPORTED, "no candidate plan fits this stream");
     ctx->tune.bins_per_partition = bS;
-    ctx->tune.rows_per_chunk = bR;
+    if (regions)
+        ctx->tune.region_terms = bR;
+    else
+        ctx->tune.rows_per_chunk = bR;
     st = crop_run_exact(ctx);
     if (st != CROP_OK) return st;
     if (bins_per_partition) *bins_per_partition = bS;

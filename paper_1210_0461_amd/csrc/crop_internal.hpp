@@ -68,6 +68,21 @@ struct RoutePlan {
     uint32_t log2_slots = 14;
     uint32_t BS = 256;
     uint32_t ss_mb = 0;      // Space-Saving micro-batch of the last top-K plan
+    bool regions = false;    // transactions: the region route (k_sb_route)
+};
+
+// Region route of a transaction stream (k_sb_route): sub-batches of
+// consecutive rows with at most max_terms terms, max_items items and
+// max_rows rows; sub-batch s is rows [row[s], row[s+1]) and its region of
+// the routed array starts at term[s] (the term prefix with every region
+// rounded up to four keys; term[n_sub] = the routed array's keys).
+// Computed once per loaded stream and set of caps.
+struct SbPlan {
+    bool valid = false;
+    uint32_t n_sub = 0, max_terms = 0, max_items = 0, max_rows = 0;
+    uint32_t hdr_stride = 0;   // u16 per bin-start row of a sub-batch (>= NB + 1)
+    uint32_t hdrT_stride = 0;  // u16 per transposed row of a bin (>= n_sub)
+    std::vector<uint32_t> row, term;
 };
 
 struct Input {
@@ -204,6 +219,8 @@ struct crop_ctx {
         counter;
     crop::DevBuf ss_state, topk_buf, scratch, learn_ws;
     crop::DevBuf part_stats;   // grouped bins: entries and terms of each partition
+    crop::SbPlan sb;           // region route: sub-batch plan of the loaded stream
+    crop::DevBuf routed, sb_row, sb_term, sb_hdr, sb_hdrT, sb_tsum;
     crop::BatchState batch;    // batched streams
     crop::DevBuf cs_buf;       // Count-Sketch counters [t][P * B]
     crop::CsParams cs{};       // ... of the last Count-Sketch run
@@ -242,6 +259,16 @@ hipError_t launch_check_pairs(const uint32_t *qx, const uint32_t *qy, uint64_t n
 hipError_t launch_hash_pairs(const uint32_t *qx, const uint32_t *qy, uint64_t n,
                              const HashParams &hp, uint32_t P, uint32_t *h, uint32_t *part,
                              hipStream_t s);
+
+// Region route (k_sbroute.hip): the sub-batch regions and their bin-start
+// rows, then the transposed rows and bin_off (bin-contiguous offsets), then
+// optionally the bin-contiguous keys themselves.
+size_t sb_route_smem_bytes(uint32_t NB, uint32_t max_rows, uint32_t max_items,
+                           uint32_t max_terms, uint32_t key_bytes);
+uint32_t sb_threads();
+hipError_t launch_sb_route(const crop_ctx *c, hipStream_t s);
+hipError_t launch_sb_headers(const crop_ctx *c, hipStream_t s);
+hipError_t launch_sb_collect(const crop_ctx *c, void *keys_out, hipStream_t s);
 
 hipError_t launch_tx_count(const crop_ctx *c, uint32_t *cnt, hipStream_t s);
 // Owned shares with windowed enumeration (plan.win_kb > 0).

@@ -89,4 +89,45 @@ __host__ __device__ inline bool win_layout_ok(uint32_t lead, uint32_t rows, uint
     return 4 * t.end <= smem_bytes;
 }
 
+// LDS image of a sub-batch of the region route (k_sb_route): hist, the
+// NB + 1 bin counters (then their exclusive starts); ro and tp, the rows + 1
+// item offsets and term prefixes of its transactions; xh, (item, h_b) of
+// each of its items, 8-byte aligned; keys, its terms sorted by bin, 16-byte
+// aligned (they leave LDS in 16-byte loads).  All offsets in 32-bit words.
+struct SbLayout {
+    uint32_t hist, ro, tp, xh, keys, end;
+};
+
+__host__ __device__ inline SbLayout sb_layout(uint32_t NB, uint32_t max_rows, uint32_t max_items,
+                                              uint32_t max_terms, uint32_t key_bytes)
+{
+    SbLayout t;
+    t.hist = 0;
+    t.ro = NB + 1;
+    t.tp = t.ro + max_rows + 1;
+    t.xh = (t.tp + max_rows + 1 + 1) & ~1u;
+    t.keys = (t.xh + 2 * max_items + 3) & ~3u;  // 16-byte loads of the sorted keys
+    t.end = t.keys + max_terms * (key_bytes / 4);
+    return t;
+}
+
+// What k_sb_route relies on, checked on the host before its launch with
+// `smem_bytes` of dynamic LDS: the arrays in order without overlap, xh and
+// 64-bit keys 8-byte aligned, the image inside the allocation, and at most
+// 65,535 terms (bin ranks and region offsets are 16-bit) and 8,192 bins.
+__host__ __device__ inline bool sb_layout_ok(uint32_t NB, uint32_t max_rows, uint32_t max_items,
+                                             uint32_t max_terms, uint32_t key_bytes,
+                                             size_t smem_bytes)
+{
+    if (key_bytes != 4 && key_bytes != 8) return false;
+    if (NB == 0 || NB > 8192 || max_terms > 65535 || max_rows == 0) return false;
+    const SbLayout t = sb_layout(NB, max_rows, max_items, max_terms, key_bytes);
+    if (t.ro < t.hist + NB + 1 || t.tp < t.ro + max_rows + 1) return false;
+    if (t.xh < t.tp + max_rows + 1 || t.xh % 2 != 0) return false;
+    if (t.keys < t.xh + 2 * (size_t)max_items || t.keys % 4 != 0) return false;
+    if (max_terms % (16 / key_bytes) != 0) return false;  // whole 16-byte stores
+    if (t.end < t.keys + (size_t)max_terms * (key_bytes / 4)) return false;
+    return 4 * (size_t)t.end <= smem_bytes;
+}
+
 }  // namespace crop

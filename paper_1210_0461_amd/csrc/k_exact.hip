@@ -400,16 +400,123 @@ __device__ void packed_spill_rounds(uint64_t *tab, Spilled<uint32_t, uint32_t> *
     }
 }
 
+// One wavefront batch of the packed table: U keys per lane with weights
+// wt[u] (0: no key).  Copies of the wavefront's lead key merge into its
+// lowest lane first.  Every key then looks at its home slot only: a hit
+// adds its weight (no wait), a free home is claimed with a compare-and-swap
+// (issued for all keys before any result is looked at).  A key whose home
+// holds another key -- for good: slots are never freed -- goes to the
+// wavefront's queue q (2 x 64 entries, qn of them in use), which is drained
+// a full wavefront at a time by linear probing from home + 1, so the probe
+// loops run with every lane busy; flush drains what is left (the
+// wavefront's last batch of the bin).  With ins false a key that is not
+// present is spilled instead (k0: the bin's spill segment).  Returns the
+// keys this lane inserted.
+template <int U, int LOG2S>
+__device__ inline uint32_t packed_insert_batch(uint64_t *tab, const uint32_t (&cur)[U],
+                                               uint32_t (&wt)[U], bool ins,
+                                               Spilled<uint32_t, uint32_t> *spill, uint32_t k0,
+                                               uint32_t *s_nspill, uint2 *q, uint32_t &qn,
+                                               bool flush)
+{
+    constexpr uint32_t MASK = (1u << LOG2S) - 1;
+    const uint32_t lane = lane_id();
+    uint32_t n_new = 0, hs[U];
+    uint64_t v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        wave_merge_lead(cur[u], wt[u]);
+        hs[u] = slot_of(cur[u], LOG2S);
+        v[u] = tab[hs[u]];
+    }
+    uint32_t slow = 0, cas = 0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (!wt[u]) continue;
+        const uint32_t k = (uint32_t)v[u];
+        if (k == cur[u]) {
+            atomicAdd(count_word(&tab[hs[u]]), wt[u]);
+        } else if (k == kEmpty32) {
+            // absent: no key of this probe sequence lies past a free slot
+            if (ins)
+                cas |= 1u << u;
+            else
+                spill[k0 + atomicAdd(s_nspill, 1u)] = Spilled<uint32_t, uint32_t>{cur[u], wt[u]};
+        } else {
+            slow |= 1u << u;
+        }
+    }
+    uint64_t old[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        if ((cas >> u) & 1u)
+            old[u] = atomicCAS((unsigned long long *)&tab[hs[u]], (unsigned long long)kFreeSlot,
+                               ((unsigned long long)wt[u] << 32) | cur[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (!((cas >> u) & 1u)) continue;
+        if (old[u] == kFreeSlot)
+            ++n_new;
+        else if ((uint32_t)old[u] == cur[u])
+            atomicAdd(count_word(&tab[hs[u]]), wt[u]);
+        else
+            slow |= 1u << u;  // another key took the home slot
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const bool sl = (slow >> u) & 1u;
+        const uint64_t m = __ballot(sl);
+        if (sl) q[qn + __popcll(m & ((1ull << lane) - 1))] = make_uint2(cur[u], wt[u]);
+        qn += (uint32_t)__popcll(m);
+        // drain: the queue holds fewer than 64 keys between drains, so at
+        // most 2 x 64 after an enqueue
+        while (qn >= (uint32_t)kWave || (u == U - 1 && flush && qn)) {
+            const uint32_t take = qn < (uint32_t)kWave ? qn : (uint32_t)kWave;
+            const uint32_t base = qn - take;
+            bool live = lane < take;
+            const uint2 e = live ? q[base + lane] : make_uint2(kEmpty32, 0u);
+            qn = base;
+            uint32_t at = (slot_of(e.x, LOG2S) + 1) & MASK;
+            uint64_t val = live ? tab[at] : 0;
+            while (live) {
+                const uint32_t k = (uint32_t)val;
+                if (k == e.x) {
+                    atomicAdd(count_word(&tab[at]), e.y);
+                    live = false;
+                } else if (k == kEmpty32) {
+                    if (!ins) {
+                        spill[k0 + atomicAdd(s_nspill, 1u)] = Spilled<uint32_t, uint32_t>{e.x, e.y};
+                        live = false;
+                    } else {
+                        const uint64_t o = atomicCAS((unsigned long long *)&tab[at],
+                                                     (unsigned long long)kFreeSlot,
+                                                     ((unsigned long long)e.y << 32) | e.x);
+                        if (o == kFreeSlot) {
+                            ++n_new;
+                            live = false;
+                        } else {
+                            val = o;  // taken meanwhile: look at the new occupant
+                        }
+                    }
+                } else {
+                    at = (at + 1) & MASK;
+                    val = tab[at];
+                }
+            }
+        }
+    }
+    return n_new;
+}
+
 // Flat variant of the packed aggregation: every wavefront walks its own
-// batches of the bin (64 U keys: U per lane), merges the copies of its lead
-// key, reads the U home slots together, adds hits without waiting for
-// anything and sends only collisions and new keys on to probe.  There is no barrier between
+// batches of the bin (64 U keys: U per lane, two batches loaded ahead) and
+// runs them through packed_insert_batch.  There is no barrier between
 // batches: a wavefront decides whether it may insert from the workgroup's
 // insert counter, read before each batch and raised by the batch's inserts
 // right after it.  A wavefront has at most one batch whose inserts are not
-// yet counted, so when the last batch allowed to insert read at most
-// cap_soft, the table never holds more than cap_soft + (BS / 64) * 64 U =
-// cap_soft + BS U keys.
+// yet counted, and a batch inserts at most its own 64 U keys plus the fewer
+// than 64 it found queued, so when the last batch allowed to insert read at
+// most cap_soft, the table never holds more than cap_soft + BS (U + 1) keys.
 template <int BS, int LOG2S, int U>
 __global__ void __launch_bounds__(BS)
 k_aggregate_flat(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ keys,
@@ -418,12 +525,12 @@ k_aggregate_flat(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ ke
                  uint32_t *counter, uint32_t cap_soft, const uint32_t *__restrict__ order)
 {
     constexpr uint32_t S = 1u << LOG2S;
-    constexpr uint32_t MASK = S - 1;
     constexpr uint32_t NW = BS / kWave;       // wavefronts
     constexpr uint32_t WB = kWave * U;        // keys of one wavefront batch
     static_assert(S % BS == 0, "table size must be a multiple of the block size");
     static_assert(S > BS * U, "a batch must fit in the table");
     __shared__ uint64_t tab[S];
+    __shared__ uint2 s_q[NW][2 * kWave];  // each wavefront's queue of keys to probe
     __shared__ uint32_t s_occ, s_nout, s_nspill, s_bin;
     __shared__ int s_insert;
     const uint32_t lane = lane_id();
@@ -446,17 +553,22 @@ k_aggregate_flat(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ ke
         }
         const uint32_t last = k1 - 1;  // read only when the bin is not empty
         uint32_t base = k0 + wave * WB;
-        uint32_t cur[U] = {};
+        uint32_t cur[U] = {}, nx1[U] = {};
         if (base < k1) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) cur[u] = keys[min(base + u * kWave + lane, last)];
+            for (int u = 0; u < U; ++u) {
+                cur[u] = keys[min(base + u * kWave + lane, last)];
+                nx1[u] = keys[min(base + NW * WB + u * kWave + lane, last)];
+            }
         }
         __syncthreads();
+        uint32_t qn = 0;
         for (; base < k1; base += NW * WB) {
-            const uint32_t nb = base + NW * WB;
-            uint32_t nx[U];
+            // two batches in flight ahead of the one being inserted
+            const uint32_t nb = base + 2 * NW * WB;
+            uint32_t nx2[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) nx[u] = keys[min(nb + u * kWave + lane, last)];
+            for (int u = 0; u < U; ++u) nx2[u] = keys[min(nb + u * kWave + lane, last)];
             const bool ins =
                 __hip_atomic_load(&s_occ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <=
                 cap_soft;
@@ -464,92 +576,18 @@ k_aggregate_flat(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ ke
             // (a hot pair fills most of its bin; one atomic instead of many)
             uint32_t wt[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                wt[u] = base + u * kWave + lane < k1 ? 1u : 0u;
-                wave_merge_lead(cur[u], wt[u]);
-            }
-            uint64_t v[U];
-            uint32_t hs[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                hs[u] = slot_of(cur[u], LOG2S);
-                v[u] = tab[hs[u]];
-            }
-            uint32_t pend = 0;
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (!wt[u]) continue;
-                if ((uint32_t)v[u] == cur[u])
-                    atomicAdd(count_word(&tab[hs[u]]), wt[u]);
-                else
-                    pend |= 1u << u;
-            }
-            // New keys whose home slot was free: all compare-and-swaps are
-            // issued before any result is looked at.
-            uint32_t n_new = 0;
-            if (ins) {
-                uint64_t old[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    old[u] = v[u];
-                    if (((pend >> u) & 1u) && (uint32_t)v[u] == kEmpty32)
-                        old[u] = atomicCAS((unsigned long long *)&tab[hs[u]],
-                                           (unsigned long long)kFreeSlot,
-                                           ((uint64_t)wt[u] << 32) | cur[u]);
-                }
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (!((pend >> u) & 1u) || (uint32_t)v[u] != kEmpty32) continue;
-                    if (old[u] == kFreeSlot) {
-                        ++n_new;
-                        pend &= ~(1u << u);
-                    } else if ((uint32_t)old[u] == cur[u]) {
-                        atomicAdd(count_word(&tab[hs[u]]), wt[u]);
-                        pend &= ~(1u << u);
-                    } else {
-                        v[u] = old[u];  // another key took the home slot: probe on
-                    }
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (!((pend >> u) & 1u)) continue;
-                const uint32_t key = cur[u];
-                const uint32_t wk = wt[u];
-                uint32_t sl = hs[u];
-                uint64_t val = v[u];
-                for (;;) {
-                    const uint32_t k = (uint32_t)val;
-                    if (k == key) {
-                        atomicAdd(count_word(&tab[sl]), wk);
-                        break;
-                    }
-                    if (k == kEmpty32) {
-                        if (!ins) {
-                            const uint32_t p = atomicAdd(&s_nspill, 1u);
-                            spill[k0 + p] = Spilled<uint32_t, uint32_t>{key, wk};
-                            break;
-                        }
-                        const uint64_t old = atomicCAS((unsigned long long *)&tab[sl],
-                                                       (unsigned long long)kFreeSlot,
-                                                       ((uint64_t)wk << 32) | key);
-                        if (old == kFreeSlot) {
-                            ++n_new;
-                            break;
-                        }
-                        val = old;  // taken meanwhile: look at the new occupant
-                        continue;
-                    }
-                    sl = (sl + 1) & MASK;
-                    val = tab[sl];
-                }
-            }
+            for (int u = 0; u < U; ++u) wt[u] = base + u * kWave + lane < k1 ? 1u : 0u;
+            const uint32_t n_new = packed_insert_batch<U, LOG2S>(
+                tab, cur, wt, ins, spill, k0, &s_nspill, s_q[wave], qn, base + NW * WB >= k1);
             uint32_t tot = n_new;
 #pragma unroll
             for (int d = 32; d >= 1; d >>= 1) tot += __shfl_xor(tot, d, kWave);
             if (lane == 0 && tot) atomicAdd(&s_occ, tot);
 #pragma unroll
-            for (int u = 0; u < U; ++u) cur[u] = nx[u];
+            for (int u = 0; u < U; ++u) {
+                cur[u] = nx1[u];
+                nx1[u] = nx2[u];
+            }
         }
         __syncthreads();  // keys of the bin are consumed; the spill list is complete
         // a wavefront may have spilled a key that a slower one inserted
@@ -576,11 +614,12 @@ static uint32_t persistent_grid(uint32_t NB)
 
 // Keys per thread and batch of the flat aggregation.  A batch starts
 // inserting only while the table holds at most kPackedCapSoft keys, so it
-// never holds more than kPackedCapSoft + 1024 * kFlatU: that must leave free
-// slots, or a probe could run forever.
+// never holds more than kPackedCapSoft + 1024 * (kFlatU + 1): that must
+// leave free slots, or a probe could run forever.
 constexpr int kFlatU = 4;
-constexpr uint32_t kPackedCapSoft = (1u << 14) - 1024 * kFlatU - 1024;
-static_assert(kPackedCapSoft + 1024 * kFlatU < (1u << 14), "packed table must keep free slots");
+constexpr uint32_t kPackedCapSoft = (1u << 14) - 1024 * (kFlatU + 1) - 1024;
+static_assert(kPackedCapSoft + 1024 * (kFlatU + 1) < (1u << 14),
+              "packed table must keep free slots");
 
 hipError_t launch_aggregate_counts(const crop_ctx *c, hipStream_t s)
 {

@@ -1,0 +1,353 @@
+// Term routing by sorted sub-batch regions.
+//
+// Every term of the stream goes to its routing bin by the consistent hash
+// (Section 5: h(x, y) = h_a(x) + h_b(y) mod 2^32; Section 6, Theorem 1:
+// owners hold equal intervals of the hash space, and a bin is a finer
+// interval inside one).  A sub-batch is a run of consecutive transactions
+// with at most max_terms terms.  Its workgroup enumerates every pair x < y,
+// takes each key's rank inside its bin with one LDS atomic, counting-sorts
+// the keys by bin in LDS and writes them as one contiguous region of the
+// routed array, together with a row of 16-bit bin starts inside the region.
+// The region of sub-batch s begins at sb_term[s], the stream's term prefix
+// with every region rounded up to whole 16-byte groups of keys, known from
+// the offsets alone: no count pass and no count matrix are needed, and every
+// HBM write is a 16-byte store of consecutive keys.
+//
+// Bin b is then one run per region.  k_sb_headers transposes the start rows
+// (so a bin's starts are contiguous) and sums them over the sub-batches: the
+// sum of the starts of bin b is the number of keys in bins below b, i.e. the
+// offset of bin b in a bin-contiguous layout.  k_sb_collect builds that
+// layout, which the per-bin kernels (the exact aggregation) read.  The
+// route takes packed 32-bit keys (fewer than 2^16 items); 64-bit keys stay
+// on the chunk route.
+#include "crop_device.hpp"
+#include "crop_enum.hpp"
+#include "crop_internal.hpp"
+#include "crop_layout.hpp"
+#include "crop_runs.hpp"
+
+namespace crop {
+
+namespace {
+
+constexpr int kSbBS = 1024;           // threads of a route workgroup
+constexpr int kCollectBS = 256;          // threads of a collect workgroup
+constexpr uint32_t kCollectPart = 512;   // sub-batches of a collect part (8 header tiles)
+constexpr uint32_t kCollectD = 8;        // spans of 64 keys in flight per wavefront
+
+// One sub-batch: rows [sb_row[s], sb_row[s+1]); its region of the routed
+// array starts at sb_base[s], a multiple of four keys.  Thread t enumerates
+// terms [t Q, t Q + Q) of the sub-batch in row-major order ((a, b) with
+// a < b over the positions of a row), so a thread's terms are consecutive
+// pairs of one or two rows; the LDS read of the next term's partner is
+// issued before the current term is hashed and ranked.
+template <int BS, int Q, class KeyT>
+__global__ void __launch_bounds__(BS)
+k_sb_route(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items, HashParams hp,
+           BinMap bm, uint32_t NB, SbLayout lay, const uint32_t *__restrict__ sb_row,
+           const uint32_t *__restrict__ sb_base, uint32_t hdr_stride,
+           KeyT *__restrict__ routed, uint16_t *__restrict__ hdr)
+{
+    constexpr uint32_t KPQ = 16 / sizeof(KeyT);  // keys per 16-byte store
+    extern __shared__ uint32_t smem[];
+    __shared__ uint32_t s_tmp[BS / kWave + 1];
+    uint32_t *hist = smem + lay.hist;
+    uint32_t *ro = smem + lay.ro;
+    uint32_t *tp = smem + lay.tp;
+    uint2 *xh = reinterpret_cast<uint2 *>(smem + lay.xh);
+    KeyT *sorted = reinterpret_cast<KeyT *>(smem + lay.keys);
+
+    const uint32_t s = blockIdx.x;
+    const uint32_t r0 = sb_row[s], R = sb_row[s + 1] - r0;
+    const uint32_t t0 = sb_base[s];
+    const uint32_t p0 = off[r0];
+    const uint32_t m = off[r0 + R] - p0;
+    for (uint32_t i = threadIdx.x; i <= R; i += BS) ro[i] = off[r0 + i] - p0;
+    for (uint32_t k = threadIdx.x; k < m; k += BS) {
+        const uint32_t x = items[p0 + k];
+        xh[k] = make_uint2(x, hash_b(hp, x));
+    }
+    for (uint32_t b = threadIdx.x; b < NB; b += BS) hist[b] = 0;
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < R; i += BS) {
+        const uint32_t L = ro[i + 1] - ro[i];
+        tp[i] = L * (L - 1) / 2;
+    }
+    __syncthreads();
+    lds_exclusive_scan<BS>(tp, R, s_tmp);
+    const uint32_t nt = tp[R];
+
+    KeyT key[Q];
+    uint32_t code[Q];  // (bin << 16) | rank inside the bin, or kEmpty32
+#pragma unroll
+    for (int u = 0; u < Q; ++u) {
+        code[u] = kEmpty32;
+        key[u] = 0;
+    }
+    const uint32_t tb = threadIdx.x * Q;
+    if (tb < nt) {
+        // the row of term tb: tp[row] <= tb < tp[row + 1]
+        uint32_t lo = 0, hi = R;
+        while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (tp[mid] <= tb) lo = mid;
+            else hi = mid;
+        }
+        uint32_t row = lo, base = ro[row], L = ro[row + 1] - base;
+        uint32_t k = tb - tp[row], a = 0;
+        while (k >= L - 1 - a) {
+            k -= L - 1 - a;
+            ++a;
+        }
+        uint32_t b = a + 1 + k;
+        uint32_t x = xh[base + a].x, ha = hash_a(hp, x);
+        uint2 yh_next = xh[base + b];
+#pragma unroll
+        for (int u = 0; u < Q; ++u) {
+            if (tb + u < nt) {
+                const uint2 yh = yh_next;
+                const uint32_t cx = x, cha = ha;
+                if (u + 1 < Q && tb + u + 1 < nt) {
+                    // the next term: (a, b + 1), else (a + 1, a + 2), else the
+                    // first pair of the next row with two or more items (one
+                    // exists: terms remain)
+                    if (++b == L) {
+                        ++a;
+                        b = a + 1;
+                        if (b == L) {
+                            do {
+                                ++row;
+                                base = ro[row];
+                                L = ro[row + 1] - base;
+                            } while (L < 2);
+                            a = 0;
+                            b = 1;
+                        }
+                        x = xh[base + a].x;
+                        ha = hash_a(hp, x);
+                    }
+                    yh_next = xh[base + b];
+                }
+                const uint32_t bin = bm.local(cha + yh.y);
+                key[u] = pack_key<KeyT>(cx, yh.x);
+                if (bin < NB) code[u] = (bin << 16) | atomicAdd(&hist[bin], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    lds_exclusive_scan<BS>(hist, NB, s_tmp);  // hist[NB] = kept terms
+    // every slot is read before any key is placed
+    uint32_t pos[Q];
+#pragma unroll
+    for (int u = 0; u < Q; ++u)
+        pos[u] = code[u] != kEmpty32 ? hist[code[u] >> 16] + (code[u] & 0xFFFFu) : kEmpty32;
+#pragma unroll
+    for (int u = 0; u < Q; ++u)
+        if (pos[u] != kEmpty32) sorted[pos[u]] = key[u];
+    __syncthreads();
+    // the region in 16-byte stores (its tail past the kept keys is padding)
+    const uint32_t kept = hist[NB];
+    const uint32_t nq = (kept + KPQ - 1) / KPQ;
+    const uint4 *src = reinterpret_cast<const uint4 *>(sorted);
+    uint4 *dst = reinterpret_cast<uint4 *>(routed + t0);
+    constexpr uint32_t QPT = Q / KPQ;  // 16-byte groups per thread: BS QPT = the LDS keys
+    uint4 v[QPT];
+#pragma unroll
+    for (uint32_t j = 0; j < QPT; ++j) v[j] = src[threadIdx.x + j * BS];
+#pragma unroll
+    for (uint32_t j = 0; j < QPT; ++j) {
+        const uint32_t i = threadIdx.x + j * BS;
+        if (i < nq) dst[i] = v[j];
+    }
+    uint16_t *hrow = hdr + (size_t)s * hdr_stride;
+    for (uint32_t b = threadIdx.x; b <= NB; b += BS) hrow[b] = (uint16_t)hist[b];
+}
+
+// Tiles of 64 sub-batches x 64 bin starts: hdrT[b][s] = hdr[s][b] for
+// b <= NB; tsum[t][b] = tile t's sum of hdr[s][b], and bin_off[b] += it
+// (bin_off zeroed before): summed over all sub-batches that is the number
+// of kept keys in bins below b, and tsum[t][b + 1] - tsum[t][b] is the
+// number of keys of bin b in tile t.
+__global__ void __launch_bounds__(256)
+k_sb_headers(const uint16_t *__restrict__ hdr, uint32_t hdr_stride, uint32_t n_sub, uint32_t NB,
+             uint16_t *__restrict__ hdrT, uint32_t hdrT_stride, uint32_t *__restrict__ bin_off,
+             uint32_t *__restrict__ tsum)
+{
+    __shared__ uint16_t tile[64][66];
+    __shared__ uint32_t part[4][64];
+    const uint32_t b0 = blockIdx.x * 64, s0 = blockIdx.y * 64;
+    const uint32_t c = threadIdx.x & 63, q = threadIdx.x >> 6;
+    uint32_t sum = 0;
+    for (uint32_t r = q; r < 64; r += 4) {
+        const uint32_t s = s0 + r, b = b0 + c;
+        uint16_t v = 0;
+        if (s < n_sub && b <= NB) v = hdr[(size_t)s * hdr_stride + b];
+        tile[r][c] = v;
+        sum += v;
+    }
+    part[q][c] = sum;
+    __syncthreads();
+    if (q == 0 && b0 + c <= NB) {
+        const uint32_t t = part[0][c] + part[1][c] + part[2][c] + part[3][c];
+        tsum[(size_t)blockIdx.y * (NB + 1) + b0 + c] = t;
+        if (t) atomicAdd(&bin_off[b0 + c], t);
+    }
+    for (uint32_t k = q; k < 64; k += 4) {
+        const uint32_t b = b0 + k, s = s0 + c;
+        if (b <= NB && s < n_sub) hdrT[(size_t)b * hdrT_stride + s] = tile[c][k];
+    }
+}
+
+// Bin-contiguous copy of the routed keys: bin b's runs, in sub-batch order,
+// to keys_out[bin_off[b] ...).  A bin is split into parts of kCollectPart
+// sub-batches, one workgroup each, so a heavy bin does not hold one
+// workgroup while the others finish; the parts of consecutive bins run on
+// one XCD, whose L2 then serves the regions' lines to all of them.  A part
+// finds its offset inside its bin from the header tile sums.  Thread t lists
+// the non-empty runs of CPT consecutive sub-batches; each wavefront then
+// copies a contiguous share of the part's keys, kCollectD spans of 64 at a
+// time, all of their loads in flight before the first store.
+__global__ void __launch_bounds__(kCollectBS)
+k_sb_collect(const uint16_t *__restrict__ hdrT, uint32_t hdrT_stride, uint32_t n_sub,
+             uint32_t NB, uint32_t n_parts, const uint32_t *__restrict__ tsum,
+             const uint32_t *__restrict__ sb_base, const uint32_t *__restrict__ routed,
+             const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ keys_out)
+{
+    constexpr uint32_t BS = kCollectBS, NW = BS / kWave, D = kCollectD;
+    constexpr uint32_t CPT = kCollectPart / BS, TPP = kCollectPart / 64;
+    __shared__ uint32_t rb[kCollectPart], rp[kCollectPart + 1], s_tmp[NW + 1];
+    __shared__ uint32_t wflag[NW][kWave];
+    const uint32_t id = xcd_contiguous(blockIdx.x, gridDim.x);
+    const uint32_t b = id / n_parts, g = id % n_parts;
+    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
+    wflag[wave][lane] = 0;
+    // keys of bin b in the header tiles before this part
+    uint32_t before = 0;
+    for (uint32_t t = threadIdx.x; t < g * TPP; t += BS)
+        before += tsum[(size_t)t * (NB + 1) + b + 1] - tsum[(size_t)t * (NB + 1) + b];
+    uint32_t tmp;
+    before = block_exclusive_scan<BS>(before, s_tmp, &tmp);
+    before = tmp;
+    uint32_t tag = 0;
+    uint32_t *out = keys_out + bin_off[b] + before;
+    const uint32_t s1 = g * kCollectPart + threadIdx.x * CPT;
+    uint32_t len[CPT], pos[CPT], nr = 0, nk = 0;
+#pragma unroll
+    for (uint32_t k = 0; k < CPT; ++k) {
+        len[k] = 0;
+        pos[k] = 0;
+        if (s1 + k < n_sub) {
+            const uint32_t a = hdrT[(size_t)b * hdrT_stride + s1 + k];
+            len[k] = hdrT[(size_t)(b + 1) * hdrT_stride + s1 + k] - a;
+            pos[k] = sb_base[s1 + k] + a;
+        }
+        nr += len[k] ? 1u : 0u;
+        nk += len[k];
+    }
+    uint32_t tr, tk;
+    uint32_t ri = block_exclusive_scan<BS>(nr, s_tmp, &tr);
+    uint32_t kp = block_exclusive_scan<BS>(nk, s_tmp, &tk);
+#pragma unroll
+    for (uint32_t k = 0; k < CPT; ++k) {
+        if (len[k]) {
+            rb[ri] = pos[k];
+            rp[ri] = kp;
+            ++ri;
+            kp += len[k];
+        }
+    }
+    if (threadIdx.x == 0) rp[tr] = tk;
+    __syncthreads();
+    // wavefront w copies positions [w q, w q + q) of the part
+    const uint32_t q = (tk + NW * kWave - 1) / (NW * kWave) * kWave;
+    uint32_t c = wave * q;
+    const uint32_t e = min(tk, c + q);
+    if (c >= e) return;
+    uint32_t r0 = sb_find_run(c, tr, rp);
+    for (; c < e; c += D * kWave) {
+        uint32_t v[D];
+#pragma unroll
+        for (uint32_t d = 0; d < D; ++d) {
+            const uint32_t cd = c + d * kWave;
+            if (cd < e) {  // wavefront-uniform
+                const uint32_t src = sb_span(cd, r0, tr, rb, rp, wflag[wave], ++tag);
+                if (cd + lane < e) v[d] = routed[src];
+            }
+        }
+#pragma unroll
+        for (uint32_t d = 0; d < D; ++d) {
+            const uint32_t i = c + d * kWave + lane;
+            if (i < e) out[i] = v[d];
+        }
+    }
+}
+
+}  // namespace
+
+size_t sb_route_smem_bytes(uint32_t NB, uint32_t max_rows, uint32_t max_items,
+                           uint32_t max_terms, uint32_t key_bytes)
+{
+    return 4 * (size_t)sb_layout(NB, max_rows, max_items, max_terms, key_bytes).end;
+}
+
+// Terms per route thread: the sub-batch holds kSbBS * Q terms at most.
+uint32_t sb_threads() { return kSbBS; }
+
+hipError_t launch_sb_route(const crop_ctx *c, hipStream_t s)
+{
+    const RoutePlan &pl = c->plan;
+    const SbPlan &sp = c->sb;
+    const uint32_t kb = c->in.wide_keys ? 8 : 4;
+    const SbLayout lay = sb_layout(pl.NB, sp.max_rows, sp.max_items, sp.max_terms, kb);
+    const size_t sm = 4 * (size_t)lay.end;
+    if (!sb_layout_ok(pl.NB, sp.max_rows, sp.max_items, sp.max_terms, kb, sm))
+        return hipErrorInvalidConfiguration;
+    const uint32_t Q = sp.max_terms / kSbBS;
+    if (Q * kSbBS != sp.max_terms) return hipErrorInvalidConfiguration;
+    const uint32_t *row = c->sb_row.as<uint32_t>(), *term = c->sb_term.as<uint32_t>();
+    uint16_t *hdr = c->sb_hdr.as<uint16_t>();
+#define SB_LAUNCH(QQ, KT)                                                                    \
+    hipLaunchKernelGGL((k_sb_route<kSbBS, QQ, KT>), dim3(sp.n_sub), dim3(kSbBS), sm, s,       \
+                       c->in.off, c->in.items, c->hp, bin_map(pl), pl.NB, lay, row, term,     \
+                       sp.hdr_stride, c->routed.as<KT>(), hdr)
+    if (c->in.wide_keys) return hipErrorInvalidConfiguration;  // packed keys only
+    if (Q == 16)
+        SB_LAUNCH(16, uint32_t);
+    else if (Q == 24)
+        SB_LAUNCH(24, uint32_t);
+    else
+        return hipErrorInvalidConfiguration;
+#undef SB_LAUNCH
+    return hipGetLastError();
+}
+
+hipError_t launch_sb_headers(const crop_ctx *c, hipStream_t s)
+{
+    const RoutePlan &pl = c->plan;
+    const SbPlan &sp = c->sb;
+    uint32_t *bin_off = c->bin_off.as<uint32_t>();
+    hipError_t e = launch_zero32(bin_off, pl.NB + 1, s);
+    if (e != hipSuccess || sp.n_sub == 0) return e;  // an empty stream: every bin empty
+    dim3 grid((pl.NB + 1 + 63) / 64, (sp.n_sub + 63) / 64);
+    hipLaunchKernelGGL(k_sb_headers, grid, dim3(256), 0, s, c->sb_hdr.as<uint16_t>(),
+                       sp.hdr_stride, sp.n_sub, pl.NB, c->sb_hdrT.as<uint16_t>(), sp.hdrT_stride,
+                       bin_off, c->sb_tsum.as<uint32_t>());
+    return hipGetLastError();
+}
+
+hipError_t launch_sb_collect(const crop_ctx *c, void *keys_out, hipStream_t s)
+{
+    const RoutePlan &pl = c->plan;
+    const SbPlan &sp = c->sb;
+    if (pl.NB == 0 || sp.n_sub == 0) return hipSuccess;
+    if (c->in.wide_keys) return hipErrorInvalidValue;  // 64-bit keys stay on the chunk route
+    const uint32_t n_parts = (sp.n_sub + kCollectPart - 1) / kCollectPart;
+    hipLaunchKernelGGL(k_sb_collect, dim3(pl.NB * n_parts), dim3(kCollectBS), 0, s,
+                       c->sb_hdrT.as<uint16_t>(), sp.hdrT_stride, sp.n_sub, pl.NB, n_parts,
+                       c->sb_tsum.as<uint32_t>(), c->sb_term.as<uint32_t>(),
+                       c->routed.as<uint32_t>(), c->bin_off.as<uint32_t>(),
+                       static_cast<uint32_t *>(keys_out));
+    return hipGetLastError();
+}
+
+}  // namespace crop

@@ -41,7 +41,7 @@ def test_binding_names_match_c_functions():
 
 def test_static_calls_without_gpu():
     import paper_1210_0461_amd as crop
-    assert crop.crop_abi_version() == 3
+    assert crop.crop_abi_version() == 4
     assert crop.crop_status_string(0) == "ok"
     assert crop.crop_status_string(-4) == "output buffer too small"
 

@@ -214,9 +214,21 @@ def test_autotune_choice_and_invariance(crop, ctx):
     crop.crop_set_seed(ctx, SEED)
     crop.crop_load_transactions(ctx, st.off, st.items, st.n)
     S, R, ms = crop.crop_autotune(ctx, 1)
-    assert 1 <= S <= 8192 // P and R in (64, 96, 128, 192, 256, 48, 32, 24, 16, 12, 8) and ms > 0
     t = crop.crop_get_tuning(ctx)
-    assert t["bins_per_partition"] == S and t["rows_per_chunk"] == R
+    assert 1 <= S <= 8192 // P and ms > 0 and t["bins_per_partition"] == S
+    # the region route tunes its terms per sub-batch, the chunk routes their
+    # rows per chunk
+    if t["route"] == crop.CROP_ROUTE_REGIONS:
+        assert R == 0 and t["region_terms"] in (16384, 24576)
+    else:
+        assert R in (64, 96, 128, 192, 256, 48, 32, 24, 16, 12, 8) and t["rows_per_chunk"] == R
+    # the chunk route takes the same tuner and gives the same result
+    crop.crop_set_tuning(ctx, route=crop.CROP_ROUTE_CHUNKS)
+    S2, R2, _ = crop.crop_autotune(ctx, 1)
+    assert R2 in (64, 96, 128, 192, 256, 48, 32, 24, 16, 12, 8)
+    assert crop.crop_get_tuning(ctx)["route"] == crop.CROP_ROUTE_CHUNKS
+    crop.crop_set_tuning(ctx)
+    crop.crop_autotune(ctx, 1)
     ref = oracle.tx_exact(st.off, st.items, P, SEED)
     sizes, terms = crop.crop_result_sizes(ctx, P)
     assert np.array_equal(sizes, ref["part_sizes"]) and np.array_equal(terms, ref["part_terms"])

@@ -51,3 +51,56 @@ def test_chunk_layout_alignment_and_bounds(tmp_path):
     assert out.returncode == 0, out.stdout
     n, bad = map(int, out.stdout.split()[-2:])
     assert n > 10000 and bad == 0
+
+
+PROG_SB = r"""
+#include <cstdio>
+#include "crop_layout.hpp"
+using namespace crop;
+int main() {
+    long bad = 0, n = 0;
+    const uint32_t nbs[] = {1, 2, 3, 63, 64, 65, 1000, 1024, 3072, 4097, 8191, 8192};
+    const uint32_t terms[] = {16, 1024, 16384, 24576, 65532};
+    for (uint32_t NB : nbs)
+        for (uint32_t T : terms)
+            for (uint32_t kb = 4; kb <= 8; kb += 4)
+                for (uint32_t rows = 1; rows < 3000; rows += (rows < 40 ? 1 : 211))
+                    for (uint32_t items = 0; items < 9000; items += (items < 40 ? 1 : 377)) {
+                        const SbLayout t = sb_layout(NB, rows, items, T, kb);
+                        const size_t sm = 4 * (size_t)t.end;
+                        ++n;
+                        bool ok = sb_layout_ok(NB, rows, items, T, kb, sm);
+                        ok = ok && t.ro >= t.hist + NB + 1;               // hist: NB + 1 words
+                        ok = ok && t.tp >= t.ro + rows + 1;               // ro, tp: rows + 1
+                        ok = ok && t.xh >= t.tp + rows + 1 && (4 * t.xh) % 8 == 0;
+                        ok = ok && t.keys >= t.xh + 2 * items && (4 * t.keys) % 16 == 0;
+                        ok = ok && (size_t)t.end >= t.keys + (size_t)T * kb / 4;
+                        ok = ok && !sb_layout_ok(NB, rows, items, T, kb, sm - 4);  // tight bound
+                        if (!ok) { if (bad < 5) printf("bad NB=%u T=%u kb=%u rows=%u items=%u\n", NB, T, kb, rows, items); ++bad; }
+                    }
+    // refused: too many bins or terms, a key width other than 4 or 8
+    if (sb_layout_ok(8193, 10, 10, 1024, 4, 1u << 30)) ++bad;
+    if (sb_layout_ok(64, 10, 10, 65536, 4, 1u << 30)) ++bad;
+    if (sb_layout_ok(64, 10, 10, 1024, 2, 1u << 30)) ++bad;
+    if (sb_layout_ok(64, 10, 10, 1022, 4, 1u << 30)) ++bad;  // not whole 16-byte groups
+    printf("%ld %ld\n", n, bad);
+    return bad ? 1 : 0;
+}
+"""
+
+
+def test_region_route_layout_alignment_and_bounds(tmp_path):
+    """The LDS image of a region-route sub-batch (bin counters, row offsets
+    and term prefixes, staged items, sorted keys): arrays in order without
+    overlap, the staged items 8-byte aligned and the sorted keys 16-byte
+    aligned (they leave LDS in 16-byte loads), the image inside the dynamic
+    allocation, and the 16-bit limits refused."""
+    src = tmp_path / "sb_layout.cpp"
+    exe = tmp_path / "sb_layout"
+    src.write_text(PROG_SB)
+    subprocess.run(["g++", "-std=c++17", "-O1", "-I", CSRC, str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0, out.stdout
+    n, bad = map(int, out.stdout.split()[-2:])
+    assert n > 10000 and bad == 0
