@@ -364,6 +364,16 @@ crop_status crop_batch_read_stream(crop_ctx *ctx, uint32_t stream, crop_mem wher
  * transactions of the loaded stream: counts, pair occurrences, lengths,
  * first/second-half counts and the rank of the item's count. */
 crop_status crop_item_features(crop_ctx *ctx, uint32_t prefix_T, float *feat);
+/* crop_item_features for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): same arguments and output, but the per-item statistics live
+ * in a fixed per-GPU array of 2^21 32-bit words (8 MiB) inside the library
+ * instead of a workspace it allocates, so 8 n_items + prefix_T + 66 must be
+ * at most 2^21 (CROP_E_CAPACITY otherwise, with the size in the detail).
+ * Nothing is allocated by this call.  All calls on one GPU share that
+ * array: calls that overlap on one GPU (other streams or contexts) race,
+ * and the caller must order them. */
+crop_status crop_item_features_noalloc(crop_ctx *ctx, uint32_t prefix_T, float *feat);
 
 /* Candidate pairs x < y among the M items with the largest prefix counts
  * (ties by smaller id), in (x, y) order: cx, cy of capacity cap >= M(M-1)/2;

@@ -131,6 +131,7 @@ _SIGS.update({
     "crop_batch_result_sizes": ([_vp, _u32, _vp, _vp], _i32),
     "crop_batch_read_stream": ([_vp, _u32, _i32, _vp, _vp, _vp, _u64, _pu64, _vp], _i32),
     "crop_item_features": ([_vp, _u32, _vp], _i32),
+    "crop_item_features_noalloc": ([_vp, _u32, _vp], _i32),
     "crop_top_item_pairs": ([_vp, _u32, _u32, _vp, _vp, _u64, _pu64], _i32),
     "crop_lookup_exact": ([_vp, _vp, _vp, _u64, _vp], _i32),
     "crop_pair_inputs": ([_vp, _vp, _vp, _vp, _vp, _u64, _vp, _vp], _i32),
@@ -524,6 +525,12 @@ def _dev(a, name):
 def crop_item_features(ctx, prefix_T: int, feat) -> None:
     """feat: float32 device tensor [n_items, 16]."""
     _check(ctx, _lib.crop_item_features(ctx, prefix_T, _dev(feat, "feat")))
+
+
+def crop_item_features_noalloc(ctx, prefix_T: int, feat) -> None:
+    """crop_item_features with the library's fixed per-GPU workspace (no
+    allocation); feat: float32 device tensor [n_items, 16]."""
+    _check(ctx, _lib.crop_item_features_noalloc(ctx, prefix_T, _dev(feat, "feat")))
 
 
 def crop_top_item_pairs(ctx, prefix_T: int, M: int, cx, cy) -> int:

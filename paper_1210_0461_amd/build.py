@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcrop.so")
 SOURCES = ["api.hip", "k_route.hip", "k_exact.hip", "k_result.hip", "k_topk.hip",
-           "k_learned.hip", "batch.hip", "k_cs.hip", "predictor.hip", "k_sbroute.hip"]
+           "k_learned.hip", "batch.hip", "k_cs.hip", "predictor.hip", "k_sbroute.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -689,6 +689,9 @@ crop_status crop_create(crop_ctx **out, int hip_device)
     if (!ctx) return CROP_E_NOMEM;
     ctx->device = hip_device;
     ctx->hp = make_hash_params(ctx->seed);
+    // the fixed workspace of the no-allocation entry point on this device; a
+    // failure is reported by that entry point
+    (void)noalloc_setup(hip_device);
     if (hipStreamCreateWithFlags(&ctx->own_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
         crop_destroy(ctx);

@@ -344,6 +344,9 @@ hipError_t launch_cs_estimate(const CsParams &cp, const void *cs, bool fp, const
 
 // Learned seeding (k_learned.hip).
 size_t item_stats_words(uint32_t n, uint32_t Tp);
+// The fixed workspace of crop_item_features_noalloc (noalloc.hip): resolve
+// this device's copy, with `device` current; once per device.
+hipError_t noalloc_setup(int device);
 hipError_t launch_item_features(const uint32_t *off, const uint32_t *items, uint32_t n,
                                 uint32_t Tp, uint32_t *ws, float *feat, hipStream_t s);
 hipError_t launch_top_pairs(const uint32_t *ws, uint32_t n, uint32_t Tp, uint32_t M,
