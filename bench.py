@@ -857,7 +857,7 @@ def main():
     dom_ms = stage_ms[dom]
     achieved = per_term * terms / (dom_ms * 1e-3) / 1e9
     digest = source_digest("k_route.hip", "k_sbroute.hip", "k_exact.hip", "crop_device.hpp",
-                           "crop_enum.hpp", "crop_hash.hpp", "crop_runs.hpp")
+                           "crop_enum.hpp", "crop_hash.hpp", "crop_layout.hpp", "crop_runs.hpp")
     traffic = traffic_from_profiles(kernel_names[dom], digest)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -90,7 +90,8 @@ __host__ __device__ inline bool win_layout_ok(uint32_t lead, uint32_t rows, uint
 }
 
 // LDS image of a sub-batch of the region route (k_sb_route): hist, the
-// NB + 1 bin counters (then their exclusive starts); ro and tp, the rows + 1
+// NB + 1 bin counters (then their exclusive starts) and a discard counter;
+// ro and tp, the rows + 1
 // item offsets and term prefixes of its transactions; xh, (item, h_b) of
 // each of its items, 8-byte aligned; keys, its terms sorted by bin, 16-byte
 // aligned (they leave LDS in 16-byte loads).  All offsets in 32-bit words.
@@ -103,7 +104,7 @@ __host__ __device__ inline SbLayout sb_layout(uint32_t NB, uint32_t max_rows, ui
 {
     SbLayout t;
     t.hist = 0;
-    t.ro = NB + 1;
+    t.ro = NB + 2;
     t.tp = t.ro + max_rows + 1;
     t.xh = (t.tp + max_rows + 1 + 1) & ~1u;
     t.keys = (t.xh + 2 * max_items + 3) & ~3u;  // 16-byte loads of the sorted keys
@@ -122,7 +123,7 @@ __host__ __device__ inline bool sb_layout_ok(uint32_t NB, uint32_t max_rows, uin
     if (key_bytes != 4 && key_bytes != 8) return false;
     if (NB == 0 || NB > 8192 || max_terms > 65535 || max_rows == 0) return false;
     const SbLayout t = sb_layout(NB, max_rows, max_items, max_terms, key_bytes);
-    if (t.ro < t.hist + NB + 1 || t.tp < t.ro + max_rows + 1) return false;
+    if (t.ro < t.hist + NB + 2 || t.tp < t.ro + max_rows + 1) return false;
     if (t.xh < t.tp + max_rows + 1 || t.xh % 2 != 0) return false;
     if (t.keys < t.xh + 2 * (size_t)max_items || t.keys % 4 != 0) return false;
     if (max_terms % (16 / key_bytes) != 0) return false;  // whole 16-byte stores

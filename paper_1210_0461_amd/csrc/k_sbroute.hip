@@ -33,7 +33,7 @@ namespace {
 constexpr int kSbBS = 1024;           // threads of a route workgroup
 constexpr int kCollectBS = 256;          // threads of a collect workgroup
 constexpr uint32_t kCollectPart = 512;   // sub-batches of a collect part (8 header tiles)
-constexpr uint32_t kCollectD = 8;        // spans of 64 keys in flight per wavefront
+constexpr uint32_t kCollectD = 16;       // spans of 64 keys in flight per wavefront
 
 // One sub-batch: rows [sb_row[s], sb_row[s+1]); its region of the routed
 // array starts at sb_base[s], a multiple of four keys.  Thread t enumerates
@@ -77,15 +77,15 @@ k_sb_route(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
     lds_exclusive_scan<BS>(tp, R, s_tmp);
     const uint32_t nt = tp[R];
 
+    // Each term takes its rank inside its bin with one LDS atomic, issued
+    // for every term (a term outside the run's bins counts in the discard
+    // counter hist[NB + 1]) and not waited for until the placement: nothing
+    // in the loop needs its result.
     KeyT key[Q];
-    uint32_t code[Q];  // (bin << 16) | rank inside the bin, or kEmpty32
-#pragma unroll
-    for (int u = 0; u < Q; ++u) {
-        code[u] = kEmpty32;
-        key[u] = 0;
-    }
+    uint32_t bins[Q], rank[Q];
     const uint32_t tb = threadIdx.x * Q;
-    if (tb < nt) {
+    const uint32_t nv = tb < nt ? min((uint32_t)Q, nt - tb) : 0u;  // this thread's terms
+    if (nv) {
         // the row of term tb: tp[row] <= tb < tp[row + 1]
         uint32_t lo = 0, hi = R;
         while (hi - lo > 1) {
@@ -100,38 +100,53 @@ k_sb_route(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
             ++a;
         }
         uint32_t b = a + 1 + k;
-        uint32_t x = xh[base + a].x, ha = hash_a(hp, x);
-        uint2 yh_next = xh[base + b];
+        // x: the first item of the current term, x1: the item after it (the
+        // x of the next a), yh: the current term's partner and its h_b
+        uint32_t x = xh[base + a].x, x1 = xh[base + a + 1].x;
+        uint32_t ha = hash_a(hp, x);
+        uint2 yh = xh[base + b];
 #pragma unroll
         for (int u = 0; u < Q; ++u) {
-            if (tb + u < nt) {
-                const uint2 yh = yh_next;
-                const uint32_t cx = x, cha = ha;
-                if (u + 1 < Q && tb + u + 1 < nt) {
-                    // the next term: (a, b + 1), else (a + 1, a + 2), else the
-                    // first pair of the next row with two or more items (one
-                    // exists: terms remain)
-                    if (++b == L) {
-                        ++a;
-                        b = a + 1;
-                        if (b == L) {
-                            do {
-                                ++row;
-                                base = ro[row];
-                                L = ro[row + 1] - base;
-                            } while (L < 2);
-                            a = 0;
-                            b = 1;
-                        }
-                        x = xh[base + a].x;
-                        ha = hash_a(hp, x);
+            // the next term (a, b + 1), else (a + 1, a + 2), else the first
+            // pair of the next row with two or more items (one exists: terms
+            // remain); its partner's read is issued before this term's rank
+            uint2 yn = yh;
+            uint32_t nx = x, nha = ha;
+            if ((uint32_t)u + 1 < nv) {
+                if (++b == L) {
+                    ++a;
+                    b = a + 1;
+                    if (b == L) {
+                        do {
+                            ++row;
+                            base = ro[row];
+                            L = ro[row + 1] - base;
+                        } while (L < 2);
+                        a = 0;
+                        b = 1;
+                        nx = xh[base].x;
+                    } else {
+                        nx = x1;
                     }
-                    yh_next = xh[base + b];
+                    nha = hash_a(hp, nx);
                 }
-                const uint32_t bin = bm.local(cha + yh.y);
-                key[u] = pack_key<KeyT>(cx, yh.x);
-                if (bin < NB) code[u] = (bin << 16) | atomicAdd(&hist[bin], 1u);
+                yn = xh[base + b];
             }
+            const uint32_t bin = bm.local(ha + yh.y);
+            bins[u] = ((uint32_t)u < nv && bin < NB) ? bin : NB + 1;
+            key[u] = pack_key<KeyT>(x, yh.x);
+            rank[u] = atomicAdd(&hist[bins[u]], 1u);
+            yh = yn;
+            x = nx;
+            ha = nha;
+            if (b == a + 1) x1 = yh.x;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < Q; ++u) {
+            bins[u] = NB + 1;
+            key[u] = 0;
+            rank[u] = 0;
         }
     }
     __syncthreads();
@@ -139,8 +154,7 @@ k_sb_route(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
     // every slot is read before any key is placed
     uint32_t pos[Q];
 #pragma unroll
-    for (int u = 0; u < Q; ++u)
-        pos[u] = code[u] != kEmpty32 ? hist[code[u] >> 16] + (code[u] & 0xFFFFu) : kEmpty32;
+    for (int u = 0; u < Q; ++u) pos[u] = bins[u] < NB ? hist[bins[u]] + rank[u] : kEmpty32;
 #pragma unroll
     for (int u = 0; u < Q; ++u)
         if (pos[u] != kEmpty32) sorted[pos[u]] = key[u];
@@ -164,14 +178,11 @@ k_sb_route(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
 }
 
 // Tiles of 64 sub-batches x 64 bin starts: hdrT[b][s] = hdr[s][b] for
-// b <= NB; tsum[t][b] = tile t's sum of hdr[s][b], and bin_off[b] += it
-// (bin_off zeroed before): summed over all sub-batches that is the number
-// of kept keys in bins below b, and tsum[t][b + 1] - tsum[t][b] is the
-// number of keys of bin b in tile t.
+// b <= NB, and tsum[t][b] = tile t's sum of hdr[s][b] (k_sb_tile_scan turns
+// these into offsets).
 __global__ void __launch_bounds__(256)
 k_sb_headers(const uint16_t *__restrict__ hdr, uint32_t hdr_stride, uint32_t n_sub, uint32_t NB,
-             uint16_t *__restrict__ hdrT, uint32_t hdrT_stride, uint32_t *__restrict__ bin_off,
-             uint32_t *__restrict__ tsum)
+             uint16_t *__restrict__ hdrT, uint32_t hdrT_stride, uint32_t *__restrict__ tsum)
 {
     __shared__ uint16_t tile[64][66];
     __shared__ uint32_t part[4][64];
@@ -187,15 +198,40 @@ k_sb_headers(const uint16_t *__restrict__ hdr, uint32_t hdr_stride, uint32_t n_s
     }
     part[q][c] = sum;
     __syncthreads();
-    if (q == 0 && b0 + c <= NB) {
-        const uint32_t t = part[0][c] + part[1][c] + part[2][c] + part[3][c];
-        tsum[(size_t)blockIdx.y * (NB + 1) + b0 + c] = t;
-        if (t) atomicAdd(&bin_off[b0 + c], t);
-    }
+    if (q == 0 && b0 + c <= NB)
+        tsum[(size_t)blockIdx.y * (NB + 1) + b0 + c] =
+            part[0][c] + part[1][c] + part[2][c] + part[3][c];
     for (uint32_t k = q; k < 64; k += 4) {
         const uint32_t b = b0 + k, s = s0 + c;
         if (b <= NB && s < n_sub) hdrT[(size_t)b * hdrT_stride + s] = tile[c][k];
     }
+}
+
+// Per bin start b <= NB, over the header tiles t: tsum[t][b] <- the sum of
+// the tiles before t (in place), and bin_off[b] <- the sum of all of them.
+// The sum of the starts of bin b over every sub-batch is the number of kept
+// keys in bins below b, i.e. bin b's offset in a bin-contiguous layout, and
+// tsum[t][b + 1] - tsum[t][b] (after the scan) is the number of keys of bin
+// b in the tiles before t.
+__global__ void __launch_bounds__(256)
+k_sb_tile_scan(uint32_t *__restrict__ tsum, uint32_t n_tiles, uint32_t NB,
+               uint32_t *__restrict__ bin_off)
+{
+    const uint32_t b = blockIdx.x * 256 + threadIdx.x;
+    if (b > NB) return;
+    uint32_t run = 0;
+    for (uint32_t t0 = 0; t0 < n_tiles; t0 += 8) {  // eight loads in flight
+        uint32_t v[8];
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k)
+            v[k] = t0 + k < n_tiles ? tsum[(size_t)(t0 + k) * (NB + 1) + b] : 0u;
+#pragma unroll
+        for (uint32_t k = 0; k < 8; ++k) {
+            if (t0 + k < n_tiles) tsum[(size_t)(t0 + k) * (NB + 1) + b] = run;
+            run += v[k];
+        }
+    }
+    bin_off[b] = run;
 }
 
 // Bin-contiguous copy of the routed keys: bin b's runs, in sub-batch order,
@@ -203,7 +239,7 @@ k_sb_headers(const uint16_t *__restrict__ hdr, uint32_t hdr_stride, uint32_t n_s
 // sub-batches, one workgroup each, so a heavy bin does not hold one
 // workgroup while the others finish; the parts of consecutive bins run on
 // one XCD, whose L2 then serves the regions' lines to all of them.  A part
-// finds its offset inside its bin from the header tile sums.  Thread t lists
+// finds its offset inside its bin from the scanned header tile sums.  Thread t lists
 // the non-empty runs of CPT consecutive sub-batches; each wavefront then
 // copies a contiguous share of the part's keys, kCollectD spans of 64 at a
 // time, all of their loads in flight before the first store.
@@ -221,15 +257,11 @@ k_sb_collect(const uint16_t *__restrict__ hdrT, uint32_t hdrT_stride, uint32_t n
     const uint32_t b = id / n_parts, g = id % n_parts;
     const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
     wflag[wave][lane] = 0;
-    // keys of bin b in the header tiles before this part
-    uint32_t before = 0;
-    for (uint32_t t = threadIdx.x; t < g * TPP; t += BS)
-        before += tsum[(size_t)t * (NB + 1) + b + 1] - tsum[(size_t)t * (NB + 1) + b];
-    uint32_t tmp;
-    before = block_exclusive_scan<BS>(before, s_tmp, &tmp);
-    before = tmp;
+    // the part's output: bin b's offset plus its keys in the header tiles
+    // before the part (the scanned tile sums)
+    const uint32_t *pre = tsum + (size_t)g * TPP * (NB + 1);
+    uint32_t *out = keys_out + bin_off[b] + (pre[b + 1] - pre[b]);
     uint32_t tag = 0;
-    uint32_t *out = keys_out + bin_off[b] + before;
     const uint32_t s1 = g * kCollectPart + threadIdx.x * CPT;
     uint32_t len[CPT], pos[CPT], nr = 0, nk = 0;
 #pragma unroll
@@ -326,12 +358,14 @@ hipError_t launch_sb_headers(const crop_ctx *c, hipStream_t s)
     const RoutePlan &pl = c->plan;
     const SbPlan &sp = c->sb;
     uint32_t *bin_off = c->bin_off.as<uint32_t>();
-    hipError_t e = launch_zero32(bin_off, pl.NB + 1, s);
-    if (e != hipSuccess || sp.n_sub == 0) return e;  // an empty stream: every bin empty
-    dim3 grid((pl.NB + 1 + 63) / 64, (sp.n_sub + 63) / 64);
+    if (sp.n_sub == 0) return launch_zero32(bin_off, pl.NB + 1, s);  // every bin empty
+    const uint32_t n_tiles = (sp.n_sub + 63) / 64;
+    dim3 grid((pl.NB + 1 + 63) / 64, n_tiles);
     hipLaunchKernelGGL(k_sb_headers, grid, dim3(256), 0, s, c->sb_hdr.as<uint16_t>(),
                        sp.hdr_stride, sp.n_sub, pl.NB, c->sb_hdrT.as<uint16_t>(), sp.hdrT_stride,
-                       bin_off, c->sb_tsum.as<uint32_t>());
+                       c->sb_tsum.as<uint32_t>());
+    hipLaunchKernelGGL(k_sb_tile_scan, dim3((pl.NB + 1 + 255) / 256), dim3(256), 0, s,
+                       c->sb_tsum.as<uint32_t>(), n_tiles, pl.NB, bin_off);
     return hipGetLastError();
 }
 

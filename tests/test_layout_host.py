@@ -70,7 +70,7 @@ int main() {
                         const size_t sm = 4 * (size_t)t.end;
                         ++n;
                         bool ok = sb_layout_ok(NB, rows, items, T, kb, sm);
-                        ok = ok && t.ro >= t.hist + NB + 1;               // hist: NB + 1 words
+                        ok = ok && t.ro >= t.hist + NB + 2;               // hist: NB + 2 words
                         ok = ok && t.tp >= t.ro + rows + 1;               // ro, tp: rows + 1
                         ok = ok && t.xh >= t.tp + rows + 1 && (4 * t.xh) % 8 == 0;
                         ok = ok && t.keys >= t.xh + 2 * items && (4 * t.keys) % 16 == 0;
