@@ -190,6 +190,8 @@ __device__ inline typename GroupMask<G>::T group_bits(uint64_t b, uint32_t gsh)
 
 __device__ inline uint32_t lowest_bit(uint32_t m) { return (uint32_t)__builtin_ctz(m); }
 __device__ inline uint32_t lowest_bit(uint64_t m) { return (uint32_t)__builtin_ctzll(m); }
+__device__ inline uint32_t bit_count(uint32_t m) { return (uint32_t)__popc(m); }
+__device__ inline uint32_t bit_count(uint64_t m) { return (uint32_t)__popcll(m); }
 
 template <class KeyT> __device__ inline KeyT empty_key();
 template <> __device__ inline uint32_t empty_key<uint32_t>() { return kEmpty32; }
@@ -254,7 +256,9 @@ __device__ inline uint32_t table_add(KeyT *hk, uint32_t *hw, float *hv, uint32_t
 //      with transaction counts small enough, one G-lane minimum over packed
 //      (kind, count, slot) offers takes all three decisions without a ballot
 //      (the ballots' round trips through scalar registers set the pace of
-//      the serial chain).
+//      the serial chain); a bin of one bucket with transaction counts
+//      instead takes level steps: every slot at the minimum count takes
+//      one update at once, which reaches the same state.
 // Merging and reordering a bucket's updates keeps Space-Saving's bounds
 // (Section 4), which hold for any order of weighted updates.  Counts and
 // overestimations are 32-bit words: uint32 for transactions, fp32 bits for
@@ -606,10 +610,52 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                             }
                         }
                     };
-                    if (pack)
-                        chain([&](KeyT key, uint32_t w, float) { step_packed(key, w); });
-                    else
+                    // Level steps (transactions): with ties broken by the
+                    // lowest slot, the single steps take the slots at the
+                    // minimum level (free slots below every count, then
+                    // count c at level c + 1) one by one in slot order, and
+                    // each taken slot rises by its weight (at least one)
+                    // above that level.  One step therefore applies the
+                    // next updates to all slots at the minimum level at
+                    // once, the r-th slot in slot order taking the r-th
+                    // update, read from the update list in LDS; the state is
+                    // the one the single steps reach.
+                    using M = typename GroupMask<G>::T;
+                    auto chain_level = [&]() {
+                        // pinned slots and padding never take an update; with
+                        // every slot pinned all updates drop
+                        const uint32_t fixed = ((f & kPinned) ? 0xFFFFFFFFu : 0u) | notreal;
+                        if (__builtin_amdgcn_ballot_w64(fixed == 0u) == 0) return;
+                        const M below = ((M)1 << j) - (M)1;
+                        for (uint32_t pos = e0; pos < e1;) {
+                            // level offer: 0 free, c + 1 used (counts stay
+                            // below 2^26), all ones if fixed
+                            const uint32_t lvl = ((f & kUsed) ? c + 1u : 0u) | fixed;
+                            const uint32_t mn = group_min<G>(lvl);
+                            // (the group is lanes [0, G) of its wavefront:
+                            // its ballot bits need no shift)
+                            const M at = group_bits<G>(__builtin_amdgcn_ballot_w64(lvl == mn), 0);
+                            const uint32_t take = min(bit_count(at), e1 - pos);
+                            const uint32_t rank = bit_count(at & below);
+                            if (lvl == mn && rank < take) {
+                                const KeyT nk = t_k[pos + rank];
+                                const uint32_t nw = t_w[pos + rank];
+                                e = mn ? c : 0u;
+                                c = mn ? c + nw : nw;
+                                k = nk;
+                                f |= kUsed;
+                            }
+                            pos += take;
+                        }
+                    };
+                    if constexpr (!OUTER) {
+                        if (pack)
+                            chain_level();
+                        else
+                            chain([&](KeyT key, uint32_t w, float val) { step(key, w, val); });
+                    } else {
                         chain([&](KeyT key, uint32_t w, float val) { step(key, w, val); });
+                    }
                 } else {
                     auto chain = [&](auto apply) {
                         KeyT nk = t_k[e0];
