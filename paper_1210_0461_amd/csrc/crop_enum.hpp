@@ -119,6 +119,7 @@ struct WinLds {
     uint32_t *hist;  // (rows << kb) + 1: exclusive starts, then (after placement) ends
     uint2 *yh;       // (item, h_b) in (row, bucket) order
     uint16_t *row;   // chunk row of each sorted entry
+    uint16_t *rin;   // chunk row of each entry in input order
 };
 
 __device__ inline WinLds win_lds(uint32_t *smem, uint32_t lead, uint32_t rows, uint32_t kb,
@@ -129,12 +130,16 @@ __device__ inline WinLds win_lds(uint32_t *smem, uint32_t lead, uint32_t rows, u
     L.hist = smem + t.hist;
     L.yh = reinterpret_cast<uint2 *>(smem + t.yh);
     L.row = reinterpret_cast<uint16_t *>(smem + t.row);
+    L.rin = reinterpret_cast<uint16_t *>(smem + t.rin);
     return L;
 }
 
 // Stage rows [r0, r1) bucket-sorted; returns the number of entries.  After
 // the call hist[i] holds the end of (row, bucket) slot i, so slot i spans
-// [i ? hist[i - 1] : 0, hist[i]).
+// [i ? hist[i - 1] : 0, hist[i]).  Each row first marks its entries with
+// its index (LDS stores only); then one thread per entry loads its item
+// (coalesced), hashes it and counts, and after the scan loads, hashes and
+// places it again.
 template <int BS>
 __device__ inline uint32_t stage_tx_win(const uint32_t *__restrict__ off,
                                         const uint32_t *__restrict__ items, uint32_t r0,
@@ -146,22 +151,23 @@ __device__ inline uint32_t stage_tx_win(const uint32_t *__restrict__ off,
     const uint32_t nh = (r1 - r0) << kb;
     const uint32_t sh = 32 - kb;
     for (uint32_t i = threadIdx.x; i <= nh; i += BS) L.hist[i] = 0;
-    __syncthreads();
     for (uint32_t r = r0 + threadIdx.x; r < r1; r += BS) {
-        const uint32_t base = (r - r0) << kb;
-        for (uint32_t k = off[r]; k < off[r + 1]; ++k)
-            atomicAdd(&L.hist[base + (hash_b(hp, items[k]) >> sh)], 1u);
+        const uint32_t a = off[r] - p0, e = off[r + 1] - p0;
+        for (uint32_t k = a; k < e; ++k) L.rin[k] = (uint16_t)(r - r0);
+    }
+    __syncthreads();
+    for (uint32_t k = threadIdx.x; k < m; k += BS) {
+        const uint32_t hb = hash_b(hp, items[p0 + k]);
+        atomicAdd(&L.hist[((uint32_t)L.rin[k] << kb) + (hb >> sh)], 1u);
     }
     __syncthreads();
     lds_exclusive_scan<BS>(L.hist, nh, s_tmp);
-    for (uint32_t r = r0 + threadIdx.x; r < r1; r += BS) {
-        const uint32_t base = (r - r0) << kb;
-        for (uint32_t k = off[r]; k < off[r + 1]; ++k) {
-            const uint32_t y = items[k], hb = hash_b(hp, y);
-            const uint32_t pos = atomicAdd(&L.hist[base + (hb >> sh)], 1u);
-            L.yh[pos] = make_uint2(y, hb);
-            L.row[pos] = (uint16_t)(r - r0);
-        }
+    for (uint32_t k = threadIdx.x; k < m; k += BS) {
+        const uint32_t y = items[p0 + k], hb = hash_b(hp, y);
+        const uint32_t r = L.rin[k];
+        const uint32_t pos = atomicAdd(&L.hist[(r << kb) + (hb >> sh)], 1u);
+        L.yh[pos] = make_uint2(y, hb);
+        L.row[pos] = (uint16_t)r;
     }
     __syncthreads();
     return m;

@@ -62,7 +62,7 @@ __host__ __device__ inline bool tx_layout_ok(uint32_t lead, uint32_t max_items, 
 // in (row, bucket) order, 8-byte aligned; row, the chunk row of each sorted
 // entry (u16, padded to a whole word).
 struct WinLayout {
-    size_t hist, yh, row, end;
+    size_t hist, yh, row, rin, end;
 };
 
 __host__ __device__ inline WinLayout win_layout(uint32_t lead, uint32_t rows, uint32_t kb,
@@ -73,7 +73,8 @@ __host__ __device__ inline WinLayout win_layout(uint32_t lead, uint32_t rows, ui
     const size_t nh = ((size_t)rows << kb) + 1;
     t.yh = (t.hist + nh + 1) & ~(size_t)1;
     t.row = t.yh + 2 * (size_t)max_items;
-    t.end = t.row + ((size_t)max_items + 1) / 2;
+    t.rin = t.row + ((size_t)max_items + 1) / 2;
+    t.end = t.rin + ((size_t)max_items + 1) / 2;
     return t;
 }
 
@@ -84,7 +85,7 @@ __host__ __device__ inline bool win_layout_ok(uint32_t lead, uint32_t rows, uint
     if (t.hist < lead || t.yh % 2 != 0) return false;
     if (t.yh < t.hist + ((size_t)rows << kb) + 1) return false;
     if (t.row < t.yh + 2 * (size_t)max_items) return false;
-    if (2 * (t.end - t.row) < max_items) return false;
+    if (2 * (t.rin - t.row) < max_items || 2 * (t.end - t.rin) < max_items) return false;
     if (rows > 65535 || max_items > 65535) return false;  // u16 rows and positions
     return 4 * t.end <= smem_bytes;
 }

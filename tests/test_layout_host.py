@@ -104,3 +104,50 @@ def test_region_route_layout_alignment_and_bounds(tmp_path):
     assert out.returncode == 0, out.stdout
     n, bad = map(int, out.stdout.split()[-2:])
     assert n > 10000 and bad == 0
+
+
+PROG_WIN = r"""
+#include <cstdio>
+#include "crop_layout.hpp"
+using namespace crop;
+int main() {
+    long bad = 0, n = 0;
+    for (uint32_t lead = 0; lead < 8200; lead += (lead < 40 ? 1 : 389))
+        for (uint32_t rows = 1; rows <= 512; rows += (rows < 20 ? 1 : 61))
+            for (uint32_t kb = 2; kb <= 5; ++kb)
+                for (uint32_t m = 0; m < 12000; m += (m < 40 ? 1 : 523)) {
+                    const WinLayout t = win_layout(lead, rows, kb, m);
+                    const size_t sm = 4 * t.end;
+                    ++n;
+                    bool ok = win_layout_ok(lead, rows, kb, m, sm);
+                    ok = ok && t.hist >= lead;                                  // after the bin words
+                    ok = ok && t.yh >= t.hist + ((size_t)rows << kb) + 1;       // bucket words
+                    ok = ok && (4 * t.yh) % 8 == 0;                             // uint2 entries
+                    ok = ok && 4 * t.row >= 4 * t.yh + 8 * (size_t)m;
+                    ok = ok && 4 * t.rin >= 4 * t.row + 2 * (size_t)m;          // u16 rows, sorted
+                    ok = ok && 4 * t.end >= 4 * t.rin + 2 * (size_t)m;          // u16 rows, input order
+                    ok = ok && !win_layout_ok(lead, rows, kb, m, sm - 4);       // tight bound
+                    if (!ok) { if (bad < 5) printf("bad lead=%u rows=%u kb=%u m=%u\n", lead, rows, kb, m); ++bad; }
+                }
+    if (win_layout_ok(0, 65536, 2, 10, 1u << 30)) ++bad;   // rows beyond 16 bits
+    if (win_layout_ok(0, 10, 2, 65536, 1u << 30)) ++bad;   // entries beyond 16 bits
+    printf("%ld %ld\n", n, bad);
+    return bad ? 1 : 0;
+}
+"""
+
+
+def test_window_layout_alignment_and_bounds(tmp_path):
+    """The LDS image of a chunk staged for windowed enumeration (bin words,
+    (row, bucket) words, (item, h_b) entries, sorted and input-order rows):
+    arrays in order without overlap, entries 8-byte aligned, the image inside
+    the dynamic allocation, and the 16-bit limits refused."""
+    src = tmp_path / "win_layout.cpp"
+    exe = tmp_path / "win_layout"
+    src.write_text(PROG_WIN)
+    subprocess.run(["g++", "-std=c++17", "-O1", "-I", CSRC, str(src), "-o", str(exe)],
+                   check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True)
+    assert out.returncode == 0, out.stdout
+    n, bad = map(int, out.stdout.split()[-2:])
+    assert n > 10000 and bad == 0
