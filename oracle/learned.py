@@ -70,7 +70,12 @@ def item_stats(off, items, n: int, Tp: int):
 
 
 def item_features(st, Tp: int) -> np.ndarray:
-    """16 fp64 features per item from the prefix statistics."""
+    """16 fp64 features per item from the prefix statistics.
+
+    Parity unpinned: the features are this project's own definition (the
+    paper has no learned component), so nothing outside it fixes their
+    values; the statistics they are computed from are pinned against dense
+    forms, the features themselves only by shape and finiteness."""
     A = st["A"].astype(np.float64)
     S1 = st["S1"].astype(np.float64)
     S2 = st["S2"].astype(np.float64)
