@@ -850,9 +850,13 @@ def main():
     out_bytes = 8 * distinct
     alg_bytes = in_bytes + out_bytes
     per_term = alg_bytes / terms
+    # the aggregation reads the region route's runs in place (k_aggregate_regions)
+    # or the chunk route's bin-contiguous keys (k_aggregate_flat)
+    regions = "route" in stage_ms
     kernel_names = {"count": "k_tx_count", "scan": "k_colsum/k_colbase/k_colapply",
-                    "scatter": "k_tx_scatter_direct", "aggregate": "k_aggregate_flat",
-                    "route": "k_sb_route", "headers": "k_sb_headers", "collect": "k_sb_collect"}
+                    "scatter": "k_tx_scatter_direct",
+                    "aggregate": "k_aggregate_regions" if regions else "k_aggregate_flat",
+                    "route": "k_sb_route", "headers": "k_sb_headers"}
     dom = max(stage_ms, key=stage_ms.get)
     dom_ms = stage_ms[dom]
     achieved = per_term * terms / (dom_ms * 1e-3) / 1e9

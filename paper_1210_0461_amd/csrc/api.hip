@@ -1005,8 +1005,6 @@ crop_status crop_run_exact(crop_ctx *ctx)
         CK(launch_bin_order(pl.NB, ctx->bin_off.as<uint32_t>(), ctx->bin_order.as<uint32_t>(),
                             s));
         STAGE("headers");
-        CK(launch_sb_collect(ctx, ctx->keys.p, s));
-        STAGE("collect");
     } else {
         if (pl.n_chunks) CK(outer ? launch_op_count(ctx, cnt, s)
                                   : pl.n_wg ? launch_tx_count_ranges(ctx, cnt, s)
@@ -1033,7 +1031,9 @@ crop_status crop_run_exact(crop_ctx *ctx)
         CK(launch_zero32(ps_n, 2 * ctx->P, s));
         if (outer) CK(launch_part_stats(ctx, true, ps_w, nullptr, s));
     }
-    CK(outer ? launch_aggregate_sums(ctx, s) : launch_aggregate_counts(ctx, s));
+    CK(outer     ? launch_aggregate_sums(ctx, s)
+       : regions ? launch_aggregate_regions(ctx, s)
+                 : launch_aggregate_counts(ctx, s));
     STAGE("aggregate");
     if (pl.g) {
         CK(launch_part_stats(ctx, false, ps_n, outer ? nullptr : ps_w, s));

@@ -268,7 +268,6 @@ size_t sb_route_smem_bytes(uint32_t NB, uint32_t max_rows, uint32_t max_items,
 uint32_t sb_threads();
 hipError_t launch_sb_route(const crop_ctx *c, hipStream_t s);
 hipError_t launch_sb_headers(const crop_ctx *c, hipStream_t s);
-hipError_t launch_sb_collect(const crop_ctx *c, void *keys_out, hipStream_t s);
 
 hipError_t launch_tx_count(const crop_ctx *c, uint32_t *cnt, hipStream_t s);
 // Owned shares with windowed enumeration (plan.win_kb > 0).
@@ -305,6 +304,7 @@ uint32_t batch_scan_tiles(uint32_t NBtot);
 hipError_t launch_batch_scan(const BatchDev &b, uint32_t *cnt, uint32_t *tot, uint32_t *tiles,
                              uint32_t *bin_off, uint32_t *counter, hipStream_t s);
 
+hipError_t launch_aggregate_regions(const crop_ctx *c, hipStream_t s);
 hipError_t launch_aggregate_counts(const crop_ctx *c, hipStream_t s);
 hipError_t launch_aggregate_sums(const crop_ctx *c, hipStream_t s);
 

@@ -24,13 +24,13 @@
 
 #include "crop_device.hpp"
 #include "crop_internal.hpp"
+#include "crop_runs.hpp"
 
 namespace crop {
 
 namespace {
 
 template <class KeyT> struct Empty;
-template <> struct Empty<uint32_t> { static constexpr uint32_t v = kEmpty32; };
 template <> struct Empty<uint64_t> { static constexpr uint64_t v = kEmpty64; };
 
 template <class KeyT>
@@ -601,6 +601,158 @@ k_aggregate_flat(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ ke
     }
 }
 
+// The packed aggregation fed straight from the region route: bin b's keys
+// are one run in each sub-batch region (its bin starts in the transposed
+// header), read where the route wrote them instead of from a bin-contiguous
+// copy.  Wavefront w takes the sub-batches [w n_sub / NW, (w + 1) n_sub /
+// NW), 64 at a time: one lane per sub-batch reads the run of bin b (the
+// header words of the next 64 already loaded), the non-empty runs are
+// listed in the wavefront's own LDS (routed position, keys before), and
+// sb_span maps 64 consecutive positions of the list to routed positions.  U
+// such spans make a batch for packed_insert_batch, two batches loaded
+// ahead, as in k_aggregate_flat; the output (distinct keys and counts from
+// bin_off[b], the spill segment there) is the same.
+template <int BS, int LOG2S, int U>
+__global__ void __launch_bounds__(BS)
+k_aggregate_regions(const uint16_t *__restrict__ hdrT, uint32_t hdrT_stride, uint32_t n_sub,
+                    const uint32_t *__restrict__ sb_base, const uint32_t *__restrict__ routed,
+                    const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ keys,
+                    uint32_t *__restrict__ w_out, uint32_t *__restrict__ bin_size,
+                    Spilled<uint32_t, uint32_t> *__restrict__ spill, uint32_t NB,
+                    uint32_t *counter, uint32_t cap_soft, const uint32_t *__restrict__ order)
+{
+    constexpr uint32_t S = 1u << LOG2S;
+    constexpr uint32_t NW = BS / kWave;
+    static_assert(S % BS == 0, "table size must be a multiple of the block size");
+    static_assert(S > BS * U, "a batch must fit in the table");
+    __shared__ uint64_t tab[S];
+    __shared__ uint2 s_q[NW][2 * kWave];  // each wavefront's queue of keys to probe
+    __shared__ uint32_t s_rb[NW][kWave], s_rp[NW][kWave + 1], s_flag[NW][kWave];
+    __shared__ uint32_t s_occ, s_nout, s_nspill, s_bin;
+    __shared__ int s_insert;
+    const uint32_t lane = lane_id();
+    // (wavefront-uniform, so the wavefront's LDS arrays get scalar bases)
+    const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    uint32_t *rb = s_rb[wave], *rp = s_rp[wave], *wflag = s_flag[wave];
+    wflag[lane] = 0;
+    uint32_t tag = 0;  // the span tags only grow, so old flags never match
+
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const uint32_t i = atomicAdd(counter, 1u);
+            s_bin = i < NB ? order[i] : NB;
+        }
+        __syncthreads();
+        const uint32_t b = s_bin;
+        if (b >= NB) break;
+        const uint32_t k0 = bin_off[b];
+        for (uint32_t s = threadIdx.x; s < S; s += BS) tab[s] = kFreeSlot;
+        if (threadIdx.x == 0) {
+            s_occ = 0;
+            s_nout = 0;
+            s_nspill = 0;
+        }
+        // this wavefront's sub-batches, and the header words of the next 64
+        uint32_t g = (uint32_t)(((uint64_t)n_sub * wave) / NW);
+        const uint32_t g_end = (uint32_t)(((uint64_t)n_sub * (wave + 1)) / NW);
+        const uint16_t *h0 = hdrT + (size_t)b * hdrT_stride, *h1 = h0 + hdrT_stride;
+        uint32_t na = 0, ne = 0, nbase = 0;
+        auto load_rows = [&]() {
+            const uint32_t sb = g + lane;
+            na = ne = nbase = 0;
+            if (sb < g_end) {
+                na = h0[sb];
+                ne = h1[sb];
+                nbase = sb_base[sb];
+            }
+        };
+        load_rows();
+        // the listed runs: count, keys, next position and the run holding it
+        uint32_t nr = 0, tk = 0, c = 0, r0 = 0;
+        // Positions c .. c + 63 of the listed runs (a new list once they are
+        // used up): the key of each valid lane, kEmpty32 (never a packed
+        // pair) elsewhere; false when the wavefront's keys are done
+        // (wavefront-uniform).
+        auto span = [&](uint32_t &key) {
+            while (c >= tk && g < g_end) {
+                const uint32_t len = ne - na;
+                const uint32_t incl = wave_inclusive_scan(len);
+                const uint64_t nz = __ballot(len != 0u);
+                // the last list's reads are complete before it is rewritten
+                __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                if (len) {
+                    const uint32_t ri = __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(nz >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)nz, 0u));
+                    rb[ri] = nbase + na;
+                    rp[ri] = incl - len;
+                }
+                nr = (uint32_t)__popcll(nz);
+                tk = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+                if (lane == 0) rp[nr] = tk;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                c = 0;
+                r0 = 0;
+                g += kWave;
+                load_rows();
+            }
+            if (c >= tk) {
+                key = kEmpty32;
+                return false;
+            }
+            const uint32_t src = sb_span(c, r0, nr, rb, rp, wflag, ++tag);
+            key = c + lane < tk ? routed[src] : kEmpty32;
+            c += kWave;
+            return true;
+        };
+        auto batch = [&](uint32_t (&k)[U]) {
+            bool any = false;
+#pragma unroll
+            for (int u = 0; u < U; ++u) any = span(k[u]) || any;
+            return any;
+        };
+        uint32_t cur[U], nx1[U];
+        bool a0 = batch(cur);
+        bool a1 = batch(nx1);
+        __syncthreads();  // the table is clear
+        uint32_t qn = 0;
+        while (a0) {
+            uint32_t nx2[U];
+            const bool a2 = batch(nx2);
+            const bool ins =
+                __hip_atomic_load(&s_occ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <=
+                cap_soft;
+            uint32_t wt[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) wt[u] = cur[u] != kEmpty32 ? 1u : 0u;
+            // the last batch of the wavefront drains its queue
+            const uint32_t n_new = packed_insert_batch<U, LOG2S>(tab, cur, wt, ins, spill, k0,
+                                                                 &s_nspill, s_q[wave], qn, !a1);
+            uint32_t tot = n_new;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) tot += __shfl_xor(tot, d, kWave);
+            if (lane == 0 && tot) atomicAdd(&s_occ, tot);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                cur[u] = nx1[u];
+                nx1[u] = nx2[u];
+            }
+            a0 = a1;
+            a1 = a2;
+        }
+        __syncthreads();  // keys of the bin are consumed; the spill list is complete
+        packed_absorb_spill<BS, LOG2S>(tab, spill, k0, &s_nspill);
+        packed_dump<BS, LOG2S>(tab, keys + k0, w_out + k0, &s_nout);
+        __syncthreads();
+        packed_spill_rounds<BS, LOG2S>(tab, spill, k0, keys, w_out, cap_soft, &s_occ, &s_nout,
+                                       &s_nspill, &s_insert);
+        if (threadIdx.x == 0) bin_size[b] = s_nout;
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 static uint32_t persistent_grid(uint32_t NB)
@@ -620,6 +772,22 @@ constexpr int kFlatU = 4;
 constexpr uint32_t kPackedCapSoft = (1u << 14) - 1024 * (kFlatU + 1) - 1024;
 static_assert(kPackedCapSoft + 1024 * (kFlatU + 1) < (1u << 14),
               "packed table must keep free slots");
+
+hipError_t launch_aggregate_regions(const crop_ctx *c, hipStream_t s)
+{
+    const RoutePlan &pl = c->plan;
+    const SbPlan &sp = c->sb;
+    if (pl.NB == 0) return hipSuccess;
+    if (c->in.wide_keys) return hipErrorInvalidValue;  // 64-bit keys stay on the chunk route
+    hipLaunchKernelGGL((k_aggregate_regions<1024, 14, kFlatU>), dim3(persistent_grid(pl.NB)),
+                       dim3(1024), 0, s, c->sb_hdrT.as<uint16_t>(), sp.hdrT_stride, sp.n_sub,
+                       c->sb_term.as<uint32_t>(), c->routed.as<uint32_t>(),
+                       c->bin_off.as<uint32_t>(), c->keys.as<uint32_t>(),
+                       c->out_cnt.as<uint32_t>(), c->bin_size.as<uint32_t>(),
+                       c->spill.as<Spilled<uint32_t, uint32_t>>(), pl.NB,
+                       c->counter.as<uint32_t>(), kPackedCapSoft, c->bin_order.as<uint32_t>());
+    return hipGetLastError();
+}
 
 hipError_t launch_aggregate_counts(const crop_ctx *c, hipStream_t s)
 {

@@ -16,24 +16,20 @@
 // Bin b is then one run per region.  k_sb_headers transposes the start rows
 // (so a bin's starts are contiguous) and sums them over the sub-batches: the
 // sum of the starts of bin b is the number of keys in bins below b, i.e. the
-// offset of bin b in a bin-contiguous layout.  k_sb_collect builds that
-// layout, which the per-bin kernels (the exact aggregation) read.  The
-// route takes packed 32-bit keys (fewer than 2^16 items); 64-bit keys stay
-// on the chunk route.
+// offset of bin b's results in a bin-contiguous layout.  The exact
+// aggregation reads each bin's runs where they are (k_aggregate_regions).
+// The route takes packed 32-bit keys (fewer than 2^16 items); 64-bit keys
+// stay on the chunk route.
 #include "crop_device.hpp"
 #include "crop_enum.hpp"
 #include "crop_internal.hpp"
 #include "crop_layout.hpp"
-#include "crop_runs.hpp"
 
 namespace crop {
 
 namespace {
 
-constexpr int kSbBS = 1024;           // threads of a route workgroup
-constexpr int kCollectBS = 256;          // threads of a collect workgroup
-constexpr uint32_t kCollectPart = 512;   // sub-batches of a collect part (8 header tiles)
-constexpr uint32_t kCollectD = 16;       // spans of 64 keys in flight per wavefront
+constexpr int kSbBS = 1024;  // threads of a route workgroup
 
 // One sub-batch: rows [sb_row[s], sb_row[s+1]); its region of the routed
 // array starts at sb_base[s], a multiple of four keys.  Thread t enumerates
@@ -178,8 +174,8 @@ k_sb_route(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
 }
 
 // Tiles of 64 sub-batches x 64 bin starts: hdrT[b][s] = hdr[s][b] for
-// b <= NB, and tsum[t][b] = tile t's sum of hdr[s][b] (k_sb_tile_scan turns
-// these into offsets).
+// b <= NB, and tsum[t][b] = tile t's sum of hdr[s][b] (k_sb_tile_scan adds
+// them up).
 __global__ void __launch_bounds__(256)
 k_sb_headers(const uint16_t *__restrict__ hdr, uint32_t hdr_stride, uint32_t n_sub, uint32_t NB,
              uint16_t *__restrict__ hdrT, uint32_t hdrT_stride, uint32_t *__restrict__ tsum)
@@ -207,14 +203,11 @@ k_sb_headers(const uint16_t *__restrict__ hdr, uint32_t hdr_stride, uint32_t n_s
     }
 }
 
-// Per bin start b <= NB, over the header tiles t: tsum[t][b] <- the sum of
-// the tiles before t (in place), and bin_off[b] <- the sum of all of them.
-// The sum of the starts of bin b over every sub-batch is the number of kept
-// keys in bins below b, i.e. bin b's offset in a bin-contiguous layout, and
-// tsum[t][b + 1] - tsum[t][b] (after the scan) is the number of keys of bin
-// b in the tiles before t.
+// Per bin start b <= NB: bin_off[b] <- the sum over the header tiles.  The
+// sum of the starts of bin b over every sub-batch is the number of kept keys
+// in bins below b, i.e. bin b's offset in a bin-contiguous layout.
 __global__ void __launch_bounds__(256)
-k_sb_tile_scan(uint32_t *__restrict__ tsum, uint32_t n_tiles, uint32_t NB,
+k_sb_tile_scan(const uint32_t *__restrict__ tsum, uint32_t n_tiles, uint32_t NB,
                uint32_t *__restrict__ bin_off)
 {
     const uint32_t b = blockIdx.x * 256 + threadIdx.x;
@@ -226,92 +219,9 @@ k_sb_tile_scan(uint32_t *__restrict__ tsum, uint32_t n_tiles, uint32_t NB,
         for (uint32_t k = 0; k < 8; ++k)
             v[k] = t0 + k < n_tiles ? tsum[(size_t)(t0 + k) * (NB + 1) + b] : 0u;
 #pragma unroll
-        for (uint32_t k = 0; k < 8; ++k) {
-            if (t0 + k < n_tiles) tsum[(size_t)(t0 + k) * (NB + 1) + b] = run;
-            run += v[k];
-        }
+        for (uint32_t k = 0; k < 8; ++k) run += v[k];
     }
     bin_off[b] = run;
-}
-
-// Bin-contiguous copy of the routed keys: bin b's runs, in sub-batch order,
-// to keys_out[bin_off[b] ...).  A bin is split into parts of kCollectPart
-// sub-batches, one workgroup each, so a heavy bin does not hold one
-// workgroup while the others finish; the parts of consecutive bins run on
-// one XCD, whose L2 then serves the regions' lines to all of them.  A part
-// finds its offset inside its bin from the scanned header tile sums.  Thread t lists
-// the non-empty runs of CPT consecutive sub-batches; each wavefront then
-// copies a contiguous share of the part's keys, kCollectD spans of 64 at a
-// time, all of their loads in flight before the first store.
-__global__ void __launch_bounds__(kCollectBS)
-k_sb_collect(const uint16_t *__restrict__ hdrT, uint32_t hdrT_stride, uint32_t n_sub,
-             uint32_t NB, uint32_t n_parts, const uint32_t *__restrict__ tsum,
-             const uint32_t *__restrict__ sb_base, const uint32_t *__restrict__ routed,
-             const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ keys_out)
-{
-    constexpr uint32_t BS = kCollectBS, NW = BS / kWave, D = kCollectD;
-    constexpr uint32_t CPT = kCollectPart / BS, TPP = kCollectPart / 64;
-    __shared__ uint32_t rb[kCollectPart], rp[kCollectPart + 1], s_tmp[NW + 1];
-    __shared__ uint32_t wflag[NW][kWave];
-    const uint32_t id = xcd_contiguous(blockIdx.x, gridDim.x);
-    const uint32_t b = id / n_parts, g = id % n_parts;
-    const uint32_t lane = lane_id(), wave = threadIdx.x / kWave;
-    wflag[wave][lane] = 0;
-    // the part's output: bin b's offset plus its keys in the header tiles
-    // before the part (the scanned tile sums)
-    const uint32_t *pre = tsum + (size_t)g * TPP * (NB + 1);
-    uint32_t *out = keys_out + bin_off[b] + (pre[b + 1] - pre[b]);
-    uint32_t tag = 0;
-    const uint32_t s1 = g * kCollectPart + threadIdx.x * CPT;
-    uint32_t len[CPT], pos[CPT], nr = 0, nk = 0;
-#pragma unroll
-    for (uint32_t k = 0; k < CPT; ++k) {
-        len[k] = 0;
-        pos[k] = 0;
-        if (s1 + k < n_sub) {
-            const uint32_t a = hdrT[(size_t)b * hdrT_stride + s1 + k];
-            len[k] = hdrT[(size_t)(b + 1) * hdrT_stride + s1 + k] - a;
-            pos[k] = sb_base[s1 + k] + a;
-        }
-        nr += len[k] ? 1u : 0u;
-        nk += len[k];
-    }
-    uint32_t tr, tk;
-    uint32_t ri = block_exclusive_scan<BS>(nr, s_tmp, &tr);
-    uint32_t kp = block_exclusive_scan<BS>(nk, s_tmp, &tk);
-#pragma unroll
-    for (uint32_t k = 0; k < CPT; ++k) {
-        if (len[k]) {
-            rb[ri] = pos[k];
-            rp[ri] = kp;
-            ++ri;
-            kp += len[k];
-        }
-    }
-    if (threadIdx.x == 0) rp[tr] = tk;
-    __syncthreads();
-    // wavefront w copies positions [w q, w q + q) of the part
-    const uint32_t q = (tk + NW * kWave - 1) / (NW * kWave) * kWave;
-    uint32_t c = wave * q;
-    const uint32_t e = min(tk, c + q);
-    if (c >= e) return;
-    uint32_t r0 = sb_find_run(c, tr, rp);
-    for (; c < e; c += D * kWave) {
-        uint32_t v[D];
-#pragma unroll
-        for (uint32_t d = 0; d < D; ++d) {
-            const uint32_t cd = c + d * kWave;
-            if (cd < e) {  // wavefront-uniform
-                const uint32_t src = sb_span(cd, r0, tr, rb, rp, wflag[wave], ++tag);
-                if (cd + lane < e) v[d] = routed[src];
-            }
-        }
-#pragma unroll
-        for (uint32_t d = 0; d < D; ++d) {
-            const uint32_t i = c + d * kWave + lane;
-            if (i < e) out[i] = v[d];
-        }
-    }
 }
 
 }  // namespace
@@ -366,21 +276,6 @@ hipError_t launch_sb_headers(const crop_ctx *c, hipStream_t s)
                        c->sb_tsum.as<uint32_t>());
     hipLaunchKernelGGL(k_sb_tile_scan, dim3((pl.NB + 1 + 255) / 256), dim3(256), 0, s,
                        c->sb_tsum.as<uint32_t>(), n_tiles, pl.NB, bin_off);
-    return hipGetLastError();
-}
-
-hipError_t launch_sb_collect(const crop_ctx *c, void *keys_out, hipStream_t s)
-{
-    const RoutePlan &pl = c->plan;
-    const SbPlan &sp = c->sb;
-    if (pl.NB == 0 || sp.n_sub == 0) return hipSuccess;
-    if (c->in.wide_keys) return hipErrorInvalidValue;  // 64-bit keys stay on the chunk route
-    const uint32_t n_parts = (sp.n_sub + kCollectPart - 1) / kCollectPart;
-    hipLaunchKernelGGL(k_sb_collect, dim3(pl.NB * n_parts), dim3(kCollectBS), 0, s,
-                       c->sb_hdrT.as<uint16_t>(), sp.hdrT_stride, sp.n_sub, pl.NB, n_parts,
-                       c->sb_tsum.as<uint32_t>(), c->sb_term.as<uint32_t>(),
-                       c->routed.as<uint32_t>(), c->bin_off.as<uint32_t>(),
-                       static_cast<uint32_t *>(keys_out));
     return hipGetLastError();
 }
 
