@@ -713,27 +713,30 @@ k_aggregate_regions(const uint16_t *__restrict__ hdrT, uint32_t hdrT_stride, uin
             for (int u = 0; u < U; ++u) any = span(k[u]) || any;
             return any;
         };
-        uint32_t cur[U], nx1[U];
-        bool a0 = batch(cur);
-        bool a1 = batch(nx1);
         __syncthreads();  // the table is clear
+        // batch i + 2 is loaded while batch i is inserted (one call site of
+        // batch, so its spans are inlined once); the first two iterations
+        // only load
+        uint32_t cur[U], nx1[U], nx2[U];
+        bool a0 = false, a1 = false;
         uint32_t qn = 0;
-        while (a0) {
-            uint32_t nx2[U];
+        for (int it = -2;; ++it) {
             const bool a2 = batch(nx2);
-            const bool ins =
-                __hip_atomic_load(&s_occ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <=
-                cap_soft;
-            uint32_t wt[U];
+            if (it >= 0) {
+                if (!a0) break;  // wavefront-uniform: this wavefront's keys are done
+                const bool ins = __hip_atomic_load(&s_occ, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP) <= cap_soft;
+                uint32_t wt[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) wt[u] = cur[u] != kEmpty32 ? 1u : 0u;
-            // the last batch of the wavefront drains its queue
-            const uint32_t n_new = packed_insert_batch<U, LOG2S>(tab, cur, wt, ins, spill, k0,
-                                                                 &s_nspill, s_q[wave], qn, !a1);
-            uint32_t tot = n_new;
+                for (int u = 0; u < U; ++u) wt[u] = cur[u] != kEmpty32 ? 1u : 0u;
+                // the last batch of the wavefront drains its queue
+                const uint32_t n_new = packed_insert_batch<U, LOG2S>(
+                    tab, cur, wt, ins, spill, k0, &s_nspill, s_q[wave], qn, !a1);
+                uint32_t tot = n_new;
 #pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) tot += __shfl_xor(tot, d, kWave);
-            if (lane == 0 && tot) atomicAdd(&s_occ, tot);
+                for (int d = 32; d >= 1; d >>= 1) tot += __shfl_xor(tot, d, kWave);
+                if (lane == 0 && tot) atomicAdd(&s_occ, tot);
+            }
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 cur[u] = nx1[u];
