@@ -36,8 +36,9 @@ constexpr int kSbBS = 1024;  // threads of a route workgroup
 // terms [t Q, t Q + Q) of the sub-batch in row-major order ((a, b) with
 // a < b over the positions of a row), so a thread's terms are consecutive
 // pairs of one or two rows; the LDS read of the next term's partner is
-// issued before the current term is hashed and ranked.
-template <int BS, int Q, class KeyT>
+// issued before the current term is hashed and ranked.  DROP: an owned
+// share, where most terms fall outside the run's bins and take no rank.
+template <int BS, int Q, class KeyT, bool DROP>
 __global__ void __launch_bounds__(BS)
 k_sb_route(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items, HashParams hp,
            BinMap bm, uint32_t NB, SbLayout lay, const uint32_t *__restrict__ sb_row,
@@ -73,10 +74,11 @@ k_sb_route(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
     lds_exclusive_scan<BS>(tp, R, s_tmp);
     const uint32_t nt = tp[R];
 
-    // Each term takes its rank inside its bin with one LDS atomic, issued
-    // for every term (a term outside the run's bins counts in the discard
-    // counter hist[NB + 1]) and not waited for until the placement: nothing
-    // in the loop needs its result.
+    // Each term takes its rank inside its bin with one LDS atomic, not waited
+    // for until the placement: nothing in the loop needs its result.  A full
+    // run issues it for every term (a term past the thread's count counts in
+    // the discard counter hist[NB + 1]); an owned share only for its own
+    // terms, since the discarded majority would queue on that one word.
     KeyT key[Q];
     uint32_t bins[Q], rank[Q];
     const uint32_t tb = threadIdx.x * Q;
@@ -131,7 +133,10 @@ k_sb_route(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
             const uint32_t bin = bm.local(ha + yh.y);
             bins[u] = ((uint32_t)u < nv && bin < NB) ? bin : NB + 1;
             key[u] = pack_key<KeyT>(x, yh.x);
-            rank[u] = atomicAdd(&hist[bins[u]], 1u);
+            if (DROP)
+                rank[u] = bins[u] < NB ? atomicAdd(&hist[bins[u]], 1u) : 0u;
+            else
+                rank[u] = atomicAdd(&hist[bins[u]], 1u);
             yh = yn;
             x = nx;
             ha = nha;
@@ -248,15 +253,20 @@ hipError_t launch_sb_route(const crop_ctx *c, hipStream_t s)
     if (Q * kSbBS != sp.max_terms) return hipErrorInvalidConfiguration;
     const uint32_t *row = c->sb_row.as<uint32_t>(), *term = c->sb_term.as<uint32_t>();
     uint16_t *hdr = c->sb_hdr.as<uint16_t>();
-#define SB_LAUNCH(QQ, KT)                                                                    \
-    hipLaunchKernelGGL((k_sb_route<kSbBS, QQ, KT>), dim3(sp.n_sub), dim3(kSbBS), sm, s,       \
+    const bool drop = pl.nu < pl.M;  // an owned share
+#define SB_LAUNCH(QQ, KT, DR)                                                                \
+    hipLaunchKernelGGL((k_sb_route<kSbBS, QQ, KT, DR>), dim3(sp.n_sub), dim3(kSbBS), sm, s,   \
                        c->in.off, c->in.items, c->hp, bin_map(pl), pl.NB, lay, row, term,     \
                        sp.hdr_stride, c->routed.as<KT>(), hdr)
     if (c->in.wide_keys) return hipErrorInvalidConfiguration;  // packed keys only
-    if (Q == 16)
-        SB_LAUNCH(16, uint32_t);
+    if (Q == 16 && drop)
+        SB_LAUNCH(16, uint32_t, true);
+    else if (Q == 16)
+        SB_LAUNCH(16, uint32_t, false);
+    else if (Q == 24 && drop)
+        SB_LAUNCH(24, uint32_t, true);
     else if (Q == 24)
-        SB_LAUNCH(24, uint32_t);
+        SB_LAUNCH(24, uint32_t, false);
     else
         return hipErrorInvalidConfiguration;
 #undef SB_LAUNCH
