@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "api_util.hpp"
+#include "crop_device.hpp"
 #include "crop_layout.hpp"
 
 using namespace crop;
@@ -1001,9 +1002,10 @@ crop_status crop_run_exact(crop_ctx *ctx)
         if (ctx->sb.n_sub) CK(launch_sb_route(ctx, s));
         STAGE("route");
         CK(launch_sb_headers(ctx, s));
-        CK(launch_zero32(ctx->counter.as<uint32_t>(), 2, s));
+        // one bin counter and one ordered range of bins per XCD
+        CK(launch_zero32(ctx->counter.as<uint32_t>(), crop::kNumXcd, s));
         CK(launch_bin_order(pl.NB, ctx->bin_off.as<uint32_t>(), ctx->bin_order.as<uint32_t>(),
-                            s));
+                            s, crop::kNumXcd));
         STAGE("headers");
     } else {
         if (pl.n_chunks) CK(outer ? launch_op_count(ctx, cnt, s)

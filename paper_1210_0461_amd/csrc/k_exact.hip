@@ -637,10 +637,27 @@ k_aggregate_regions(const uint16_t *__restrict__ hdrT, uint32_t hdrT_stride, uin
     wflag[lane] = 0;
     uint32_t tag = 0;  // the span tags only grow, so old flags never match
 
+    // Bins are dealt per XCD: the workgroups of XCD x (block % 8) take the
+    // x-th eighth of the bins, heaviest first, then in index order
+    // (counter[x]; order[] is ordered per eighth), so the bins in flight on
+    // one XCD are neighbours whose runs share lines in its L2.  A workgroup
+    // whose eighth is dealt out takes bins of the next eighths.
+    const uint32_t home = blockIdx.x % kNumXcd;
     for (;;) {
         if (threadIdx.x == 0) {
-            const uint32_t i = atomicAdd(counter, 1u);
-            s_bin = i < NB ? order[i] : NB;
+            uint32_t bin = NB;
+            for (uint32_t k = 0; k < (uint32_t)kNumXcd && bin == NB; ++k) {
+                const uint32_t x = (home + k) % kNumXcd;
+                const uint32_t lo = (uint32_t)((uint64_t)NB * x / kNumXcd);
+                const uint32_t hi = (uint32_t)((uint64_t)NB * (x + 1) / kNumXcd);
+                // an eighth already dealt out is not counted further
+                if (__hip_atomic_load(&counter[x], __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_AGENT) >= hi - lo)
+                    continue;
+                const uint32_t i = atomicAdd(&counter[x], 1u);
+                if (lo + i < hi) bin = order[lo + i];
+            }
+            s_bin = bin;
         }
         __syncthreads();
         const uint32_t b = s_bin;

@@ -511,24 +511,30 @@ k_colbase(uint32_t NB, uint32_t *__restrict__ bin_off, uint32_t *__restrict__ co
     }
 }
 
-// One workgroup: order[] lists the bins with more than twice the mean term
-// count first (in index order), then the others, so that the persistent
-// aggregation workgroups start the longest bins first.
+// One workgroup per segment of the bins (segment g: bins [g NB / n_seg,
+// (g + 1) NB / n_seg)): order[] lists, in place of the segment, its bins
+// with more than twice the mean term count first (in index order), then
+// the others, so that the persistent aggregation workgroups start the
+// longest bins first.
 __global__ void __launch_bounds__(1024)
 k_bin_order(uint32_t NB, const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ order)
 {
     __shared__ uint32_t s_tmp[1024 / kWave + 1];
     __shared__ uint32_t s_nheavy;
     const uint64_t thresh = 2ull * bin_off[NB] / (NB ? NB : 1);
-    const uint32_t per = (NB + 1023) / 1024;
-    const uint32_t b0 = threadIdx.x * per, b1 = min(NB, b0 + per);
+    const uint32_t lo = (uint32_t)((uint64_t)NB * blockIdx.x / gridDim.x);
+    const uint32_t hi = (uint32_t)((uint64_t)NB * (blockIdx.x + 1) / gridDim.x);
+    const uint32_t per = (hi - lo + 1023) / 1024;
+    const uint32_t b0 = min(hi, lo + threadIdx.x * per), b1 = min(hi, b0 + per);
     uint32_t nh = 0;
     for (uint32_t b = b0; b < b1; ++b) nh += (bin_off[b + 1] - bin_off[b]) > thresh;
     uint32_t total;
     uint32_t h = block_exclusive_scan<1024>(nh, s_tmp, &total);
     if (threadIdx.x == 0) s_nheavy = total;
     __syncthreads();
-    uint32_t l = s_nheavy + b0 - h;  // light bins before b0 = b0 - heavy bins before b0
+    // light bins of the segment before b0 = (b0 - lo) - heavy bins before b0
+    uint32_t l = lo + s_nheavy + (b0 - lo) - h;
+    h += lo;
     for (uint32_t b = b0; b < b1; ++b) {
         if ((bin_off[b + 1] - bin_off[b]) > thresh)
             order[h++] = b;
@@ -932,9 +938,10 @@ hipError_t launch_op_scatter(const crop_ctx *c, const uint32_t *cur, void *keys,
     return hipGetLastError();
 }
 
-hipError_t launch_bin_order(uint32_t NB, const uint32_t *bin_off, uint32_t *order, hipStream_t s)
+hipError_t launch_bin_order(uint32_t NB, const uint32_t *bin_off, uint32_t *order, hipStream_t s,
+                            uint32_t n_seg)
 {
-    hipLaunchKernelGGL(k_bin_order, dim3(1), dim3(1024), 0, s, NB, bin_off, order);
+    hipLaunchKernelGGL(k_bin_order, dim3(n_seg), dim3(1024), 0, s, NB, bin_off, order);
     return hipGetLastError();
 }
 
