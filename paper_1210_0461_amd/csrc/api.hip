@@ -714,7 +714,9 @@ void crop_destroy(crop_ctx *ctx)
     for (DevBuf *b : {&ctx->cnt_mat, &ctx->part_buf, &ctx->bin_off, &ctx->bin_size,
                       &ctx->bin_order, &ctx->keys,
                       &ctx->vals, &ctx->out_cnt, &ctx->spill, &ctx->counter, &ctx->ss_state,
-                      &ctx->topk_buf, &ctx->scratch, &ctx->learn_ws, &ctx->in.d_op_chunks,
+                      &ctx->topk_buf, &ctx->scratch, &ctx->learn_ws, &ctx->seed_sel,
+                      &ctx->part_stats, &ctx->routed, &ctx->sb_row, &ctx->sb_term,
+                      &ctx->sb_hdr, &ctx->sb_hdrT, &ctx->sb_tsum, &ctx->in.d_op_chunks,
                       &bt.d_crow, &bt.d_cstream, &bt.d_streams, &bt.d_bin_stream, &bt.tot,
                       &bt.tiles, &ctx->cs_buf, &ctx->amp_buf})
         b->release();
@@ -1601,7 +1603,9 @@ crop_status crop_select_seeds(crop_ctx *ctx, const float *score, const uint32_t 
     if (n >= (1ull << 32)) return fail(ctx, CROP_E_UNSUPPORTED, "too many candidates");
     if (R > n) return fail(ctx, CROP_E_ARG, "R exceeds the candidate count");
     DeviceGuard g(ctx->device);
-    CK(launch_select_seeds(score, cx, cy, (uint32_t)n, R, sx, sy, ctx->stream));
+    CK(ctx->seed_sel.ensure(((size_t)R + 2) * 4));
+    CK(launch_select_seeds(score, cx, cy, (uint32_t)n, R, sx, sy, ctx->seed_sel.as<uint32_t>(),
+                           ctx->stream));
     return CROP_OK;
 }
 

@@ -218,6 +218,7 @@ struct crop_ctx {
     crop::DevBuf cnt_mat, part_buf, bin_off, bin_size, bin_order, keys, vals, out_cnt, spill,
         counter;
     crop::DevBuf ss_state, topk_buf, scratch, learn_ws;
+    crop::DevBuf seed_sel;     // seed selection: threshold words and the selected candidates
     crop::DevBuf part_stats;   // grouped bins: entries and terms of each partition
     crop::SbPlan sb;           // region route: sub-batch plan of the loaded stream
     crop::DevBuf routed, sb_row, sb_term, sb_hdr, sb_hdrT, sb_tsum;
@@ -366,8 +367,10 @@ hipError_t launch_mlp_grad(const float *params, const float *Z, const float *y, 
                            float *grad, float *loss, hipStream_t s);
 hipError_t launch_mlp_score(const float *params, const float *Z, uint64_t N, float *out,
                             hipStream_t s);
+// sel: 2 + R words of workspace.
 hipError_t launch_select_seeds(const float *score, const uint32_t *cx, const uint32_t *cy,
-                               uint32_t n, uint32_t R, uint32_t *sx, uint32_t *sy, hipStream_t s);
+                               uint32_t n, uint32_t R, uint32_t *sx, uint32_t *sy, uint32_t *sel,
+                               hipStream_t s);
 hipError_t launch_max_index(const uint32_t *idx, uint64_t n, uint32_t *out, hipStream_t s);
 int mlp_param_count();
 int mlp_batch_max();

@@ -486,31 +486,102 @@ k_mlp_score(const float *__restrict__ params, const float *__restrict__ Z, uint6
     }
 }
 
-// rank of candidate i = #{j : score_j > score_i, or equal with j < i};
-// the R best become seeds in rank order.
-__global__ void __launch_bounds__(256)
-k_select_seeds(const float *__restrict__ score, const uint32_t *__restrict__ cx,
-               const uint32_t *__restrict__ cy, uint32_t n, uint32_t R,
-               uint32_t *__restrict__ sx, uint32_t *__restrict__ sy)
+// Seeds: the R best candidates by (score desc, index asc), in that order.
+// Scores become order-preserving words (-0 taken as +0, so equal scores
+// give equal words).
+__device__ inline uint32_t score_word(float f)
 {
-    __shared__ float tile[256];
-    const uint32_t i = blockIdx.x * 256 + threadIdx.x;
-    const float me = i < n ? score[i] : 0.0f;
-    uint32_t rank = 0;
-    for (uint32_t b = 0; b < n; b += 256) {
-        __syncthreads();
-        if (b + threadIdx.x < n) tile[threadIdx.x] = score[b + threadIdx.x];
-        __syncthreads();
-        const uint32_t lim = min(256u, n - b);
-        if (i < n)
-            for (uint32_t q = 0; q < lim; ++q) {
-                const float o = tile[q];
-                rank += (o > me || (o == me && b + q < i)) ? 1u : 0u;
-            }
+    const uint32_t b = __float_as_uint(f == 0.0f ? 0.0f : f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
+// One workgroup: the R-th best word t by radix selection (four 8-bit digits,
+// most significant first), then the selected candidates in index order:
+// every word above t and the first `need` (by index) equal to t, where need
+// is what R leaves after the words above t.  sel[0] = t, sel[1] = need,
+// sel[2 ..] = the R selected indices.
+__global__ void __launch_bounds__(1024)
+k_seed_threshold(const float *__restrict__ score, uint32_t n, uint32_t R, uint32_t *__restrict__ sel)
+{
+    constexpr uint32_t BS = 1024;
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t s_tmp[BS / kWave + 1];
+    __shared__ uint32_t s_prefix, s_need;
+    if (threadIdx.x == 0) {
+        s_prefix = 0;
+        s_need = R;
     }
-    if (i < n && rank < R) {
-        sx[rank] = cx[i];
-        sy[rank] = cy[i];
+    for (int shift = 24; shift >= 0; shift -= 8) {
+        for (uint32_t d = threadIdx.x; d < 256; d += BS) hist[d] = 0;
+        __syncthreads();
+        const uint32_t prefix = s_prefix;
+        for (uint32_t i = threadIdx.x; i < n; i += BS) {
+            const uint32_t u = score_word(score[i]);
+            // the digits above this one agree with the prefix chosen so far
+            if (shift == 24 || ((u ^ prefix) >> (shift + 8)) == 0)
+                atomicAdd(&hist[(u >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t need = s_need, cum = 0, d = 255;
+            for (;; --d) {
+                if (cum + hist[d] >= need || d == 0) break;
+                cum += hist[d];
+            }
+            s_prefix = prefix | (d << shift);
+            s_need = need - cum;
+        }
+        __syncthreads();
+    }
+    const uint32_t t = s_prefix, need = s_need;
+    uint32_t eq_seen = 0, taken = 0;
+    for (uint32_t base = 0; base < n; base += BS) {
+        const uint32_t i = base + threadIdx.x;
+        const uint32_t u = i < n ? score_word(score[i]) : 0u;
+        const bool eq = i < n && u == t;
+        uint32_t n_eq;
+        const uint32_t eq_before = block_exclusive_scan<BS>(eq ? 1u : 0u, s_tmp, &n_eq);
+        const bool take = (i < n && u > t) || (eq && eq_seen + eq_before < need);
+        uint32_t n_take;
+        const uint32_t pos = block_exclusive_scan<BS>(take ? 1u : 0u, s_tmp, &n_take);
+        if (take) sel[2 + taken + pos] = i;
+        eq_seen += n_eq;
+        taken += n_take;
+    }
+    if (threadIdx.x == 0) {
+        sel[0] = t;
+        sel[1] = need;
+    }
+}
+
+// Rank of selected candidate p among the R selected (better: larger word,
+// or equal word and smaller index); seeds written in rank order.
+__global__ void __launch_bounds__(256)
+k_seed_rank(const float *__restrict__ score, const uint32_t *__restrict__ cx,
+            const uint32_t *__restrict__ cy, uint32_t R, const uint32_t *__restrict__ sel,
+            uint32_t *__restrict__ sx, uint32_t *__restrict__ sy)
+{
+    __shared__ uint32_t tw[256], ti[256];
+    const uint32_t p = blockIdx.x * 256 + threadIdx.x;
+    const uint32_t me = p < R ? sel[2 + p] : 0u;
+    const uint32_t mw = p < R ? score_word(score[me]) : 0u;
+    uint32_t rank = 0;
+    for (uint32_t b = 0; b < R; b += 256) {
+        __syncthreads();
+        if (b + threadIdx.x < R) {
+            const uint32_t j = sel[2 + b + threadIdx.x];
+            ti[threadIdx.x] = j;
+            tw[threadIdx.x] = score_word(score[j]);
+        }
+        __syncthreads();
+        const uint32_t lim = min(256u, R - b);
+        if (p < R)
+            for (uint32_t q = 0; q < lim; ++q)
+                rank += (tw[q] > mw || (tw[q] == mw && ti[q] < me)) ? 1u : 0u;
+    }
+    if (p < R) {
+        sx[rank] = cx[me];
+        sy[rank] = cy[me];
     }
 }
 
@@ -629,10 +700,12 @@ hipError_t launch_mlp_score(const float *params, const float *Z, uint64_t N, flo
 }
 
 hipError_t launch_select_seeds(const float *score, const uint32_t *cx, const uint32_t *cy,
-                               uint32_t n, uint32_t R, uint32_t *sx, uint32_t *sy, hipStream_t s)
+                               uint32_t n, uint32_t R, uint32_t *sx, uint32_t *sy, uint32_t *sel,
+                               hipStream_t s)
 {
-    if (!n) return hipSuccess;
-    hipLaunchKernelGGL(k_select_seeds, dim3((n + 255) / 256), dim3(256), 0, s, score, cx, cy, n, R,
+    if (!n || !R) return hipSuccess;
+    hipLaunchKernelGGL(k_seed_threshold, dim3(1), dim3(1024), 0, s, score, n, R, sel);
+    hipLaunchKernelGGL(k_seed_rank, dim3((R + 255) / 256), dim3(256), 0, s, score, cx, cy, R, sel,
                        sx, sy);
     return hipGetLastError();
 }
