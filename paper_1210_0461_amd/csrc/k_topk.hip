@@ -394,16 +394,16 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
             }
             load_batch(next);  // the next micro-batch, used after step 4
             __syncthreads();
-            // 2. a bin of one bucket takes its hits in one parallel step: every
-            // monitored slot looks its key up in the merge table and takes the
-            // merged weight, and the entry is marked consumed (keys are only
-            // read here, so probe chains stay intact).  A micro-batch holds
-            // each key once, so a key that is not monitored now cannot become
-            // monitored before its own update: every update left for step 4
-            // is a miss.  Any order of the updates keeps the Section 4
-            // bounds.  (Bins of many buckets would scan all their slots per
-            // micro-batch; they keep the hit test in step 4.)
-            for (uint32_t q = threadIdx.x; ONE && q < nslot; q += BS) {
+            // 2. the hits in one parallel step (bins of one bucket, and bins
+            // of transaction counts): every monitored slot looks its key up
+            // in the merge table and takes the merged weight, and the entry
+            // is marked consumed (keys are only read here, so probe chains
+            // stay intact).  A micro-batch holds each key once, so a key that
+            // is not monitored now cannot become monitored before its own
+            // update: every update left for step 4 is a miss.  Any order of
+            // the updates keeps the Section 4 bounds.  (Outer-product bins of
+            // many buckets keep the hit test in step 4.)
+            for (uint32_t q = threadIdx.x; (ONE || !OUTER) && q < nslot; q += BS) {
                 if (!(s_f[q] & kUsed)) continue;
                 const KeyT key = s_k[q];
                 uint32_t sl = slot_of(key, LOG2HS);
@@ -451,9 +451,10 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                 }
                 if (threadIdx.x == 0) s_pos[0] = total;  // the bucket's end
             } else {
+                // (entries consumed as hits in step 2 are left out)
                 for (uint32_t i = threadIdx.x; i < HS; i += BS) {
                     const KeyT key = h_k[i];
-                    if (key == empty_key<KeyT>()) continue;
+                    if (key == empty_key<KeyT>() || h_w[i] == kConsumed) continue;
                     atomicAdd(&s_pos[(uint32_t)(bucket_of_key(key, hp, PB, narrow) - bucket0)],
                               1u);
                 }
@@ -461,7 +462,7 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                 lds_exclusive_scan_rt(s_pos, nbk, s_tmp);
                 for (uint32_t i = threadIdx.x; i < HS; i += BS) {
                     const KeyT key = h_k[i];
-                    if (key == empty_key<KeyT>()) continue;
+                    if (key == empty_key<KeyT>() || h_w[i] == kConsumed) continue;
                     const uint32_t lb = (uint32_t)(bucket_of_key(key, hp, PB, narrow) - bucket0);
                     const uint32_t p = atomicAdd(&s_pos[lb], 1u);  // becomes the bucket's end
                     t_k[p] = key;
@@ -573,6 +574,47 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                     c = win ? cw : c;
                     f = win ? (uint8_t)(f | kUsed) : f;
                 };
+                // Level steps (transactions): with ties broken by the
+                // lowest slot, the single steps take the slots at the
+                // minimum level (free slots below every count, then
+                // count c at level c + 1) one by one in slot order, and
+                // each taken slot rises by its weight (at least one)
+                // above that level.  One step therefore applies the
+                // next updates to all slots at the minimum level at
+                // once, the r-th slot in slot order taking the r-th
+                // update, read from the update list in LDS; the state is
+                // the one the single steps reach.
+                // (the group's ballot bits start at lane gsh; a bin of one
+                // bucket has lanes [0, G): no shift, and its bits stay
+                // scalar)
+                using M = typename GroupMask<G>::T;
+                const uint32_t sh = ONE ? 0u : gsh;
+                auto chain_level = [&]() {
+                    // pinned slots and padding never take an update; with
+                    // every slot of the bucket pinned all updates drop
+                    const uint32_t fixed = ((f & kPinned) ? 0xFFFFFFFFu : 0u) | notreal;
+                    if (group_bits<G>(__builtin_amdgcn_ballot_w64(fixed == 0u), sh) == 0)
+                        return;
+                    const M below = ((M)1 << j) - (M)1;
+                    for (uint32_t pos = e0; pos < e1;) {
+                        // level offer: 0 free, c + 1 used (counts stay
+                        // below 2^26), all ones if fixed
+                        const uint32_t lvl = ((f & kUsed) ? c + 1u : 0u) | fixed;
+                        const uint32_t mn = group_min<G>(lvl);
+                        const M at = group_bits<G>(__builtin_amdgcn_ballot_w64(lvl == mn), sh);
+                        const uint32_t take = min(bit_count(at), e1 - pos);
+                        const uint32_t rank = bit_count(at & below);
+                        if (lvl == mn && rank < take) {
+                            const KeyT nk = t_k[pos + rank];
+                            const uint32_t nw = t_w[pos + rank];
+                            e = mn ? c : 0u;
+                            c = mn ? c + nw : nw;
+                            k = nk;
+                            f |= kUsed;
+                        }
+                        pos += take;
+                    }
+                };
                 if constexpr (ONE) {
                     // G updates per LDS load: lane j holds update p0 + j and
                     // each update is broadcast from its lane in turn, so the
@@ -610,44 +652,6 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                             }
                         }
                     };
-                    // Level steps (transactions): with ties broken by the
-                    // lowest slot, the single steps take the slots at the
-                    // minimum level (free slots below every count, then
-                    // count c at level c + 1) one by one in slot order, and
-                    // each taken slot rises by its weight (at least one)
-                    // above that level.  One step therefore applies the
-                    // next updates to all slots at the minimum level at
-                    // once, the r-th slot in slot order taking the r-th
-                    // update, read from the update list in LDS; the state is
-                    // the one the single steps reach.
-                    using M = typename GroupMask<G>::T;
-                    auto chain_level = [&]() {
-                        // pinned slots and padding never take an update; with
-                        // every slot pinned all updates drop
-                        const uint32_t fixed = ((f & kPinned) ? 0xFFFFFFFFu : 0u) | notreal;
-                        if (__builtin_amdgcn_ballot_w64(fixed == 0u) == 0) return;
-                        const M below = ((M)1 << j) - (M)1;
-                        for (uint32_t pos = e0; pos < e1;) {
-                            // level offer: 0 free, c + 1 used (counts stay
-                            // below 2^26), all ones if fixed
-                            const uint32_t lvl = ((f & kUsed) ? c + 1u : 0u) | fixed;
-                            const uint32_t mn = group_min<G>(lvl);
-                            // (the group is lanes [0, G) of its wavefront:
-                            // its ballot bits need no shift)
-                            const M at = group_bits<G>(__builtin_amdgcn_ballot_w64(lvl == mn), 0);
-                            const uint32_t take = min(bit_count(at), e1 - pos);
-                            const uint32_t rank = bit_count(at & below);
-                            if (lvl == mn && rank < take) {
-                                const KeyT nk = t_k[pos + rank];
-                                const uint32_t nw = t_w[pos + rank];
-                                e = mn ? c : 0u;
-                                c = mn ? c + nw : nw;
-                                k = nk;
-                                f |= kUsed;
-                            }
-                            pos += take;
-                        }
-                    };
                     if constexpr (!OUTER) {
                         if (pack)
                             chain_level();
@@ -673,10 +677,15 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                             apply(key, w, val);
                         }
                     };
-                    if (pack)
-                        chain([&](KeyT key, uint32_t w, float) { step_packed(key, w); });
-                    else
+                    if constexpr (!OUTER) {
+                        // transactions: the hits were taken in step 2
+                        if (pack)
+                            chain_level();
+                        else
+                            chain([&](KeyT key, uint32_t w, float val) { step(key, w, val); });
+                    } else {
                         chain([&](KeyT key, uint32_t w, float val) { step(key, w, val); });
+                    }
                 }
                 if (real) {
                     s_k[sidx] = k;
