@@ -134,6 +134,21 @@ def mlp_forward(params, Z):
     return out, dict(Z=Z, a1=a1, h1=h1, a2=a2, h2=h2, W2=W2, w3=w3)
 
 
+def mlp_score_bf16(params, Z):
+    """bf16 scoring (this project's reading of a bf16 inference pass; the
+    paper has none): the weights W1, W2, w3, the inputs and both hidden
+    layers' activations are rounded to bfloat16 (nearest even); biases stay
+    as given; products and sums in fp64.  Returns out[N]."""
+    rb = lambda a: np.asarray(bf16_round(np.asarray(a, np.float32)), np.float64)
+    W1, W2, w3 = rb(params["W1"]), rb(params["W2"]), rb(params["w3"])
+    b1 = np.asarray(params["b1"], np.float64)
+    b2 = np.asarray(params["b2"], np.float64)
+    b3 = float(np.asarray(params["b3"], np.float64).reshape(-1)[0])
+    h1 = rb(np.maximum(rb(Z) @ W1.T + b1, 0.0))
+    h2 = rb(np.maximum(h1 @ W2.T + b2, 0.0))
+    return h2 @ w3 + b3
+
+
 def mlp_backward(params, Z, y):
     """Loss = mean((out - y)^2).  Returns (loss, grads dict) in fp64, by the
     chain rule written out layer by layer."""

@@ -453,34 +453,69 @@ __device__ inline float bf16_rne(float x)
     return __uint_as_float(u & 0xFFFF0000u);
 }
 
-// Scores with bf16-rounded weights and inputs, fp32 accumulation; one
-// thread per sample, weights in LDS.
+// bf16 pairs for the dot-product instruction (element 0 in the low half).
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+
+__device__ inline uint32_t bf16_pair(float lo, float hi)
+{
+    return (__float_as_uint(bf16_rne(lo)) >> 16) | (__float_as_uint(bf16_rne(hi)) & 0xFFFF0000u);
+}
+
+// a.lo * b.lo + a.hi * b.hi + c with bf16 operands, in fp32
+__device__ inline float dot2_bf16(uint32_t a, uint32_t b, float c)
+{
+    return __builtin_amdgcn_fdot2_f32_bf16(__builtin_bit_cast(bf16x2_t, a),
+                                           __builtin_bit_cast(bf16x2_t, b), c, false);
+}
+
+// bf16 inference: weights, inputs and each layer's activations rounded to
+// bf16 (nearest even), products and sums in fp32 through the bf16
+// dot-product instruction (two products per step); biases in fp32.  One
+// thread per sample, the weight pairs in LDS.
 __global__ void __launch_bounds__(256)
 k_mlp_score(const float *__restrict__ params, const float *__restrict__ Z, uint64_t N,
             float *__restrict__ out)
 {
-    __shared__ float W[(kParams + 3) & ~3];
-    for (uint32_t p = threadIdx.x; p < kParams; p += 256) W[p] = bf16_rne(params[p]);
+    constexpr int P1 = kH * kIn / 2, P2 = kH * kH / 2, P3 = kH / 2;
+    __shared__ uint32_t W1[P1], W2[P2], W3[P3];
+    __shared__ float B1[kH], B2[kH], B3;
+    for (uint32_t p = threadIdx.x; p < (uint32_t)P1; p += 256)
+        W1[p] = bf16_pair(params[oW1 + 2 * p], params[oW1 + 2 * p + 1]);
+    for (uint32_t p = threadIdx.x; p < (uint32_t)P2; p += 256)
+        W2[p] = bf16_pair(params[oW2 + 2 * p], params[oW2 + 2 * p + 1]);
+    for (uint32_t p = threadIdx.x; p < (uint32_t)P3; p += 256)
+        W3[p] = bf16_pair(params[oW3 + 2 * p], params[oW3 + 2 * p + 1]);
+    for (uint32_t p = threadIdx.x; p < (uint32_t)kH; p += 256) {
+        B1[p] = params[oB1 + p];
+        B2[p] = params[oB2 + p];
+    }
+    if (threadIdx.x == 0) B3 = params[oB3];
     __syncthreads();
     for (uint64_t s = (uint64_t)blockIdx.x * 256 + threadIdx.x; s < N;
          s += (uint64_t)gridDim.x * 256) {
-        float z[kIn];
+        uint32_t z[kIn / 2];
 #pragma unroll
-        for (int k = 0; k < kIn; ++k) z[k] = bf16_rne(Z[s * kIn + k]);
-        float h1[kH];
+        for (int k = 0; k < kIn / 2; ++k) z[k] = bf16_pair(Z[s * kIn + 2 * k], Z[s * kIn + 2 * k + 1]);
+        uint32_t h1[kH / 2];
 #pragma unroll
-        for (int i = 0; i < kH; ++i) {
-            float a = W[oB1 + i];
+        for (int i = 0; i < kH; i += 2) {
+            float a0 = B1[i], a1 = B1[i + 1];
 #pragma unroll
-            for (int k = 0; k < kIn; ++k) a = fmaf(W[oW1 + i * kIn + k], z[k], a);
-            h1[i] = fmaxf(a, 0.0f);
+            for (int k = 0; k < kIn / 2; ++k) {
+                a0 = dot2_bf16(W1[i * (kIn / 2) + k], z[k], a0);
+                a1 = dot2_bf16(W1[(i + 1) * (kIn / 2) + k], z[k], a1);
+            }
+            h1[i / 2] = bf16_pair(fmaxf(a0, 0.0f), fmaxf(a1, 0.0f));
         }
-        float o = W[oB3];
-        for (int i = 0; i < kH; ++i) {
-            float a = W[oB2 + i];
+        float o = B3;
+        for (int i = 0; i < kH; i += 2) {
+            float a0 = B2[i], a1 = B2[i + 1];
 #pragma unroll
-            for (int k = 0; k < kH; ++k) a = fmaf(W[oW2 + i * kH + k], h1[k], a);
-            o = fmaf(W[oW3 + i], fmaxf(a, 0.0f), o);
+            for (int k = 0; k < kH / 2; ++k) {
+                a0 = dot2_bf16(W2[i * (kH / 2) + k], h1[k], a0);
+                a1 = dot2_bf16(W2[(i + 1) * (kH / 2) + k], h1[k], a1);
+            }
+            o = dot2_bf16(W3[i / 2], bf16_pair(fmaxf(a0, 0.0f), fmaxf(a1, 0.0f)), o);
         }
         out[s] = o;
     }

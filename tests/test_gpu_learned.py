@@ -267,11 +267,18 @@ def test_mlp_score_bf16(crop, ctx, torch, N):
         out = torch.empty(N, dtype=torch.float32, device="cuda")
         crop.crop_mlp_score(ctx, mlp, torch.from_numpy(Z).cuda(), out)
         got = out.cpu().numpy().astype(np.float64)
-        wb = {k: L.bf16_round(w[k]) for k in KEYS}
-        want_bf, _ = L.mlp_forward(wb, L.bf16_round(Z))
-        np.testing.assert_allclose(got, want_bf, rtol=0, atol=1e-4 * (np.abs(want_bf).max() + 1))
-        # bf16 rounding (relative 2^-9 per weight and input) costs about a
-        # per mille of the score's scale against the fp32 network
+        want_bf = L.mlp_score_bf16(w, Z)
+        # the GPU sums in fp32, the oracle in fp64: an activation that lies
+        # at a bfloat16 rounding boundary can round the other way (about one
+        # in 2^16), moving its sample's score by one bfloat16 step of that
+        # activation's contribution; every other sample agrees to fp32 sums
+        err = np.abs(got - want_bf)
+        scale = np.abs(want_bf).max() + 1
+        assert np.quantile(err, 0.99) <= 1e-4 * scale, err.max()
+        assert err.max() <= 1e-2 * scale, err.max()
+        # bf16 rounding (relative 2^-9 per weight, input and activation)
+        # costs about a per mille of the score's scale against the fp32
+        # network
         want_32, _ = L.mlp_forward({k: w[k] for k in KEYS}, Z)
         rms = lambda a: float(np.sqrt(np.mean(np.square(a))))
         assert rms(got - want_32) <= 1e-2 * (rms(want_32) + 1e-3), rms(got - want_32)

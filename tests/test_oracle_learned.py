@@ -107,6 +107,46 @@ def test_bf16_round_matches_torch():
     assert np.array_equal(learned.bf16_round(a), ref)
 
 
+def test_bf16_score_matches_torch_bf16_layers():
+    """bf16 scoring against torch's own bfloat16 Linear layers (fp32
+    accumulation, every layer's output rounded to bfloat16): with biases
+    that bfloat16 represents, the two readings coincide up to the rare
+    activation that rounds the other way from an fp32 sum."""
+    rng = np.random.default_rng(5)
+    p = {k: v.astype(np.float32) for k, v in datagen.mlp_init_weights(8).items()}
+    for k in ("b1", "b2", "b3"):
+        p[k] = learned.bf16_round(rng.normal(0, 0.3, p[k].shape).astype(np.float32))
+    Z = rng.normal(0, 2, (2000, 32)).astype(np.float32)
+    got = learned.mlp_score_bf16(p, Z)
+    bf = torch.bfloat16
+    z = torch.tensor(Z).to(bf)
+    h1 = torch.relu(torch.nn.functional.linear(z, torch.tensor(p["W1"]).to(bf), torch.tensor(p["b1"]).to(bf)))
+    h2 = torch.relu(torch.nn.functional.linear(h1, torch.tensor(p["W2"]).to(bf), torch.tensor(p["b2"]).to(bf)))
+    w3 = torch.tensor(learned.bf16_round(p["w3"])).to(torch.float64)
+    want = (h2.to(torch.float64) @ w3 + float(p["b3"][0])).numpy()
+    err = np.abs(got - want)
+    scale = np.abs(want).max() + 1
+    assert np.quantile(err, 0.99) <= 1e-6 * scale
+    assert err.max() <= 1e-2 * scale
+
+
+def test_bf16_score_equals_fp64_network_without_rounding():
+    """Weights, inputs and every activation exactly representable in
+    bfloat16 (small dyadic values, one hidden unit path): no rounding
+    happens and the bf16 score is the fp64 network's."""
+    p = {"W1": np.zeros((64, 32), np.float32), "b1": np.zeros(64, np.float32),
+         "W2": np.zeros((64, 64), np.float32), "b2": np.zeros(64, np.float32),
+         "w3": np.zeros(64, np.float32), "b3": np.array([0.25], np.float32)}
+    p["W1"][0, :4] = [0.5, -0.25, 1.0, 0.125]
+    p["W2"][3, 0] = 2.0
+    p["w3"][3] = -0.75
+    Z = np.array([[1.0, 2.0, 0.5, 4.0] + [0.0] * 28, [-1.0, 0.0, 0.0, 0.0] + [0.0] * 28],
+                 np.float32)
+    want, _ = learned.mlp_forward(p, Z)
+    assert np.array_equal(learned.mlp_score_bf16(p, Z), want)
+    assert want[0] == 0.25 + (-0.75) * 2.0 * 1.0  # relu(0.5 - 0.5 + 0.5 + 0.5) = 1.0
+
+
 def test_item_stats_match_dense_forms():
     st = datagen.tiny_transactions(11, T=80, n=30, cap=20, mean_len=7.0)
     Tp = learned.prefix_len(st.T)
