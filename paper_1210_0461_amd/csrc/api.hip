@@ -359,8 +359,12 @@ static crop_status plan_regions(crop_ctx *ctx, bool *ok)
     st = plan_sb_rows(ctx, S, I, R, &fits);
     if (st != CROP_OK || !fits) return st;
     SbPlan &sp = ctx->sb;
-    sp.hdr_stride = (pl.NB + 1 + 63) & ~63u;
-    sp.hdrT_stride = (sp.n_sub + 63) & ~63u;
+    sp.segs.assign(1, SbSeg{});
+    SbSeg &sg = sp.segs[0];
+    sg.bm = bin_map(pl);
+    sg.NB = pl.NB;
+    sg.n_sub = sp.n_sub;
+    layout_sb_segments(sp);
     pl.regions = true;
     pl.n_chunks = 0;
     pl.R = 0;
@@ -454,18 +458,60 @@ crop_status ensure_route_buffers(crop_ctx *ctx, size_t key_bytes, bool sums)
     return CROP_OK;
 }
 
+// Strides, tiles and offsets of the segments of a region plan (their NB,
+// bin0, sub0, n_sub, bm and key0 set): header rows of NB + 1 starts rounded
+// to 64, transposed rows of n_sub rounded to 64, 64 x 64 header tiles, the
+// segments' blocks one after another; NBmax for the route's LDS image.
+void layout_sb_segments(SbPlan &sp)
+{
+    sp.NBmax = 0;
+    sp.n_tiles = 0;
+    sp.hdr_words = sp.hdrT_words = sp.tsum_words = 0;
+    for (SbSeg &g : sp.segs) {
+        g.hs = (g.NB + 1 + 63) & ~63u;
+        g.hts = (g.n_sub + 63) & ~63u;
+        g.btiles = (g.NB + 1 + 63) / 64;
+        g.tile0 = sp.n_tiles;
+        g.hdr0 = sp.hdr_words;
+        g.hdrT0 = sp.hdrT_words;
+        g.tsum0 = sp.tsum_words;
+        const uint32_t sub_tiles = (g.n_sub + 63) / 64;
+        sp.n_tiles += g.btiles * sub_tiles;
+        sp.hdr_words += (uint64_t)g.n_sub * g.hs;
+        sp.hdrT_words += (uint64_t)(g.NB + 1) * g.hts;
+        sp.tsum_words += (uint64_t)sub_tiles * (g.NB + 1);
+        sp.NBmax = std::max(sp.NBmax, g.NB);
+    }
+}
+
 // Region route: the routed array (the padded regions of every sub-batch;
-// terms an owned share drops leave gaps), the sub-batches' bin-start rows
-// and their transpose.
+// terms an owned share drops leave gaps), the sub-batches' bin-start rows,
+// their transpose and tile sums, and the segments on the device (copied
+// when they changed).
 crop_status ensure_region_buffers(crop_ctx *ctx)
 {
     const SbPlan &sp = ctx->sb;
     const size_t kb = ctx->in.wide_keys ? 8 : 4;
     // the padded regions, and one more 16-byte group past the last
     CK(ctx->routed.ensure((sp.term.empty() ? 0 : (size_t)sp.term.back()) * kb + 64));
-    CK(ctx->sb_hdr.ensure((size_t)sp.n_sub * sp.hdr_stride * 2));
-    CK(ctx->sb_hdrT.ensure(((size_t)ctx->plan.NB + 1) * sp.hdrT_stride * 2));
-    CK(ctx->sb_tsum.ensure((((size_t)sp.n_sub + 63) / 64) * ((size_t)ctx->plan.NB + 1) * 4));
+    CK(ctx->sb_hdr.ensure(sp.hdr_words * 2));
+    CK(ctx->sb_hdrT.ensure(sp.hdrT_words * 2));
+    CK(ctx->sb_tsum.ensure(sp.tsum_words * 4));
+    const size_t seg_bytes = sp.segs.size() * sizeof(SbSeg);
+    std::vector<SbSeg> &up = ctx->sb_seg_host;
+    auto same = [](const SbSeg &x, const SbSeg &y) {
+        return x.bm.M == y.bm.M && x.bm.u0 == y.bm.u0 && x.bm.nu == y.bm.nu && x.bm.g == y.bm.g &&
+               x.NB == y.NB && x.bin0 == y.bin0 && x.sub0 == y.sub0 && x.n_sub == y.n_sub &&
+               x.hs == y.hs && x.hts == y.hts && x.tile0 == y.tile0 && x.btiles == y.btiles &&
+               x.key0 == y.key0 && x.hdr0 == y.hdr0 && x.hdrT0 == y.hdrT0 && x.tsum0 == y.tsum0;
+    };
+    bool changed = up.size() != sp.segs.size() || !ctx->sb_seg.p;
+    for (size_t i = 0; !changed && i < up.size(); ++i) changed = !same(up[i], sp.segs[i]);
+    if (changed) {
+        CK(ctx->sb_seg.ensure(std::max<size_t>(seg_bytes, 1)));
+        if (seg_bytes) CK(hipMemcpy(ctx->sb_seg.p, sp.segs.data(), seg_bytes, hipMemcpyHostToDevice));
+        up = sp.segs;
+    }
     return CROP_OK;
 }
 
@@ -716,7 +762,8 @@ void crop_destroy(crop_ctx *ctx)
                       &ctx->vals, &ctx->out_cnt, &ctx->spill, &ctx->counter, &ctx->ss_state,
                       &ctx->topk_buf, &ctx->scratch, &ctx->learn_ws, &ctx->seed_sel,
                       &ctx->part_stats, &ctx->routed, &ctx->sb_row, &ctx->sb_term,
-                      &ctx->sb_hdr, &ctx->sb_hdrT, &ctx->sb_tsum, &ctx->in.d_op_chunks,
+                      &ctx->sb_hdr, &ctx->sb_hdrT, &ctx->sb_tsum, &ctx->sb_seg,
+                      &ctx->sb_subseg, &ctx->sb_binseg, &ctx->in.d_op_chunks,
                       &bt.d_crow, &bt.d_cstream, &bt.d_streams, &bt.d_bin_stream, &bt.tot,
                       &bt.tiles, &ctx->cs_buf, &ctx->amp_buf})
         b->release();

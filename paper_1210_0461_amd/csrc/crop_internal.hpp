@@ -77,12 +77,30 @@ struct RoutePlan {
 // the routed array starts at term[s] (the term prefix with every region
 // rounded up to four keys; term[n_sub] = the routed array's keys).
 // Computed once per loaded stream and set of caps.
+// One segment of the region route: a stream with its own kept bins and
+// sub-batches (an exact run is one segment, a batched run one per stream).
+// Its header rows (one per sub-batch, hs >= NB + 1 bin starts), their
+// transpose (one row per bin start, hts >= n_sub) and its header tile sums
+// (one row of NB + 1 per 64 sub-batches) sit at their offsets in the run's
+// arrays; its bins' results start after key0 kept keys.
+struct SbSeg {
+    BinMap bm;                     // hash -> kept bin of the segment
+    uint32_t NB, bin0;             // kept bins, first bin in the run's numbering
+    uint32_t sub0, n_sub;          // its sub-batches
+    uint32_t hs, hts;              // header and transposed row strides (u16)
+    uint32_t tile0, btiles;        // first header tile (64 x 64), bin tiles per tile row
+    uint32_t key0;                 // kept keys of the segments before
+    uint64_t hdr0, hdrT0, tsum0;   // offsets of its header, transpose (u16), tile sums (u32)
+};
+
 struct SbPlan {
     bool valid = false;
     uint32_t n_sub = 0, max_terms = 0, max_items = 0, max_rows = 0;
-    uint32_t hdr_stride = 0;   // u16 per bin-start row of a sub-batch (>= NB + 1)
-    uint32_t hdrT_stride = 0;  // u16 per transposed row of a bin (>= n_sub)
     std::vector<uint32_t> row, term;
+    // segments of the last planned run, and the sizes of its header arrays
+    std::vector<SbSeg> segs;
+    uint32_t NBmax = 0, n_tiles = 0;
+    uint64_t hdr_words = 0, hdrT_words = 0, tsum_words = 0;
 };
 
 struct Input {
@@ -222,6 +240,9 @@ struct crop_ctx {
     crop::DevBuf part_stats;   // grouped bins: entries and terms of each partition
     crop::SbPlan sb;           // region route: sub-batch plan of the loaded stream
     crop::DevBuf routed, sb_row, sb_term, sb_hdr, sb_hdrT, sb_tsum;
+    crop::DevBuf sb_seg;       // the segments on the device (sb.segs)
+    crop::DevBuf sb_subseg, sb_binseg;  // segment of each sub-batch / bin (several segments)
+    std::vector<crop::SbSeg> sb_seg_host;  // ... as last uploaded
     crop::BatchState batch;    // batched streams
     crop::DevBuf cs_buf;       // Count-Sketch counters [t][P * B]
     crop::CsParams cs{};       // ... of the last Count-Sketch run
@@ -267,6 +288,7 @@ hipError_t launch_hash_pairs(const uint32_t *qx, const uint32_t *qy, uint64_t n,
 size_t sb_route_smem_bytes(uint32_t NB, uint32_t max_rows, uint32_t max_items,
                            uint32_t max_terms, uint32_t key_bytes);
 uint32_t sb_threads();
+void layout_sb_segments(SbPlan &sp);
 hipError_t launch_sb_route(const crop_ctx *c, hipStream_t s);
 hipError_t launch_sb_headers(const crop_ctx *c, hipStream_t s);
 

@@ -614,7 +614,8 @@ k_aggregate_flat(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ ke
 // bin_off[b], the spill segment there) is the same.
 template <int BS, int LOG2S, int U>
 __global__ void __launch_bounds__(BS)
-k_aggregate_regions(const uint16_t *__restrict__ hdrT, uint32_t hdrT_stride, uint32_t n_sub,
+k_aggregate_regions(const uint16_t *__restrict__ hdrT, const SbSeg *__restrict__ segs,
+                    const uint32_t *__restrict__ bin_seg,
                     const uint32_t *__restrict__ sb_base, const uint32_t *__restrict__ routed,
                     const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ keys,
                     uint32_t *__restrict__ w_out, uint32_t *__restrict__ bin_size,
@@ -669,10 +670,14 @@ k_aggregate_regions(const uint16_t *__restrict__ hdrT, uint32_t hdrT_stride, uin
             s_nout = 0;
             s_nspill = 0;
         }
-        // this wavefront's sub-batches, and the header words of the next 64
+        // the bin's segment (its sub-batches and transposed header rows),
+        // this wavefront's share of the sub-batches, and the header words of
+        // the next 64
+        const SbSeg &sg = segs[bin_seg ? bin_seg[b] : 0u];
+        const uint32_t n_sub = sg.n_sub, sub0 = sg.sub0;
         uint32_t g = (uint32_t)(((uint64_t)n_sub * wave) / NW);
         const uint32_t g_end = (uint32_t)(((uint64_t)n_sub * (wave + 1)) / NW);
-        const uint16_t *h0 = hdrT + (size_t)b * hdrT_stride, *h1 = h0 + hdrT_stride;
+        const uint16_t *h0 = hdrT + sg.hdrT0 + (size_t)(b - sg.bin0) * sg.hts, *h1 = h0 + sg.hts;
         uint32_t na = 0, ne = 0, nbase = 0;
         auto load_rows = [&]() {
             const uint32_t sb = g + lane;
@@ -680,7 +685,7 @@ k_aggregate_regions(const uint16_t *__restrict__ hdrT, uint32_t hdrT_stride, uin
             if (sb < g_end) {
                 na = h0[sb];
                 ne = h1[sb];
-                nbase = sb_base[sb];
+                nbase = sb_base[sub0 + sb];
             }
         };
         load_rows();
@@ -800,7 +805,8 @@ hipError_t launch_aggregate_regions(const crop_ctx *c, hipStream_t s)
     if (pl.NB == 0) return hipSuccess;
     if (c->in.wide_keys) return hipErrorInvalidValue;  // 64-bit keys stay on the chunk route
     hipLaunchKernelGGL((k_aggregate_regions<1024, 14, kFlatU>), dim3(persistent_grid(pl.NB)),
-                       dim3(1024), 0, s, c->sb_hdrT.as<uint16_t>(), sp.hdrT_stride, sp.n_sub,
+                       dim3(1024), 0, s, c->sb_hdrT.as<uint16_t>(), c->sb_seg.as<SbSeg>(),
+                       sp.segs.size() > 1 ? c->sb_binseg.as<uint32_t>() : nullptr,
                        c->sb_term.as<uint32_t>(), c->routed.as<uint32_t>(),
                        c->bin_off.as<uint32_t>(), c->keys.as<uint32_t>(),
                        c->out_cnt.as<uint32_t>(), c->bin_size.as<uint32_t>(),

@@ -41,8 +41,8 @@ constexpr int kSbBS = 1024;  // threads of a route workgroup
 template <int BS, int Q, class KeyT, bool DROP>
 __global__ void __launch_bounds__(BS)
 k_sb_route(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items, HashParams hp,
-           BinMap bm, uint32_t NB, SbLayout lay, const uint32_t *__restrict__ sb_row,
-           const uint32_t *__restrict__ sb_base, uint32_t hdr_stride,
+           const SbSeg *__restrict__ segs, const uint32_t *__restrict__ sub_seg, SbLayout lay,
+           const uint32_t *__restrict__ sb_row, const uint32_t *__restrict__ sb_base,
            KeyT *__restrict__ routed, uint16_t *__restrict__ hdr)
 {
     constexpr uint32_t KPQ = 16 / sizeof(KeyT);  // keys per 16-byte store
@@ -55,6 +55,11 @@ k_sb_route(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
     KeyT *sorted = reinterpret_cast<KeyT *>(smem + lay.keys);
 
     const uint32_t s = blockIdx.x;
+    // the sub-batch's segment: its bins, and where its header row goes
+    const SbSeg &sg = segs[sub_seg ? sub_seg[s] : 0u];
+    const BinMap bm = sg.bm;
+    const uint32_t NB = sg.NB;
+    uint16_t *hrow = hdr + sg.hdr0 + (size_t)(s - sg.sub0) * sg.hs;
     const uint32_t r0 = sb_row[s], R = sb_row[s + 1] - r0;
     const uint32_t t0 = sb_base[s];
     const uint32_t p0 = off[r0];
@@ -174,59 +179,86 @@ k_sb_route(const uint32_t *__restrict__ off, const uint32_t *__restrict__ items,
         const uint32_t i = threadIdx.x + j * BS;
         if (i < nq) dst[i] = v[j];
     }
-    uint16_t *hrow = hdr + (size_t)s * hdr_stride;
     for (uint32_t b = threadIdx.x; b <= NB; b += BS) hrow[b] = (uint16_t)hist[b];
 }
 
-// Tiles of 64 sub-batches x 64 bin starts: hdrT[b][s] = hdr[s][b] for
-// b <= NB, and tsum[t][b] = tile t's sum of hdr[s][b] (k_sb_tile_scan adds
-// them up).
+// The segment of header tile (or bin) `t`: the last segment whose first
+// tile (bin) is at most t.  field: tile0 or bin0.
+template <class F>
+__device__ inline uint32_t seg_of(const SbSeg *segs, uint32_t n_seg, uint32_t t, F first)
+{
+    uint32_t lo = 0, hi = n_seg;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (first(segs[mid]) <= t) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Tiles of 64 sub-batches x 64 bin starts of one segment (block b: tile
+// b - tile0 of its segment, bin tiles first): hdrT[p][s] = hdr[s][p] for
+// p <= NB, and tsum[t][p] = tile row t's sum of hdr[s][p] (k_sb_tile_scan
+// adds them up).
 __global__ void __launch_bounds__(256)
-k_sb_headers(const uint16_t *__restrict__ hdr, uint32_t hdr_stride, uint32_t n_sub, uint32_t NB,
-             uint16_t *__restrict__ hdrT, uint32_t hdrT_stride, uint32_t *__restrict__ tsum)
+k_sb_headers(const uint16_t *__restrict__ hdr, const SbSeg *__restrict__ segs, uint32_t n_seg,
+             uint16_t *__restrict__ hdrT, uint32_t *__restrict__ tsum)
 {
     __shared__ uint16_t tile[64][66];
     __shared__ uint32_t part[4][64];
-    const uint32_t b0 = blockIdx.x * 64, s0 = blockIdx.y * 64;
+    const SbSeg sg = segs[seg_of(segs, n_seg, blockIdx.x, [](const SbSeg &x) { return x.tile0; })];
+    const uint32_t local = blockIdx.x - sg.tile0;
+    const uint32_t NB = sg.NB, n_sub = sg.n_sub;
+    const uint32_t b0 = (local % sg.btiles) * 64, st = local / sg.btiles, s0 = st * 64;
+    const uint16_t *h = hdr + sg.hdr0;
+    uint16_t *hT = hdrT + sg.hdrT0;
     const uint32_t c = threadIdx.x & 63, q = threadIdx.x >> 6;
     uint32_t sum = 0;
     for (uint32_t r = q; r < 64; r += 4) {
         const uint32_t s = s0 + r, b = b0 + c;
         uint16_t v = 0;
-        if (s < n_sub && b <= NB) v = hdr[(size_t)s * hdr_stride + b];
+        if (s < n_sub && b <= NB) v = h[(size_t)s * sg.hs + b];
         tile[r][c] = v;
         sum += v;
     }
     part[q][c] = sum;
     __syncthreads();
     if (q == 0 && b0 + c <= NB)
-        tsum[(size_t)blockIdx.y * (NB + 1) + b0 + c] =
+        tsum[sg.tsum0 + (size_t)st * (NB + 1) + b0 + c] =
             part[0][c] + part[1][c] + part[2][c] + part[3][c];
     for (uint32_t k = q; k < 64; k += 4) {
         const uint32_t b = b0 + k, s = s0 + c;
-        if (b <= NB && s < n_sub) hdrT[(size_t)b * hdrT_stride + s] = tile[c][k];
+        if (b <= NB && s < n_sub) hT[(size_t)b * sg.hts + s] = tile[c][k];
     }
 }
 
-// Per bin start b <= NB: bin_off[b] <- the sum over the header tiles.  The
-// sum of the starts of bin b over every sub-batch is the number of kept keys
-// in bins below b, i.e. bin b's offset in a bin-contiguous layout.
+// bin_off[b] for b <= NBtot: its segment's kept keys before it (key0) plus
+// the sum of its bin starts over the segment's header tiles; the sum of the
+// starts of bin p over every sub-batch is the number of the segment's keys
+// in bins below p.  bin_off[NBtot] is the last segment's end (its start
+// column NB).
 __global__ void __launch_bounds__(256)
-k_sb_tile_scan(const uint32_t *__restrict__ tsum, uint32_t n_tiles, uint32_t NB,
-               uint32_t *__restrict__ bin_off)
+k_sb_tile_scan(const uint32_t *__restrict__ tsum, const SbSeg *__restrict__ segs, uint32_t n_seg,
+               uint32_t NBtot, uint32_t *__restrict__ bin_off)
 {
     const uint32_t b = blockIdx.x * 256 + threadIdx.x;
-    if (b > NB) return;
+    if (b > NBtot) return;
+    const uint32_t g = b < NBtot ? seg_of(segs, n_seg, b, [](const SbSeg &x) { return x.bin0; })
+                                 : n_seg - 1;
+    const SbSeg sg = segs[g];
+    const uint32_t p = b < NBtot ? b - sg.bin0 : sg.NB;
+    const uint32_t n_tiles = (sg.n_sub + 63) / 64;
+    const uint32_t *ts = tsum + sg.tsum0 + p;
     uint32_t run = 0;
     for (uint32_t t0 = 0; t0 < n_tiles; t0 += 8) {  // eight loads in flight
         uint32_t v[8];
 #pragma unroll
         for (uint32_t k = 0; k < 8; ++k)
-            v[k] = t0 + k < n_tiles ? tsum[(size_t)(t0 + k) * (NB + 1) + b] : 0u;
+            v[k] = t0 + k < n_tiles ? ts[(size_t)(t0 + k) * (sg.NB + 1)] : 0u;
 #pragma unroll
         for (uint32_t k = 0; k < 8; ++k) run += v[k];
     }
-    bin_off[b] = run;
+    bin_off[b] = sg.key0 + run;
 }
 
 }  // namespace
@@ -245,19 +277,21 @@ hipError_t launch_sb_route(const crop_ctx *c, hipStream_t s)
     const RoutePlan &pl = c->plan;
     const SbPlan &sp = c->sb;
     const uint32_t kb = c->in.wide_keys ? 8 : 4;
-    const SbLayout lay = sb_layout(pl.NB, sp.max_rows, sp.max_items, sp.max_terms, kb);
+    const SbLayout lay = sb_layout(sp.NBmax, sp.max_rows, sp.max_items, sp.max_terms, kb);
     const size_t sm = 4 * (size_t)lay.end;
-    if (!sb_layout_ok(pl.NB, sp.max_rows, sp.max_items, sp.max_terms, kb, sm))
+    if (!sb_layout_ok(sp.NBmax, sp.max_rows, sp.max_items, sp.max_terms, kb, sm))
         return hipErrorInvalidConfiguration;
     const uint32_t Q = sp.max_terms / kSbBS;
     if (Q * kSbBS != sp.max_terms) return hipErrorInvalidConfiguration;
     const uint32_t *row = c->sb_row.as<uint32_t>(), *term = c->sb_term.as<uint32_t>();
+    const SbSeg *segs = c->sb_seg.as<SbSeg>();
+    const uint32_t *sub_seg = sp.segs.size() > 1 ? c->sb_subseg.as<uint32_t>() : nullptr;
     uint16_t *hdr = c->sb_hdr.as<uint16_t>();
-    const bool drop = pl.nu < pl.M;  // an owned share
+    const bool drop = pl.nu < pl.M;  // an owned share (one segment)
 #define SB_LAUNCH(QQ, KT, DR)                                                                \
     hipLaunchKernelGGL((k_sb_route<kSbBS, QQ, KT, DR>), dim3(sp.n_sub), dim3(kSbBS), sm, s,   \
-                       c->in.off, c->in.items, c->hp, bin_map(pl), pl.NB, lay, row, term,     \
-                       sp.hdr_stride, c->routed.as<KT>(), hdr)
+                       c->in.off, c->in.items, c->hp, segs, sub_seg, lay, row, term,          \
+                       c->routed.as<KT>(), hdr)
     if (c->in.wide_keys) return hipErrorInvalidConfiguration;  // packed keys only
     if (Q == 16 && drop)
         SB_LAUNCH(16, uint32_t, true);
@@ -273,19 +307,21 @@ hipError_t launch_sb_route(const crop_ctx *c, hipStream_t s)
     return hipGetLastError();
 }
 
+// bin_off of every bin of the run (pl.NB of them) and its end.
 hipError_t launch_sb_headers(const crop_ctx *c, hipStream_t s)
 {
     const RoutePlan &pl = c->plan;
     const SbPlan &sp = c->sb;
     uint32_t *bin_off = c->bin_off.as<uint32_t>();
-    if (sp.n_sub == 0) return launch_zero32(bin_off, pl.NB + 1, s);  // every bin empty
-    const uint32_t n_tiles = (sp.n_sub + 63) / 64;
-    dim3 grid((pl.NB + 1 + 63) / 64, n_tiles);
-    hipLaunchKernelGGL(k_sb_headers, grid, dim3(256), 0, s, c->sb_hdr.as<uint16_t>(),
-                       sp.hdr_stride, sp.n_sub, pl.NB, c->sb_hdrT.as<uint16_t>(), sp.hdrT_stride,
-                       c->sb_tsum.as<uint32_t>());
+    if (sp.n_sub == 0 || sp.segs.empty()) return launch_zero32(bin_off, pl.NB + 1, s);
+    const uint32_t n_seg = (uint32_t)sp.segs.size();
+    const SbSeg *segs = c->sb_seg.as<SbSeg>();
+    if (sp.n_tiles)
+        hipLaunchKernelGGL(k_sb_headers, dim3(sp.n_tiles), dim3(256), 0, s,
+                           c->sb_hdr.as<uint16_t>(), segs, n_seg, c->sb_hdrT.as<uint16_t>(),
+                           c->sb_tsum.as<uint32_t>());
     hipLaunchKernelGGL(k_sb_tile_scan, dim3((pl.NB + 1 + 255) / 256), dim3(256), 0, s,
-                       c->sb_tsum.as<uint32_t>(), n_tiles, pl.NB, bin_off);
+                       c->sb_tsum.as<uint32_t>(), segs, n_seg, pl.NB, bin_off);
     return hipGetLastError();
 }
 
