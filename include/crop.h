@@ -328,12 +328,16 @@ crop_status crop_load_batch(crop_ctx *ctx, uint32_t n_streams, const uint64_t *t
                             crop_mem where, crop_own own);
 /* Plan knobs: routed terms aimed at per bin (each stream gets
  * ceil(terms / terms_per_bin) partitions, at most 8192) and transactions per
- * chunk (rows_per_chunk; halved while a chunk does not fit in LDS). */
+ * chunk (rows_per_chunk; halved while a chunk does not fit in LDS).  A batch
+ * whose item ids all pack into 32-bit keys takes the region route (one
+ * segment per stream: its sub-batches sorted by bin in LDS and read in place
+ * by the aggregation), where rows_per_chunk does not apply. */
 crop_status crop_batch_set_plan(crop_ctx *ctx, uint32_t terms_per_bin, uint32_t rows_per_chunk);
 /* Time every candidate plan (terms_per_bin in {15000, 30000, 60000} x
- * rows_per_chunk in {64, 128, 256}) reps times on the loaded batch, keep the
- * fastest, and remember it for later batches of the same shape in this
- * process.  Outputs (NULL allowed): the chosen knobs and its time. */
+ * rows_per_chunk in {64, 128, 256}; on the region route terms_per_bin only)
+ * reps times on the loaded batch, keep the fastest, and remember it for
+ * later batches of the same shape in this process.  Outputs (NULL allowed):
+ * the chosen knobs (rows_per_chunk 0 on the region route) and its time. */
 crop_status crop_batch_autotune(crop_ctx *ctx, uint32_t reps, uint32_t *terms_per_bin,
                                 uint32_t *rows_per_chunk, float *best_ms);
 /* Replay the run as a captured HIP graph (default 1) or launch eagerly (0;

@@ -259,8 +259,8 @@ crop_status plan_tx(crop_ctx *ctx, uint32_t S_force = 0, int g_req = -1)
 // Q, Q in {24, 16}), items and rows in proportion (about ten items and 45
 // terms per transaction of the 1M-transaction stream: a sub-batch is cut by
 // its terms, rarely by the others); the largest that fits the LDS budget.
-static bool sb_caps(uint32_t NB, uint32_t key_bytes, uint32_t want, uint32_t *S, uint32_t *I,
-                    uint32_t *R)
+bool sb_caps(uint32_t NB, uint32_t key_bytes, uint32_t want, uint32_t *S, uint32_t *I,
+             uint32_t *R)
 {
     static const uint32_t qs[] = {24, 16};
     for (int k = 0; k < 2; ++k) {
@@ -280,12 +280,16 @@ static bool sb_caps(uint32_t NB, uint32_t key_bytes, uint32_t want, uint32_t *S,
 
 // Sub-batches of the loaded stream for these caps (greedy over the rows,
 // kept until the next load); false when one transaction alone exceeds them.
-// The row and term boundaries go to the device once per plan.
-static crop_status plan_sb_rows(crop_ctx *ctx, uint32_t S, uint32_t I, uint32_t R, bool *ok)
+// cuts (a batch's stream boundaries, ascending) start a new sub-batch, so
+// that none crosses a stream; such a plan is made afresh each time.  The
+// row and term boundaries go to the device once per plan.
+crop_status plan_sb_rows(crop_ctx *ctx, uint32_t S, uint32_t I, uint32_t R, bool *ok,
+                         const std::vector<uint64_t> *cuts)
 {
     SbPlan &sp = ctx->sb;
     *ok = true;
-    if (sp.valid && sp.max_terms == S && sp.max_items == I && sp.max_rows == R) return CROP_OK;
+    if (!cuts && sp.valid && sp.max_terms == S && sp.max_items == I && sp.max_rows == R)
+        return CROP_OK;
     sp.valid = false;
     sp.row.assign(1, 0);
     sp.term.assign(1, 0);
@@ -295,6 +299,7 @@ static crop_status plan_sb_rows(crop_ctx *ctx, uint32_t S, uint32_t I, uint32_t 
     // keys, so that every region starts on 16 bytes
     uint64_t base = 0;
     uint32_t ct = 0, ci = 0, cr = 0;
+    size_t next_cut = 0;
     for (uint64_t t = 0; t < T; ++t) {
         const uint32_t L = off[t + 1] - off[t];
         const uint64_t n = L ? (uint64_t)L * (L - 1) / 2 : 0;
@@ -302,7 +307,12 @@ static crop_status plan_sb_rows(crop_ctx *ctx, uint32_t S, uint32_t I, uint32_t 
             *ok = false;
             return CROP_OK;
         }
-        if (cr && (ct + n > S || ci + L > I || cr + 1 > R)) {
+        bool cut = false;
+        while (cuts && next_cut < cuts->size() && (*cuts)[next_cut] <= t) {
+            cut = cut || (*cuts)[next_cut] == t;
+            ++next_cut;
+        }
+        if (cr && (cut || ct + n > S || ci + L > I || cr + 1 > R)) {
             base += (ct + 3) & ~3u;
             sp.row.push_back((uint32_t)t);
             sp.term.push_back((uint32_t)base);

@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "api_util.hpp"
+#include "crop_device.hpp"
 
 using namespace crop;
 
@@ -58,7 +59,83 @@ crop_status require_batch(crop_ctx *ctx)
     return CROP_OK;
 }
 
-// Plan the batch for (terms per bin, rows per chunk) and size the buffers.
+// The region route for the batch (packed keys, every transaction fitting a
+// sub-batch): one segment per stream, with the stream's P bins (one per
+// partition, the stream's own hash intervals) and its own sub-batches, which
+// never cross a stream.  *done false: the chunk plan is taken instead.
+crop_status plan_batch_regions(crop_ctx *ctx, uint32_t tpb, uint32_t NBmax, uint64_t NBtot,
+                               bool *done)
+{
+    BatchState &b = ctx->batch;
+    const Input &in = ctx->in;
+    *done = false;
+    if (in.wide_keys || in.total_terms >= (1ull << 32)) return CROP_OK;
+    uint32_t S, I, R;
+    if (!sb_caps(NBmax, 4, 0, &S, &I, &R)) return CROP_OK;
+    const std::vector<uint64_t> cuts(b.tx_off.begin() + 1, b.tx_off.end());
+    bool fits = false;
+    crop_status st = plan_sb_rows(ctx, S, I, R, &fits, &cuts);
+    if (st != CROP_OK || !fits) return st;
+    SbPlan &sp = ctx->sb;
+    const uint32_t n = b.n;
+    sp.segs.assign(n, SbSeg{});
+    std::vector<uint32_t> sub_seg(sp.n_sub), bin_seg(NBtot);
+    uint64_t key0 = 0;
+    uint32_t i = 0;  // sub-batches of the streams so far
+    for (uint32_t st = 0; st < n; ++st) {
+        SbSeg &g = sp.segs[st];
+        g.bm = BinMap{b.P[st], 0, b.P[st], 0};
+        g.NB = b.P[st];
+        g.bin0 = b.bin_base[st];
+        g.sub0 = i;
+        while (i < sp.n_sub && sp.row[i] < b.tx_off[st + 1]) sub_seg[i++] = st;
+        g.n_sub = i - g.sub0;
+        g.key0 = (uint32_t)key0;
+        key0 += b.terms[st];
+        for (uint32_t k = 0; k < g.NB; ++k) bin_seg[g.bin0 + k] = st;
+    }
+    layout_sb_segments(sp);
+    CK(ctx->sb_subseg.ensure(std::max<size_t>(sub_seg.size(), 1) * 4));
+    CK(ctx->sb_binseg.ensure(std::max<size_t>(bin_seg.size(), 1) * 4));
+    if (!sub_seg.empty())
+        CK(hipMemcpy(ctx->sb_subseg.p, sub_seg.data(), sub_seg.size() * 4, hipMemcpyHostToDevice));
+    if (!bin_seg.empty())
+        CK(hipMemcpy(ctx->sb_binseg.p, bin_seg.data(), bin_seg.size() * 4, hipMemcpyHostToDevice));
+    st = ensure_region_buffers(ctx);
+    if (st != CROP_OK) return st;
+
+    // the single-stream plan fields the shared launchers read
+    RoutePlan &pl = ctx->plan;
+    pl = RoutePlan{};
+    pl.S = 1;
+    pl.NB = (uint32_t)NBtot;
+    pl.M = NBtot;
+    pl.u0 = 0;
+    pl.nu = (uint32_t)NBtot;
+    pl.g = 0;
+    pl.regions = true;
+    pl.G = 1;
+    pl.log2_slots = 14;
+    pl.BS = 256;
+    const uint64_t nt = in.total_terms;
+    CK(ctx->bin_off.ensure(((size_t)NBtot + 1) * 4));
+    CK(ctx->bin_size.ensure(std::max<size_t>(NBtot, 1) * 4));
+    CK(ctx->bin_order.ensure(std::max<size_t>(NBtot, 1) * 4));
+    CK(ctx->keys.ensure(std::max<uint64_t>(nt, 1) * 4));
+    CK(ctx->out_cnt.ensure(std::max<uint64_t>(nt, 1) * 4));
+    CK(ctx->spill.ensure(std::max<uint64_t>(nt, 1) * spill_entry_bytes(false, false)));
+    CK(ctx->counter.ensure(64));
+    b.regions = true;
+    b.terms_per_bin = tpb;
+    b.rows_per_chunk = 0;
+    b.planned = true;
+    *done = true;
+    return CROP_OK;
+}
+
+// Plan the batch for (terms per bin, rows per chunk) and size the buffers:
+// the region route when it applies (rows per chunk unused), else one count
+// row per chunk of R transactions.
 crop_status plan_batch(crop_ctx *ctx, uint32_t tpb, uint32_t R)
 {
     BatchState &b = ctx->batch;
@@ -81,6 +158,10 @@ crop_status plan_batch(crop_ctx *ctx, uint32_t tpb, uint32_t R)
         NBmax = std::max(NBmax, b.P[s]);
     }
     if (NBtot >= (1ull << 31)) return fail(ctx, CROP_E_UNSUPPORTED, "too many routing bins");
+    b.regions = false;
+    bool done = false;
+    const crop_status rst = plan_batch_regions(ctx, tpb, NBmax, NBtot, &done);
+    if (rst != CROP_OK || done) return rst;
     // rows per chunk: halve until the largest chunk stages in LDS
     const size_t hist_bytes = (size_t)NBmax * 4;
     auto max_items_for = [&](uint32_t r) {
@@ -187,8 +268,20 @@ crop_status enqueue_batch(crop_ctx *ctx, hipStream_t s, bool stages)
 {
     const BatchState &b = ctx->batch;
     const Input &in = ctx->in;
-    uint32_t *cnt = ctx->cnt_mat.as<uint32_t>();
     uint32_t *bin_off = ctx->bin_off.as<uint32_t>();
+    if (b.regions) {
+        if (ctx->sb.n_sub) CK(launch_sb_route(ctx, s));
+        if (stages) STAGE("route");
+        CK(launch_sb_headers(ctx, s));
+        // one bin counter and one ordered range of bins per XCD
+        CK(launch_zero32(ctx->counter.as<uint32_t>(), kNumXcd, s));
+        CK(launch_bin_order(ctx->plan.NB, bin_off, ctx->bin_order.as<uint32_t>(), s, kNumXcd));
+        if (stages) STAGE("headers");
+        CK(launch_aggregate_regions(ctx, s));
+        if (stages) STAGE("aggregate");
+        return CROP_OK;
+    }
+    uint32_t *cnt = ctx->cnt_mat.as<uint32_t>();
     CK(launch_batch_count(in.off, in.items, ctx->hp, b.dev, cnt, bin_off, s));
     if (stages) STAGE("count");
     CK(launch_batch_scan(b.dev, cnt, b.tot.as<uint32_t>(), b.tiles.as<uint32_t>(), bin_off,
@@ -330,6 +423,8 @@ crop_status crop_batch_autotune(crop_ctx *ctx, uint32_t reps, uint32_t *terms_pe
         for (uint32_t R : kTunerRows) {
             st = plan_batch(ctx, tpb, R);
             if (st != CROP_OK) continue;  // a candidate that does not fit is skipped
+            // the region route has no rows per chunk: one candidate per tpb
+            if (ctx->batch.regions && R != kTunerRows[0]) continue;
             float ms = 0.0f;
             st = timed_eager_run(ctx, &ms);  // warm-up
             if (st != CROP_OK) return st;

@@ -191,6 +191,7 @@ struct BatchState {
     std::vector<uint64_t> terms;
     // plan
     bool planned = false;
+    bool regions = false;  // the plan takes the region route (one segment per stream)
     uint32_t terms_per_bin = 0, rows_per_chunk = 0;
     std::vector<uint32_t> P, bin_base, chunk0, n_chunks;
     std::vector<uint64_t> cnt_base;
@@ -289,6 +290,11 @@ size_t sb_route_smem_bytes(uint32_t NB, uint32_t max_rows, uint32_t max_items,
                            uint32_t max_terms, uint32_t key_bytes);
 uint32_t sb_threads();
 void layout_sb_segments(SbPlan &sp);
+bool sb_caps(uint32_t NB, uint32_t key_bytes, uint32_t want, uint32_t *S, uint32_t *I,
+             uint32_t *R);
+crop_status plan_sb_rows(crop_ctx *ctx, uint32_t S, uint32_t I, uint32_t R, bool *ok,
+                         const std::vector<uint64_t> *cuts = nullptr);
+crop_status ensure_region_buffers(crop_ctx *ctx);
 hipError_t launch_sb_route(const crop_ctx *c, hipStream_t s);
 hipError_t launch_sb_headers(const crop_ctx *c, hipStream_t s);
 

@@ -240,25 +240,22 @@ __device__ inline uint32_t table_add(KeyT *hk, uint32_t *hw, float *hv, uint32_t
 // bin's routed terms are read in micro-batches of MB:
 //   1. equal keys of the micro-batch are merged into one weighted update in
 //      an LDS hash table (a wave first merges the copies of its lead key);
-//   2. a bin of one bucket takes its hits first, in parallel: every
-//      monitored slot takes the merged weight of its key, if the
-//      micro-batch has it;
+//   2. the hits first, in parallel (bins of one bucket, and all bins of
+//      transaction counts): every monitored slot takes the merged weight of
+//      its key, if the micro-batch has it;
 //   3. the remaining updates are grouped by bucket with a counting sort; a
 //      bin of one bucket instead keeps them in the order of each key's first
 //      copy in the micro-batch, so the bucket sees its entries in stream
 //      order (routed keys keep the order of their chunks);
-//   4. a group of G lanes (G >= ell) applies one bucket's updates in order,
-//      lane j holding slot j in registers:
+//   4. a group of G lanes (G >= ell) applies one bucket's updates, lane j
+//      holding slot j in registers.  Transaction counts (all misses after
+//      step 2) take level steps: every slot at the minimum count takes one
+//      update at once, which reaches the state of single steps in order.
+//      Otherwise single steps:
 //        hit    one ballot finds the monitored slot (not needed after 2);
 //        free   the lowest free slot (ballot, first set bit);
 //        evict  minimum count over the unpinned slots by a G-lane butterfly,
-//               the lowest slot among equal minima by a ballot;
-//      with transaction counts small enough, one G-lane minimum over packed
-//      (kind, count, slot) offers takes all three decisions without a ballot
-//      (the ballots' round trips through scalar registers set the pace of
-//      the serial chain); a bin of one bucket with transaction counts
-//      instead takes level steps: every slot at the minimum count takes
-//      one update at once, which reaches the same state.
+//               the lowest slot among equal minima by a ballot.
 // Merging and reordering a bucket's updates keeps Space-Saving's bounds
 // (Section 4), which hold for any order of weighted updates.  Counts and
 // overestimations are 32-bit words: uint32 for transactions, fp32 bits for
@@ -536,44 +533,16 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                         }
                     }
                 };
-                // Transaction counts: while every count of the bin stays
-                // below 2^(30 - log2 G) - 1 (a count is at most the bin's
-                // largest initial count plus its k1 - k0 terms of unit
-                // weight), one minimum over packed words decides an update
-                // without ballots.  Lane j offers
-                //   j                               if its slot holds the key,
-                //   2^30 | j                        if its slot is free,
-                //   2^31 | count << log2 G | j      if it may be evicted,
-                //   all ones                        otherwise (pinned, padding);
-                // the smallest offer is the hit, else the lowest free slot,
-                // else the lowest slot of minimum count, as in step.
+                // Transaction counts take level steps (below) while every
+                // count of the bin stays below 2^(30 - log2 G) - 1 (a count
+                // is at most the bin's largest initial count plus its
+                // k1 - k0 terms of unit weight); otherwise, and for outer
+                // products, single steps.
                 constexpr uint32_t LOGG = G == 16 ? 4u : G == 32 ? 5u : 6u;
                 constexpr uint32_t kPackLim = 1u << (30 - LOGG);
                 const uint32_t cmax0 = __builtin_amdgcn_readfirstlane(s_cmax);  // uniform
                 const bool pack = !OUTER && (uint64_t)cmax0 + (k1 - k0) < kPackLim - 1;
-                // (written as chains of single-condition selects: conditions
-                // joined with && become scalar mask operations whose round
-                // trips through scalar registers slow the serial chain)
                 const uint32_t notreal = real ? 0u : 0xFFFFFFFFu;
-                auto step_packed = [&](const KeyT key, const uint32_t w) {
-                    const uint32_t offer_used =
-                        (f & kPinned) ? 0xFFFFFFFFu : (0x80000000u | (c << LOGG) | j);
-                    uint32_t mine = (f & kUsed) ? offer_used : (0x40000000u | j);
-                    if constexpr (!ONE) mine = (k == key) ? ((f & kUsed) ? j : mine) : mine;
-                    mine |= notreal;
-                    const uint32_t mn = group_min<G>(mine);
-                    // the winner offered the minimum; nobody wins when every
-                    // offer is all ones (then mn + 1 wraps to 0)
-                    const uint32_t tag = mine == mn ? mn + 1u : 0u;
-                    const bool win = tag != 0u;
-                    const uint32_t kind = mn >> 30;  // 0 hit, 1 free slot, 2 or 3 evict
-                    const uint32_t cw = kind == 1u ? w : c + w;
-                    const uint32_t ew = kind == 1u ? 0u : c;
-                    e = win ? (kind == 0u ? e : ew) : e;
-                    k = win ? (kind == 0u ? k : key) : k;
-                    c = win ? cw : c;
-                    f = win ? (uint8_t)(f | kUsed) : f;
-                };
                 // Level steps (transactions): with ties broken by the
                 // lowest slot, the single steps take the slots at the
                 // minimum level (free slots below every count, then

@@ -119,7 +119,8 @@ def test_autotune_choice_and_invariance(crop, ctx):
     tx, off, items, n = make_batch(streams)
     crop.crop_load_batch(ctx, tx, off, items, n)
     tpb, R, ms = crop.crop_batch_autotune(ctx, 1)
-    assert tpb in (15000, 30000, 60000) and R in (64, 128, 256, 32, 16, 8, 4, 2, 1)
+    # R is 0 on the region route (no chunks), else the chunk's rows
+    assert tpb in (15000, 30000, 60000) and R in (0, 64, 128, 256, 32, 16, 8, 4, 2, 1)
     assert ms > 0
     crop.crop_run_exact_batched(ctx)
     for k in (0, 5, 11, 23):
