@@ -589,7 +589,7 @@ crop_status plan_ss(crop_ctx *ctx, uint32_t *nbk_out, uint64_t *PB_out, int *g_o
     uint64_t pick = 0;
     if (!wide) {
         pick = pick_for(kSsBatchTxLarge);
-        if (pick >= 1) MB = kSsBatchTxLarge;
+        if (pick) MB = kSsBatchTxLarge;
     }
     if (MB != kSsBatchTxLarge) pick = pick_for(MB);
     *g_out = -1;
