@@ -130,9 +130,13 @@ crop_status crop_set_seed(crop_ctx *ctx, uint64_t seed);
 crop_status crop_set_summary(crop_ctx *ctx, uint32_t counters_per_partition,
                              uint32_t counters_per_bucket);
 /* Own only partitions [p_begin, p_end) (0, 0: all, the default): exact runs
- * then enumerate every term but route and keep only those whose hash lies in
- * the owned interval [ceil(p_begin 2^32 / P), ceil(p_end 2^32 / P)) -- the
- * share of one processor in Section 5 (Lemma 1) and Section 6 (Theorem 1).
+ * then route and keep only the terms whose hash lies in the owned interval
+ * [ceil(p_begin 2^32 / P), ceil(p_end 2^32 / P)) -- the share of one
+ * processor in Section 5 (Lemma 1) and Section 6 (Theorem 1).  A share of at
+ * most half the hash space visits only the h_b windows of each transaction
+ * that can hold owned terms (window tuning CROP_WINDOW_AUTO, the default);
+ * a larger share, or CROP_WINDOW_OFF, enumerates every term and drops the
+ * unowned ones.
  * Partitions outside the range read back empty.  crop_set_partitions resets
  * the range; top-K and Count-Sketch runs reject an owned range. */
 crop_status crop_set_owned_partitions(crop_ctx *ctx, uint32_t p_begin, uint32_t p_end);
