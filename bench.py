@@ -682,8 +682,8 @@ def run_outer(args):
 
 def run_shards(args):
     """One GPU's share of a G-GPU run: the exact path owning P/G partitions of
-    the 1M-transaction stream (every term enumerated, 1/G routed and kept),
-    for each of the G shares, against the whole run."""
+    the 1M-transaction stream (its terms found through Lemma 1's h_b windows
+    of every transaction), for each of the G shares, against the whole run."""
     import numpy as np
     import torch
     import datagen

@@ -509,8 +509,9 @@ __device__ inline uint32_t packed_insert_batch(uint64_t *tab, const uint32_t (&c
 }
 
 // Flat variant of the packed aggregation: every wavefront walks its own
-// batches of the bin (64 U keys: U per lane, two batches loaded ahead) and
-// runs them through packed_insert_batch.  There is no barrier between
+// batches of the bin (64 U keys: U per lane, two batches loaded ahead, in
+// three register sets used in turn) and runs them through
+// packed_insert_batch.  There is no barrier between
 // batches: a wavefront decides whether it may insert from the workgroup's
 // insert counter, read before each batch and raised by the batch's inserts
 // right after it.  A wavefront has at most one batch whose inserts are not
@@ -553,41 +554,53 @@ k_aggregate_flat(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ ke
         }
         const uint32_t last = k1 - 1;  // read only when the bin is not empty
         uint32_t base = k0 + wave * WB;
-        uint32_t cur[U] = {}, nx1[U] = {};
-        if (base < k1) {
+        // the batch at bb (positions past the bin read its last key)
+        auto load = [&](uint32_t (&k)[U], uint32_t bb) {
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                cur[u] = keys[min(base + u * kWave + lane, last)];
-                nx1[u] = keys[min(base + NW * WB + u * kWave + lane, last)];
-            }
-        }
-        __syncthreads();
+            for (int u = 0; u < U; ++u) k[u] = keys[min(bb + u * kWave + lane, last)];
+        };
         uint32_t qn = 0;
-        for (; base < k1; base += NW * WB) {
-            // two batches in flight ahead of the one being inserted
-            const uint32_t nb = base + 2 * NW * WB;
-            uint32_t nx2[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) nx2[u] = keys[min(nb + u * kWave + lane, last)];
+        auto insert = [&](const uint32_t (&k)[U], uint32_t bb) {
             const bool ins =
                 __hip_atomic_load(&s_occ, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <=
                 cap_soft;
             // copies of each wavefront's lead key merge into its lowest lane
             // (a hot pair fills most of its bin; one atomic instead of many)
-            uint32_t wt[U];
+            uint32_t cur[U], wt[U];
 #pragma unroll
-            for (int u = 0; u < U; ++u) wt[u] = base + u * kWave + lane < k1 ? 1u : 0u;
+            for (int u = 0; u < U; ++u) {
+                cur[u] = k[u];
+                wt[u] = bb + u * kWave + lane < k1 ? 1u : 0u;
+            }
             const uint32_t n_new = packed_insert_batch<U, LOG2S>(
-                tab, cur, wt, ins, spill, k0, &s_nspill, s_q[wave], qn, base + NW * WB >= k1);
+                tab, cur, wt, ins, spill, k0, &s_nspill, s_q[wave], qn, bb + NW * WB >= k1);
             uint32_t tot = n_new;
 #pragma unroll
             for (int d = 32; d >= 1; d >>= 1) tot += __shfl_xor(tot, d, kWave);
             if (lane == 0 && tot) atomicAdd(&s_occ, tot);
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                cur[u] = nx1[u];
-                nx1[u] = nx2[u];
-            }
+        };
+        // three batches in rotation by name (register copies would wait for
+        // the loads being copied): batch i + 2 is loaded while batch i is
+        // inserted
+        uint32_t kA[U], kB[U], kC[U];
+        if (base < k1) {
+            load(kA, base);
+            load(kB, base + NW * WB);
+        }
+        __syncthreads();
+        for (;;) {
+            if (base >= k1) break;
+            load(kC, base + 2 * NW * WB);
+            insert(kA, base);
+            base += NW * WB;
+            if (base >= k1) break;
+            load(kA, base + 2 * NW * WB);
+            insert(kB, base);
+            base += NW * WB;
+            if (base >= k1) break;
+            load(kB, base + 2 * NW * WB);
+            insert(kC, base);
+            base += NW * WB;
         }
         __syncthreads();  // keys of the bin are consumed; the spill list is complete
         // a wavefront may have spilled a key that a slower one inserted
@@ -692,10 +705,9 @@ k_aggregate_regions(const uint16_t *__restrict__ hdrT, const SbSeg *__restrict__
         // the listed runs: count, keys, next position and the run holding it
         uint32_t nr = 0, tk = 0, c = 0, r0 = 0;
         // Positions c .. c + 63 of the listed runs (a new list once they are
-        // used up): the key of each valid lane, kEmpty32 (never a packed
-        // pair) elsewhere; false when the wavefront's keys are done
-        // (wavefront-uniform).
-        auto span = [&](uint32_t &key) {
+        // used up): the load of each lane's key (ok: the lane has one);
+        // false when the wavefront's keys are done (wavefront-uniform).
+        auto span = [&](uint32_t &key, bool &ok) {
             while (c >= tk && g < g_end) {
                 const uint32_t len = ne - na;
                 const uint32_t incl = wave_inclusive_scan(len);
@@ -720,52 +732,69 @@ k_aggregate_regions(const uint16_t *__restrict__ hdrT, const SbSeg *__restrict__
                 g += kWave;
                 load_rows();
             }
-            if (c >= tk) {
-                key = kEmpty32;
-                return false;
+            // the load is issued on every path (lanes without a key read
+            // word 0), so every batch issues the same loads and the waits
+            // for a batch count only the loads issued after it
+            const bool more = c < tk;
+            uint32_t src = 0;
+            ok = false;
+            if (more) {
+                src = sb_span(c, r0, nr, rb, rp, wflag, ++tag);
+                ok = c + lane < tk;
+                c += kWave;
             }
-            const uint32_t src = sb_span(c, r0, nr, rb, rp, wflag, ++tag);
-            key = c + lane < tk ? routed[src] : kEmpty32;
-            c += kWave;
-            return true;
+            key = routed[ok ? src : 0u];
+            return more;
         };
-        auto batch = [&](uint32_t (&k)[U]) {
+        // U spans: the raw loads in k (not read until the batch is inserted)
+        // and a bit per span of the lanes that hold a key
+        auto batch = [&](uint32_t (&k)[U], uint32_t &m) {
             bool any = false;
-#pragma unroll
-            for (int u = 0; u < U; ++u) any = span(k[u]) || any;
-            return any;
-        };
-        __syncthreads();  // the table is clear
-        // batch i + 2 is loaded while batch i is inserted (one call site of
-        // batch, so its spans are inlined once); the first two iterations
-        // only load
-        uint32_t cur[U], nx1[U], nx2[U];
-        bool a0 = false, a1 = false;
-        uint32_t qn = 0;
-        for (int it = -2;; ++it) {
-            const bool a2 = batch(nx2);
-            if (it >= 0) {
-                if (!a0) break;  // wavefront-uniform: this wavefront's keys are done
-                const bool ins = __hip_atomic_load(&s_occ, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_WORKGROUP) <= cap_soft;
-                uint32_t wt[U];
-#pragma unroll
-                for (int u = 0; u < U; ++u) wt[u] = cur[u] != kEmpty32 ? 1u : 0u;
-                // the last batch of the wavefront drains its queue
-                const uint32_t n_new = packed_insert_batch<U, LOG2S>(
-                    tab, cur, wt, ins, spill, k0, &s_nspill, s_q[wave], qn, !a1);
-                uint32_t tot = n_new;
-#pragma unroll
-                for (int d = 32; d >= 1; d >>= 1) tot += __shfl_xor(tot, d, kWave);
-                if (lane == 0 && tot) atomicAdd(&s_occ, tot);
-            }
+            m = 0;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                cur[u] = nx1[u];
-                nx1[u] = nx2[u];
+                bool ok;
+                any = span(k[u], ok) || any;
+                m |= ok ? 1u << u : 0u;
             }
-            a0 = a1;
-            a1 = a2;
+            return any;
+        };
+        uint32_t qn = 0;
+        auto insert = [&](const uint32_t (&k)[U], uint32_t m, bool last) {
+            const bool ins = __hip_atomic_load(&s_occ, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP) <= cap_soft;
+            uint32_t cur[U], wt[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = (m >> u) & 1u;
+                cur[u] = ok ? k[u] : kEmpty32;
+                wt[u] = ok ? 1u : 0u;
+            }
+            // the last batch of the wavefront drains its queue
+            const uint32_t n_new = packed_insert_batch<U, LOG2S>(
+                tab, cur, wt, ins, spill, k0, &s_nspill, s_q[wave], qn, last);
+            uint32_t tot = n_new;
+#pragma unroll
+            for (int d = 32; d >= 1; d >>= 1) tot += __shfl_xor(tot, d, kWave);
+            if (lane == 0 && tot) atomicAdd(&s_occ, tot);
+        };
+        __syncthreads();  // the table is clear
+        // Three batches in rotation by name (no register copies, which
+        // would wait for the loads being copied): batch i + 2 is loaded
+        // while batch i is inserted.  A batch without keys ends the
+        // wavefront's share (wavefront-uniform).
+        uint32_t kA[U], kB[U], kC[U], mA, mB, mC;
+        bool aA = batch(kA, mA), aB = batch(kB, mB), aC;
+        for (;;) {
+            aC = batch(kC, mC);
+            if (!aA) break;
+            insert(kA, mA, !aB);
+            aA = batch(kA, mA);
+            if (!aB) break;
+            insert(kB, mB, !aC);
+            aB = batch(kB, mB);
+            if (!aC) break;
+            insert(kC, mC, !aA);
         }
         __syncthreads();  // keys of the bin are consumed; the spill list is complete
         packed_absorb_spill<BS, LOG2S>(tab, spill, k0, &s_nspill);
