@@ -22,16 +22,38 @@ __device__ inline uint32_t xcd_contiguous(uint32_t b, uint32_t n)
 
 __device__ inline uint32_t lane_id() { return __lane_id(); }
 
-// Inclusive scan of v across the 64 lanes of a wave.
+// Inclusive scan of v across the 64 lanes of a wave (every lane active),
+// in DPP moves: shifts by 1, 2, 4 and 8 lanes inside each row of 16 (lanes
+// shifted in from outside the row read 0), then the last lane of row 0 is
+// added to row 1 and of row 2 to row 3 (row_bcast:15), then the last lane
+// of row 1 to rows 2 and 3 (row_bcast:31).  No LDS round trip.
 __device__ inline uint32_t wave_inclusive_scan(uint32_t v)
 {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        uint32_t o = __shfl_up(v, d, kWave);
-        if (lane >= (uint32_t)d) v += o;
-    }
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);  // row_shr:1
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);  // row_shr:2
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);  // row_shr:4
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);  // row_shr:8
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
     return v;
+}
+
+// Sum over the wave of per-lane counts, wave-uniform: one ballot per bit of
+// the counts (no LDS round trip), as many as the largest count needs.
+__device__ inline uint32_t wave_count_sum(uint32_t v)
+{
+    uint32_t tot = 0;
+    for (uint32_t bit = 0; bit < 32; ++bit) {
+        tot += (uint32_t)__popcll(__ballot((v >> bit) & 1u)) << bit;
+        if (__ballot((v >> bit) > 1u) == 0) break;
+    }
+    return tot;
+}
+
+// v of lane `src`, a wave-uniform lane index (one readlane, no LDS).
+__device__ inline uint32_t lane_value(uint32_t v, uint32_t src)
+{
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)src);
 }
 
 // Exclusive scan over the block; returns this thread's prefix and the

@@ -36,9 +36,9 @@ template <> struct Empty<uint64_t> { static constexpr uint64_t v = kEmpty64; };
 template <class KeyT>
 __device__ inline KeyT shfl_key(KeyT k, int src)
 {
-    if (sizeof(KeyT) == 4) return (KeyT)__shfl((int)k, src, kWave);
-    uint32_t lo = (uint32_t)__shfl((int)(uint32_t)k, src, kWave);
-    uint32_t hi = (uint32_t)__shfl((int)(uint32_t)((uint64_t)k >> 32), src, kWave);
+    if (sizeof(KeyT) == 4) return (KeyT)lane_value((uint32_t)k, (uint32_t)src);
+    uint32_t lo = lane_value((uint32_t)k, (uint32_t)src);
+    uint32_t hi = lane_value((uint32_t)((uint64_t)k >> 32), (uint32_t)src);
     return (KeyT)(((uint64_t)hi << 32) | lo);
 }
 
@@ -73,7 +73,7 @@ __device__ inline void wave_merge_lead(uint32_t key, uint32_t &w)
     const uint64_t act = __ballot(open);
     if (act == 0) return;
     const int leader = __ffsll((long long)act) - 1;
-    const uint32_t lk = (uint32_t)__shfl((int)key, leader, kWave);
+    const uint32_t lk = lane_value(key, (uint32_t)leader);
     const bool eq = open && key == lk;
     const uint64_t m = __ballot(eq);
     if (eq) w = (lane_id() == (uint32_t)leader) ? (uint32_t)__popcll(m) : 0u;
@@ -138,7 +138,7 @@ __device__ inline void table_dump(const Table<KeyT, W> &t, uint32_t S, KeyT *key
         uint32_t base = 0;
         if (n) {
             if (lane == (uint32_t)(__ffsll((long long)m) - 1)) base = atomicAdd(s_nout, n);
-            base = __shfl(base, __ffsll((long long)m) - 1, kWave);
+            base = lane_value(base, (uint32_t)(__ffsll((long long)m) - 1));
         }
         if (has) {
             uint32_t r = (uint32_t)__popcll(m & ((1ull << lane) - 1));
@@ -315,7 +315,7 @@ __device__ inline void packed_dump(const uint64_t *tab, uint32_t *keys_out, uint
         if (n) {
             const int first = __ffsll((long long)m) - 1;
             if (lane == (uint32_t)first) base = atomicAdd(s_nout, n);
-            base = __shfl(base, first, kWave);
+            base = lane_value(base, (uint32_t)first);
         }
         if (has) {
             const uint32_t r = (uint32_t)__popcll(m & ((1ull << lane) - 1));
@@ -574,9 +574,7 @@ k_aggregate_flat(const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ ke
             }
             const uint32_t n_new = packed_insert_batch<U, LOG2S>(
                 tab, cur, wt, ins, spill, k0, &s_nspill, s_q[wave], qn, bb + NW * WB >= k1);
-            uint32_t tot = n_new;
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) tot += __shfl_xor(tot, d, kWave);
+            const uint32_t tot = wave_count_sum(n_new);
             if (lane == 0 && tot) atomicAdd(&s_occ, tot);
         };
         // three batches in rotation by name (register copies would wait for
@@ -773,9 +771,7 @@ k_aggregate_regions(const uint16_t *__restrict__ hdrT, const SbSeg *__restrict__
             // the last batch of the wavefront drains its queue
             const uint32_t n_new = packed_insert_batch<U, LOG2S>(
                 tab, cur, wt, ins, spill, k0, &s_nspill, s_q[wave], qn, last);
-            uint32_t tot = n_new;
-#pragma unroll
-            for (int d = 32; d >= 1; d >>= 1) tot += __shfl_xor(tot, d, kWave);
+            const uint32_t tot = wave_count_sum(n_new);
             if (lane == 0 && tot) atomicAdd(&s_occ, tot);
         };
         __syncthreads();  // the table is clear

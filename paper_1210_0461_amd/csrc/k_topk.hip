@@ -373,7 +373,14 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
                 } else {
                     const uint64_t vm = __ballot(valid);
                     if (!vm) continue;
-                    const KeyT lead = (KeyT)__shfl(key, __ffsll((long long)vm) - 1, kWave);
+                    const uint32_t src = (uint32_t)(__ffsll((long long)vm) - 1);
+                    KeyT lead;
+                    if constexpr (sizeof(KeyT) == 4)
+                        lead = (KeyT)lane_value((uint32_t)key, src);
+                    else
+                        lead = (KeyT)(((uint64_t)lane_value((uint32_t)((uint64_t)key >> 32), src)
+                                       << 32) |
+                                      lane_value((uint32_t)key, src));
                     const bool same = valid && key == lead;
                     const uint64_t m = __ballot(same);
                     if (same) {
