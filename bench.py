@@ -92,6 +92,12 @@ def calibrate_copy():
     print(json.dumps({"calibration": "copy", "bytes_read": 4 * n, "bytes_written": 4 * n}))
 
 
+# The sources of the exact path's kernels: the recorded PMC traffic is used
+# only while they hash to the digest it was taken with.
+STEP_SOURCES = ("k_route.hip", "k_sbroute.hip", "k_exact.hip", "crop_device.hpp",
+                "crop_enum.hpp", "crop_hash.hpp", "crop_layout.hpp", "crop_runs.hpp")
+
+
 def source_digest(*names):
     h = hashlib.sha256()
     for n in names:
@@ -860,8 +866,7 @@ def main():
     dom = max(stage_ms, key=stage_ms.get)
     dom_ms = stage_ms[dom]
     achieved = per_term * terms / (dom_ms * 1e-3) / 1e9
-    digest = source_digest("k_route.hip", "k_sbroute.hip", "k_exact.hip", "crop_device.hpp",
-                           "crop_enum.hpp", "crop_hash.hpp", "crop_layout.hpp", "crop_runs.hpp")
+    digest = source_digest(*STEP_SOURCES)
     traffic = traffic_from_profiles(kernel_names[dom], digest)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
