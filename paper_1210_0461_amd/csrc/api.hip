@@ -1061,10 +1061,9 @@ crop_status crop_run_exact(crop_ctx *ctx)
         if (ctx->sb.n_sub) CK(launch_sb_route(ctx, s));
         STAGE("route");
         CK(launch_sb_headers(ctx, s));
-        // one bin counter and one ordered range of bins per XCD
-        CK(launch_zero32(ctx->counter.as<uint32_t>(), crop::kNumXcd, s));
+        // one ordered range of bins and one bin counter (cleared) per XCD
         CK(launch_bin_order(pl.NB, ctx->bin_off.as<uint32_t>(), ctx->bin_order.as<uint32_t>(),
-                            s, crop::kNumXcd));
+                            s, crop::kNumXcd, ctx->counter.as<uint32_t>(), crop::kNumXcd));
         STAGE("headers");
     } else {
         if (pl.n_chunks) CK(outer ? launch_op_count(ctx, cnt, s)

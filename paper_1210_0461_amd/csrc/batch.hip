@@ -273,9 +273,9 @@ crop_status enqueue_batch(crop_ctx *ctx, hipStream_t s, bool stages)
         if (ctx->sb.n_sub) CK(launch_sb_route(ctx, s));
         if (stages) STAGE("route");
         CK(launch_sb_headers(ctx, s));
-        // one bin counter and one ordered range of bins per XCD
-        CK(launch_zero32(ctx->counter.as<uint32_t>(), kNumXcd, s));
-        CK(launch_bin_order(ctx->plan.NB, bin_off, ctx->bin_order.as<uint32_t>(), s, kNumXcd));
+        // one ordered range of bins and one bin counter (cleared) per XCD
+        CK(launch_bin_order(ctx->plan.NB, bin_off, ctx->bin_order.as<uint32_t>(), s, kNumXcd,
+                            ctx->counter.as<uint32_t>(), kNumXcd));
         if (stages) STAGE("headers");
         CK(launch_aggregate_regions(ctx, s));
         if (stages) STAGE("aggregate");

@@ -322,9 +322,10 @@ hipError_t launch_scan_counts(uint32_t *cnt, uint32_t n_chunks, uint32_t NB, uin
 
 // order[] <- bins with more than twice the mean term count first.
 // n_seg > 1: each of n_seg equal segments of the bins ordered on its own
-// (the region aggregation's per-XCD bin ranges)
+// (the region aggregation's per-XCD bin ranges); zero[0 .. n_zero) <- 0
+// (n_zero at most 1024)
 hipError_t launch_bin_order(uint32_t NB, const uint32_t *bin_off, uint32_t *order, hipStream_t s,
-                            uint32_t n_seg = 1);
+                            uint32_t n_seg = 1, uint32_t *zero = nullptr, uint32_t n_zero = 0);
 
 hipError_t launch_batch_count(const uint32_t *off, const uint32_t *items, const HashParams &hp,
                               const BatchDev &b, uint32_t *cnt, const uint32_t *bin_off,

@@ -515,11 +515,14 @@ k_colbase(uint32_t NB, uint32_t *__restrict__ bin_off, uint32_t *__restrict__ co
 // (g + 1) NB / n_seg)): order[] lists, in place of the segment, its bins
 // with more than twice the mean term count first (in index order), then
 // the others, so that the persistent aggregation workgroups start the
-// longest bins first.
+// longest bins first.  The first workgroup also clears the n_zero words at
+// zero (the aggregation's bin counters), which saves a launch.
 __global__ void __launch_bounds__(1024)
-k_bin_order(uint32_t NB, const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ order)
+k_bin_order(uint32_t NB, const uint32_t *__restrict__ bin_off, uint32_t *__restrict__ order,
+            uint32_t *__restrict__ zero, uint32_t n_zero)
 {
     __shared__ uint32_t s_tmp[1024 / kWave + 1];
+    if (blockIdx.x == 0 && threadIdx.x < n_zero) zero[threadIdx.x] = 0;
     __shared__ uint32_t s_nheavy;
     const uint64_t thresh = 2ull * bin_off[NB] / (NB ? NB : 1);
     const uint32_t lo = (uint32_t)((uint64_t)NB * blockIdx.x / gridDim.x);
@@ -939,9 +942,11 @@ hipError_t launch_op_scatter(const crop_ctx *c, const uint32_t *cur, void *keys,
 }
 
 hipError_t launch_bin_order(uint32_t NB, const uint32_t *bin_off, uint32_t *order, hipStream_t s,
-                            uint32_t n_seg)
+                            uint32_t n_seg, uint32_t *zero, uint32_t n_zero)
 {
-    hipLaunchKernelGGL(k_bin_order, dim3(n_seg), dim3(1024), 0, s, NB, bin_off, order);
+    if (n_zero > 1024 || (n_zero && !zero)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_bin_order, dim3(n_seg), dim3(1024), 0, s, NB, bin_off, order, zero,
+                       n_zero);
     return hipGetLastError();
 }
 
