@@ -582,14 +582,17 @@ crop_status plan_ss(crop_ctx *ctx, uint32_t *nbk_out, uint64_t *PB_out, int *g_o
         return pick;
     };
     // Packed transaction keys merge micro-batches of kSsBatchTxLarge terms
-    // when the bins fit with them (measured faster: fewer, longer merged
-    // update lists per bucket; bins of one bucket, whose updates take level
-    // steps, 3.57 -> 3.35 ms for the 1M-transaction stream at P = 1).
+    // when bins of several buckets fit with them (measured faster: fewer,
+    // longer merged update lists per bucket).  Bins of one bucket keep
+    // kSsBatchTx: the time of their run is set by the heaviest bins, and on
+    // two 1M-transaction streams of the same law (P = 1, 16,384 counters)
+    // the larger batch took 3.30 instead of 3.44 ms on one and 3.54 instead
+    // of 3.24 ms on the other.
     uint32_t MB = outer ? kSsBatchOuter : wide ? kSsBatchWide : kSsBatchTx;
     uint64_t pick = 0;
     if (!wide) {
         pick = pick_for(kSsBatchTxLarge);
-        if (pick) MB = kSsBatchTxLarge;
+        if (pick > 1) MB = kSsBatchTxLarge;
     }
     if (MB != kSsBatchTxLarge) pick = pick_for(MB);
     *g_out = -1;

@@ -346,7 +346,7 @@ hipError_t launch_ss_clear(const SsState &S, hipStream_t s);
 hipError_t launch_ss_pin(const SsState &S, const uint32_t *sx, const uint32_t *sy, uint32_t ns,
                          uint8_t *dup, uint32_t r_max, const HashParams &hp, uint64_t PB,
                          uint32_t ell, uint32_t *n_pinned, hipStream_t s);
-constexpr uint32_t kSsBatchTxLarge = 2048;  // ... of packed transaction keys, when the bins fit
+constexpr uint32_t kSsBatchTxLarge = 2048;  // ... of packed keys, bins of several buckets
 constexpr uint32_t kSsBatchTx = 1024;    // routed terms per Space-Saving micro-batch
 constexpr uint32_t kSsBatchWide = 1024;   // ... with 64-bit keys
 constexpr uint32_t kSsBatchOuter = 1024;  // ... of outer-product terms

@@ -106,6 +106,56 @@ k_ss_pin(const uint32_t *__restrict__ sx, const uint32_t *__restrict__ sy, uint3
     atomicAdd(n_pinned, 1u);
 }
 
+// The same pinning for at most kPinLds seeds in one workgroup: the seeds'
+// pairs and buckets are staged in LDS, then every seed scans the earlier
+// ones there (a duplicate pair first, then the earlier non-duplicate seeds
+// of its bucket), all lanes reading the same earlier seed at once and eight
+// reads in flight.
+constexpr uint32_t kPinLds = 4096;
+__global__ void __launch_bounds__(1024)
+k_ss_pin_lds(const uint32_t *__restrict__ sx, const uint32_t *__restrict__ sy, uint32_t ns,
+             uint32_t r_max, HashParams hp, uint64_t PB, uint32_t ell,
+             uint64_t *__restrict__ key, uint8_t *__restrict__ flag, uint32_t *__restrict__ n_pinned)
+{
+    __shared__ uint64_t s_k[kPinLds];
+    __shared__ uint32_t s_b[kPinLds];
+    __shared__ uint8_t s_d[kPinLds];
+    for (uint32_t i = threadIdx.x; i < ns; i += 1024) {
+        const uint32_t x = sx[i], y = sy[i];
+        s_k[i] = ((uint64_t)x << 32) | y;
+        s_b[i] = interval_of(hash_a(hp, x) + hash_b(hp, y), PB);
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < ns; i += 1024) {
+        const uint64_t k = s_k[i];
+        uint32_t d = 0;
+#pragma unroll 8
+        for (uint32_t t = 0; t < i; ++t) d |= s_k[t] == k ? 1u : 0u;
+        s_d[i] = (uint8_t)d;
+    }
+    __syncthreads();
+    // (every lane of a wavefront runs the same rounds, so the pinned count
+    // is summed per wavefront)
+    for (uint32_t i0 = 0; i0 < ns; i0 += 1024) {
+        const uint32_t i = i0 + threadIdx.x;
+        uint32_t pinned = 0;
+        if (i < ns && !s_d[i]) {
+            const uint32_t b = s_b[i];
+            uint32_t r = 0;
+#pragma unroll 8
+            for (uint32_t t = 0; t < i; ++t) r += (s_b[t] == b && !s_d[t]) ? 1u : 0u;
+            if (r < r_max) {
+                const uint64_t slot = (uint64_t)b * ell + r;
+                key[slot] = s_k[i];
+                flag[slot] = kUsed | kPinned;
+                pinned = 1;
+            }
+        }
+        const uint32_t tot = wave_count_sum(pinned);
+        if (lane_id() == 0 && tot) atomicAdd(n_pinned, tot);
+    }
+}
+
 __global__ void __launch_bounds__(256) k_zero32(uint32_t *p, uint32_t n)
 {
     for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) p[i] = 0;
@@ -1136,6 +1186,11 @@ hipError_t launch_ss_pin(const SsState &S, const uint32_t *sx, const uint32_t *s
                          uint32_t ell, uint32_t *n_pinned, hipStream_t s)
 {
     if (ns == 0) return hipSuccess;
+    if (ns <= kPinLds) {
+        hipLaunchKernelGGL(k_ss_pin_lds, dim3(1), dim3(1024), 0, s, sx, sy, ns, r_max, hp, PB,
+                           ell, S.key, S.flag, n_pinned);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(k_seed_dups, dim3((ns + 255) / 256), dim3(256), 0, s, sx, sy, ns, dup);
     hipLaunchKernelGGL(k_ss_pin, dim3((ns + 255) / 256), dim3(256), 0, s, sx, sy, ns, dup, r_max,
                        hp, PB, ell, S.key, S.flag, n_pinned);

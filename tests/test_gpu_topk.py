@@ -149,10 +149,11 @@ def test_recall_matches_sequential_oracle(crop, ctx):
     assert np.mean(rec_gpu) >= np.mean(rec_orc) - 0.04
 
 
-def test_seeded_pins_exact_and_placement(crop, ctx):
+@pytest.mark.parametrize("n_top", [60, 5000])  # one workgroup in LDS / the many-seed kernels
+def test_seeded_pins_exact_and_placement(crop, ctx, n_top):
     st = datagen.config_small()
     exact, r = exact_map(st)
-    top = oracle.topk(oracle.pack_keys(r["x"], r["y"]), r["cnt"], 60)
+    top = oracle.topk(oracle.pack_keys(r["x"], r["y"]), r["cnt"], n_top)
     sx, sy = r["x"][top], r["y"][top]
     sx = np.concatenate([sx, sx[:5]])  # duplicates are skipped
     sy = np.concatenate([sy, sy[:5]])
