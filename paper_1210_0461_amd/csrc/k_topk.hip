@@ -853,7 +853,9 @@ k_topk_hist(const uint64_t *__restrict__ key, RankBy rv,
          t += (uint64_t)gridDim.x * 256) {
         const uint64_t i = cand ? cand[t] : t;
         if (!(flag[i] & kUsed)) continue;
-        const Comp c = comp_of(key, rv, i, sh);
+        // the digits of passes 0 .. 3 come from the ranked value alone: the
+        // slot's key (8 of its 17 bytes) is not read for them
+        const Comp c = pass < 4 ? Comp{{rv(i) << sh, 0u, 0u}} : comp_of(key, rv, i, sh);
         if (!prefix_match(c, st, pass)) continue;
         atomicAdd(&h[digit_of(c, pass)], 1u);
     }
@@ -866,10 +868,10 @@ k_topk_hist(const uint64_t *__restrict__ key, RankBy rv,
 // which the running count reaches the remaining rank (else 0); the new
 // remaining rank excludes the digits above d.  Lane L holds digits
 // 255 - 4L .. 252 - 4L, so a scan over lanes gives every running count.
-__global__ void __launch_bounds__(64)
-k_topk_pick(uint32_t *__restrict__ st, uint32_t *__restrict__ hist, uint32_t pass, uint32_t K)
+// (one full wavefront, lane = its lane; st and hist in global memory or LDS)
+__device__ inline void topk_pick_wave(uint32_t *st, uint32_t *hist, uint32_t pass, uint32_t K,
+                                      uint32_t lane)
 {
-    const uint32_t lane = threadIdx.x;
     uint32_t h[4], local = 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -918,6 +920,43 @@ k_topk_pick(uint32_t *__restrict__ st, uint32_t *__restrict__ hist, uint32_t pas
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) hist[4 * lane + q] = 0;
+}
+
+__global__ void __launch_bounds__(64)
+k_topk_pick(uint32_t *__restrict__ st, uint32_t *__restrict__ hist, uint32_t pass, uint32_t K)
+{
+    topk_pick_wave(st, hist, pass, K, threadIdx.x);
+}
+
+// Passes 2 .. 11 over the compacted candidates in one workgroup: the
+// histogram and the selection state in LDS, each pass a histogram of the
+// candidates that match the prefix so far and a pick by the first
+// wavefront (the same steps as k_topk_hist and k_topk_pick, without a launch
+// per pass).  The state goes back to st at the end.
+__global__ void __launch_bounds__(1024)
+k_topk_finish(const uint64_t *__restrict__ key, RankBy rv, const uint8_t *__restrict__ flag,
+              const uint32_t *__restrict__ cand, uint32_t *__restrict__ st, uint32_t K)
+{
+    __shared__ uint32_t h[256], s_st[8];
+    if (threadIdx.x < 8) s_st[threadIdx.x] = st[threadIdx.x];
+    __syncthreads();
+    const uint32_t m = s_st[4];
+    const uint32_t sh = count_shift(s_st);
+    for (uint32_t pass = 2; pass < 12; ++pass) {
+        if (threadIdx.x < 256) h[threadIdx.x] = 0;
+        __syncthreads();
+        for (uint32_t t = threadIdx.x; t < m; t += 1024) {
+            const uint32_t i = cand[t];
+            if (!(flag[i] & kUsed)) continue;
+            const Comp c = comp_of(key, rv, i, sh);
+            if (!prefix_match(c, s_st, pass)) continue;
+            atomicAdd(&h[digit_of(c, pass)], 1u);
+        }
+        __syncthreads();
+        if (threadIdx.x < kWave) topk_pick_wave(s_st, h, pass, K, threadIdx.x);
+        __syncthreads();
+    }
+    if (threadIdx.x < 8) st[threadIdx.x] = s_st[threadIdx.x];
 }
 
 __device__ inline bool comp_ge(const Comp &a, const uint32_t *t)
@@ -1284,14 +1323,15 @@ hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, bool by_lower, 
     const RankBy rv{S.cnt, S.err, by_lower, outer, err_is_lower};
     hipLaunchKernelGGL(k_topk_max, dim3(grid_for(S.nslots, 1024)), dim3(256), 0, s, rv, S.flag,
                        S.nslots, st);
-    for (uint32_t pass = 0; pass < 12; ++pass) {
+    // the first two digits over every slot, then the rest over the
+    // candidates that share them, in one workgroup
+    for (uint32_t pass = 0; pass < 2; ++pass) {
         hipLaunchKernelGGL(k_topk_hist, dim3(g), dim3(256), 0, s, S.key, rv, S.flag, S.nslots,
-                           pass < 2 ? nullptr : cand, st, pass, hist);
+                           nullptr, st, pass, hist);
         hipLaunchKernelGGL(k_topk_pick, dim3(1), dim3(64), 0, s, st, hist, pass, K);
-        if (pass == 1)
-            hipLaunchKernelGGL(k_topk_compact, dim3(g), dim3(256), 0, s, rv, S.flag, S.nslots, st,
-                               cand);
     }
+    hipLaunchKernelGGL(k_topk_compact, dim3(g), dim3(256), 0, s, rv, S.flag, S.nslots, st, cand);
+    hipLaunchKernelGGL(k_topk_finish, dim3(1), dim3(1024), 0, s, S.key, rv, S.flag, cand, st, K);
     hipLaunchKernelGGL(k_topk_collect, dim3(g), dim3(256), 0, s, S.key, rv, cand, st, sel);
     const uint32_t gr = (K + 255) / 256 ? (K + 255) / 256 : 1;
     hipLaunchKernelGGL(k_zero32, dim3(grid_for(K, 1024)), dim3(256), 0, s, rank, K);
