@@ -932,21 +932,28 @@ k_topk_pick(uint32_t *__restrict__ st, uint32_t *__restrict__ hist, uint32_t pas
 // histogram and the selection state in LDS, each pass a histogram of the
 // candidates that match the prefix so far and a pick by the first
 // wavefront (the same steps as k_topk_hist and k_topk_pick, without a launch
-// per pass).  The state goes back to st at the end.
+// per pass).  After a pass over the global list, the candidates that still
+// match the prefix are copied into an LDS list; once they fit (at most
+// kFinishList), later passes read only that list.  The global list is left
+// as it is (k_topk_collect reads it), and the state goes back to st at the
+// end.
+constexpr uint32_t kFinishList = 8192;
 __global__ void __launch_bounds__(1024)
 k_topk_finish(const uint64_t *__restrict__ key, RankBy rv, const uint8_t *__restrict__ flag,
               const uint32_t *__restrict__ cand, uint32_t *__restrict__ st, uint32_t K)
 {
-    __shared__ uint32_t h[256], s_st[8];
+    __shared__ uint32_t h[256], s_st[8], s_list[kFinishList], s_n;
     if (threadIdx.x < 8) s_st[threadIdx.x] = st[threadIdx.x];
     __syncthreads();
     const uint32_t m = s_st[4];
     const uint32_t sh = count_shift(s_st);
+    bool local = false;  // workgroup-uniform: the LDS list holds the candidates
+    uint32_t n = m;
     for (uint32_t pass = 2; pass < 12; ++pass) {
         if (threadIdx.x < 256) h[threadIdx.x] = 0;
         __syncthreads();
-        for (uint32_t t = threadIdx.x; t < m; t += 1024) {
-            const uint32_t i = cand[t];
+        for (uint32_t t = threadIdx.x; t < n; t += 1024) {
+            const uint32_t i = local ? s_list[t] : cand[t];
             if (!(flag[i] & kUsed)) continue;
             const Comp c = comp_of(key, rv, i, sh);
             if (!prefix_match(c, s_st, pass)) continue;
@@ -955,6 +962,23 @@ k_topk_finish(const uint64_t *__restrict__ key, RankBy rv, const uint8_t *__rest
         __syncthreads();
         if (threadIdx.x < kWave) topk_pick_wave(s_st, h, pass, K, threadIdx.x);
         __syncthreads();
+        if (!local && pass + 1 < 12) {
+            if (threadIdx.x == 0) s_n = 0;
+            __syncthreads();
+            for (uint32_t t = threadIdx.x; t < m; t += 1024) {
+                const uint32_t i = cand[t];
+                if (!(flag[i] & kUsed)) continue;
+                if (!prefix_match(comp_of(key, rv, i, sh), s_st, pass + 1)) continue;
+                const uint32_t j = atomicAdd(&s_n, 1u);
+                if (j < kFinishList) s_list[j] = i;
+            }
+            __syncthreads();
+            if (s_n <= kFinishList) {
+                local = true;
+                n = s_n;
+            }
+            __syncthreads();  // s_n is read by every thread before any reset
+        }
     }
     if (threadIdx.x < 8) st[threadIdx.x] = s_st[threadIdx.x];
 }
