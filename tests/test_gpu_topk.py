@@ -77,6 +77,28 @@ def test_small_config_invariants_and_topk(crop, ctx, P, C, ell):
     check_topk_is_summary_topk(s, top, 100)
 
 
+def test_topk_all_counts_equal(crop, ctx):
+    """20,000 distinct pairs, each once: every monitored slot holds count 1,
+    so the ranked value never narrows the candidates and the selection is
+    decided by the keys alone (more than 8,192 candidates stay tied through
+    the passes over the count)."""
+    rng = np.random.default_rng(77)
+    n = 400
+    a, b = np.triu_indices(n, 1)
+    pick = np.sort(rng.choice(a.size, 20000, replace=False))
+    items = np.stack([a[pick], b[pick]], axis=1).reshape(-1).astype(np.uint32)
+    off = np.arange(0, items.size + 1, 2, dtype=np.uint32)
+    st = datagen.Transactions(off, items, n)
+    exact, _ = exact_map(st)
+    assert set(exact.values()) == {1}
+    # 4,096 buckets of 16 slots hold at most 13 of these keys each: all kept
+    s, top = run_tx_topk(crop, ctx, st, 1, 1 << 16, 16, 100)
+    assert int(s["used"].sum()) == 20000
+    assert set(s["cnt"][s["used"]].tolist()) == {1}
+    check_invariants(s, exact, SEED)
+    check_topk_is_summary_topk(s, top, 100)
+
+
 @pytest.mark.parametrize("P,C,ell", [(1, 64, 4), (4, 1024, 16)])
 def test_topk_by_either_bound(crop, ctx, P, C, ell):
     """The default report ranks by guaranteed count (count - overestimation);
