@@ -839,23 +839,22 @@ __device__ inline bool prefix_match(const Comp &c, const uint32_t *prefix, uint3
 // Selection state in device memory:
 //   st[0..2] prefix words, st[3] remaining rank, st[4] candidate count,
 //   st[5] selected count, st[6] used slots, st[7] largest count, hist[256].
+//
+// Histogram of one of the first four digits (the ranked value's bytes) over
+// every used slot that matches the prefix so far; the slot's key (8 of its
+// 17 bytes) is not read.
 __global__ void __launch_bounds__(256)
-k_topk_hist(const uint64_t *__restrict__ key, RankBy rv,
-            const uint8_t *__restrict__ flag, uint64_t n, const uint32_t *__restrict__ cand,
+k_topk_hist(RankBy rv, const uint8_t *__restrict__ flag, uint64_t n,
             const uint32_t *__restrict__ st, uint32_t pass, uint32_t *__restrict__ hist)
 {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
-    const uint64_t m = cand ? st[4] : n;
     const uint32_t sh = count_shift(st);
-    for (uint64_t t = (uint64_t)blockIdx.x * 256 + threadIdx.x; t < m;
-         t += (uint64_t)gridDim.x * 256) {
-        const uint64_t i = cand ? cand[t] : t;
+    for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+         i += (uint64_t)gridDim.x * 256) {
         if (!(flag[i] & kUsed)) continue;
-        // the digits of passes 0 .. 3 come from the ranked value alone: the
-        // slot's key (8 of its 17 bytes) is not read for them
-        const Comp c = pass < 4 ? Comp{{rv(i) << sh, 0u, 0u}} : comp_of(key, rv, i, sh);
+        const Comp c{{rv(i) << sh, 0u, 0u}};
         if (!prefix_match(c, st, pass)) continue;
         atomicAdd(&h[digit_of(c, pass)], 1u);
     }
@@ -1350,8 +1349,8 @@ hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, bool by_lower, 
     // the first two digits over every slot, then the rest over the
     // candidates that share them, in one workgroup
     for (uint32_t pass = 0; pass < 2; ++pass) {
-        hipLaunchKernelGGL(k_topk_hist, dim3(g), dim3(256), 0, s, S.key, rv, S.flag, S.nslots,
-                           nullptr, st, pass, hist);
+        hipLaunchKernelGGL(k_topk_hist, dim3(g), dim3(256), 0, s, rv, S.flag, S.nslots, st, pass,
+                           hist);
         hipLaunchKernelGGL(k_topk_pick, dim3(1), dim3(64), 0, s, st, hist, pass, K);
     }
     hipLaunchKernelGGL(k_topk_compact, dim3(g), dim3(256), 0, s, rv, S.flag, S.nslots, st, cand);
