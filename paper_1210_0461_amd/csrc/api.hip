@@ -1180,7 +1180,10 @@ static crop_status run_topk_impl(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
     for (uint32_t i = 0; i < t; ++i) ip.hp[i] = make_hash_params(ctx->seed + i);
     st = run_begin(ctx);
     if (st != CROP_OK) return st;
-    CK(launch_ss_clear(ctx->ss, s));
+    // without seeds the summary kernel starts every bin empty and writes
+    // every slot, so the state needs no clearing; pinned seeds go into
+    // cleared state, which the kernel then reads
+    if (ns) CK(launch_ss_clear(ctx->ss, s));
     CK(launch_zero32(tv.st, 8 + 256 + 1, s));
     if (ns)
         CK(launch_ss_pin(ctx->ss, sx, sy, (uint32_t)ns, tv.dup, r_max, ctx->hp, PB, ctx->ss_ell,
@@ -1215,7 +1218,7 @@ static crop_status run_topk_impl(crop_ctx *ctx, uint32_t K, const uint32_t *sx,
                      : pl.n_wg ? launch_tx_scatter_ranges(ctx, cnt, ctx->keys.p, s)
                                : launch_tx_scatter(ctx, cnt, ctx->keys.p, s));
         if (i == 0) STAGE("scatter");
-        CK(launch_ss_bins(ctx, Si, nbk, PB, s));
+        CK(launch_ss_bins(ctx, Si, nbk, PB, s, ns == 0));
         if (i == 0) STAGE("summaries");
     }
     ctx->hp = hg.saved;

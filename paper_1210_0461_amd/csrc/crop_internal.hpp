@@ -352,8 +352,10 @@ constexpr uint32_t kSsBatchWide = 1024;   // ... with 64-bit keys
 constexpr uint32_t kSsBatchOuter = 1024;  // ... of outer-product terms
 size_t ss_bins_smem_bytes(uint32_t nbk, uint32_t ell, bool wide_key, bool outer, uint32_t MB);
 uint32_t ss_block_threads(uint32_t nbk, uint32_t ell);
+// fresh: start every bin from empty summaries instead of reading the
+// (cleared, pinned) state; every slot is written back either way
 hipError_t launch_ss_bins(const crop_ctx *c, const SsState &S, uint32_t nbk, uint64_t PB,
-                          hipStream_t s);
+                          hipStream_t s, bool fresh = false);
 hipError_t launch_zero32(uint32_t *p, uint32_t n, hipStream_t s);
 hipError_t launch_topk(const SsState &S, uint32_t K, bool outer, bool by_lower, bool err_is_lower,
                        const uint8_t *votes, uint32_t *st, uint32_t *hist, uint32_t *cand,

@@ -317,7 +317,7 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
             uint32_t nbk, uint32_t ell, HashParams hp, uint64_t PB, bool narrow,
             uint32_t *counter, uint64_t *__restrict__ g_key, uint32_t *__restrict__ g_cnt,
             uint32_t *__restrict__ g_err, float *__restrict__ g_val, uint8_t *__restrict__ g_flag,
-            uint32_t *__restrict__ g_key32)
+            uint32_t *__restrict__ g_key32, bool fresh)
 {
     static_assert(G == 16 || G == 32 || G == 64, "group width");
     static_assert((MB & (MB - 1)) == 0, "micro-batch is a power of two");
@@ -362,7 +362,19 @@ k_ss_groups(const uint32_t *__restrict__ bin_off, const uint32_t *__restrict__ o
         if (q >= NB) break;
         const uint32_t b = order[q];
         const uint64_t g0 = (uint64_t)b * nslot;
+        // the bin's state: empty when the run starts from empty summaries
+        // (fresh: nothing pinned; every slot of every bin is written back
+        // below, so the global state needs no clearing), else as cleared and
+        // pinned before the launch
         for (uint32_t s = threadIdx.x; s < nslot; s += BS) {
+            if (fresh) {
+                s_k[s] = (KeyT)0;
+                s_c[s] = 0;
+                s_e[s] = 0;
+                if (OUTER) s_v[s] = 0.0f;
+                s_f[s] = 0;
+                continue;
+            }
             const uint64_t g = g_key[g0 + s];
             // seeded slots carry a 64-bit pair key; narrow runs compare packed keys
             s_k[s] = narrow ? (KeyT)(((uint32_t)(g >> 32) << 16) | (uint32_t)(g & 0xFFFFu))
@@ -1281,7 +1293,7 @@ uint32_t ss_block_threads(uint32_t nbk, uint32_t ell)
 template <int G, class KeyT, bool OUTER, int MB>
 static void launch_ss_k(const crop_ctx *c, const SsState &S, uint32_t nbk, uint64_t PB,
                         uint32_t grid, uint32_t bs, bool narrow, const KeyT *keys,
-                        const float *vals, hipStream_t s)
+                        const float *vals, bool fresh, hipStream_t s)
 {
     const RoutePlan &pl = c->plan;
     const uint32_t ell = c->ss_ell;
@@ -1290,36 +1302,39 @@ static void launch_ss_k(const crop_ctx *c, const SsState &S, uint32_t nbk, uint6
         hipLaunchKernelGGL((k_ss_groups<G, KeyT, OUTER, MB, true>), dim3(grid), dim3(bs), sm, s,
                            c->bin_off.as<uint32_t>(), c->bin_order.as<uint32_t>(), keys, vals,
                            pl.NB, nbk, ell, c->hp, PB, narrow, c->counter.as<uint32_t>(), S.key,
-                           S.cnt, S.err, S.val, S.flag, S.key32);
+                           S.cnt, S.err, S.val, S.flag, S.key32, fresh);
     else
         hipLaunchKernelGGL((k_ss_groups<G, KeyT, OUTER, MB, false>), dim3(grid), dim3(bs), sm, s,
                            c->bin_off.as<uint32_t>(), c->bin_order.as<uint32_t>(), keys, vals,
                            pl.NB, nbk, ell, c->hp, PB, narrow, c->counter.as<uint32_t>(), S.key,
-                           S.cnt, S.err, S.val, S.flag, S.key32);
+                           S.cnt, S.err, S.val, S.flag, S.key32, fresh);
 }
 
 template <int G>
 static void launch_ss_g(const crop_ctx *c, const SsState &S, uint32_t nbk, uint64_t PB,
-                        uint32_t grid, uint32_t bs, hipStream_t s)
+                        uint32_t grid, uint32_t bs, bool fresh, hipStream_t s)
 {
     const RoutePlan &pl = c->plan;
     if (c->in.mode == Mode::Outer)
         launch_ss_k<G, uint64_t, true, kSsBatchOuter>(c, S, nbk, PB, grid, bs, false,
                                                        c->keys.as<uint64_t>(),
-                                                       c->vals.as<float>(), s);
+                                                       c->vals.as<float>(), fresh, s);
     else if (c->in.wide_keys)
         launch_ss_k<G, uint64_t, false, kSsBatchWide>(c, S, nbk, PB, grid, bs, false,
-                                                       c->keys.as<uint64_t>(), nullptr, s);
+                                                       c->keys.as<uint64_t>(), nullptr, fresh,
+                                                       s);
     else if (pl.ss_mb == kSsBatchTxLarge)
         launch_ss_k<G, uint32_t, false, kSsBatchTxLarge>(c, S, nbk, PB, grid, bs, true,
-                                                          c->keys.as<uint32_t>(), nullptr, s);
+                                                          c->keys.as<uint32_t>(), nullptr, fresh,
+                                                          s);
     else
         launch_ss_k<G, uint32_t, false, kSsBatchTx>(c, S, nbk, PB, grid, bs, true,
-                                                     c->keys.as<uint32_t>(), nullptr, s);
+                                                     c->keys.as<uint32_t>(), nullptr, fresh,
+                                                     s);
 }
 
 hipError_t launch_ss_bins(const crop_ctx *c, const SsState &S, uint32_t nbk, uint64_t PB,
-                          hipStream_t s)
+                          hipStream_t s, bool fresh)
 {
     int dev = 0, cus = 256;
     if (hipGetDevice(&dev) == hipSuccess)
@@ -1328,9 +1343,9 @@ hipError_t launch_ss_bins(const crop_ctx *c, const SsState &S, uint32_t nbk, uin
     const uint32_t bs = ss_block_threads(nbk, ell);
     const uint32_t grid = std::min<uint32_t>(c->plan.NB, 4 * (uint32_t)cus);
     switch (ss_group_width(ell)) {
-    case 16: launch_ss_g<16>(c, S, nbk, PB, grid, bs, s); break;
-    case 32: launch_ss_g<32>(c, S, nbk, PB, grid, bs, s); break;
-    default: launch_ss_g<64>(c, S, nbk, PB, grid, bs, s); break;
+    case 16: launch_ss_g<16>(c, S, nbk, PB, grid, bs, fresh, s); break;
+    case 32: launch_ss_g<32>(c, S, nbk, PB, grid, bs, fresh, s); break;
+    default: launch_ss_g<64>(c, S, nbk, PB, grid, bs, fresh, s); break;
     }
     return hipGetLastError();
 }
